@@ -1,0 +1,217 @@
+"""Python access to the FP64 CPU oracle — TEST INFRASTRUCTURE ONLY.
+
+The oracle (``hjpd_oracle.c``) is a plain sequential double-precision
+implementation of the primal-dual splitting of Lin, Chow and Osher
+(arXiv 1803.01215, section 5.1 Algorithm 1 and Appendix A.1.1 for optimal
+control; Algorithm 3 and Appendix A.2.1 for games).  Only ``tests/``, the
+smoke check and the CPU-baseline leg of the benchmark may import this module.
+It shares no code with the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hjpd_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+H_CNORM, H_QUADROTOR, H_PURSUIT_EVASION, H_LINEAR_TANH = 0, 1, 2, 3
+G_NORM, G_QUAD_SHIFT, G_PAIR_DIST, G_QUAD_FORM = 0, 1, 2, 3
+PT_CONVERGED, PT_MAXITER, PT_NONFINITE, PT_BADINPUT = 0, 1, 2, 3
+ARR_X, ARR_P, ARR_Y, ARR_Q = 0, 1, 2, 3
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, OpenMP across points only)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int), ("g", ctypes.c_int), ("d", ctypes.c_int), ("d_y", ctypes.c_int),
+                ("hp", ctypes.POINTER(ctypes.c_double)), ("gp", ctypes.POINTER(ctypes.c_double))]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        D = ctypes.POINTER(ctypes.c_double)
+        I = ctypes.POINTER(ctypes.c_int)
+        P = ctypes.POINTER(_Problem)
+        _lib.or_solve.argtypes = [P, ctypes.c_long, D, D, I, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                  D, I, I, D, D, ctypes.c_int]
+        _lib.or_solve.restype = ctypes.c_int
+        _lib.or_splitmix64_mix.argtypes = [ctypes.c_uint64]
+        _lib.or_splitmix64_mix.restype = ctypes.c_uint64
+        _lib.or_splitmix64_at.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        _lib.or_splitmix64_at.restype = ctypes.c_uint64
+        _lib.or_init_noise.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        _lib.or_init_noise.restype = ctypes.c_double
+        _lib.or_shrink2.argtypes = [D, ctypes.c_double, ctypes.c_int, D]
+        _lib.or_H.argtypes = [P, D, D, ctypes.c_double]
+        _lib.or_H.restype = ctypes.c_double
+        _lib.or_grad_x_H.argtypes = [P, D, D, ctypes.c_double, D]
+        _lib.or_prox_p.argtypes = [P, D, D, ctypes.c_double, ctypes.c_double, D]
+        _lib.or_g.argtypes = [P, D]
+        _lib.or_g.restype = ctypes.c_double
+        _lib.or_prox_g.argtypes = [P, D, ctypes.c_double, D]
+        _lib.or_prox_g.restype = ctypes.c_int
+        _lib.or_game_H.argtypes = [P, D, D, D, D]
+        _lib.or_game_H.restype = ctypes.c_double
+        _lib.or_game_prox_p.argtypes = [P, D, D, D, D, ctypes.c_double, D]
+        _lib.or_game_prox_q.argtypes = [P, D, D, D, D, ctypes.c_double, D]
+        _lib.or_game_grad_x.argtypes = [P, D, D, D, D, D]
+        _lib.or_game_grad_y.argtypes = [P, D, D, D, D, D]
+        _lib.or_game_prox_x0.argtypes = [P, D, D, ctypes.c_double, D]
+        _lib.or_game_stretch_y0.argtypes = [P, D, D, ctypes.c_double, D]
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+@dataclass
+class Problem:
+    """One problem family instance: Hamiltonian H, initial cost g and their parameters."""
+    H: int
+    g: int
+    d: int
+    d_y: int
+    hp: np.ndarray
+    gp: np.ndarray
+
+    def __post_init__(self):
+        self.hp = np.ascontiguousarray(self.hp, dtype=np.float64).ravel()
+        self.gp = np.ascontiguousarray(self.gp, dtype=np.float64).ravel()
+        self._c = _Problem(self.H, self.g, self.d, self.d_y, _dp(self.hp), _dp(self.gp))
+
+    @property
+    def c(self):
+        return ctypes.byref(self._c)
+
+    # --- point-wise pieces (for pinning tests) ---
+    def H_val(self, x, p, s=0.0):
+        x = np.ascontiguousarray(x, np.float64); p = np.ascontiguousarray(p, np.float64)
+        return lib().or_H(self.c, _dp(x), _dp(p), s)
+
+    def grad_x_H(self, x, p, s=0.0):
+        x = np.ascontiguousarray(x, np.float64); p = np.ascontiguousarray(p, np.float64)
+        out = np.zeros(self.d)
+        lib().or_grad_x_H(self.c, _dp(x), _dp(p), s, _dp(out))
+        return out
+
+    def prox_p(self, x, v, lam, s=0.0):
+        x = np.ascontiguousarray(x, np.float64); v = np.ascontiguousarray(v, np.float64)
+        out = np.zeros(self.d)
+        lib().or_prox_p(self.c, _dp(x), _dp(v), lam, s, _dp(out))
+        return out
+
+    def g_val(self, x0):
+        x0 = np.ascontiguousarray(x0, np.float64)
+        return lib().or_g(self.c, _dp(x0))
+
+    def prox_g(self, v, tau):
+        v = np.ascontiguousarray(v, np.float64)
+        out = np.zeros(self.d)
+        assert lib().or_prox_g(self.c, _dp(v), tau, _dp(out)) == 0
+        return out
+
+    def game_H(self, x, y, p, q):
+        a = [np.ascontiguousarray(z, np.float64) for z in (x, y, p, q)]
+        return lib().or_game_H(self.c, *[_dp(z) for z in a])
+
+    def _game_vec(self, fn, n_out, *args):
+        a = [np.ascontiguousarray(z, np.float64) if isinstance(z, (np.ndarray, list, tuple)) else z for z in args]
+        out = np.zeros(n_out)
+        conv = [(_dp(z) if isinstance(z, np.ndarray) else z) for z in a]
+        fn(self.c, *conv, _dp(out))
+        return out
+
+    def game_prox_p(self, x, y, q, v, lam):
+        return self._game_vec(lib().or_game_prox_p, self.d - self.d_y, x, y, q, v, lam)
+
+    def game_prox_q(self, x, y, p, v, lam):
+        return self._game_vec(lib().or_game_prox_q, self.d_y, x, y, p, v, lam)
+
+    def game_grad_x(self, x, y, p, q):
+        return self._game_vec(lib().or_game_grad_x, self.d - self.d_y, x, y, p, q)
+
+    def game_grad_y(self, x, y, p, q):
+        return self._game_vec(lib().or_game_grad_y, self.d_y, x, y, p, q)
+
+    def game_prox_x0(self, v, y0, tau):
+        return self._game_vec(lib().or_game_prox_x0, self.d - self.d_y, v, y0, tau)
+
+    def game_stretch_y0(self, v, x0, tau):
+        return self._game_vec(lib().or_game_stretch_y0, self.d_y, v, x0, tau)
+
+
+@dataclass
+class Result:
+    phi: np.ndarray
+    iters: np.ndarray
+    status: np.ndarray
+    x_traj: np.ndarray | None
+    p_traj: np.ndarray | None
+
+
+def solve(pb: Problem, x, t, N, *, sigma, tau, theta=1.0, tol=1e-8, max_iter=5000, fixed_iters=False,
+          seed=0, N_max=None, ids=None, traj=False, threads=0) -> Result:
+    """Run the oracle over a batch of points.
+
+    x: [n, d]; t: [n]; N: [n] (intervals per point).  ids: each point's
+    index in the full workload (selects its random start), default 0..n-1.
+    In fixed-iteration mode exactly max_iter iterations are run (unless a
+    non-finite value stops the point first).
+    """
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, pb.d)
+    n = x.shape[0]
+    t = np.ascontiguousarray(np.broadcast_to(np.asarray(t, np.float64), (n,)))
+    N = np.ascontiguousarray(np.broadcast_to(np.asarray(N, np.int32), (n,))).astype(np.int32)
+    if N_max is None:
+        N_max = int(N.max()) if n else 1
+    phi = np.zeros(n); iters = np.zeros(n, np.int32); status = np.zeros(n, np.int32)
+    xt = np.zeros((n, N_max + 1, pb.d)) if traj else None
+    pt = np.zeros((n, N_max + 1, pb.d)) if traj else None
+    idp = None
+    if ids is not None:
+        ids = np.ascontiguousarray(ids, np.int64)
+        idp = ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    I = ctypes.POINTER(ctypes.c_int)
+    rc = lib().or_solve(pb.c, n, _dp(x), _dp(t), N.ctypes.data_as(I), sigma, tau, theta, tol, int(max_iter),
+                        int(bool(fixed_iters)), int(seed) & (2**64 - 1), int(N_max), idp, _dp(phi),
+                        iters.ctypes.data_as(I), status.ctypes.data_as(I),
+                        _dp(xt) if traj else None, _dp(pt) if traj else None, int(threads))
+    if rc != 0:
+        raise ValueError("oracle: unsupported problem")
+    return Result(phi, iters, status, xt, pt)
+
+
+def init_noise(seed, point, arr, j, i):
+    return lib().or_init_noise(int(seed) & (2**64 - 1), int(point), arr, j, i)
+
+
+def splitmix64_at(seed, k):
+    return lib().or_splitmix64_at(int(seed) & (2**64 - 1), int(k))
+
+
+def shrink2(v, lam):
+    v = np.ascontiguousarray(v, np.float64)
+    out = np.zeros_like(v)
+    lib().or_shrink2(_dp(v), lam, v.size, _dp(out))
+    return out

@@ -1,0 +1,620 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test checks the oracle against a fact the paper or plain mathematics
+fixes: a published generator test vector, the proximal-map definition (eq.
+prox) solved by brute force, the Hamiltonian as a max/min over controls
+(section 2) evaluated by brute force on dynamics written independently here,
+central differences, the classical Hopf-Lax closed form (section 2.1), the
+discrete Riccati recursion of the linear-quadratic case, the envelope identity
+of the discrete saddle, direct shooting of the discretised control problem
+(section 4.1), and stationarity of an independently written Lagrangian.
+"""
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import minimize
+
+import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _rng(k):
+    return np.random.default_rng(9000 + k)
+
+
+# --------------------------------------------------------------------------
+# Random start generator
+# --------------------------------------------------------------------------
+
+def test_splitmix64_matches_published_vectors(oracle_mod):
+    vals = [int(l) for l in open(os.path.join(HERE, "golden", "splitmix64_seed1234567.txt"))
+            if l.strip() and not l.startswith("#")]
+    got = [oracle_mod.splitmix64_at(1234567, k) for k in range(1, 6)]
+    assert got == vals
+
+
+def test_init_noise_range_and_spread(oracle_mod):
+    v = np.array([oracle_mod.init_noise(77, pt, arr, j, i)
+                  for pt in range(8) for arr in range(4) for j in range(6) for i in range(5)])
+    assert v.min() >= -0.1 and v.max() < 0.1
+    assert abs(v.mean()) < 0.01
+    assert len(np.unique(v)) == v.size
+    # uniform on [-0.1, 0.1]: variance 0.01/3
+    assert abs(v.var() - 0.01 / 3) < 0.0008
+
+
+# --------------------------------------------------------------------------
+# Dynamics written independently of the oracle (physical, forward time).
+# --------------------------------------------------------------------------
+
+def _rot(axis, a):
+    c, s = np.cos(a), np.sin(a)
+    if axis == "x":
+        return np.array([[1, 0, 0], [0, c, -s], [0, s, c]])
+    if axis == "y":
+        return np.array([[c, 0, s], [0, 1, 0], [-s, 0, c]])
+    return np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]])
+
+
+def quad_f_phys(x, u, hp):
+    """Quadrotor-like dynamics: r' = v, v' = (u1/m) R e3 - g e3, eta' = W omega,
+    omega' = J^{-1} u_{2:4}; R = Rz(psi) Ry(theta) Rx(phi); W is the inverse of
+    the map from Euler-angle rates to body rates, pitch clamped inside it."""
+    m, J, gz, clamp = hp[0], hp[1:4], hp[4], hp[5]
+    v, eta, om = x[3:6], x[6:9], x[9:12]
+    ph, th, ps = eta
+    R = _rot("z", ps) @ _rot("y", th) @ _rot("x", ph)
+    thc = np.clip(th, -clamp, clamp)
+    E = np.array([[1, 0, -np.sin(thc)],
+                  [0, np.cos(ph), np.sin(ph) * np.cos(thc)],
+                  [0, -np.sin(ph), np.cos(ph) * np.cos(thc)]])
+    Wm = np.linalg.inv(E)
+    f = np.zeros(12)
+    f[0:3] = v
+    f[3:6] = (u[0] / m) * R[:, 2] - gz * np.array([0, 0, 1.0])
+    f[6:9] = Wm @ om
+    f[9:12] = u[1:4] / J
+    return f
+
+
+def pe_f_phys(X, uP, uE, kappa):
+    def pm(s, u):
+        v = s[3:6]
+        return np.concatenate([v, -kappa * np.linalg.norm(v) * v + u])
+    return np.concatenate([pm(X[0:6], uP), pm(X[6:12], uE)])
+
+
+def lt_f_phys(x, u, A, eps):
+    return A @ x + eps * np.tanh(x) + u
+
+
+def H_by_max_over_controls(f_phys, L, p, m_u, rng):
+    """Paper's initial-value Hamiltonian H = max_u <-f_phys(u), p> - L(u)
+    (time-reversed dynamics, section 2.1), by numerical maximisation."""
+    obj = lambda u: -(np.dot(-f_phys(u), p) - L(u))
+    best = None
+    for _ in range(3):
+        r = minimize(obj, rng.standard_normal(m_u), method="BFGS", options={"gtol": 1e-11})
+        if best is None or r.fun < best.fun:
+            best = r
+    return -best.fun
+
+
+# --------------------------------------------------------------------------
+# Hamiltonians vs brute force over the controls
+# --------------------------------------------------------------------------
+
+def test_cnorm_H_is_max_over_unit_ball(oracle_mod):
+    rng = _rng(1)
+    alpha = 0.5
+    pb = oracle_mod.Problem(W.H_CNORM, W.G_NORM, 3, 0, [alpha], [1.0])
+    for _ in range(20):
+        x, p = rng.standard_normal(3), rng.standard_normal(3)
+        c = 1 + alpha * np.sin(x[0]) * np.cos(x[1])
+        # max over ||u|| <= 1 of <c u, p>: dense sampling of the sphere, then polish
+        u = rng.standard_normal((200000, 3))
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        brute = (c * u @ p).max()
+        h = pb.H_val(x, p)
+        assert brute <= h + 1e-12
+        assert h - brute < 1e-3 * np.linalg.norm(p) * c
+        # exact maximiser u = p/|p| attains it
+        assert abs(c * np.linalg.norm(p) - h) < 1e-12
+
+
+def test_quadrotor_H_is_max_over_controls(oracle_mod):
+    rng = _rng(2)
+    hp = W.QUAD_PARAMS
+    pb = oracle_mod.Problem(W.H_QUADROTOR, W.G_QUAD_SHIFT, 12, 0, hp, np.zeros(13))
+    for _ in range(12):
+        x = rng.uniform(-1, 1, 12)
+        x[7] = rng.uniform(-1.6, 1.6)  # pitch on both sides of the clamp
+        p = rng.standard_normal(12) * np.array([1, 1, 1, 1, 1, 1, 1, 1, 1, 0.01, 0.01, 0.01])
+        brute = H_by_max_over_controls(lambda u: quad_f_phys(x, u, hp), lambda u: 0.5 * u @ u, p, 4, rng)
+        assert abs(brute - pb.H_val(x, p)) < 1e-8 * max(1, abs(brute))
+
+
+def test_pursuit_H_is_minmax_over_controls_and_isaacs(oracle_mod):
+    rng = _rng(3)
+    kappa, wP, wE = W.PE_PARAMS
+    pb = oracle_mod.Problem(W.H_PURSUIT_EVASION, W.G_PAIR_DIST, 12, 6, W.PE_PARAMS, [0.5])
+    for _ in range(10):
+        X = rng.uniform(-1, 1, 12)
+        p, q = rng.standard_normal(6), rng.standard_normal(6)
+        P = np.concatenate([p, -q])  # full costate (p, -q), section 4.2
+        # terminal-value H_c = min_uP max_uE <P, f> + |uP|^2/2 - |uE|^2/(2 wE)
+        def inner_max(uP):
+            obj = lambda uE: -(P @ pe_f_phys(X, uP, uE, kappa) + 0.5 * uP @ uP - 0.5 / wE * uE @ uE)
+            return -minimize(obj, np.zeros(3), method="BFGS", options={"gtol": 1e-11}).fun
+        minmax = minimize(inner_max, np.zeros(3), method="BFGS", options={"gtol": 1e-10}).fun
+
+        def inner_min(uE):
+            obj = lambda uP: P @ pe_f_phys(X, uP, uE, kappa) + 0.5 * uP @ uP - 0.5 / wE * uE @ uE
+            return minimize(obj, np.zeros(3), method="BFGS", options={"gtol": 1e-11}).fun
+        maxmin = -minimize(lambda uE: -inner_min(uE), np.zeros(3), method="BFGS", options={"gtol": 1e-10}).fun
+        assert abs(minmax - maxmin) < 1e-7  # Isaacs condition holds
+        H_paper = -minmax                   # initial-value convention
+        assert abs(H_paper - pb.game_H(X[:6], X[6:], p, q)) < 1e-7
+        assert abs(H_paper - pb.H_val(X, P)) < 1e-7
+
+
+def test_linear_tanh_H_is_max_over_controls(oracle_mod):
+    rng = _rng(4)
+    d, eps = 5, 0.1
+    A = rng.standard_normal((d, d)) / np.sqrt(d)
+    pb = oracle_mod.Problem(W.H_LINEAR_TANH, W.G_QUAD_FORM, d, 0, np.concatenate([[eps], A.ravel()]), np.eye(d))
+    for _ in range(10):
+        x, p = rng.standard_normal(d), rng.standard_normal(d)
+        brute = H_by_max_over_controls(lambda u: lt_f_phys(x, u, A, eps), lambda u: 0.5 * u @ u, p, d, rng)
+        assert abs(brute - pb.H_val(x, p)) < 1e-8 * max(1, abs(brute))
+
+
+# --------------------------------------------------------------------------
+# Gradients in x vs central differences
+# --------------------------------------------------------------------------
+
+def _fd_grad(f, x, h=1e-6):
+    g = np.zeros_like(x)
+    for i in range(x.size):
+        e = np.zeros_like(x); e[i] = h
+        g[i] = (f(x + e) - f(x - e)) / (2 * h)
+    return g
+
+
+@pytest.mark.parametrize("family", ["cnorm", "quadrotor", "lintanh"])
+def test_grad_x_H_matches_central_differences(oracle_mod, family):
+    rng = _rng(5)
+    if family == "cnorm":
+        pb = oracle_mod.Problem(W.H_CNORM, W.G_NORM, 4, 0, [0.7], [1.0]); d = 4
+    elif family == "quadrotor":
+        pb = oracle_mod.Problem(W.H_QUADROTOR, W.G_QUAD_SHIFT, 12, 0, W.QUAD_PARAMS, np.zeros(13)); d = 12
+    else:
+        d = 6
+        A = rng.standard_normal((d, d))
+        pb = oracle_mod.Problem(W.H_LINEAR_TANH, W.G_QUAD_FORM, d, 0, np.concatenate([[0.3], A.ravel()]), np.eye(d))
+    for _ in range(15):
+        x, p = rng.uniform(-1.2, 1.2, d), rng.standard_normal(d)
+        if family == "quadrotor":
+            x[7] = rng.choice([rng.uniform(-1.25, 1.25), rng.uniform(1.35, 1.5)])
+            p[9:] *= 0.01  # keeps |H| moderate so differences are not rounding-bound
+        g = pb.grad_x_H(x, p)
+        fd = _fd_grad(lambda z: pb.H_val(z, p), x)
+        assert np.max(np.abs(g - fd)) < 1e-6 * max(1, np.max(np.abs(fd)))
+
+
+def test_game_grads_match_central_differences(oracle_mod):
+    rng = _rng(6)
+    pb = oracle_mod.Problem(W.H_PURSUIT_EVASION, W.G_PAIR_DIST, 12, 6, W.PE_PARAMS, [0.5])
+    for _ in range(15):
+        x, y, p, q = rng.uniform(-1, 1, 6), rng.uniform(-1, 1, 6), rng.standard_normal(6), rng.standard_normal(6)
+        gx = pb.game_grad_x(x, y, p, q)
+        gy = pb.game_grad_y(x, y, p, q)
+        assert np.allclose(gx, _fd_grad(lambda z: pb.game_H(z, y, p, q), x), atol=1e-7)
+        assert np.allclose(gy, _fd_grad(lambda z: pb.game_H(x, z, p, q), y), atol=1e-7)
+        # full-state gradient in the (X, P) form agrees
+        g = pb.grad_x_H(np.concatenate([x, y]), np.concatenate([p, -q]))
+        assert np.allclose(g, np.concatenate([gx, gy]), atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Proximal maps vs their definition (eq. prox), by brute-force minimisation
+# --------------------------------------------------------------------------
+
+def _argmin(obj, x0, rng, starts=4):
+    best = None
+    for k in range(starts):
+        s = x0 if k == 0 else x0 + 0.3 * rng.standard_normal(x0.size)
+        r = minimize(obj, s, method="Powell", options={"xtol": 1e-12, "ftol": 1e-15, "maxfev": 200000})
+        if best is None or r.fun < best.fun:
+            best = r
+    return best
+
+
+def test_shrink2_is_prox_of_scaled_norm(oracle_mod):
+    rng = _rng(7)
+    for _ in range(20):
+        v = rng.standard_normal(4) * rng.choice([0.1, 1, 3])
+        lam = rng.uniform(0.05, 2)
+        out = oracle_mod.shrink2(v, lam)
+        obj = lambda y: lam * np.linalg.norm(y) + 0.5 * np.sum((y - v) ** 2)
+        r = _argmin(obj, v.copy(), rng)
+        assert obj(out) <= r.fun + 1e-10
+        assert np.allclose(out, r.x, atol=1e-5)
+    assert np.all(oracle_mod.shrink2(np.zeros(3), 0.5) == 0)
+
+
+@pytest.mark.parametrize("family", ["cnorm", "quadrotor", "lintanh"])
+def test_prox_p_is_argmin(oracle_mod, family):
+    rng = _rng(8)
+    if family == "cnorm":
+        d = 3
+        pb = oracle_mod.Problem(W.H_CNORM, W.G_NORM, d, 0, [0.5], [1.0])
+        Hf = lambda x, p: (1 + 0.5 * np.sin(x[0]) * np.cos(x[1])) * np.linalg.norm(p)
+    elif family == "quadrotor":
+        d = 12
+        hp = W.QUAD_PARAMS
+        pb = oracle_mod.Problem(W.H_QUADROTOR, W.G_QUAD_SHIFT, d, 0, hp, np.zeros(13))
+        # H = -<p, f0> + |B^T p|^2/2, with f0 and B from the independent dynamics
+        def Hf(x, p):
+            f0 = quad_f_phys(x, np.zeros(4), hp)
+            B = np.stack([quad_f_phys(x, e, hp) - f0 for e in np.eye(4)], axis=1)
+            return -p @ f0 + 0.5 * np.sum((B.T @ p) ** 2)
+    else:
+        d = 4
+        A = rng.standard_normal((d, d))
+        pb = oracle_mod.Problem(W.H_LINEAR_TANH, W.G_QUAD_FORM, d, 0, np.concatenate([[0.2], A.ravel()]), np.eye(d))
+        Hf = lambda x, p: -p @ (A @ x + 0.2 * np.tanh(x)) + 0.5 * p @ p
+    for _ in range(8):
+        x, v = rng.uniform(-1, 1, d), rng.standard_normal(d)
+        lam = rng.uniform(0.01, 0.5) if family != "quadrotor" else rng.uniform(1e-6, 1e-4)
+        out = pb.prox_p(x, v, lam)
+        obj = lambda p: lam * Hf(x, p) + 0.5 * np.sum((p - v) ** 2)
+        if family == "cnorm":
+            r = _argmin(obj, v.copy(), rng)
+            assert obj(out) <= r.fun + 1e-10
+            assert np.allclose(out, r.x, atol=1e-5)
+        else:
+            # smooth strongly convex objective: its gradient vanishes at the prox
+            g = _fd_grad(obj, out, h=1e-6)
+            assert np.max(np.abs(g)) < 1e-6 * max(1, np.max(np.abs(v)))
+
+
+def test_prox_g_is_argmin(oracle_mod):
+    rng = _rng(9)
+    d = 4
+    a = rng.standard_normal(d)
+    Q = rng.standard_normal((d, d))
+    Q = Q @ Q.T + np.eye(d) + 0.3 * rng.standard_normal((d, d))  # not symmetric: g uses (Q+Q^T)/2
+    cases = [
+        (oracle_mod.Problem(W.H_CNORM, W.G_NORM, d, 0, [0.0], [1.5]), lambda y: np.linalg.norm(y) - 1.5),
+        (oracle_mod.Problem(W.H_CNORM, W.G_QUAD_SHIFT, d, 0, [0.0], np.concatenate([[1.0], a])),
+         lambda y: 0.5 * np.sum((y - a) ** 2) - 1.0),
+        (oracle_mod.Problem(W.H_LINEAR_TANH, W.G_QUAD_FORM, d, 0, np.zeros(1 + d * d), Q.ravel()),
+         lambda y: 0.5 * y @ Q @ y),
+    ]
+    for pb, gf in cases:
+        for _ in range(6):
+            v, tau = rng.standard_normal(d) * 2, rng.uniform(0.05, 1.0)
+            assert abs(pb.g_val(v) - gf(v)) < 1e-12
+            out = pb.prox_g(v, tau)
+            obj = lambda y: tau * gf(y) + 0.5 * np.sum((y - v) ** 2)
+            r = _argmin(obj, v.copy(), rng)
+            assert obj(out) <= r.fun + 1e-10
+            assert np.allclose(out, r.x, atol=1e-5)
+
+
+def test_game_node0_maps_are_argmin_argmax(oracle_mod):
+    rng = _rng(10)
+    pb = oracle_mod.Problem(W.H_PURSUIT_EVASION, W.G_PAIR_DIST, 12, 6, W.PE_PARAMS, [0.5])
+    g = lambda x, y: np.linalg.norm(x[:3] - y[:3]) - 0.5
+    for _ in range(6):
+        v, y0, x0 = rng.uniform(-1, 1, 6), rng.uniform(-1, 1, 6), rng.uniform(-1, 1, 6)
+        tau = rng.uniform(0.005, 0.2)
+        assert abs(pb.g_val(np.concatenate([x0, y0])) - g(x0, y0)) < 1e-12
+        out = pb.game_prox_x0(v, y0, tau)
+        obj = lambda x: tau * g(x, y0) + 0.5 * np.sum((x - v) ** 2)
+        r = _argmin(obj, v.copy(), rng)
+        assert obj(out) <= r.fun + 1e-10 and np.allclose(out, r.x, atol=1e-5)
+        out = pb.game_stretch_y0(v, x0, tau)
+        obj = lambda y: -tau * g(x0, y) + 0.5 * np.sum((y - v) ** 2)
+        r = _argmin(obj, v.copy(), rng)
+        assert obj(out) <= r.fun + 1e-10 and np.allclose(out, r.x, atol=1e-5)
+    # tie-break at v = r_P: move by tau along e_1
+    x0 = np.array([0.3, -0.2, 0.1, 0, 0, 0.0])
+    out = pb.game_stretch_y0(x0.copy(), x0, 0.1)
+    assert np.allclose(out[:3], x0[:3] + [0.1, 0, 0])
+
+
+# --------------------------------------------------------------------------
+# Whole-path pins
+# --------------------------------------------------------------------------
+
+def test_eikonal_matches_hopf_lax_closed_form(oracle_mod):
+    """H = ||p||, g = ||x|| - 1: the discrete problem is min over ||x_0 - x|| <= t
+    of g(x_0) exactly, i.e. phi = max(||x|| - t, 0) - 1 (classical Lax formula,
+    section 2.1).  For ||x|| > t the minimiser x_0 = x (1 - t/||x||) is unique and
+    every multiplier equals x/||x||."""
+    w = W.eikonal2d(64)
+    pb = oracle_mod.Problem(w.H, w.g, w.d, w.d_y, w.hp, w.gp)
+    r = oracle_mod.solve(pb, w.x, w.t, w.N, sigma=w.sigma, tau=w.tau, tol=1e-26, max_iter=30000,
+                         seed=w.init_seed, traj=True)
+    nx = np.linalg.norm(w.x, axis=1)
+    exact = np.maximum(nx - w.t, 0) - 1
+    assert np.max(np.abs(r.phi - exact)) < 1e-9
+    far = nx > w.t + 0.05
+    x0_exact = w.x * (1 - w.t / nx)[:, None]
+    assert np.max(np.abs(r.x_traj[far, 0, :] - x0_exact[far])) < 1e-6
+    assert np.max(np.abs(r.p_traj[far, -1, :] - (w.x / nx[:, None])[far])) < 1e-6
+    # default tolerance of the workload: value still within 1e-6
+    r2 = oracle_mod.solve(pb, w.x, w.t, w.N, sigma=w.sigma, tau=w.tau, tol=w.tol, max_iter=w.max_iter,
+                          seed=w.init_seed)
+    assert np.all(r2.status == 0)
+    assert np.max(np.abs(r2.phi - exact)) < 1e-6
+
+
+def test_cnorm_constant_speed_matches_closed_form(oracle_mod):
+    """c = 1 (alpha = 0), g = ||x-a||^2/2 - 1: phi = max(||x - a|| - t, 0)^2/2 - 1 exactly."""
+    w = W.cnorm10(48, alpha=0.0)
+    pb = oracle_mod.Problem(w.H, w.g, w.d, w.d_y, w.hp, w.gp)
+    r = oracle_mod.solve(pb, w.x, w.t, w.N, sigma=w.sigma, tau=w.tau, tol=1e-26, max_iter=40000,
+                         seed=w.init_seed)
+    a = w.gp[1:]
+    exact = 0.5 * np.maximum(np.linalg.norm(w.x - a, axis=1) - w.t, 0) ** 2 - 1
+    assert np.max(np.abs(r.phi - exact)) < 1e-9
+
+
+def test_linear_quadratic_matches_discrete_riccati(oracle_mod):
+    """eps = 0: H = -<p, A x> + |p|^2/2, g = x^T Q x/2.  Eliminating p_j gives
+    min sum |M x_j - x_{j-1}|^2/(2 delta) + g(x_0), M = I + delta A, whose value is
+    x^T P_N x / 2 with P_0 = Q_s, P_j = M^T P_{j-1} (I + delta P_{j-1})^{-1} M."""
+    rng = _rng(11)
+    d, N, t = 6, 12, 0.8
+    A = rng.standard_normal((d, d)) / np.sqrt(d)  # not symmetric: catches A vs A^T
+    Mq = rng.standard_normal((d, d))
+    Q = Mq @ Mq.T / d + 0.5 * np.eye(d)
+    pb = oracle_mod.Problem(W.H_LINEAR_TANH, W.G_QUAD_FORM, d, 0, np.concatenate([[0.0], A.ravel()]), Q.ravel())
+    x = rng.standard_normal((6, d))
+    r = oracle_mod.solve(pb, x, t, N, sigma=1.0, tau=0.25, tol=1e-28, max_iter=20000, seed=5)
+    delta = t / N
+    M = np.eye(d) + delta * A
+    P = Q.copy()
+    for _ in range(N):
+        P = M.T @ P @ np.linalg.solve(np.eye(d) + delta * P, M)
+    exact = 0.5 * np.einsum("ni,ij,nj->n", x, P, x)
+    assert np.max(np.abs(r.phi - exact) / np.maximum(1, np.abs(exact))) < 1e-10
+
+
+def _envelope_check(oracle_mod, pb, x, t, N, sigma, h=1e-5, tol=1e-28, max_iter=30000, rtol=1e-6):
+    r = oracle_mod.solve(pb, x[None], t, N, sigma=sigma, tau=0.25 / sigma, tol=tol, max_iter=max_iter,
+                         seed=3, traj=True)
+    pN = r.p_traj[0, N]
+    delta = t / N
+    env = pN - delta * pb.grad_x_H(x, pN, t)
+    fd = np.zeros_like(x)
+    for i in range(x.size):
+        e = np.zeros_like(x); e[i] = h
+        rp = oracle_mod.solve(pb, (x + e)[None], t, N, sigma=sigma, tau=0.25 / sigma, tol=tol, max_iter=max_iter, seed=3)
+        rm = oracle_mod.solve(pb, (x - e)[None], t, N, sigma=sigma, tau=0.25 / sigma, tol=tol, max_iter=max_iter, seed=3)
+        fd[i] = (rp.phi[0] - rm.phi[0]) / (2 * h)
+    assert np.max(np.abs(env - fd)) < rtol * max(1, np.max(np.abs(fd))), (env, fd)
+
+
+def test_envelope_identity_state_dependent_eikonal(oracle_mod):
+    """grad_x phi_delta = p_N - delta grad_x H(x, p_N): the value is the
+    Lagrangian at a stationary point and x enters only as x_N."""
+    rng = _rng(12)
+    w = W.cnorm10(4)
+    pb = oracle_mod.Problem(w.H, w.g, w.d, w.d_y, w.hp, w.gp)
+    for k in range(2):
+        _envelope_check(oracle_mod, pb, w.x[k], float(w.t[k]), 32, w.sigma)
+
+
+def test_envelope_identity_linear_tanh(oracle_mod):
+    rng = _rng(13)
+    d = 5
+    A = rng.standard_normal((d, d)) / np.sqrt(d)
+    Q = np.eye(d) + 0.2 * np.ones((d, d))
+    pb = oracle_mod.Problem(W.H_LINEAR_TANH, W.G_QUAD_FORM, d, 0, np.concatenate([[0.1], A.ravel()]), Q.ravel())
+    _envelope_check(oracle_mod, pb, rng.standard_normal(d), 1.0, 10, 1.0)
+
+
+def _shoot_min(f_phys_step, g, x, N, t, m_u, rng, starts=4, bounds_unit_ball=False):
+    """Direct shooting of the backward-Euler discretisation (section 4.1):
+    from x_N = x, x_{j-1} = x_j + delta f_phys(x_j, u_j) (physical time runs
+    from node N down to node 0), cost g(x_0) + delta sum_j L(u_j)."""
+    delta = t / N
+
+    def cost(U):
+        U = U.reshape(N, m_u)
+        s = x.copy()
+        run = 0.0
+        for j in range(N, 0, -1):
+            f, L = f_phys_step(s, U[j - 1])
+            s = s + delta * f
+            run += delta * L
+        return g(s) + run
+    best = None
+    for k in range(starts):
+        U0 = 0.1 * rng.standard_normal(N * m_u)
+        if bounds_unit_ball:
+            cons = [{"type": "ineq", "fun": (lambda U, j=j: 1.0 - np.sum(U.reshape(N, m_u)[j] ** 2))} for j in range(N)]
+            r = minimize(cost, U0, method="SLSQP", constraints=cons, options={"ftol": 1e-14, "maxiter": 2000})
+        else:
+            r = minimize(cost, U0, method="BFGS", options={"gtol": 1e-10})
+        if best is None or r.fun < best.fun:
+            best = r
+    return best.fun
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+def test_state_dependent_eikonal_matches_direct_shooting(oracle_mod, N):
+    """alpha != 0: phi equals the minimum over feasible discrete trajectories
+    (speed c(x_j) with ||u_j|| <= 1), found by SLSQP from several starts."""
+    rng = _rng(14 + N)
+    alpha, d = 0.5, 2
+    a = np.array([0.4, -0.3])
+    pb = oracle_mod.Problem(W.H_CNORM, W.G_QUAD_SHIFT, d, 0, [alpha], np.concatenate([[1.0], a]))
+    c = lambda z: 1 + alpha * np.sin(z[0]) * np.cos(z[1])
+    g = lambda z: 0.5 * np.sum((z - a) ** 2) - 1.0
+    step = lambda s, u: (c(s) * u, 0.0)
+    for _ in range(3):
+        x = rng.uniform(-1.5, 1.5, d)
+        t = rng.uniform(0.2, 0.8)
+        r = oracle_mod.solve(pb, x[None], t, N, sigma=1.0, tau=0.25, tol=1e-26, max_iter=40000, seed=1)
+        assert r.status[0] == 0
+        brute = _shoot_min(step, g, x, N, t, d, rng, bounds_unit_ball=True)
+        assert abs(r.phi[0] - brute) < 1e-6, (r.phi[0], brute)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_quadrotor_matches_direct_shooting(oracle_mod, N):
+    rng = _rng(20 + N)
+    hp = W.QUAD_PARAMS
+    pb = oracle_mod.Problem(W.H_QUADROTOR, W.G_QUAD_SHIFT, 12, 0, hp, np.zeros(13))
+    g = lambda z: 0.5 * z @ z
+    step = lambda s, u: (quad_f_phys(s, u, hp), 0.5 * u @ u)
+    for _ in range(2):
+        x = rng.uniform(-0.5, 0.5, 12)
+        t = 0.05 * N
+        r = oracle_mod.solve(pb, x[None], t, N, sigma=2.0, tau=0.125, tol=1e-26, max_iter=60000, seed=2)
+        brute = _shoot_min(step, g, x, N, t, 4, rng)
+        assert abs(r.phi[0] - brute) < 1e-6 * max(1, abs(brute)), (r.phi[0], brute)
+
+
+def test_linear_tanh_matches_direct_shooting(oracle_mod):
+    rng = _rng(30)
+    d, N, t, eps = 3, 3, 0.6, 0.4
+    A = rng.standard_normal((d, d))
+    Q = np.diag([1.0, 2.0, 0.5])
+    pb = oracle_mod.Problem(W.H_LINEAR_TANH, W.G_QUAD_FORM, d, 0, np.concatenate([[eps], A.ravel()]), Q.ravel())
+    step = lambda s, u: (lt_f_phys(s, u, A, eps), 0.5 * u @ u)
+    for _ in range(3):
+        x = rng.standard_normal(d)
+        r = oracle_mod.solve(pb, x[None], t, N, sigma=1.0, tau=0.25, tol=1e-28, max_iter=20000, seed=4)
+        brute = _shoot_min(step, lambda z: 0.5 * z @ Q @ z, x, N, t, d, rng)
+        assert abs(r.phi[0] - brute) < 1e-7 * max(1, abs(brute))
+
+
+def _pe_lagrangian(Z, N, dx, dy, hp, x_t, y_t, gp, delta):
+    """Lagrangian of eq. discgenlaxhopfdg written independently: free variables
+    x_0..x_{N-1}, y_0..y_{N-1}, p_1..p_N, q_1..q_N; H from the independent
+    dynamics at the full costate (p, -q)."""
+    kappa, wP, wE = hp
+    o = 0
+    xs = Z[o:o + N * dx].reshape(N, dx); o += N * dx
+    ys = Z[o:o + N * dy].reshape(N, dy); o += N * dy
+    ps = Z[o:o + N * dx].reshape(N, dx); o += N * dx
+    qs = Z[o:o + N * dy].reshape(N, dy)
+    xs = np.vstack([xs, x_t]); ys = np.vstack([ys, y_t])
+    L = np.linalg.norm(xs[0, :3] - ys[0, :3]) - gp[0]
+    for j in range(1, N + 1):
+        X = np.concatenate([xs[j], ys[j]])
+        P = np.concatenate([ps[j - 1], -qs[j - 1]])
+        f0 = pe_f_phys(X, np.zeros(3), np.zeros(3), kappa)
+        Hc = P @ f0 - 0.5 * wP * P[3:6] @ P[3:6] + 0.5 * wE * P[9:12] @ P[9:12]
+        L += ps[j - 1] @ (xs[j] - xs[j - 1]) - qs[j - 1] @ (ys[j] - ys[j - 1]) - delta * (-Hc)
+    return L
+
+
+def test_pursuit_fixed_point_is_stationary_for_independent_lagrangian(oracle_mod):
+    """Parity beyond H for the game is pinned by first-order optimality: at the
+    oracle's converged iterate, the Lagrangian written independently above has
+    zero gradient in every free block."""
+    rng = _rng(31)
+    pb = oracle_mod.Problem(W.H_PURSUIT_EVASION, W.G_PAIR_DIST, 12, 6, W.PE_PARAMS, [0.5])
+    for _ in range(2):
+        X = np.concatenate([rng.uniform(-1, 1, 3), rng.uniform(-.3, .3, 3), rng.uniform(-1, 1, 3) + 2,
+                            rng.uniform(-.3, .3, 3)])
+        N, t = 6, 0.3
+        r = oracle_mod.solve(pb, X[None], t, N, sigma=8.0, tau=0.25 / 8, tol=1e-28, max_iter=200000, seed=6,
+                             traj=True)
+        xt, pt = r.x_traj[0], r.p_traj[0]
+        Z = np.concatenate([xt[:N, :6].ravel(), xt[:N, 6:].ravel(), pt[1:, :6].ravel(), pt[1:, 6:].ravel()])
+        Lf = lambda z: _pe_lagrangian(z, N, 6, 6, W.PE_PARAMS, X[:6], X[6:], [0.5], t / N)
+        g = _fd_grad(Lf, Z, h=1e-6)
+        assert np.max(np.abs(g)) < 1e-6, np.max(np.abs(g))
+        # and the value is the Lagrangian there
+        assert abs(Lf(Z) - r.phi[0]) < 1e-10
+
+
+def _quad_lagrangian(Z, N, hp, x_t, delta):
+    xs = np.vstack([Z[:N * 12].reshape(N, 12), x_t])
+    ps = Z[N * 12:].reshape(N, 12)
+    L = 0.5 * xs[0] @ xs[0]
+    for j in range(1, N + 1):
+        f0 = quad_f_phys(xs[j], np.zeros(4), hp)
+        B = np.stack([quad_f_phys(xs[j], e, hp) - f0 for e in np.eye(4)], axis=1)
+        H = -ps[j - 1] @ f0 + 0.5 * np.sum((B.T @ ps[j - 1]) ** 2)
+        L += ps[j - 1] @ (xs[j] - xs[j - 1]) - delta * H
+    return L
+
+
+def test_quadrotor_fixed_point_is_stationary_for_independent_lagrangian(oracle_mod):
+    rng = _rng(32)
+    hp = W.QUAD_PARAMS
+    pb = oracle_mod.Problem(W.H_QUADROTOR, W.G_QUAD_SHIFT, 12, 0, hp, np.zeros(13))
+    x = rng.uniform(-0.6, 0.6, 12)
+    N, t = 8, 0.4
+    r = oracle_mod.solve(pb, x[None], t, N, sigma=2.0, tau=0.125, tol=1e-28, max_iter=200000, seed=7, traj=True)
+    Z = np.concatenate([r.x_traj[0, :N].ravel(), r.p_traj[0, 1:].ravel()])
+    Lf = lambda z: _quad_lagrangian(z, N, hp, x, t / N)
+    g = _fd_grad(Lf, Z, h=1e-6)
+    assert np.max(np.abs(g)) < 1e-6 * max(1, np.max(np.abs(Z)))
+    assert abs(Lf(Z) - r.phi[0]) < 1e-9 * max(1, abs(r.phi[0]))
+
+
+def test_value_nonincreasing_in_t_for_nonnegative_H(oracle_mod):
+    """H = c(x)||p|| >= 0: a longer horizon reaches more initial states, so
+    phi(x, t) cannot increase with t."""
+    w = W.cnorm10(8)
+    pb = oracle_mod.Problem(w.H, w.g, w.d, w.d_y, w.hp, w.gp)
+    ts = [0.2, 0.4, 0.6, 0.8, 1.0]
+    vals = np.stack([oracle_mod.solve(pb, w.x, np.full(w.n, tt), w.N, sigma=w.sigma, tau=w.tau, tol=1e-20,
+                                      max_iter=40000, seed=w.init_seed).phi for tt in ts])
+    assert np.all(np.diff(vals, axis=0) <= 1e-9)
+
+
+# --------------------------------------------------------------------------
+# Driver semantics: invariants, stopping rule and statuses
+# --------------------------------------------------------------------------
+
+def test_endpoint_and_dual_boundary_invariants(oracle_mod):
+    w = W.cnorm10(16)
+    pb = oracle_mod.Problem(w.H, w.g, w.d, w.d_y, w.hp, w.gp)
+    r = oracle_mod.solve(pb, w.x, w.t, w.N, sigma=w.sigma, tau=w.tau, tol=w.tol, max_iter=w.max_iter,
+                         seed=w.init_seed, traj=True)
+    assert np.array_equal(r.x_traj[:, w.N_max, :], w.x)   # x_N = x exactly
+    assert np.all(r.p_traj[:, 0, :] == 0)                 # p_0 = 0
+
+
+def test_fixed_iteration_mode_reproduces_stop_iteration(oracle_mod):
+    w = W.cnorm10(16)
+    pb = oracle_mod.Problem(w.H, w.g, w.d, w.d_y, w.hp, w.gp)
+    r = oracle_mod.solve(pb, w.x, w.t, w.N, sigma=w.sigma, tau=w.tau, tol=w.tol, max_iter=w.max_iter,
+                         seed=w.init_seed)
+    for i in range(4):
+        rf = oracle_mod.solve(pb, w.x[i:i + 1], w.t[i:i + 1], w.N[i:i + 1], sigma=w.sigma, tau=w.tau, tol=w.tol,
+                              max_iter=int(r.iters[i]), fixed_iters=True, seed=w.init_seed, ids=[i])
+        assert rf.phi[0] == r.phi[i] and rf.iters[0] == r.iters[i] and rf.status[0] == 0
+
+
+def test_statuses(oracle_mod):
+    w = W.cnorm10(6)
+    pb = oracle_mod.Problem(w.H, w.g, w.d, w.d_y, w.hp, w.gp)
+    x = w.x.copy(); t = w.t.copy(); N = w.N.copy()
+    x[1, 3] = np.nan
+    t[2] = 0.0
+    N[3] = 0
+    N[4] = 33  # beyond N_max
+    r = oracle_mod.solve(pb, x, t, N, sigma=w.sigma, tau=w.tau, tol=w.tol, max_iter=1, seed=0, N_max=32)
+    assert list(r.status) == [1, 3, 3, 3, 3, 1]
+    assert list(r.iters) == [1, 0, 0, 0, 0, 1]
+    assert np.isnan(r.phi[1:5]).all()
+    # a step size far beyond the stable range blows up: NONFINITE
+    q = W.quadrotor12()
+    q = q.subset(np.arange(4))
+    pq = oracle_mod.Problem(q.H, q.g, q.d, q.d_y, q.hp, q.gp)
+    r = oracle_mod.solve(pq, q.x, q.t, q.N, sigma=0.05, tau=5.0, tol=1e-6, max_iter=20000, seed=0, N_max=60)
+    assert np.all(r.status == 2)
