@@ -1,0 +1,217 @@
+/*
+ * hjpd — grid-free Hamilton-Jacobi solves on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the per-point primal-dual splitting method of Lin, Chow and Osher,
+ * "Splitting methods for Hamilton-Jacobi equations arising in optimal control
+ * and differential games" (arXiv 1803.01215).  For every query point (x, t)
+ * the library solves the time-discretised generalized Lax saddle problem
+ * (section 4.1, eq. disclaxBE; games: section 4.2, eq. discgenlaxhopfdg)
+ *
+ *   phi(x,t) ~ max_{p_1..p_N} min_{x_0..x_{N-1}} g(x_0)
+ *              + sum_{j=1..N} <p_j, x_j - x_{j-1}> - delta sum_{j=1..N} H(x_j, p_j, s_j),
+ *   x_N = x, delta = t/N, s_j = j delta,
+ *
+ * by the PDHG (Chambolle-Pock) type iteration of section 5.1, Algorithm 1
+ * (step-by-step in Appendix A.1.1; games: Algorithm 3 / Appendix A.2.1),
+ * and returns the value phi(x,t), the trajectory x_0..x_N and the
+ * multipliers (costates) p_0..p_N.  Points are independent: the paper notes
+ * the method is embarrassingly parallel over query points (section 7).
+ *
+ * Conventions shared by every entry point
+ *  - Every array argument is caller-owned DEVICE memory (hipMalloc'd or a
+ *    PyTorch CUDA tensor) unless stated otherwise.  The library never frees it.
+ *  - Floating-point arrays use the context's dtype (float or double).
+ *  - Layouts are row-major with the point index slowest:
+ *      x        [n][d]               query states
+ *      t        [n]                  horizons t > 0
+ *      N        [n]  int32           time intervals per point, 1 <= N <= N_max
+ *      phi      [n]                  values
+ *      iters    [n]  int32           iterations performed
+ *      status   [n]  int32           per-point HJPD_PT_* code
+ *      x_traj   [n][N_max+1][d]      trajectory x_0..x_N (nodes > N untouched)
+ *      p_traj   [n][N_max+1][d]      multipliers p_0..p_N (p_0 = 0)
+ *    For games the d coordinates of a node are (x, y): pursuer/minimiser
+ *    block first (d - d_y values), evader/maximiser block last (d_y); the
+ *    multiplier arrays hold (p, q) in the same order, and the evader's
+ *    costate is -q (section 4.2).
+ *  - Calls are asynchronous: work is enqueued on `stream` (a hipStream_t; NULL
+ *    means the default stream) and outputs are valid once the stream has
+ *    completed.  Calls on one context must not overlap in time (the context's
+ *    work queue and scratch are shared by its calls).
+ *  - Return codes are HJPD_* below; on a non-OK return hjpd_last_error()
+ *    gives a message (thread-local, valid until the next call on the thread).
+ *    Non-convergence is not an error: it is reported per point in `status`.
+ */
+#ifndef HJPD_H
+#define HJPD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hjpd_ctx hjpd_ctx; /* opaque; created and owned by the library */
+
+/* Return codes. */
+enum {
+    HJPD_OK = 0,
+    HJPD_EINVAL = 1,       /* invalid argument (checked before any device work) */
+    HJPD_ENOMEM = 2,       /* device or host allocation failed */
+    HJPD_EDEVICE = 3,      /* a HIP call failed (no device, launch failure, ...) */
+    HJPD_EUNSUPPORTED = 4  /* valid but not supported (family pair, dimension, N_max) */
+};
+
+/* Per-point status written to status[i]. */
+enum {
+    HJPD_PT_CONVERGED = 0, /* ||x^{k+1}-x^k||^2 < tol and ||p^{k+1}-p^k||^2 < tol (games: also y, q) */
+    HJPD_PT_MAXITER = 1,   /* max_iter iterations done without meeting the rule */
+    HJPD_PT_NONFINITE = 2, /* a residual, the value or an output became Inf/NaN */
+    HJPD_PT_BADINPUT = 3   /* t <= 0 or not finite, N < 1 or N > N_max, or x not finite */
+};
+
+/*
+ * Hamiltonian families.  H is given here in the paper's initial-value
+ * convention H = max_u { <f(x,u), p> - L(x,u) } with time-reversed dynamics
+ * (section 2.1).  Parameters are passed per call in `h_params` (device array
+ * of the context's dtype):
+ *
+ *  HJPD_H_CNORM          H = c(x) ||p||_2, c(x) = 1 + alpha sin(x_1) cos(x_2)
+ *                        (state-dependent eikonal, section 6.1; dynamics
+ *                        f = c(x) u, ||u|| <= 1).  h_params = [alpha].
+ *                        d in {2, 3, 4, 10}.
+ *  HJPD_H_QUADROTOR      d = 12, state (r, v, eta, omega) = position, velocity,
+ *                        Euler angles (roll, pitch, yaw), body rates.  Physical
+ *                        dynamics r' = v, v' = (u_1/m) R(eta) e_3 - g_z e_3,
+ *                        eta' = W(eta) omega, omega' = J^{-1} u_{2:4},
+ *                        R = Rz(yaw) Ry(pitch) Rx(roll), cost |u|^2/2:
+ *                        H = -<p, f0(x)> + ((b.p_v)^2 + sum_i (p_omega,i/J_i)^2)/2,
+ *                        b = R e_3 / m; the pitch inside W is clamped to [-c, c].
+ *                        h_params = [m, J_1, J_2, J_3, g_z, c].
+ *  HJPD_H_PURSUIT_EVASION d = 12, d_y = 6: two 3-D point masses with drag,
+ *                        (r, v)' = (v, -kappa |v| v + u); pursuer cost
+ *                        |u_P|^2/2, evader reward |u_E|^2/(2 w_E).  In the game
+ *                        variables H(x,y,p,q) = -<p,F(x)> + <q,F(y)>
+ *                        + w_P |p_v|^2/2 - w_E |q_v|^2/2 (costate (p,-q)).
+ *                        h_params = [kappa, w_P, w_E].
+ *  HJPD_H_LINEAR_TANH    H = -<p, A x + eps tanh(x)> + |p|^2/2 (physical
+ *                        dynamics A x + eps tanh x + u, cost |u|^2/2).
+ *                        h_params = [eps, A (d*d, row-major)].  d <= 128.
+ */
+enum { HJPD_H_CNORM = 0, HJPD_H_QUADROTOR = 1, HJPD_H_PURSUIT_EVASION = 2, HJPD_H_LINEAR_TANH = 3 };
+
+/*
+ * Initial-cost families g (g_params: device array of the context's dtype).
+ *  HJPD_G_NORM        g = ||x||_2 - r.                    g_params = [r]
+ *  HJPD_G_QUAD_SHIFT  g = ||x - a||^2/2 - c0.             g_params = [c0, a_1..a_d]
+ *  HJPD_G_PAIR_DIST   g = ||r_P - r_E||_2 - r (games; positions are the first
+ *                     three coordinates of each block).   g_params = [r]
+ *  HJPD_G_QUAD_FORM   g = x^T Q_s x / 2, Q_s = (Q + Q^T)/2. g_params = [Q (d*d)]
+ * Supported pairs: CNORM with NORM or QUAD_SHIFT; QUADROTOR with QUAD_SHIFT;
+ * PURSUIT_EVASION with PAIR_DIST; LINEAR_TANH with QUAD_FORM.
+ */
+enum { HJPD_G_NORM = 0, HJPD_G_QUAD_SHIFT = 1, HJPD_G_PAIR_DIST = 2, HJPD_G_QUAD_FORM = 3 };
+
+enum { HJPD_F32 = 0, HJPD_F64 = 1 };
+
+/* desc.flags */
+enum {
+    HJPD_PERSISTENT = 0,        /* default: persistent lane-group kernel with a device work queue */
+    HJPD_PLAIN = 1u << 0,       /* one point per lane, whole batch in one launch, no refill */
+    HJPD_FIXED_ITERS = 1u << 1, /* run exactly max_iter iterations (no tolerance stop) */
+    HJPD_GRAPH = 1u << 2,       /* capture the solve in a hipGraph and replay it on repeat calls */
+    HJPD_TIMING = 1u << 3       /* record HIP events around the main kernels (hjpd_get_timing) */
+};
+
+typedef struct {
+    int d;           /* state dimension (games: both players together) */
+    int d_y;         /* > 0 selects the game path (Algorithm 3); evader block size */
+    int H, g;        /* HJPD_H_*, HJPD_G_* */
+    int dtype;       /* HJPD_F32 or HJPD_F64 */
+    int N_max;       /* largest N of any point; sizes the trajectory outputs */
+    double sigma;    /* dual step (sigma > 0) */
+    double tau;      /* primal step (tau > 0, sigma tau <= 1/4 since ||D||_2 < 2) */
+    double theta;    /* extrapolation, 0 <= theta <= 1 (theta = 1 in the paper) */
+    double tol;      /* tolerance on the squared residuals (> 0) */
+    int max_iter;    /* iteration cap (>= 1); with HJPD_FIXED_ITERS the exact count */
+    uint64_t seed;   /* random start: counter-based SplitMix64 stream */
+    unsigned flags;  /* HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_GRAPH | HJPD_TIMING */
+    int lanes_per_point; /* persistent tile override: lanes per point (8,16,32,64), 0 = tuned/default */
+    int nodes_per_lane;  /* persistent tile override: time nodes per lane (1..4), 0 = tuned/default */
+} hjpd_desc;
+
+/*
+ * Create a context for one problem (families, dimension, dtype, steps).
+ * Validates the descriptor (EINVAL: d < 1, d_y < 0 or d_y >= d, sigma <= 0,
+ * tau <= 0, sigma*tau > 1/4, theta outside [0,1], tol <= 0, max_iter < 1,
+ * N_max < 1, unknown family or dtype, tile override out of range; EUNSUPPORTED:
+ * family pair, dimension or N_max not built), selects a GPU kernel set, and
+ * allocates the context's device workspace on the current device.
+ * *out receives the context (NULL on failure).
+ */
+int hjpd_create(const hjpd_desc *desc, hjpd_ctx **out);
+
+/*
+ * Solve n independent points (Algorithm 1 / Algorithm 3 at every point).
+ * x, t, N, h_params, g_params, phi, iters, status are required (non-NULL
+ * when n > 0); x_traj and p_traj may be NULL.  n == 0 is a no-op.
+ * The random start of point i (section 6 set-up) depends only on (seed, i,
+ * array, node, coordinate), so results do not depend on batching or on the
+ * kernel chosen, up to floating-point rounding order.
+ * EINVAL: n < 0, a required pointer NULL.  Per-point input problems are
+ * reported as HJPD_PT_BADINPUT (phi = NaN, iters = 0), not as return codes.
+ */
+int hjpd_solve_batch(hjpd_ctx *ctx, int64_t n, const void *x, const void *t, const int32_t *N,
+                     const void *h_params, const void *g_params, void *phi, void *x_traj, void *p_traj,
+                     int32_t *iters, int32_t *status, void *stream);
+
+/*
+ * Value and reverse-mode gradients for HJPD_H_LINEAR_TANH with
+ * HJPD_G_QUAD_FORM (float32): phi after exactly K_iters iterations
+ * (fixed-iteration Algorithm 1), and, for upstream weights grad_phi [n],
+ *   dphi_dx   [n][d]  = grad_phi[i] * d phi_i / d x_i
+ *   dh_params [1+d*d] = sum_i grad_phi[i] * d phi_i / d (eps, A)
+ *   dg_params [d*d]   = sum_i grad_phi[i] * d phi_i / d Q
+ * by differentiating through the K_iters unrolled iterations, with the
+ * forward iterate stored every ckpt_every iterations and each segment
+ * recomputed during the reverse sweep.  dh_params / dg_params are
+ * overwritten (not accumulated).  EINVAL: K_iters < 1, ckpt_every < 1,
+ * required pointer NULL; EUNSUPPORTED: other families or float64.
+ */
+int hjpd_value_grad(hjpd_ctx *ctx, int64_t n, const void *x, const void *t, const int32_t *N,
+                    const void *h_params, const void *g_params, const void *grad_phi, int K_iters,
+                    int ckpt_every, void *phi, void *dphi_dx, void *dh_params, void *dg_params,
+                    void *stream);
+
+/*
+ * Choose the persistent kernel's tile (lanes per point, nodes per lane) for
+ * each range of N by timing the candidates on this batch for `probe_iters`
+ * fixed iterations (default 200 if <= 0), and store the choice in the
+ * context (and in the on-disk cache named by $HJPD_TUNE_CACHE, if set).
+ * Synchronises `stream`.  Arguments as for hjpd_solve_batch; outputs are
+ * scratch here.
+ */
+int hjpd_autotune(hjpd_ctx *ctx, int64_t n, const void *x, const void *t, const int32_t *N,
+                  const void *h_params, const void *g_params, void *phi, int32_t *iters, int32_t *status,
+                  int probe_iters, void *stream);
+
+/*
+ * With HJPD_TIMING: device milliseconds of the main solve kernel(s) of the
+ * last completed hjpd_solve_batch (sum over its launches), measured with HIP
+ * events on the call's stream; *launches receives the number of main-kernel
+ * launches.  Synchronises on those events.  EINVAL if timing is off or no
+ * solve has run.
+ */
+int hjpd_get_timing(hjpd_ctx *ctx, double *ms, int *launches);
+
+/* Release the context and its device workspace.  NULL is allowed. */
+int hjpd_destroy(hjpd_ctx *ctx);
+
+/* Message for the last non-OK return on this thread ("" if none). */
+const char *hjpd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HJPD_H */

@@ -1,0 +1,625 @@
+// C-ABI of the hjpd library (declarations and contracts in include/hjpd.h).
+//
+// A solve is a short, graph-capturable stream sequence:
+//   1. k_queue_zero     clear the per-N counters;
+//   2. k_queue_count    validate each point (bad inputs get HJPD_PT_BADINPUT
+//                       and are not queued), count points per N;
+//   3. k_queue_scan     one thread: offsets of the N-buckets in descending N,
+//                       begin/end of each tile class's segment, zero the pop
+//                       counters;
+//   4. k_queue_scatter  write point ids into their bucket;
+//   5. one persistent kernel per tile class (or one plain kernel).
+// No host synchronisation and no allocation happen inside the sequence, so
+// it can be captured into a hipGraph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hjpd.h"
+#include "hjpd_launch.hpp"
+#include "hjpd_lintanh.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_OK(expr, what)                                                                 \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(HJPD_EDEVICE, std::string(what) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Queue builder kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_queue_zero(int32_t* a, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
+}
+
+template <typename T>
+__global__ void k_queue_count(int64_t n, int d, int N_max, const T* x, const T* t, const int32_t* N,
+                              int32_t* counts, T* phi, int32_t* iters, int32_t* status) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int Ni = N[i];
+  const T ti = t[i];
+  bool bad = !(ti > T(0)) || !__builtin_isfinite(ti) || Ni < 1 || Ni > N_max;
+  for (int k = 0; k < d && !bad; k++) bad = !__builtin_isfinite(x[i * d + k]);
+  if (bad) {
+    phi[i] = T(NAN);
+    iters[i] = 0;
+    status[i] = hjpd::kBadInput;
+    return;
+  }
+  atomicAdd(&counts[Ni], 1);
+}
+
+// cls_bounds: [2*ncls] (lo, hi) N-range of each class, classes disjoint.
+// cls_range:  [2*(ncls+1)] begin/end of each class; the extra last entry is
+//             the whole queue (used by the plain kernel).
+__global__ void k_queue_scan(int N_max, int ncls, const int32_t* cls_bounds, const int32_t* counts,
+                             int32_t* cursor, int32_t* cls_range, int32_t* heads) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int off = 0;
+  for (int v = N_max; v >= 1; v--) {
+    cursor[v] = off;
+    off += counts[v];
+  }
+  for (int c = 0; c < ncls; c++) {
+    const int lo = cls_bounds[2 * c], hi = cls_bounds[2 * c + 1];
+    cls_range[2 * c] = cursor[hi];
+    cls_range[2 * c + 1] = cursor[lo] + counts[lo];
+    heads[c] = 0;
+  }
+  cls_range[2 * ncls] = 0;
+  cls_range[2 * ncls + 1] = off;
+  heads[ncls] = 0;
+}
+
+template <typename T>
+__global__ void k_queue_scatter(int64_t n, int d, int N_max, const T* x, const T* t, const int32_t* N,
+                                int32_t* cursor, int32_t* queue) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int Ni = N[i];
+  const T ti = t[i];
+  bool bad = !(ti > T(0)) || !__builtin_isfinite(ti) || Ni < 1 || Ni > N_max;
+  for (int k = 0; k < d && !bad; k++) bad = !__builtin_isfinite(x[i * d + k]);
+  if (bad) return;
+  const int pos = atomicAdd(&cursor[Ni], 1);
+  queue[pos] = int32_t(i);
+}
+
+struct Cls {
+  int lo, hi, L, K;
+  const void* kern;
+  int grid;  // persistent grid (blocks of 256)
+};
+
+}  // namespace
+
+struct hjpd_ctx {
+  hjpd_desc desc;
+  int device = 0;
+  int n_cu = 0;
+  std::vector<Cls> plan;
+  const void* plain_kern = nullptr;
+  // device workspace
+  int32_t* d_cls_bounds = nullptr;  // [2*ncls]
+  int32_t* d_counts = nullptr;      // [N_max+1]
+  int32_t* d_cursor = nullptr;      // [N_max+1]
+  int32_t* d_cls_range = nullptr;   // [2*(ncls+1)]
+  int32_t* d_heads = nullptr;       // [ncls+1]
+  int ncls_alloc = 0;
+  int32_t* d_queue = nullptr;
+  int64_t queue_cap = 0;
+  void* d_work = nullptr;
+  size_t work_bytes = 0;
+  // graph replay
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  std::vector<uintptr_t> gkey;
+  // timing
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timing_valid = false;
+  int timing_launches = 0;
+  // linear-tanh (differentiation) state
+  hjpd::LtState* lt = nullptr;
+};
+
+namespace {
+
+typedef const void* (*Lookup)(int, int, int);
+
+Lookup lookup_for(const hjpd_desc& d) {
+  const bool f64 = d.dtype == HJPD_F64;
+  if (d.H == HJPD_H_CNORM && d.d_y == 0) {
+    switch (d.d) {
+      case 2: return f64 ? hjpd_lookup_cnorm2_f64 : hjpd_lookup_cnorm2_f32;
+      case 3: return f64 ? hjpd_lookup_cnorm3_f64 : hjpd_lookup_cnorm3_f32;
+      case 4: return f64 ? hjpd_lookup_cnorm4_f64 : hjpd_lookup_cnorm4_f32;
+      case 10: return f64 ? hjpd_lookup_cnorm10_f64 : hjpd_lookup_cnorm10_f32;
+    }
+    return nullptr;
+  }
+  if (d.H == HJPD_H_QUADROTOR && d.d == 12 && d.d_y == 0) return f64 ? hjpd_lookup_quad_f64 : hjpd_lookup_quad_f32;
+  if (d.H == HJPD_H_PURSUIT_EVASION && d.d == 12 && d.d_y == 6)
+    return f64 ? hjpd_lookup_pursuit_f64 : hjpd_lookup_pursuit_f32;
+  return nullptr;
+}
+
+// Default tile for a capacity class.
+hjpd::Tile default_tile(int cap) {
+  switch (cap) {
+    case 8: return {8, 1};
+    case 16: return {16, 1};
+    case 32: return {32, 1};
+    case 64: return {32, 2};
+    case 96: return {32, 3};
+    case 128: return {32, 4};
+    case 192: return {64, 3};
+    default: return {64, 4};
+  }
+}
+
+const int kCaps[] = {8, 16, 32, 64, 96, 128, 192, 256};
+
+int persistent_grid(hjpd_ctx* c, const void* kern) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, 0) != hipSuccess || nb < 1) nb = 1;
+  return nb * c->n_cu;
+}
+
+int build_plan(hjpd_ctx* c, const int* tile_override_L, const int* tile_override_K) {
+  Lookup lk = lookup_for(c->desc);
+  c->plan.clear();
+  int prev = 0;
+  for (int ci = 0; ci < 8 && prev < c->desc.N_max; ci++) {
+    const int cap = kCaps[ci];
+    Cls cl;
+    cl.lo = prev + 1;
+    cl.hi = std::min(cap, c->desc.N_max);
+    hjpd::Tile t = default_tile(cap);
+    if (tile_override_L && tile_override_L[ci] > 0) t = {tile_override_L[ci], tile_override_K[ci]};
+    if (c->desc.lanes_per_point > 0) {
+      t.L = c->desc.lanes_per_point;
+      t.K = c->desc.nodes_per_lane > 0 ? c->desc.nodes_per_lane : 1;
+      if (t.L * t.K < c->desc.N_max) return fail(HJPD_EINVAL, "tile override capacity below N_max");
+    }
+    cl.L = t.L;
+    cl.K = t.K;
+    cl.kern = lk(0, t.L, t.K);
+    if (!cl.kern) return fail(HJPD_EUNSUPPORTED, "tile not built");
+    cl.grid = persistent_grid(c, cl.kern);
+    c->plan.push_back(cl);
+    prev = cl.hi;
+    if (c->desc.lanes_per_point > 0) {  // one class covers everything
+      c->plan.back().lo = 1;
+      c->plan.back().hi = c->desc.N_max;
+      break;
+    }
+  }
+  c->plain_kern = lk(1, 0, 0);
+  return HJPD_OK;
+}
+
+int upload_plan(hjpd_ctx* c) {
+  const int ncls = int(c->plan.size());
+  if (ncls > c->ncls_alloc) {
+    if (c->d_cls_bounds) (void)hipFree(c->d_cls_bounds);
+    if (c->d_cls_range) (void)hipFree(c->d_cls_range);
+    if (c->d_heads) (void)hipFree(c->d_heads);
+    HIP_OK(hipMalloc(&c->d_cls_bounds, sizeof(int32_t) * 2 * ncls), "hipMalloc");
+    HIP_OK(hipMalloc(&c->d_cls_range, sizeof(int32_t) * 2 * (ncls + 1)), "hipMalloc");
+    HIP_OK(hipMalloc(&c->d_heads, sizeof(int32_t) * (ncls + 1)), "hipMalloc");
+    c->ncls_alloc = ncls;
+  }
+  std::vector<int32_t> b(2 * ncls);
+  for (int i = 0; i < ncls; i++) {
+    b[2 * i] = c->plan[i].lo;
+    b[2 * i + 1] = c->plan[i].hi;
+  }
+  HIP_OK(hipMemcpy(c->d_cls_bounds, b.data(), sizeof(int32_t) * 2 * ncls, hipMemcpyHostToDevice), "hipMemcpy");
+  return HJPD_OK;
+}
+
+size_t elem_size(const hjpd_desc& d) { return d.dtype == HJPD_F64 ? 8 : 4; }
+
+int validate_desc(const hjpd_desc* d) {
+  if (!d) return fail(HJPD_EINVAL, "desc is NULL");
+  if (d->d < 1) return fail(HJPD_EINVAL, "d < 1");
+  if (d->d_y < 0 || d->d_y >= d->d) return fail(HJPD_EINVAL, "d_y must satisfy 0 <= d_y < d");
+  if (!(d->sigma > 0) || !std::isfinite(d->sigma)) return fail(HJPD_EINVAL, "sigma must be > 0");
+  if (!(d->tau > 0) || !std::isfinite(d->tau)) return fail(HJPD_EINVAL, "tau must be > 0");
+  if (d->sigma * d->tau > 0.25 * (1 + 1e-12))
+    return fail(HJPD_EINVAL, "sigma*tau must be <= 1/4 (||D||_2 < 2)");
+  if (!(d->theta >= 0 && d->theta <= 1)) return fail(HJPD_EINVAL, "theta must be in [0,1]");
+  if (!(d->tol > 0) || !std::isfinite(d->tol)) return fail(HJPD_EINVAL, "tol must be > 0");
+  if (d->max_iter < 1) return fail(HJPD_EINVAL, "max_iter must be >= 1");
+  if (d->N_max < 1) return fail(HJPD_EINVAL, "N_max must be >= 1");
+  if (d->N_max > 1023) return fail(HJPD_EINVAL, "N_max must be <= 1023");
+  if (d->H < 0 || d->H > 3) return fail(HJPD_EINVAL, "unknown Hamiltonian family");
+  if (d->g < 0 || d->g > 3) return fail(HJPD_EINVAL, "unknown initial-cost family");
+  if (d->dtype != HJPD_F32 && d->dtype != HJPD_F64) return fail(HJPD_EINVAL, "unknown dtype");
+  if (d->flags & ~unsigned(HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_GRAPH | HJPD_TIMING))
+    return fail(HJPD_EINVAL, "unknown flag bits");
+  if (d->lanes_per_point != 0) {
+    const int L = d->lanes_per_point, K = d->nodes_per_lane;
+    if (!(L == 8 || L == 16 || L == 32 || L == 64) || K < 1 || K > 4)
+      return fail(HJPD_EINVAL, "tile override: lanes_per_point in {8,16,32,64}, nodes_per_lane in 1..4");
+  } else if (d->nodes_per_lane != 0) {
+    return fail(HJPD_EINVAL, "nodes_per_lane given without lanes_per_point");
+  }
+  if (d->d > 1023) return fail(HJPD_EINVAL, "d must be <= 1023");
+  // supported pairs
+  const bool game = d->d_y > 0;
+  if (d->H == HJPD_H_PURSUIT_EVASION) {
+    if (!(game && d->g == HJPD_G_PAIR_DIST && d->d == 12 && d->d_y == 6))
+      return fail(HJPD_EUNSUPPORTED, "pursuit-evasion needs d = 12, d_y = 6, g = PAIR_DIST");
+  } else if (game) {
+    return fail(HJPD_EUNSUPPORTED, "the game path is built for the pursuit-evasion family only");
+  } else if (d->H == HJPD_H_CNORM) {
+    if (!(d->g == HJPD_G_NORM || d->g == HJPD_G_QUAD_SHIFT))
+      return fail(HJPD_EUNSUPPORTED, "CNORM pairs with NORM or QUAD_SHIFT");
+    if (!(d->d == 2 || d->d == 3 || d->d == 4 || d->d == 10))
+      return fail(HJPD_EUNSUPPORTED, "CNORM is built for d in {2,3,4,10}");
+  } else if (d->H == HJPD_H_QUADROTOR) {
+    if (!(d->g == HJPD_G_QUAD_SHIFT && d->d == 12)) return fail(HJPD_EUNSUPPORTED, "QUADROTOR needs d = 12, QUAD_SHIFT");
+  } else if (d->H == HJPD_H_LINEAR_TANH) {
+    if (!(d->g == HJPD_G_QUAD_FORM)) return fail(HJPD_EUNSUPPORTED, "LINEAR_TANH pairs with QUAD_FORM");
+    if (d->dtype != HJPD_F32) return fail(HJPD_EUNSUPPORTED, "LINEAR_TANH is built for float32");
+    if (d->d > hjpd::kLtMaxD) return fail(HJPD_EUNSUPPORTED, "LINEAR_TANH is built for d <= 128");
+    if (d->N_max > hjpd::kLtMaxN) return fail(HJPD_EUNSUPPORTED, "LINEAR_TANH is built for N_max <= 64");
+    if (d->flags & (HJPD_PLAIN | HJPD_GRAPH)) return fail(HJPD_EUNSUPPORTED, "LINEAR_TANH has one kernel path");
+    return HJPD_OK;
+  }
+  if (d->N_max > hjpd::kMaxCapacity) return fail(HJPD_EUNSUPPORTED, "N_max > 256 is not built");
+  return HJPD_OK;
+}
+
+void drop_graph(hjpd_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->gkey.clear();
+}
+
+template <typename T>
+int enqueue_solve(hjpd_ctx* c, int64_t n, const void* x, const void* t, const int32_t* N, const void* hp,
+                  const void* gp, void* phi, void* xtraj, void* ptraj, int32_t* iters, int32_t* status,
+                  hipStream_t s, bool timed) {
+  const hjpd_desc& D = c->desc;
+  const int ncls = int(c->plan.size());
+  const int nb = int((n + 255) / 256);
+  hipLaunchKernelGGL(k_queue_zero, dim3((D.N_max + 1 + 255) / 256), dim3(256), 0, s, c->d_counts, D.N_max + 1);
+  hipLaunchKernelGGL(k_queue_count<T>, dim3(nb), dim3(256), 0, s, n, D.d, D.N_max, (const T*)x, (const T*)t, N,
+                     c->d_counts, (T*)phi, iters, status);
+  hipLaunchKernelGGL(k_queue_scan, dim3(1), dim3(64), 0, s, D.N_max, ncls, c->d_cls_bounds, c->d_counts, c->d_cursor,
+                     c->d_cls_range, c->d_heads);
+  hipLaunchKernelGGL(k_queue_scatter<T>, dim3(nb), dim3(256), 0, s, n, D.d, D.N_max, (const T*)x, (const T*)t, N,
+                     c->d_cursor, c->d_queue);
+  HIP_OK(hipGetLastError(), "queue kernels");
+
+  hjpd::KArgs<T> a;
+  a.x = (const T*)x;
+  a.t = (const T*)t;
+  a.N = N;
+  a.hp = (const T*)hp;
+  a.gp = (const T*)gp;
+  a.phi = (T*)phi;
+  a.xtraj = (T*)xtraj;
+  a.ptraj = (T*)ptraj;
+  a.iters = iters;
+  a.status = status;
+  a.queue = c->d_queue;
+  a.cls_range = c->d_cls_range;
+  a.heads = c->d_heads;
+  a.work = (T*)c->d_work;
+  a.work_stride = int64_t(nb) * 256;
+  a.sigma = T(D.sigma);
+  a.tau = T(D.tau);
+  a.theta = T(D.theta);
+  a.tol = T(D.tol);
+  a.max_iter = D.max_iter;
+  a.fixed = (D.flags & HJPD_FIXED_ITERS) ? 1 : 0;
+  a.N_max = D.N_max;
+  a.d = D.d;
+  a.gkind = D.g;
+  a.seed = D.seed;
+  void* args[] = {&a};
+  if (timed) HIP_OK(hipEventRecord(c->ev0, s), "hipEventRecord");
+  int launches = 0;
+  if (D.flags & HJPD_PLAIN) {
+    a.cls = ncls;
+    HIP_OK(hipLaunchKernel(c->plain_kern, dim3(nb), dim3(256), args, 0, s), "plain kernel launch");
+    launches = 1;
+  } else {
+    for (int ci = 0; ci < ncls; ci++) {
+      a.cls = ci;
+      HIP_OK(hipLaunchKernel(c->plan[ci].kern, dim3(c->plan[ci].grid), dim3(256), args, 0, s),
+             "persistent kernel launch");
+      launches++;
+    }
+  }
+  if (timed) HIP_OK(hipEventRecord(c->ev1, s), "hipEventRecord");
+  c->timing_launches = launches;
+  return HJPD_OK;
+}
+
+int ensure_capacity(hjpd_ctx* c, int64_t n) {
+  if (n > c->queue_cap) {
+    drop_graph(c);
+    if (c->d_queue) (void)hipFree(c->d_queue);
+    c->d_queue = nullptr;
+    c->queue_cap = 0;
+    if (hipMalloc(&c->d_queue, sizeof(int32_t) * n) != hipSuccess) return fail(HJPD_ENOMEM, "queue allocation");
+    c->queue_cap = n;
+  }
+  if (c->desc.flags & HJPD_PLAIN) {
+    const int64_t stride = ((n + 255) / 256) * 256;
+    const size_t need = size_t(3) * (c->desc.N_max + 1) * c->desc.d * stride * elem_size(c->desc);
+    if (need > c->work_bytes) {
+      drop_graph(c);
+      if (c->d_work) (void)hipFree(c->d_work);
+      c->d_work = nullptr;
+      c->work_bytes = 0;
+      if (hipMalloc(&c->d_work, need) != hipSuccess) return fail(HJPD_ENOMEM, "plain workspace allocation");
+      c->work_bytes = need;
+    }
+  }
+  return HJPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hjpd_last_error(void) { return g_err.c_str(); }
+
+int hjpd_create(const hjpd_desc* desc, hjpd_ctx** out) {
+  g_err.clear();
+  if (!out) return fail(HJPD_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate_desc(desc);
+  if (rc) return rc;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(HJPD_EDEVICE, "no HIP device");
+  hjpd_ctx* c = new hjpd_ctx();
+  c->desc = *desc;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(HJPD_EDEVICE, "hipGetDevice failed");
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) {
+    delete c;
+    return fail(HJPD_EDEVICE, "hipGetDeviceProperties failed");
+  }
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    delete c;
+    return fail(HJPD_EDEVICE, std::string("kernels are built for gfx950, device is ") + prop.gcnArchName);
+  }
+  c->n_cu = prop.multiProcessorCount;
+  if (desc->H == HJPD_H_LINEAR_TANH) {
+    rc = hjpd::lt_create(&c->lt, c->desc);
+    if (rc) {
+      delete c;
+      return rc;
+    }
+  } else {
+    rc = build_plan(c, nullptr, nullptr);
+    if (!rc) rc = upload_plan(c);
+    if (!rc && (hipMalloc(&c->d_counts, sizeof(int32_t) * (desc->N_max + 1)) != hipSuccess ||
+                hipMalloc(&c->d_cursor, sizeof(int32_t) * (desc->N_max + 1)) != hipSuccess))
+      rc = fail(HJPD_ENOMEM, "counter allocation");
+    if (rc) {
+      hjpd_destroy(c);
+      return rc;
+    }
+  }
+  if (desc->flags & HJPD_TIMING) {
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+      hjpd_destroy(c);
+      return fail(HJPD_EDEVICE, "hipEventCreate failed");
+    }
+  }
+  *out = c;
+  return HJPD_OK;
+}
+
+int hjpd_destroy(hjpd_ctx* c) {
+  if (!c) return HJPD_OK;
+  drop_graph(c);
+  if (c->d_cls_bounds) (void)hipFree(c->d_cls_bounds);
+  if (c->d_counts) (void)hipFree(c->d_counts);
+  if (c->d_cursor) (void)hipFree(c->d_cursor);
+  if (c->d_cls_range) (void)hipFree(c->d_cls_range);
+  if (c->d_heads) (void)hipFree(c->d_heads);
+  if (c->d_queue) (void)hipFree(c->d_queue);
+  if (c->d_work) (void)hipFree(c->d_work);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->lt) hjpd::lt_destroy(c->lt);
+  delete c;
+  return HJPD_OK;
+}
+
+int hjpd_solve_batch(hjpd_ctx* c, int64_t n, const void* x, const void* t, const int32_t* N, const void* hp,
+                     const void* gp, void* phi, void* xtraj, void* ptraj, int32_t* iters, int32_t* status,
+                     void* stream) {
+  g_err.clear();
+  if (!c) return fail(HJPD_EINVAL, "ctx is NULL");
+  if (n < 0) return fail(HJPD_EINVAL, "n < 0");
+  if (n > INT32_MAX) return fail(HJPD_EINVAL, "n must fit in int32");
+  if (n == 0) return HJPD_OK;
+  if (!x || !t || !N || !hp || !gp || !phi || !iters || !status) return fail(HJPD_EINVAL, "required pointer is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if (c->lt) {
+    return hjpd::lt_solve(c->lt, c->desc, n, x, t, N, hp, gp, phi, xtraj, ptraj, iters, status, s,
+                          (c->desc.flags & HJPD_TIMING) ? c->ev0 : nullptr, (c->desc.flags & HJPD_TIMING) ? c->ev1 : nullptr,
+                          &c->timing_launches, &c->timing_valid);
+  }
+  int rc = ensure_capacity(c, n);
+  if (rc) return rc;
+  const bool timed = (c->desc.flags & HJPD_TIMING) != 0;
+  c->timing_valid = false;
+  auto enqueue = [&](bool inner_timed) -> int {
+    if (c->desc.dtype == HJPD_F64)
+      return enqueue_solve<double>(c, n, x, t, N, hp, gp, phi, xtraj, ptraj, iters, status, s, inner_timed);
+    return enqueue_solve<float>(c, n, x, t, N, hp, gp, phi, xtraj, ptraj, iters, status, s, inner_timed);
+  };
+  if (c->desc.flags & HJPD_GRAPH) {
+    std::vector<uintptr_t> key = {uintptr_t(n),     uintptr_t(x),     uintptr_t(t),     uintptr_t(N),
+                                  uintptr_t(hp),    uintptr_t(gp),    uintptr_t(phi),   uintptr_t(xtraj),
+                                  uintptr_t(ptraj), uintptr_t(iters), uintptr_t(status), uintptr_t(s)};
+    if (!c->gexec || key != c->gkey) {
+      drop_graph(c);
+      HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      rc = enqueue(false);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(s, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return fail(HJPD_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      c->graph = g;
+      HIP_OK(hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+      c->gkey = key;
+    }
+    if (timed) HIP_OK(hipEventRecord(c->ev0, s), "hipEventRecord");
+    HIP_OK(hipGraphLaunch(c->gexec, s), "hipGraphLaunch");
+    if (timed) HIP_OK(hipEventRecord(c->ev1, s), "hipEventRecord");
+    c->timing_valid = timed;
+    return HJPD_OK;
+  }
+  rc = enqueue(timed);
+  if (rc) return rc;
+  c->timing_valid = timed;
+  return HJPD_OK;
+}
+
+int hjpd_get_timing(hjpd_ctx* c, double* ms, int* launches) {
+  g_err.clear();
+  if (!c || !ms) return fail(HJPD_EINVAL, "NULL argument");
+  if (!(c->desc.flags & HJPD_TIMING) || !c->timing_valid) return fail(HJPD_EINVAL, "no timed solve recorded");
+  HIP_OK(hipEventSynchronize(c->ev1), "hipEventSynchronize");
+  float f = 0;
+  HIP_OK(hipEventElapsedTime(&f, c->ev0, c->ev1), "hipEventElapsedTime");
+  *ms = f;
+  if (launches) *launches = c->timing_launches;
+  return HJPD_OK;
+}
+
+int hjpd_autotune(hjpd_ctx* c, int64_t n, const void* x, const void* t, const int32_t* N, const void* hp,
+                  const void* gp, void* phi, int32_t* iters, int32_t* status, int probe_iters, void* stream) {
+  g_err.clear();
+  if (!c) return fail(HJPD_EINVAL, "ctx is NULL");
+  if (c->lt) return fail(HJPD_EUNSUPPORTED, "LINEAR_TANH has a single tile");
+  if (n <= 0) return fail(HJPD_EINVAL, "n must be > 0");
+  if (!x || !t || !N || !hp || !gp || !phi || !iters || !status) return fail(HJPD_EINVAL, "required pointer is NULL");
+  if (c->desc.lanes_per_point > 0) return fail(HJPD_EINVAL, "tile fixed by the descriptor");
+  hipStream_t s = (hipStream_t)stream;
+  if (probe_iters <= 0) probe_iters = 200;
+  int rc = ensure_capacity(c, n);
+  if (rc) return rc;
+  const hjpd_desc saved = c->desc;
+  c->desc.flags = (saved.flags | HJPD_FIXED_ITERS | HJPD_TIMING) & ~unsigned(HJPD_GRAPH | HJPD_PLAIN);
+  c->desc.max_iter = probe_iters;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_OK(hipEventCreate(&e0), "hipEventCreate");
+  HIP_OK(hipEventCreate(&e1), "hipEventCreate");
+  hipEvent_t sv0 = c->ev0, sv1 = c->ev1;
+  c->ev0 = e0;
+  c->ev1 = e1;
+  drop_graph(c);
+  Lookup lk = lookup_for(c->desc);
+  const int nclass = int(c->plan.size());
+  int bestL[8] = {0}, bestK[8] = {0};
+  for (int ci = 0; ci < nclass && !rc; ci++) {
+    const int cap_hi = (ci < 8) ? kCaps[ci] : 256;
+    double best = 1e300;
+    for (int ti = 0; ti < hjpd::kNumTiles; ti++) {
+      const hjpd::Tile tl = hjpd::kTiles[ti];
+      if (tl.L * tl.K != cap_hi) continue;
+      // time the whole solve with this class's tile replaced
+      std::vector<Cls> saved_plan = c->plan;
+      c->plan[ci].L = tl.L;
+      c->plan[ci].K = tl.K;
+      c->plan[ci].kern = lk(0, tl.L, tl.K);
+      c->plan[ci].grid = persistent_grid(c, c->plan[ci].kern);
+      double ms_total = 0;
+      for (int rep = 0; rep < 2 && !rc; rep++) {
+        if (c->desc.dtype == HJPD_F64)
+          rc = enqueue_solve<double>(c, n, x, t, N, hp, gp, phi, nullptr, nullptr, iters, status, s, true);
+        else
+          rc = enqueue_solve<float>(c, n, x, t, N, hp, gp, phi, nullptr, nullptr, iters, status, s, true);
+        if (rc) break;
+        if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(HJPD_EDEVICE, "autotune sync"); break; }
+        float f = 0;
+        (void)hipEventElapsedTime(&f, e0, e1);
+        if (rep == 1) ms_total = f;
+      }
+      if (!rc && ms_total < best) {
+        best = ms_total;
+        bestL[ci] = tl.L;
+        bestK[ci] = tl.K;
+      }
+      c->plan = saved_plan;
+    }
+  }
+  c->ev0 = sv0;
+  c->ev1 = sv1;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->desc = saved;
+  if (rc) return rc;
+  rc = build_plan(c, bestL, bestK);
+  if (!rc) rc = upload_plan(c);
+  if (!rc) {
+    const char* path = std::getenv("HJPD_TUNE_CACHE");
+    if (path && *path) {
+      FILE* f = std::fopen(path, "a");
+      if (f) {
+        for (size_t ci = 0; ci < c->plan.size(); ci++)
+          std::fprintf(f, "H=%d d=%d dtype=%d class=%d..%d L=%d K=%d\n", c->desc.H, c->desc.d, c->desc.dtype,
+                       c->plan[ci].lo, c->plan[ci].hi, c->plan[ci].L, c->plan[ci].K);
+        std::fclose(f);
+      }
+    }
+  }
+  return rc;
+}
+
+int hjpd_value_grad(hjpd_ctx* c, int64_t n, const void* x, const void* t, const int32_t* N, const void* hp,
+                    const void* gp, const void* grad_phi, int K_iters, int ckpt_every, void* phi, void* dphi_dx,
+                    void* dh, void* dg, void* stream) {
+  g_err.clear();
+  if (!c) return fail(HJPD_EINVAL, "ctx is NULL");
+  if (!c->lt) return fail(HJPD_EUNSUPPORTED, "value_grad is built for LINEAR_TANH with QUAD_FORM");
+  if (n < 0 || K_iters < 1 || ckpt_every < 1) return fail(HJPD_EINVAL, "n < 0, K_iters < 1 or ckpt_every < 1");
+  if (n == 0) return HJPD_OK;
+  if (!x || !t || !N || !hp || !gp || !grad_phi || !phi || !dphi_dx || !dh || !dg)
+    return fail(HJPD_EINVAL, "required pointer is NULL");
+  return hjpd::lt_value_grad(c->lt, c->desc, n, x, t, N, hp, gp, grad_phi, K_iters, ckpt_every, phi, dphi_dx, dh, dg,
+                             (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// error helper for the linear-tanh unit
+int hjpd_fail(int code, const char* msg) { return fail(code, msg); }

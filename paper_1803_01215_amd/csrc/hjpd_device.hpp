@@ -1,0 +1,124 @@
+// Device-side helpers shared by the hjpd kernels (gfx950, wave64).
+//
+//  - the counter-based random start (section 6 set-up: every free coordinate
+//    of x_j starts within 0.1 of the query point, every multiplier within 0.1
+//    of 0): SplitMix64 (Steele, Lea, Flood 2014) evaluated at a counter built
+//    from (point, array, node, coordinate);
+//  - lane-group primitives: a query point is owned by a group of L
+//    consecutive lanes of a wavefront, each lane holding K consecutive time
+//    nodes, so the difference operator D (Appendix A.1.1: (Dz)_j = z_j -
+//    z_{j-1}, (D^T p)_j = p_j - p_{j+1}) needs one neighbour exchange per
+//    direction per iteration, done with DPP wavefront shifts;
+//  - precision-generic math wrappers (float: hardware transcendental and
+//    reciprocal instructions; double: OCML).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hjpd {
+
+enum : int { kArrX = 0, kArrP = 1, kArrY = 2, kArrQ = 3 };
+enum : int { kConverged = 0, kMaxIter = 1, kNonFinite = 2, kBadInput = 3 };
+
+// ---------------------------------------------------------------------------
+// Random start
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t sm64_finalize(uint64_t s) {
+  // SplitMix64 output mix: two xor-shift-multiply rounds and a final xor-shift.
+  s ^= s >> 30;
+  s *= 0xBF58476D1CE4E5B9ull;
+  s ^= s >> 27;
+  s *= 0x94D049BB133111EBull;
+  return s ^ (s >> 31);
+}
+
+// Uniform perturbation in [-0.1, 0.1) for (point, array, node, coordinate):
+// output number c+1 of the SplitMix64 sequence whose state starts at `seed`
+// (state after c+1 steps = seed + (c+1) * golden-ratio increment), top 53
+// bits as a double in [0,1), mapped affinely.
+__device__ __forceinline__ double start_noise(uint64_t seed, uint64_t point, int arr, int node, int coord) {
+  const uint64_t ctr = (point << 22) | (uint64_t(arr) << 20) | (uint64_t(node) << 10) | uint64_t(coord);
+  const uint64_t bits = sm64_finalize(seed + (ctr + 1ull) * 0x9E3779B97F4A7C15ull);
+  const double u = __dmul_rn(double(bits >> 11), 0x1.0p-53);
+  return __dsub_rn(__dmul_rn(0.2, u), 0.1);
+}
+
+// ---------------------------------------------------------------------------
+// Math wrappers
+// ---------------------------------------------------------------------------
+
+template <typename T> struct M;
+
+template <> struct M<float> {
+  static __device__ __forceinline__ void sincos(float a, float* s, float* c) { __sincosf(a, s, c); }
+  static __device__ __forceinline__ float sqrt(float a) { return __builtin_sqrtf(a); }
+  static __device__ __forceinline__ float rsqrt(float a) { return __frsqrt_rn(a); }
+  static __device__ __forceinline__ float rcp(float a) { return __builtin_amdgcn_rcpf(a); }
+  static __device__ __forceinline__ float tanh(float a) { return ::tanhf(a); }
+  static __device__ __forceinline__ float fmax(float a, float b) { return ::fmaxf(a, b); }
+  static __device__ __forceinline__ bool finite(float a) { return __builtin_isfinite(a); }
+};
+
+template <> struct M<double> {
+  static __device__ __forceinline__ void sincos(double a, double* s, double* c) { ::sincos(a, s, c); }
+  static __device__ __forceinline__ double sqrt(double a) { return ::sqrt(a); }
+  static __device__ __forceinline__ double rsqrt(double a) { return ::rsqrt(a); }
+  static __device__ __forceinline__ double rcp(double a) { return 1.0 / a; }
+  static __device__ __forceinline__ double tanh(double a) { return ::tanh(a); }
+  static __device__ __forceinline__ double fmax(double a, double b) { return ::fmax(a, b); }
+  static __device__ __forceinline__ bool finite(double a) { return __builtin_isfinite(a); }
+};
+
+// ---------------------------------------------------------------------------
+// Cross-lane movement.  DPP wavefront shifts (GFX9-family controls kept by
+// CDNA): wave_shr:1 gives lane i the value of lane i-1, wave_shl:1 gives lane i
+// the value of lane i+1.  Edge lanes receive garbage-free 0 / old value and
+// are overwritten by the caller (group boundaries use their own data).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int dpp_from_prev(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);  // wave_shr:1
+}
+__device__ __forceinline__ int dpp_from_next(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);  // wave_shl:1
+}
+
+__device__ __forceinline__ float from_prev(float v) {
+  return __builtin_bit_cast(float, dpp_from_prev(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ float from_next(float v) {
+  return __builtin_bit_cast(float, dpp_from_next(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double from_prev(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = uint32_t(dpp_from_prev(int(uint32_t(b))));
+  const uint32_t hi = uint32_t(dpp_from_prev(int(uint32_t(b >> 32))));
+  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+__device__ __forceinline__ double from_next(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = uint32_t(dpp_from_next(int(uint32_t(b))));
+  const uint32_t hi = uint32_t(dpp_from_next(int(uint32_t(b >> 32))));
+  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+
+// Sum over the L lanes of an aligned group (L a power of two <= 64); every
+// lane of the group receives the total.  Butterfly over xor offsets, which
+// never leaves the group.
+template <int L, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int m = 1; m < L; m <<= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+template <int L>
+__device__ __forceinline__ int group_or(int v) {
+#pragma unroll
+  for (int m = 1; m < L; m <<= 1) v |= __shfl_xor(v, m, 64);
+  return v;
+}
+
+}  // namespace hjpd

@@ -1,0 +1,433 @@
+// Problem families for the lane-group kernels.
+//
+// Each family supplies, for one time node, the pieces of one iteration of the
+// splitting of section 5 (Algorithm 1; games Algorithm 3) in the form of
+// section 5.3: the closed-form proximal map of sigma*delta*H(x_j, .) for the
+// dual step, the gradient of H in x for the single explicit primal step, H
+// itself for the value, and the initial cost g with its proximal map for
+// node 0.  Hamiltonians are in the initial-value convention
+// H = max_u {<f,p> - L} with time-reversed dynamics (section 2.1): for a
+// physically specified problem with H_c = min_u {<f_phys,p> + L}, H = -H_c.
+//
+// A `Cache` carries the state-dependent quantities evaluated at x_j^k in the
+// dual step (trigonometric values, norms) to the primal step, which uses the
+// same x_j^k.
+#pragma once
+
+#include "hjpd_device.hpp"
+
+namespace hjpd {
+
+enum : int { kGNorm = 0, kGQuadShift = 1, kGPairDist = 2, kGQuadForm = 3 };
+
+// ===========================================================================
+// Eikonal with state-dependent speed (section 6.1):
+//   H(x,p) = c(x) ||p||,  c(x) = 1 + alpha sin(x_1) cos(x_2).
+// prox of lam*H(x,.) is shrink_2(v, lam c(x)) (section 6.1.2), and
+// grad_x H = ||p|| grad c(x) with grad c = alpha (cos x1 cos x2, -sin x1 sin x2, 0...).
+// Initial cost: ||x|| - r (prox: shrink_2(v, tau)) or ||x - a||^2/2 - c0
+// (prox: (v + tau a)/(1 + tau)).
+// ===========================================================================
+template <int D_>
+struct CNorm {
+  static constexpr int D = D_;
+  static constexpr bool kGame = false;
+
+  template <typename T> struct Par {
+    T alpha;
+    int gkind;
+    T r;            // NORM radius
+    T c0;           // QUAD_SHIFT constant
+    T ta[D];        // tau * a   (QUAD_SHIFT)
+    T a[D];
+    T inv1pt;       // 1 / (1 + tau)
+  };
+  template <typename T> struct Cache {
+    T pn;           // ||p_new||
+    T gc0, gc1;     // grad c at x_j^k (first two coordinates)
+  };
+
+  template <typename T>
+  __device__ static void load(Par<T>& P, const T* hp, const T* gp, int gkind, T tau) {
+    P.alpha = hp[0];
+    P.gkind = gkind;
+    P.r = gp[0];
+    P.c0 = gp[0];
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      P.a[i] = (gkind == kGQuadShift) ? gp[1 + i] : T(0);
+      P.ta[i] = tau * P.a[i];
+    }
+    P.inv1pt = T(1) / (T(1) + tau);
+  }
+
+  template <typename T>
+  __device__ static void dual(const Par<T>& P, const T (&x)[D], T (&v)[D], T lam, Cache<T>& C) {
+    T s1, c1, s2, c2;
+    M<T>::sincos(x[0], &s1, &c1);
+    M<T>::sincos(x[1], &s2, &c2);
+    const T c = T(1) + P.alpha * s1 * c2;
+    T ss = T(0);
+#pragma unroll
+    for (int i = 0; i < D; i++) ss += v[i] * v[i];
+    const T rs = M<T>::rsqrt(ss);                 // +inf at v = 0
+    const T scale = M<T>::fmax(T(1) - lam * c * rs, T(0));
+    C.pn = scale * (ss * rs);                     // = max(||v|| - lam c, 0)
+    if (!(ss > T(0))) C.pn = T(0);
+#pragma unroll
+    for (int i = 0; i < D; i++) v[i] *= scale;
+    C.gc0 = P.alpha * c1 * c2;
+    C.gc1 = -P.alpha * s1 * s2;
+  }
+
+  // Only the first two coordinates of grad_x H are non-zero.
+  template <typename T>
+  __device__ static void grad(const Par<T>&, const T (&)[D], const T (&)[D], const Cache<T>& C, T (&g)[D]) {
+#pragma unroll
+    for (int i = 0; i < D; i++) g[i] = T(0);
+    g[0] = C.pn * C.gc0;
+    g[1] = C.pn * C.gc1;
+  }
+
+  template <typename T>
+  __device__ static T H(const Par<T>& P, const T (&x)[D], const T (&p)[D]) {
+    T s1, c1, s2, c2;
+    M<T>::sincos(x[0], &s1, &c1);
+    M<T>::sincos(x[1], &s2, &c2);
+    T ss = T(0);
+#pragma unroll
+    for (int i = 0; i < D; i++) ss += p[i] * p[i];
+    return (T(1) + P.alpha * s1 * c2) * M<T>::sqrt(ss);
+  }
+
+  template <typename T>
+  __device__ static void prox_g(const Par<T>& P, const T (&v)[D], T tau, T (&o)[D]) {
+    if (P.gkind == kGNorm) {
+      T ss = T(0);
+#pragma unroll
+      for (int i = 0; i < D; i++) ss += v[i] * v[i];
+      const T scale = M<T>::fmax(T(1) - tau * M<T>::rsqrt(ss), T(0));
+#pragma unroll
+      for (int i = 0; i < D; i++) o[i] = scale * v[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < D; i++) o[i] = (v[i] + P.ta[i]) * P.inv1pt;
+    }
+  }
+
+  template <typename T>
+  __device__ static T g(const Par<T>& P, const T (&x)[D]) {
+    T ss = T(0);
+    if (P.gkind == kGNorm) {
+#pragma unroll
+      for (int i = 0; i < D; i++) ss += x[i] * x[i];
+      return M<T>::sqrt(ss) - P.r;
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++) ss += (x[i] - P.a[i]) * (x[i] - P.a[i]);
+    return T(0.5) * ss - P.c0;
+  }
+};
+
+// ===========================================================================
+// Quadrotor-like control, d = 12: x = (r, v, eta, omega), eta = (roll phi,
+// pitch th, yaw psi).  Physical dynamics f = f0 + B u:
+//   f0 = (v, -g_z e3, W(eta) omega, 0),  B u = (0, (u_1/m) R e3, 0, J^{-1} u_{2:4}),
+//   R = Rz(psi) Ry(th) Rx(phi), W = ZYX Euler-rate matrix with the pitch
+//   clamped to [-c, c] (zero slope outside), cost |u|^2/2.
+// H = -<p, f0> + ((b.p_v)^2 + sum_i (p_w,i/J_i)^2)/2 with b = R e3 / m.
+// Dual prox of lam*H(x,.): p_r = v_r + lam vel; p_eta = v_eta + lam W omega;
+// p_v = w - lam (b.w)/(1 + lam |b|^2) b with w = v_v - lam g_z e3
+// (Sherman-Morrison); p_w,i = v_w,i / (1 + lam / J_i^2).
+// Initial cost ||x - a||^2/2 - c0.
+// ===========================================================================
+struct Quad {
+  static constexpr int D = 12;
+  static constexpr bool kGame = false;
+
+  template <typename T> struct Par {
+    T m_inv, gz, clamp;
+    T iJ2[3];                 // 1 / J_i^2
+    T c0, a[12], ta[12], inv1pt;
+  };
+  template <typename T> struct Cache {
+    T b[3];                   // R e3 / m
+    T db[3][3];               // d b / d(phi, th, psi)
+    T W01, W02, W11, W12, W21, W22;       // W (row 0 col 0 is 1, col 0 below is 0)
+    T dWf01, dWf02, dWf11, dWf12, dWf21, dWf22;  // d W / d phi
+    T dWt01, dWt02, dWt21, dWt22;                // d W / d th (rows 0 and 2)
+    T bp;                     // b . p_v (new p)
+  };
+
+  template <typename T>
+  __device__ static void load(Par<T>& P, const T* hp, const T* gp, int, T tau) {
+    P.m_inv = T(1) / hp[0];
+#pragma unroll
+    for (int i = 0; i < 3; i++) P.iJ2[i] = T(1) / (hp[1 + i] * hp[1 + i]);
+    P.gz = hp[4];
+    P.clamp = hp[5];
+    P.c0 = gp[0];
+#pragma unroll
+    for (int i = 0; i < 12; i++) {
+      P.a[i] = gp[1 + i];
+      P.ta[i] = tau * P.a[i];
+    }
+    P.inv1pt = T(1) / (T(1) + tau);
+  }
+
+  template <typename T>
+  __device__ static void geometry(const Par<T>& P, const T (&x)[12], Cache<T>& C) {
+    T sf, cf, st, ct, ss, cs;
+    M<T>::sincos(x[6], &sf, &cf);
+    M<T>::sincos(x[7], &st, &ct);
+    M<T>::sincos(x[8], &ss, &cs);
+    const T mi = P.m_inv;
+    C.b[0] = (cs * st * cf + ss * sf) * mi;
+    C.b[1] = (ss * st * cf - cs * sf) * mi;
+    C.b[2] = (ct * cf) * mi;
+    C.db[0][0] = (ss * cf - cs * st * sf) * mi;
+    C.db[0][1] = (-ss * st * sf - cs * cf) * mi;
+    C.db[0][2] = (-ct * sf) * mi;
+    C.db[1][0] = (cs * ct * cf) * mi;
+    C.db[1][1] = (ss * ct * cf) * mi;
+    C.db[1][2] = (-st * cf) * mi;
+    C.db[2][0] = (cs * sf - ss * st * cf) * mi;
+    C.db[2][1] = (cs * st * cf + ss * sf) * mi;
+    C.db[2][2] = T(0);
+    // Euler-rate matrix at the clamped pitch
+    const T th = x[7];
+    const bool inside = (th > -P.clamp) && (th < P.clamp);
+    T stc = st, ctc = ct;
+    if (!inside) M<T>::sincos(th > T(0) ? P.clamp : -P.clamp, &stc, &ctc);
+    const T sec = M<T>::rcp(ctc);
+    const T tt = stc * sec;
+    C.W01 = sf * tt;  C.W02 = cf * tt;
+    C.W11 = cf;       C.W12 = -sf;
+    C.W21 = sf * sec; C.W22 = cf * sec;
+    C.dWf01 = cf * tt;  C.dWf02 = -sf * tt;
+    C.dWf11 = -sf;      C.dWf12 = -cf;
+    C.dWf21 = cf * sec; C.dWf22 = -sf * sec;
+    const T k = inside ? T(1) : T(0);
+    const T sec2 = k * sec * sec, sect = k * sec * tt;
+    C.dWt01 = sf * sec2; C.dWt02 = cf * sec2;
+    C.dWt21 = sf * sect; C.dWt22 = cf * sect;
+  }
+
+  template <typename T>
+  __device__ static void dual(const Par<T>& P, const T (&x)[12], T (&v)[12], T lam, Cache<T>& C) {
+    geometry(P, x, C);
+    const T w0 = x[9], w1 = x[10], w2 = x[11];
+    // position costate
+    v[0] += lam * x[3];
+    v[1] += lam * x[4];
+    v[2] += lam * x[5];
+    // angle costate: + lam W omega
+    v[6] += lam * (w0 + C.W01 * w1 + C.W02 * w2);
+    v[7] += lam * (C.W11 * w1 + C.W12 * w2);
+    v[8] += lam * (C.W21 * w1 + C.W22 * w2);
+    // velocity costate
+    v[5] -= lam * P.gz;
+    const T bw = C.b[0] * v[3] + C.b[1] * v[4] + C.b[2] * v[5];
+    const T bb = C.b[0] * C.b[0] + C.b[1] * C.b[1] + C.b[2] * C.b[2];
+    const T coef = lam * bw / (T(1) + lam * bb);
+    v[3] -= coef * C.b[0];
+    v[4] -= coef * C.b[1];
+    v[5] -= coef * C.b[2];
+    // body-rate costate
+#pragma unroll
+    for (int i = 0; i < 3; i++) v[9 + i] = v[9 + i] / (T(1) + lam * P.iJ2[i]);
+    C.bp = C.b[0] * v[3] + C.b[1] * v[4] + C.b[2] * v[5];
+  }
+
+  template <typename T>
+  __device__ static void grad(const Par<T>&, const T (&x)[12], const T (&p)[12], const Cache<T>& C, T (&g)[12]) {
+    const T w0 = x[9], w1 = x[10], w2 = x[11];
+    (void)w0;
+    g[0] = g[1] = g[2] = T(0);
+    g[3] = -p[0];
+    g[4] = -p[1];
+    g[5] = -p[2];
+    const T pe0 = p[6], pe1 = p[7], pe2 = p[8];
+    const T dwf = pe0 * (C.dWf01 * w1 + C.dWf02 * w2) + pe1 * (C.dWf11 * w1 + C.dWf12 * w2) +
+                  pe2 * (C.dWf21 * w1 + C.dWf22 * w2);
+    const T dwt = pe0 * (C.dWt01 * w1 + C.dWt02 * w2) + pe2 * (C.dWt21 * w1 + C.dWt22 * w2);
+    const T bp = C.bp;
+    g[6] = -dwf + bp * (C.db[0][0] * p[3] + C.db[0][1] * p[4] + C.db[0][2] * p[5]);
+    g[7] = -dwt + bp * (C.db[1][0] * p[3] + C.db[1][1] * p[4] + C.db[1][2] * p[5]);
+    g[8] = bp * (C.db[2][0] * p[3] + C.db[2][1] * p[4]);
+    // -W^T p_eta
+    g[9] = -pe0;
+    g[10] = -(C.W01 * pe0 + C.W11 * pe1 + C.W21 * pe2);
+    g[11] = -(C.W02 * pe0 + C.W12 * pe1 + C.W22 * pe2);
+  }
+
+  template <typename T>
+  __device__ static T H(const Par<T>& P, const T (&x)[12], const T (&p)[12]) {
+    Cache<T> C;
+    geometry(P, x, C);
+    const T w0 = x[9], w1 = x[10], w2 = x[11];
+    T drift = p[0] * x[3] + p[1] * x[4] + p[2] * x[5] - P.gz * p[5];
+    drift += p[6] * (w0 + C.W01 * w1 + C.W02 * w2) + p[7] * (C.W11 * w1 + C.W12 * w2) +
+             p[8] * (C.W21 * w1 + C.W22 * w2);
+    const T bp = C.b[0] * p[3] + C.b[1] * p[4] + C.b[2] * p[5];
+    T ctrl = bp * bp;
+#pragma unroll
+    for (int i = 0; i < 3; i++) ctrl += p[9 + i] * p[9 + i] * P.iJ2[i];
+    return -drift + T(0.5) * ctrl;
+  }
+
+  template <typename T>
+  __device__ static void prox_g(const Par<T>& P, const T (&v)[12], T, T (&o)[12]) {
+#pragma unroll
+    for (int i = 0; i < 12; i++) o[i] = (v[i] + P.ta[i]) * P.inv1pt;
+  }
+
+  template <typename T>
+  __device__ static T g(const Par<T>& P, const T (&x)[12]) {
+    T ss = T(0);
+#pragma unroll
+    for (int i = 0; i < 12; i++) ss += (x[i] - P.a[i]) * (x[i] - P.a[i]);
+    return T(0.5) * ss - P.c0;
+  }
+};
+
+// ===========================================================================
+// Pursuit-evasion game, d = 12, d_y = 6 (section 4.2 / Algorithm 3).
+// Pursuer x = (r_P, v_P) minimises, evader y = (r_E, v_E) maximises; each is
+// a point mass with drag, F(r,v) = (v, -kappa |v| v), control on velocity.
+// In the game variables (costate (p, -q)):
+//   H(x,y,p,q) = -<p, F(x)> + <q, F(y)> + wP |p_v|^2/2 - wE |q_v|^2/2.
+// p-step (argmin_p lam H + |p - v|^2/2): p_r = v_r + lam v_P,
+//   p_v = (v_v - lam kappa |v_P| v_P) / (1 + lam wP);
+// q-step (argmin_q -lam H + |q - v|^2/2): q_r = v_r + lam v_E,
+//   q_v = (v_v - lam kappa |v_E| v_E) / (1 + lam wE);
+// grad_x H = -J_F(x)^T p, grad_y H = J_F(y)^T q with
+//   J_F(s)^T pi = (0, pi_r - kappa (|v| pi_v + (v.pi_v) v / |v|)).
+// Initial cost g = |r_P - r_E| - r: node-0 pursuer prox moves r_P toward
+// r_E by shrink_2; the evader's prox of -g moves r_E away from r_P by tau
+// ("stretch"; direction e_1 when they coincide).
+// ===========================================================================
+struct Pursuit {
+  static constexpr int D = 12;
+  static constexpr int DX = 6, DY = 6;
+  static constexpr bool kGame = true;
+
+  template <typename T> struct Par {
+    T kappa, wP, wE, r;
+  };
+  template <typename T> struct CacheX {
+    T nv;  // |v_P| at x_j^k
+  };
+  template <typename T> struct CacheY {
+    T nv;  // |v_E| at y_j^k
+  };
+
+  template <typename T>
+  __device__ static void load(Par<T>& P, const T* hp, const T* gp, int, T) {
+    P.kappa = hp[0];
+    P.wP = hp[1];
+    P.wE = hp[2];
+    P.r = gp[0];
+  }
+
+  template <typename T>
+  __device__ static T speed(const T (&s)[6]) {
+    return M<T>::sqrt(s[3] * s[3] + s[4] * s[4] + s[5] * s[5]);
+  }
+
+  // p-step for node j: v -> p^{k+1}
+  template <typename T>
+  __device__ static void dual_p(const Par<T>& P, const T (&x)[6], T (&v)[6], T lam, CacheX<T>& C) {
+    C.nv = speed(x);
+    const T kn = P.kappa * C.nv;
+    const T inv = T(1) / (T(1) + lam * P.wP);
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      v[i] += lam * x[3 + i];
+      v[3 + i] = (v[3 + i] - lam * kn * x[3 + i]) * inv;
+    }
+  }
+
+  template <typename T>
+  __device__ static void dual_q(const Par<T>& P, const T (&y)[6], T (&v)[6], T lam, CacheY<T>& C) {
+    C.nv = speed(y);
+    const T kn = P.kappa * C.nv;
+    const T inv = T(1) / (T(1) + lam * P.wE);
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      v[i] += lam * y[3 + i];
+      v[3 + i] = (v[3 + i] - lam * kn * y[3 + i]) * inv;
+    }
+  }
+
+  // J_F(s)^T pi with |v| precomputed
+  template <typename T>
+  __device__ static void jft(const Par<T>& P, const T (&s)[6], T nv, const T (&pi)[6], T (&o)[6]) {
+    const T vp = s[3] * pi[3] + s[4] * pi[4] + s[5] * pi[5];
+    const T w = (nv > T(0)) ? vp / nv : T(0);
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      o[i] = T(0);
+      o[3 + i] = pi[i] - P.kappa * (nv * pi[3 + i] + w * s[3 + i]);
+    }
+  }
+
+  template <typename T>
+  __device__ static void grad_x(const Par<T>& P, const T (&x)[6], const T (&p)[6], const CacheX<T>& C, T (&g)[6]) {
+    jft(P, x, C.nv, p, g);
+#pragma unroll
+    for (int i = 0; i < 6; i++) g[i] = -g[i];
+  }
+
+  template <typename T>
+  __device__ static void grad_y(const Par<T>& P, const T (&y)[6], const T (&q)[6], const CacheY<T>& C, T (&g)[6]) {
+    jft(P, y, C.nv, q, g);
+  }
+
+  template <typename T>
+  __device__ static T H(const Par<T>& P, const T (&x)[6], const T (&y)[6], const T (&p)[6], const T (&q)[6]) {
+    const T kx = P.kappa * speed(x), ky = P.kappa * speed(y);
+    T h = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      h += -(p[i] * x[3 + i]) + p[3 + i] * kx * x[3 + i];
+      h += q[i] * y[3 + i] - q[3 + i] * ky * y[3 + i];
+      h += T(0.5) * P.wP * p[3 + i] * p[3 + i] - T(0.5) * P.wE * q[3 + i] * q[3 + i];
+    }
+    return h;
+  }
+
+  template <typename T>
+  __device__ static void prox_x0(const Par<T>&, const T (&v)[6], const T (&y0)[6], T tau, T (&o)[6]) {
+    const T w0 = v[0] - y0[0], w1 = v[1] - y0[1], w2 = v[2] - y0[2];
+    const T ss = w0 * w0 + w1 * w1 + w2 * w2;
+    const T scale = M<T>::fmax(T(1) - tau * M<T>::rsqrt(ss), T(0));
+    o[0] = y0[0] + scale * w0;
+    o[1] = y0[1] + scale * w1;
+    o[2] = y0[2] + scale * w2;
+    o[3] = v[3]; o[4] = v[4]; o[5] = v[5];
+  }
+
+  template <typename T>
+  __device__ static void stretch_y0(const Par<T>&, const T (&v)[6], const T (&x0)[6], T tau, T (&o)[6]) {
+    const T w0 = v[0] - x0[0], w1 = v[1] - x0[1], w2 = v[2] - x0[2];
+    const T ss = w0 * w0 + w1 * w1 + w2 * w2;
+    if (ss > T(0)) {
+      const T scale = T(1) + tau * M<T>::rsqrt(ss);
+      o[0] = x0[0] + scale * w0;
+      o[1] = x0[1] + scale * w1;
+      o[2] = x0[2] + scale * w2;
+    } else {
+      o[0] = x0[0] + tau; o[1] = x0[1]; o[2] = x0[2];
+    }
+    o[3] = v[3]; o[4] = v[4]; o[5] = v[5];
+  }
+
+  template <typename T>
+  __device__ static T g(const Par<T>& P, const T (&x0)[6], const T (&y0)[6]) {
+    const T a = x0[0] - y0[0], b = x0[1] - y0[1], c = x0[2] - y0[2];
+    return M<T>::sqrt(a * a + b * b + c * c) - P.r;
+  }
+};
+
+}  // namespace hjpd

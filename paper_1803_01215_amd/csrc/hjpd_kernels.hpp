@@ -1,0 +1,897 @@
+// PDHG kernels for the per-point Lax saddle problem (section 5.1, Algorithm 1;
+// games: Algorithm 3), run independently at every query point.
+//
+// Persistent lane-group kernel
+//   A query point is owned by a group of L consecutive lanes of a wave64;
+//   lane l holds time nodes j = l*K + 1 .. l*K + K (x_j, p_j, z_j in VGPRs),
+//   lane 0 also holds node 0 (x_0, z_0; p_0 = 0).  Per iteration:
+//     dual step   p_j <- prox_{sigma delta H(x_j,.)}(p_j + sigma (z_j - z_{j-1})), j = 1..N
+//     node 0      x_0 <- prox_{tau g}(x_0 + tau p_1)
+//     primal step x_j <- x_j - tau (p_j - p_{j+1}) + tau delta grad_x H(x_j, p_j), j = 1..N-1
+//     extrapolate z = x_new + theta (x_new - x_old)
+//     residuals   ||x^{k+1}-x^k||^2, ||p^{k+1}-p^k||^2 summed over the group.
+//   z_{j-1} and p_{j+1} cross a lane boundary once per lane per iteration
+//   (DPP wavefront shifts).  Groups pop point ids from a device queue
+//   (sorted by N, one segment per tile class); a group whose point meets the
+//   stopping rule writes its outputs and immediately pops the next point
+//   (retire and refill), so waves stay full until the queue drains.
+//
+// Plain kernel
+//   One point per lane, the whole stacked state of the point in a global
+//   workspace laid out [node][coord][lane] (coalesced across lanes), one
+//   fused sweep over the nodes per iteration; a wave runs until all its
+//   lanes have stopped (no refill).  This is the straightforward mapping of
+//   the paper's per-point loop and serves as the baseline.
+#pragma once
+
+#include "hjpd_families.hpp"
+
+namespace hjpd {
+
+template <typename T>
+struct KArgs {
+  const T* x;            // [n][d]
+  const T* t;            // [n]
+  const int32_t* N;      // [n]
+  const T* hp;
+  const T* gp;
+  T* phi;                // [n]
+  T* xtraj;              // [n][N_max+1][d] or null
+  T* ptraj;
+  int32_t* iters;
+  int32_t* status;
+  const int32_t* queue;      // point ids sorted by N (descending)
+  const int32_t* cls_range;  // [2 * n_cls] begin/end of each class segment
+  int32_t* heads;            // per-class pop counters (zeroed by the queue builder)
+  T* work;                   // plain kernel workspace
+  int64_t work_stride;       // lanes in the plain workspace
+  int cls;
+  T sigma, tau, theta, tol;
+  int max_iter, fixed, N_max, d, gkind;
+  uint64_t seed;
+};
+
+template <typename T, int D>
+__device__ __forceinline__ bool all_finite(const T (&v)[D]) {
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < D; i++) ok = ok && M<T>::finite(v[i]);
+  return ok;
+}
+
+template <typename T>
+__device__ __forceinline__ T init_x(T xt, uint64_t seed, int64_t pt, int arr, int j, int i) {
+  return T(double(xt) + start_noise(seed, uint64_t(pt), arr, j, i));
+}
+
+// ---------------------------------------------------------------------------
+// Persistent lane-group kernel, optimal-control path (Algorithm 1).
+// ---------------------------------------------------------------------------
+template <typename T, class F, int L, int K>
+__global__ void __launch_bounds__(256) k_group_control(KArgs<T> a) {
+  constexpr int D = F::D;
+  const int lane = threadIdx.x & 63;
+  const int l = lane & (L - 1);
+  const int leader = lane - l;
+
+  typename F::template Par<T> P;
+  F::load(P, a.hp, a.gp, a.gkind, a.tau);
+  const int beg = a.cls_range[2 * a.cls], end = a.cls_range[2 * a.cls + 1];
+  int32_t* head = a.heads + a.cls;
+  const T sigma = a.sigma, tau = a.tau, theta = a.theta;
+
+  T x[K][D], p[K][D], z[K][D], x0[D], z0[D];
+  T delta = T(0), sd = T(0), td = T(0);
+  int Np = 0, k = 0;
+  int64_t pt = -1;
+  bool active = false;
+
+  auto pop_and_init = [&]() {
+    int idx = 0;
+    if (l == 0) idx = atomicAdd(head, 1);
+    idx = __shfl(idx, leader, 64);
+    const int qi = beg + idx;
+    active = qi < end;
+    if (!active) return;
+    pt = a.queue[qi];
+    Np = a.N[pt];
+    delta = a.t[pt] / T(Np);
+    sd = sigma * delta;
+    td = tau * delta;
+    k = 0;
+    T xt[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) xt[i] = a.x[pt * a.d + i];
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      const int j = 1 + l * K + kk;
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        x[kk][i] = (j < Np) ? init_x(xt[i], a.seed, pt, kArrX, j, i) : xt[i];
+        p[kk][i] = (j <= Np) ? T(start_noise(a.seed, uint64_t(pt), kArrP, j, i)) : T(0);
+        z[kk][i] = x[kk][i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      x0[i] = init_x(xt[i], a.seed, pt, kArrX, 0, i);
+      z0[i] = x0[i];
+    }
+  };
+
+  pop_and_init();
+
+  while (__any(active)) {
+    // ---- dual step -------------------------------------------------------
+    T zprev[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      const T s = from_prev(z[K - 1][i]);
+      zprev[i] = (l == 0) ? z0[i] : s;
+    }
+    typename F::template Cache<T> C[K];
+    T rp = T(0), rx = T(0);
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      const int j = 1 + l * K + kk;
+      T v[D];
+#pragma unroll
+      for (int i = 0; i < D; i++) v[i] = p[kk][i] + sigma * (z[kk][i] - (kk == 0 ? zprev[i] : z[kk - 1][i]));
+      F::dual(P, x[kk], v, sd, C[kk]);
+      if (j <= Np) {
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+          const T dp = v[i] - p[kk][i];
+          rp += dp * dp;
+          p[kk][i] = v[i];
+        }
+      }
+    }
+    // ---- node 0 -----------------------------------------------------------
+    T pnext[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      const T s = from_next(p[0][i]);
+      pnext[i] = (l == L - 1) ? T(0) : s;
+    }
+    if (l == 0) {
+      T v0[D], xn0[D];
+#pragma unroll
+      for (int i = 0; i < D; i++) v0[i] = x0[i] + tau * p[0][i];
+      F::prox_g(P, v0, tau, xn0);
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        const T dx = xn0[i] - x0[i];
+        rx += dx * dx;
+        z0[i] = xn0[i] + theta * dx;
+        x0[i] = xn0[i];
+      }
+    }
+    // ---- primal step --------------------------------------------------------
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      const int j = 1 + l * K + kk;
+      if (j < Np) {
+        T g[D];
+        F::grad(P, x[kk], p[kk], C[kk], g);
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+          const T pp = (kk == K - 1) ? pnext[i] : p[kk + 1][i];
+          const T xn = x[kk][i] - tau * (p[kk][i] - pp) + td * g[i];
+          const T dx = xn - x[kk][i];
+          rx += dx * dx;
+          z[kk][i] = xn + theta * dx;
+          x[kk][i] = xn;
+        }
+      }
+    }
+    // ---- stopping rule (section 6 set-up) ------------------------------------
+    k++;
+    const T rxs = group_sum<L>(rx), rps = group_sum<L>(rp);
+    const bool fin = M<T>::finite(rxs + rps);
+    const bool small = (rxs < a.tol) && (rps < a.tol);
+    const bool done = active && (!fin || (!a.fixed && small) || k >= a.max_iter);
+    if (done) {
+      // value: Lagrangian at the last iterate (Algorithm 1)
+      T xprev[D];
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        const T s = from_prev(x[K - 1][i]);
+        xprev[i] = (l == 0) ? x0[i] : s;
+      }
+      T acc = T(0);
+      int bad = 0;
+#pragma unroll
+      for (int kk = 0; kk < K; kk++) {
+        const int j = 1 + l * K + kk;
+        if (j <= Np) {
+          T s = T(0);
+#pragma unroll
+          for (int i = 0; i < D; i++) s += p[kk][i] * (x[kk][i] - (kk == 0 ? xprev[i] : x[kk - 1][i]));
+          acc += s - delta * F::H(P, x[kk], p[kk]);
+          bad |= !(all_finite<T, D>(x[kk]) && all_finite<T, D>(p[kk]));
+        }
+      }
+      if (l == 0) {
+        acc += F::g(P, x0);
+        bad |= !all_finite<T, D>(x0);
+      }
+      acc = group_sum<L>(acc);
+      bad = group_or<L>(bad);
+      int st = !fin ? kNonFinite : (small ? kConverged : kMaxIter);
+      if (bad || !M<T>::finite(acc)) st = kNonFinite;
+      if (l == 0) {
+        a.phi[pt] = acc;
+        a.iters[pt] = k;
+        a.status[pt] = st;
+      }
+      const int64_t base = pt * int64_t(a.N_max + 1) * a.d;
+      if (a.xtraj) {
+#pragma unroll
+        for (int kk = 0; kk < K; kk++) {
+          const int j = 1 + l * K + kk;
+          if (j <= Np)
+#pragma unroll
+            for (int i = 0; i < D; i++) a.xtraj[base + j * D + i] = x[kk][i];
+        }
+        if (l == 0)
+#pragma unroll
+          for (int i = 0; i < D; i++) a.xtraj[base + i] = x0[i];
+      }
+      if (a.ptraj) {
+#pragma unroll
+        for (int kk = 0; kk < K; kk++) {
+          const int j = 1 + l * K + kk;
+          if (j <= Np)
+#pragma unroll
+            for (int i = 0; i < D; i++) a.ptraj[base + j * D + i] = p[kk][i];
+        }
+        if (l == 0)
+#pragma unroll
+          for (int i = 0; i < D; i++) a.ptraj[base + i] = T(0);
+      }
+      pop_and_init();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent lane-group kernel, game path (Algorithm 3) for games whose
+// Hamiltonian separates as H = Hx(x, p) + Hy(y, q): block order p, q, x, y.
+// ---------------------------------------------------------------------------
+template <typename T, class F, int L, int K>
+__global__ void __launch_bounds__(256) k_group_game(KArgs<T> a) {
+  constexpr int DX = F::DX, DY = F::DY, D = F::D;
+  const int lane = threadIdx.x & 63;
+  const int l = lane & (L - 1);
+  const int leader = lane - l;
+
+  typename F::template Par<T> P;
+  F::load(P, a.hp, a.gp, a.gkind, a.tau);
+  const int beg = a.cls_range[2 * a.cls], end = a.cls_range[2 * a.cls + 1];
+  int32_t* head = a.heads + a.cls;
+  const T sigma = a.sigma, tau = a.tau, theta = a.theta;
+
+  T x[K][DX], p[K][DX], z[K][DX], y[K][DY], q[K][DY], w[K][DY];
+  T x0[DX], z0[DX], y0[DY], w0[DY];
+  T delta = T(0), sd = T(0), td = T(0);
+  int Np = 0, k = 0;
+  int64_t pt = -1;
+  bool active = false;
+
+  auto pop_and_init = [&]() {
+    int idx = 0;
+    if (l == 0) idx = atomicAdd(head, 1);
+    idx = __shfl(idx, leader, 64);
+    const int qi = beg + idx;
+    active = qi < end;
+    if (!active) return;
+    pt = a.queue[qi];
+    Np = a.N[pt];
+    delta = a.t[pt] / T(Np);
+    sd = sigma * delta;
+    td = tau * delta;
+    k = 0;
+    T xt[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) xt[i] = a.x[pt * a.d + i];
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      const int j = 1 + l * K + kk;
+#pragma unroll
+      for (int i = 0; i < DX; i++) {
+        x[kk][i] = (j < Np) ? init_x(xt[i], a.seed, pt, kArrX, j, i) : xt[i];
+        p[kk][i] = (j <= Np) ? T(start_noise(a.seed, uint64_t(pt), kArrP, j, i)) : T(0);
+        z[kk][i] = x[kk][i];
+      }
+#pragma unroll
+      for (int i = 0; i < DY; i++) {
+        y[kk][i] = (j < Np) ? init_x(xt[DX + i], a.seed, pt, kArrY, j, i) : xt[DX + i];
+        q[kk][i] = (j <= Np) ? T(start_noise(a.seed, uint64_t(pt), kArrQ, j, i)) : T(0);
+        w[kk][i] = y[kk][i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < DX; i++) {
+      x0[i] = init_x(xt[i], a.seed, pt, kArrX, 0, i);
+      z0[i] = x0[i];
+    }
+#pragma unroll
+    for (int i = 0; i < DY; i++) {
+      y0[i] = init_x(xt[DX + i], a.seed, pt, kArrY, 0, i);
+      w0[i] = y0[i];
+    }
+  };
+
+  pop_and_init();
+
+  while (__any(active)) {
+    T zprev[DX], wprev[DY];
+#pragma unroll
+    for (int i = 0; i < DX; i++) {
+      const T s = from_prev(z[K - 1][i]);
+      zprev[i] = (l == 0) ? z0[i] : s;
+    }
+#pragma unroll
+    for (int i = 0; i < DY; i++) {
+      const T s = from_prev(w[K - 1][i]);
+      wprev[i] = (l == 0) ? w0[i] : s;
+    }
+    typename F::template CacheX<T> CX[K];
+    typename F::template CacheY<T> CY[K];
+    T rp = T(0), rq = T(0), rx = T(0), ry = T(0);
+    // ---- p block, then q block ----------------------------------------------
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      const int j = 1 + l * K + kk;
+      T v[DX];
+#pragma unroll
+      for (int i = 0; i < DX; i++) v[i] = p[kk][i] + sigma * (z[kk][i] - (kk == 0 ? zprev[i] : z[kk - 1][i]));
+      F::dual_p(P, x[kk], v, sd, CX[kk]);
+      T u[DY];
+#pragma unroll
+      for (int i = 0; i < DY; i++) u[i] = q[kk][i] + sigma * (w[kk][i] - (kk == 0 ? wprev[i] : w[kk - 1][i]));
+      F::dual_q(P, y[kk], u, sd, CY[kk]);
+      if (j <= Np) {
+#pragma unroll
+        for (int i = 0; i < DX; i++) {
+          const T dp = v[i] - p[kk][i];
+          rp += dp * dp;
+          p[kk][i] = v[i];
+        }
+#pragma unroll
+        for (int i = 0; i < DY; i++) {
+          const T dq = u[i] - q[kk][i];
+          rq += dq * dq;
+          q[kk][i] = u[i];
+        }
+      }
+    }
+    T pnext[DX], qnext[DY];
+#pragma unroll
+    for (int i = 0; i < DX; i++) {
+      const T s = from_next(p[0][i]);
+      pnext[i] = (l == L - 1) ? T(0) : s;
+    }
+#pragma unroll
+    for (int i = 0; i < DY; i++) {
+      const T s = from_next(q[0][i]);
+      qnext[i] = (l == L - 1) ? T(0) : s;
+    }
+    // ---- x block: node 0 (prox of g(., y_0^k)), then descent steps ----------
+    if (l == 0) {
+      T v0[DX], xn0[DX];
+#pragma unroll
+      for (int i = 0; i < DX; i++) v0[i] = x0[i] + tau * p[0][i];
+      F::prox_x0(P, v0, y0, tau, xn0);
+#pragma unroll
+      for (int i = 0; i < DX; i++) {
+        const T dx = xn0[i] - x0[i];
+        rx += dx * dx;
+        z0[i] = xn0[i] + theta * dx;
+        x0[i] = xn0[i];
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      const int j = 1 + l * K + kk;
+      if (j < Np) {
+        T g[DX];
+        F::grad_x(P, x[kk], p[kk], CX[kk], g);
+#pragma unroll
+        for (int i = 0; i < DX; i++) {
+          const T pp = (kk == K - 1) ? pnext[i] : p[kk + 1][i];
+          const T xn = x[kk][i] - tau * (p[kk][i] - pp) + td * g[i];
+          const T dx = xn - x[kk][i];
+          rx += dx * dx;
+          z[kk][i] = xn + theta * dx;
+          x[kk][i] = xn;
+        }
+      }
+    }
+    // ---- y block: node 0 (prox of -g(x_0^{k+1}, .)), then ascent steps ------
+    if (l == 0) {
+      T u0[DY], yn0[DY];
+#pragma unroll
+      for (int i = 0; i < DY; i++) u0[i] = y0[i] + tau * q[0][i];
+      F::stretch_y0(P, u0, x0, tau, yn0);
+#pragma unroll
+      for (int i = 0; i < DY; i++) {
+        const T dy = yn0[i] - y0[i];
+        ry += dy * dy;
+        w0[i] = yn0[i] + theta * dy;
+        y0[i] = yn0[i];
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      const int j = 1 + l * K + kk;
+      if (j < Np) {
+        T g[DY];
+        F::grad_y(P, y[kk], q[kk], CY[kk], g);
+#pragma unroll
+        for (int i = 0; i < DY; i++) {
+          const T qq = (kk == K - 1) ? qnext[i] : q[kk + 1][i];
+          const T yn = y[kk][i] - tau * (q[kk][i] - qq) - td * g[i];
+          const T dy = yn - y[kk][i];
+          ry += dy * dy;
+          w[kk][i] = yn + theta * dy;
+          y[kk][i] = yn;
+        }
+      }
+    }
+    // ---- stopping rule ------------------------------------------------------------
+    k++;
+    const T rxs = group_sum<L>(rx), rps = group_sum<L>(rp), rys = group_sum<L>(ry), rqs = group_sum<L>(rq);
+    const bool fin = M<T>::finite(rxs + rps + rys + rqs);
+    const bool small = (rxs < a.tol) && (rps < a.tol) && (rys < a.tol) && (rqs < a.tol);
+    const bool done = active && (!fin || (!a.fixed && small) || k >= a.max_iter);
+    if (done) {
+      T xprev[DX], yprev[DY];
+#pragma unroll
+      for (int i = 0; i < DX; i++) {
+        const T s = from_prev(x[K - 1][i]);
+        xprev[i] = (l == 0) ? x0[i] : s;
+      }
+#pragma unroll
+      for (int i = 0; i < DY; i++) {
+        const T s = from_prev(y[K - 1][i]);
+        yprev[i] = (l == 0) ? y0[i] : s;
+      }
+      T acc = T(0);
+      int bad = 0;
+#pragma unroll
+      for (int kk = 0; kk < K; kk++) {
+        const int j = 1 + l * K + kk;
+        if (j <= Np) {
+          T s = T(0);
+#pragma unroll
+          for (int i = 0; i < DX; i++) s += p[kk][i] * (x[kk][i] - (kk == 0 ? xprev[i] : x[kk - 1][i]));
+#pragma unroll
+          for (int i = 0; i < DY; i++) s -= q[kk][i] * (y[kk][i] - (kk == 0 ? yprev[i] : y[kk - 1][i]));
+          acc += s - delta * F::H(P, x[kk], y[kk], p[kk], q[kk]);
+          bad |= !(all_finite<T, DX>(x[kk]) && all_finite<T, DX>(p[kk]) && all_finite<T, DY>(y[kk]) &&
+                   all_finite<T, DY>(q[kk]));
+        }
+      }
+      if (l == 0) {
+        acc += F::g(P, x0, y0);
+        bad |= !(all_finite<T, DX>(x0) && all_finite<T, DY>(y0));
+      }
+      acc = group_sum<L>(acc);
+      bad = group_or<L>(bad);
+      int st = !fin ? kNonFinite : (small ? kConverged : kMaxIter);
+      if (bad || !M<T>::finite(acc)) st = kNonFinite;
+      if (l == 0) {
+        a.phi[pt] = acc;
+        a.iters[pt] = k;
+        a.status[pt] = st;
+      }
+      const int64_t base = pt * int64_t(a.N_max + 1) * a.d;
+      if (a.xtraj) {
+#pragma unroll
+        for (int kk = 0; kk < K; kk++) {
+          const int j = 1 + l * K + kk;
+          if (j <= Np) {
+#pragma unroll
+            for (int i = 0; i < DX; i++) a.xtraj[base + j * D + i] = x[kk][i];
+#pragma unroll
+            for (int i = 0; i < DY; i++) a.xtraj[base + j * D + DX + i] = y[kk][i];
+          }
+        }
+        if (l == 0) {
+#pragma unroll
+          for (int i = 0; i < DX; i++) a.xtraj[base + i] = x0[i];
+#pragma unroll
+          for (int i = 0; i < DY; i++) a.xtraj[base + DX + i] = y0[i];
+        }
+      }
+      if (a.ptraj) {
+#pragma unroll
+        for (int kk = 0; kk < K; kk++) {
+          const int j = 1 + l * K + kk;
+          if (j <= Np) {
+#pragma unroll
+            for (int i = 0; i < DX; i++) a.ptraj[base + j * D + i] = p[kk][i];
+#pragma unroll
+            for (int i = 0; i < DY; i++) a.ptraj[base + j * D + DX + i] = q[kk][i];
+          }
+        }
+        if (l == 0)
+#pragma unroll
+          for (int i = 0; i < D; i++) a.ptraj[base + i] = T(0);
+      }
+      pop_and_init();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Plain kernel, optimal-control path: one point per lane.
+// Workspace arrays X, P, Z, each [N_max+1][D][S] (S = lanes launched).
+// One fused sweep per iteration: the dual step of node j+1 (reads the old
+// z_j, z_{j+1}) precedes the primal step of node j (writes z_j).
+// ---------------------------------------------------------------------------
+template <typename T, class F>
+__global__ void __launch_bounds__(256) k_plain_control(KArgs<T> a) {
+  constexpr int D = F::D;
+  const int64_t slot = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t S = a.work_stride;
+  const int beg = a.cls_range[0], end = a.cls_range[1];
+  if (slot >= S || beg + slot >= end) return;
+  const int64_t pt = a.queue[beg + slot];
+  typename F::template Par<T> P;
+  F::load(P, a.hp, a.gp, a.gkind, a.tau);
+  const T sigma = a.sigma, tau = a.tau, theta = a.theta;
+  const int Np = a.N[pt];
+  const T delta = a.t[pt] / T(Np), sd = sigma * delta, td = tau * delta;
+  const int64_t arr = int64_t(a.N_max + 1) * D * S;
+  T* WX = a.work;
+  T* WP = a.work + arr;
+  T* WZ = a.work + 2 * arr;
+  auto at = [&](int j, int i) { return (int64_t(j) * D + i) * S + slot; };
+
+  T xt[D];
+#pragma unroll
+  for (int i = 0; i < D; i++) xt[i] = a.x[pt * a.d + i];
+  for (int j = 0; j <= Np; j++) {
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      const T xv = (j < Np) ? init_x(xt[i], a.seed, pt, kArrX, j, i) : xt[i];
+      WX[at(j, i)] = xv;
+      WZ[at(j, i)] = xv;
+      WP[at(j, i)] = (j >= 1) ? T(start_noise(a.seed, uint64_t(pt), kArrP, j, i)) : T(0);
+    }
+  }
+
+  int k = 0, st = kMaxIter;
+  for (;;) {
+    T rx = T(0), rp = T(0);
+    typename F::template Cache<T> Cj, Cn;
+    T xj[D], pj[D], xn1[D], pn1[D], zm[D];
+    // node 1 dual (uses z_0, z_1 old)
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      zm[i] = WZ[at(0, i)];
+      xj[i] = WX[at(1, i)];
+      const T z1 = WZ[at(1, i)];
+      const T pold = WP[at(1, i)];
+      pj[i] = pold + sigma * (z1 - zm[i]);
+      zm[i] = z1;
+    }
+    {
+      T pold[D];
+#pragma unroll
+      for (int i = 0; i < D; i++) pold[i] = WP[at(1, i)];
+      F::dual(P, xj, pj, sd, Cj);
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        const T dp = pj[i] - pold[i];
+        rp += dp * dp;
+      }
+    }
+    // node 0
+    {
+      T x0[D], v0[D], xn0[D];
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        x0[i] = WX[at(0, i)];
+        v0[i] = x0[i] + tau * pj[i];
+      }
+      F::prox_g(P, v0, tau, xn0);
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        const T dx = xn0[i] - x0[i];
+        rx += dx * dx;
+        WX[at(0, i)] = xn0[i];
+        WZ[at(0, i)] = xn0[i] + theta * dx;
+      }
+    }
+    for (int j = 1; j <= Np; j++) {
+      // dual step of node j+1 (reads old z_j kept in zm, old z_{j+1})
+      if (j < Np) {
+        T pold[D];
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+          xn1[i] = WX[at(j + 1, i)];
+          const T z1 = WZ[at(j + 1, i)];
+          pold[i] = WP[at(j + 1, i)];
+          pn1[i] = pold[i] + sigma * (z1 - zm[i]);
+          zm[i] = z1;
+        }
+        F::dual(P, xn1, pn1, sd, Cn);
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+          const T dp = pn1[i] - pold[i];
+          rp += dp * dp;
+        }
+        // primal step of node j
+        T g[D];
+        F::grad(P, xj, pj, Cj, g);
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+          const T xn = xj[i] - tau * (pj[i] - pn1[i]) + td * g[i];
+          const T dx = xn - xj[i];
+          rx += dx * dx;
+          WX[at(j, i)] = xn;
+          WZ[at(j, i)] = xn + theta * dx;
+          WP[at(j, i)] = pj[i];
+          xj[i] = xn1[i];
+          pj[i] = pn1[i];
+        }
+        Cj = Cn;
+      } else {
+#pragma unroll
+        for (int i = 0; i < D; i++) WP[at(j, i)] = pj[i];
+      }
+    }
+    k++;
+    const bool fin = M<T>::finite(rx + rp);
+    const bool small = (rx < a.tol) && (rp < a.tol);
+    if (!fin) { st = kNonFinite; break; }
+    if (!a.fixed && small) { st = kConverged; break; }
+    if (k >= a.max_iter) { st = small ? kConverged : kMaxIter; break; }
+  }
+
+  // value and outputs
+  const int64_t base = pt * int64_t(a.N_max + 1) * a.d;
+  T xprev[D], acc = T(0);
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+    xprev[i] = WX[at(0, i)];
+    ok = ok && M<T>::finite(xprev[i]);
+    if (a.xtraj) a.xtraj[base + i] = xprev[i];
+    if (a.ptraj) a.ptraj[base + i] = T(0);
+  }
+  acc = F::g(P, xprev);
+  for (int j = 1; j <= Np; j++) {
+    T xv[D], pv[D], s = T(0);
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      xv[i] = WX[at(j, i)];
+      pv[i] = WP[at(j, i)];
+      s += pv[i] * (xv[i] - xprev[i]);
+      xprev[i] = xv[i];
+      ok = ok && M<T>::finite(xv[i]) && M<T>::finite(pv[i]);
+      if (a.xtraj) a.xtraj[base + j * D + i] = xv[i];
+      if (a.ptraj) a.ptraj[base + j * D + i] = pv[i];
+    }
+    acc += s - delta * F::H(P, xv, pv);
+  }
+  if (!ok || !M<T>::finite(acc)) st = kNonFinite;
+  a.phi[pt] = acc;
+  a.iters[pt] = k;
+  a.status[pt] = st;
+}
+
+// ---------------------------------------------------------------------------
+// Plain kernel, game path: one point per lane, workspace X, P, Z (DX) and
+// Y, Q, W (DY), each [N_max+1][dim][S].
+// ---------------------------------------------------------------------------
+template <typename T, class F>
+__global__ void __launch_bounds__(256) k_plain_game(KArgs<T> a) {
+  constexpr int DX = F::DX, DY = F::DY, D = F::D;
+  const int64_t slot = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t S = a.work_stride;
+  const int beg = a.cls_range[0], end = a.cls_range[1];
+  if (slot >= S || beg + slot >= end) return;
+  const int64_t pt = a.queue[beg + slot];
+  typename F::template Par<T> P;
+  F::load(P, a.hp, a.gp, a.gkind, a.tau);
+  const T sigma = a.sigma, tau = a.tau, theta = a.theta;
+  const int Np = a.N[pt];
+  const T delta = a.t[pt] / T(Np), sd = sigma * delta, td = tau * delta;
+  const int64_t ax = int64_t(a.N_max + 1) * DX * S, ay = int64_t(a.N_max + 1) * DY * S;
+  T* WX = a.work;
+  T* WP = WX + ax;
+  T* WZ = WP + ax;
+  T* WY = WZ + ax;
+  T* WQ = WY + ay;
+  T* WW = WQ + ay;
+  auto ix = [&](int j, int i) { return (int64_t(j) * DX + i) * S + slot; };
+  auto iy = [&](int j, int i) { return (int64_t(j) * DY + i) * S + slot; };
+
+  T xt[D];
+#pragma unroll
+  for (int i = 0; i < D; i++) xt[i] = a.x[pt * a.d + i];
+  for (int j = 0; j <= Np; j++) {
+#pragma unroll
+    for (int i = 0; i < DX; i++) {
+      const T v = (j < Np) ? init_x(xt[i], a.seed, pt, kArrX, j, i) : xt[i];
+      WX[ix(j, i)] = v;
+      WZ[ix(j, i)] = v;
+      WP[ix(j, i)] = (j >= 1) ? T(start_noise(a.seed, uint64_t(pt), kArrP, j, i)) : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < DY; i++) {
+      const T v = (j < Np) ? init_x(xt[DX + i], a.seed, pt, kArrY, j, i) : xt[DX + i];
+      WY[iy(j, i)] = v;
+      WW[iy(j, i)] = v;
+      WQ[iy(j, i)] = (j >= 1) ? T(start_noise(a.seed, uint64_t(pt), kArrQ, j, i)) : T(0);
+    }
+  }
+
+  int k = 0, st = kMaxIter;
+  for (;;) {
+    T rx = T(0), rp = T(0), ry = T(0), rq = T(0);
+    typename F::template CacheX<T> CXj, CXn;
+    typename F::template CacheY<T> CYj, CYn;
+    T xj[DX], pj[DX], zm[DX], yj[DY], qj[DY], wm[DY];
+    T xn1[DX], pn1[DX], yn1[DY], qn1[DY];
+    auto dual_node = [&](int jn, T (&xv)[DX], T (&pv)[DX], T (&yv)[DY], T (&qv)[DY],
+                         typename F::template CacheX<T>& cx, typename F::template CacheY<T>& cy) {
+      T pold[DX], qold[DY];
+#pragma unroll
+      for (int i = 0; i < DX; i++) {
+        xv[i] = WX[ix(jn, i)];
+        const T zz = WZ[ix(jn, i)];
+        pold[i] = WP[ix(jn, i)];
+        pv[i] = pold[i] + sigma * (zz - zm[i]);
+        zm[i] = zz;
+      }
+#pragma unroll
+      for (int i = 0; i < DY; i++) {
+        yv[i] = WY[iy(jn, i)];
+        const T ww = WW[iy(jn, i)];
+        qold[i] = WQ[iy(jn, i)];
+        qv[i] = qold[i] + sigma * (ww - wm[i]);
+        wm[i] = ww;
+      }
+      F::dual_p(P, xv, pv, sd, cx);
+      F::dual_q(P, yv, qv, sd, cy);
+#pragma unroll
+      for (int i = 0; i < DX; i++) {
+        const T d = pv[i] - pold[i];
+        rp += d * d;
+      }
+#pragma unroll
+      for (int i = 0; i < DY; i++) {
+        const T d = qv[i] - qold[i];
+        rq += d * d;
+      }
+    };
+#pragma unroll
+    for (int i = 0; i < DX; i++) zm[i] = WZ[ix(0, i)];
+#pragma unroll
+    for (int i = 0; i < DY; i++) wm[i] = WW[iy(0, i)];
+    dual_node(1, xj, pj, yj, qj, CXj, CYj);
+    // node 0: x_0 with the old y_0, then y_0 with the new x_0
+    {
+      T x0[DX], y0[DY], v0[DX], u0[DY], xn0[DX], yn0[DY];
+#pragma unroll
+      for (int i = 0; i < DX; i++) { x0[i] = WX[ix(0, i)]; v0[i] = x0[i] + tau * pj[i]; }
+#pragma unroll
+      for (int i = 0; i < DY; i++) { y0[i] = WY[iy(0, i)]; u0[i] = y0[i] + tau * qj[i]; }
+      F::prox_x0(P, v0, y0, tau, xn0);
+      F::stretch_y0(P, u0, xn0, tau, yn0);
+#pragma unroll
+      for (int i = 0; i < DX; i++) {
+        const T d = xn0[i] - x0[i];
+        rx += d * d;
+        WX[ix(0, i)] = xn0[i];
+        WZ[ix(0, i)] = xn0[i] + theta * d;
+      }
+#pragma unroll
+      for (int i = 0; i < DY; i++) {
+        const T d = yn0[i] - y0[i];
+        ry += d * d;
+        WY[iy(0, i)] = yn0[i];
+        WW[iy(0, i)] = yn0[i] + theta * d;
+      }
+    }
+    for (int j = 1; j <= Np; j++) {
+      if (j < Np) {
+        dual_node(j + 1, xn1, pn1, yn1, qn1, CXn, CYn);
+        T gx[DX], gy[DY];
+        F::grad_x(P, xj, pj, CXj, gx);
+        F::grad_y(P, yj, qj, CYj, gy);
+#pragma unroll
+        for (int i = 0; i < DX; i++) {
+          const T xn = xj[i] - tau * (pj[i] - pn1[i]) + td * gx[i];
+          const T d = xn - xj[i];
+          rx += d * d;
+          WX[ix(j, i)] = xn;
+          WZ[ix(j, i)] = xn + theta * d;
+          WP[ix(j, i)] = pj[i];
+          xj[i] = xn1[i];
+          pj[i] = pn1[i];
+        }
+#pragma unroll
+        for (int i = 0; i < DY; i++) {
+          const T yn = yj[i] - tau * (qj[i] - qn1[i]) - td * gy[i];
+          const T d = yn - yj[i];
+          ry += d * d;
+          WY[iy(j, i)] = yn;
+          WW[iy(j, i)] = yn + theta * d;
+          WQ[iy(j, i)] = qj[i];
+          yj[i] = yn1[i];
+          qj[i] = qn1[i];
+        }
+        CXj = CXn;
+        CYj = CYn;
+      } else {
+#pragma unroll
+        for (int i = 0; i < DX; i++) WP[ix(j, i)] = pj[i];
+#pragma unroll
+        for (int i = 0; i < DY; i++) WQ[iy(j, i)] = qj[i];
+      }
+    }
+    k++;
+    const bool fin = M<T>::finite(rx + rp + ry + rq);
+    const bool small = rx < a.tol && rp < a.tol && ry < a.tol && rq < a.tol;
+    if (!fin) { st = kNonFinite; break; }
+    if (!a.fixed && small) { st = kConverged; break; }
+    if (k >= a.max_iter) { st = small ? kConverged : kMaxIter; break; }
+  }
+
+  const int64_t base = pt * int64_t(a.N_max + 1) * a.d;
+  T xprev[DX], yprev[DY];
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < DX; i++) {
+    xprev[i] = WX[ix(0, i)];
+    ok = ok && M<T>::finite(xprev[i]);
+    if (a.xtraj) a.xtraj[base + i] = xprev[i];
+  }
+#pragma unroll
+  for (int i = 0; i < DY; i++) {
+    yprev[i] = WY[iy(0, i)];
+    ok = ok && M<T>::finite(yprev[i]);
+    if (a.xtraj) a.xtraj[base + DX + i] = yprev[i];
+  }
+  if (a.ptraj)
+#pragma unroll
+    for (int i = 0; i < D; i++) a.ptraj[base + i] = T(0);
+  T acc = F::g(P, xprev, yprev);
+  for (int j = 1; j <= Np; j++) {
+    T xv[DX], pv[DX], yv[DY], qv[DY], s = T(0);
+#pragma unroll
+    for (int i = 0; i < DX; i++) {
+      xv[i] = WX[ix(j, i)];
+      pv[i] = WP[ix(j, i)];
+      s += pv[i] * (xv[i] - xprev[i]);
+      xprev[i] = xv[i];
+      ok = ok && M<T>::finite(xv[i]) && M<T>::finite(pv[i]);
+      if (a.xtraj) a.xtraj[base + j * D + i] = xv[i];
+      if (a.ptraj) a.ptraj[base + j * D + i] = pv[i];
+    }
+#pragma unroll
+    for (int i = 0; i < DY; i++) {
+      yv[i] = WY[iy(j, i)];
+      qv[i] = WQ[iy(j, i)];
+      s -= qv[i] * (yv[i] - yprev[i]);
+      yprev[i] = yv[i];
+      ok = ok && M<T>::finite(yv[i]) && M<T>::finite(qv[i]);
+      if (a.xtraj) a.xtraj[base + j * D + DX + i] = yv[i];
+      if (a.ptraj) a.ptraj[base + j * D + DX + i] = qv[i];
+    }
+    acc += s - delta * F::H(P, xv, yv, pv, qv);
+  }
+  if (!ok || !M<T>::finite(acc)) st = kNonFinite;
+  a.phi[pt] = acc;
+  a.iters[pt] = k;
+  a.status[pt] = st;
+}
+
+}  // namespace hjpd

@@ -1,0 +1,57 @@
+// Kernel lookup shared by the instantiation units and the C-ABI layer.
+#pragma once
+
+#include "hjpd_kernels.hpp"
+
+namespace hjpd {
+
+// Persistent tiles (lanes per point L, nodes per lane K) that are compiled.
+// Capacity L*K bounds the N a tile can hold.
+struct Tile { int L, K; };
+inline constexpr Tile kTiles[] = {{8, 1},  {16, 1}, {8, 2},  {32, 1}, {16, 2}, {8, 4},  {64, 1},
+                                  {32, 2}, {16, 4}, {32, 3}, {64, 2}, {32, 4}, {64, 3}, {64, 4}};
+inline constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+inline constexpr int kMaxCapacity = 256;
+
+template <typename T, class F, int L, int K>
+const void* group_ptr() {
+  if constexpr (F::kGame)
+    return reinterpret_cast<const void*>(&k_group_game<T, F, L, K>);
+  else
+    return reinterpret_cast<const void*>(&k_group_control<T, F, L, K>);
+}
+
+template <typename T, class F>
+const void* pick_kernel(int plain, int L, int K) {
+  if (plain) {
+    if constexpr (F::kGame)
+      return reinterpret_cast<const void*>(&k_plain_game<T, F>);
+    else
+      return reinterpret_cast<const void*>(&k_plain_control<T, F>);
+  }
+#define HJPD_TILE_CASE(LL, KK) \
+  if (L == LL && K == KK) return group_ptr<T, F, LL, KK>();
+  HJPD_TILE_CASE(8, 1) HJPD_TILE_CASE(16, 1) HJPD_TILE_CASE(8, 2) HJPD_TILE_CASE(32, 1) HJPD_TILE_CASE(16, 2) HJPD_TILE_CASE(8, 4) HJPD_TILE_CASE(64, 1)
+  HJPD_TILE_CASE(32, 2) HJPD_TILE_CASE(16, 4) HJPD_TILE_CASE(32, 3) HJPD_TILE_CASE(64, 2) HJPD_TILE_CASE(32, 4) HJPD_TILE_CASE(64, 3) HJPD_TILE_CASE(64, 4)
+#undef HJPD_TILE_CASE
+  return nullptr;
+}
+
+}  // namespace hjpd
+
+// One lookup function per (family shape, dtype), defined in its own
+// translation unit so the instantiations compile in parallel.
+#define HJPD_DECLARE_LOOKUP(name) const void* hjpd_lookup_##name(int plain, int L, int K);
+HJPD_DECLARE_LOOKUP(cnorm2_f32)
+HJPD_DECLARE_LOOKUP(cnorm2_f64)
+HJPD_DECLARE_LOOKUP(cnorm3_f32)
+HJPD_DECLARE_LOOKUP(cnorm3_f64)
+HJPD_DECLARE_LOOKUP(cnorm4_f32)
+HJPD_DECLARE_LOOKUP(cnorm4_f64)
+HJPD_DECLARE_LOOKUP(cnorm10_f32)
+HJPD_DECLARE_LOOKUP(cnorm10_f64)
+HJPD_DECLARE_LOOKUP(quad_f32)
+HJPD_DECLARE_LOOKUP(quad_f64)
+HJPD_DECLARE_LOOKUP(pursuit_f32)
+HJPD_DECLARE_LOOKUP(pursuit_f64)
+#undef HJPD_DECLARE_LOOKUP

@@ -1,0 +1,130 @@
+"""ctypes binding of libhjpd (the C ABI declared in include/hjpd.h).
+
+The functions below carry the C names and only marshal arguments: torch
+tensors (device memory) become raw pointers, the stream becomes a
+hipStream_t.  Every step of the solve runs in the library's HIP kernels; if
+the library is missing, loading raises instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libhjpd.so")
+
+HJPD_OK, HJPD_EINVAL, HJPD_ENOMEM, HJPD_EDEVICE, HJPD_EUNSUPPORTED = 0, 1, 2, 3, 4
+HJPD_PT_CONVERGED, HJPD_PT_MAXITER, HJPD_PT_NONFINITE, HJPD_PT_BADINPUT = 0, 1, 2, 3
+HJPD_H_CNORM, HJPD_H_QUADROTOR, HJPD_H_PURSUIT_EVASION, HJPD_H_LINEAR_TANH = 0, 1, 2, 3
+HJPD_G_NORM, HJPD_G_QUAD_SHIFT, HJPD_G_PAIR_DIST, HJPD_G_QUAD_FORM = 0, 1, 2, 3
+HJPD_F32, HJPD_F64 = 0, 1
+HJPD_PERSISTENT, HJPD_PLAIN, HJPD_FIXED_ITERS, HJPD_GRAPH, HJPD_TIMING = 0, 1, 2, 4, 8
+
+EXPORTED = ["hjpd_create", "hjpd_solve_batch", "hjpd_value_grad", "hjpd_autotune", "hjpd_get_timing",
+            "hjpd_destroy", "hjpd_last_error"]
+
+
+class HjpdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("hjpd error %d: %s" % (code, msg))
+        self.code = code
+
+
+class hjpd_desc(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("d_y", ctypes.c_int), ("H", ctypes.c_int), ("g", ctypes.c_int),
+                ("dtype", ctypes.c_int), ("N_max", ctypes.c_int), ("sigma", ctypes.c_double),
+                ("tau", ctypes.c_double), ("theta", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint),
+                ("lanes_per_point", ctypes.c_int), ("nodes_per_lane", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load():
+    """Load libhjpd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libhjpd.so not built: run __graft_entry__.build() or "
+                              "python paper_1803_01215_amd/build.py")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32p = ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p
+        lib.hjpd_create.argtypes = [ctypes.POINTER(hjpd_desc), ctypes.POINTER(ctypes.c_void_p)]
+        lib.hjpd_create.restype = ctypes.c_int
+        lib.hjpd_solve_batch.argtypes = [vp, i64, vp, vp, i32p, vp, vp, vp, vp, vp, i32p, i32p, vp]
+        lib.hjpd_solve_batch.restype = ctypes.c_int
+        lib.hjpd_value_grad.argtypes = [vp, i64, vp, vp, i32p, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp,
+                                        vp, vp]
+        lib.hjpd_value_grad.restype = ctypes.c_int
+        lib.hjpd_autotune.argtypes = [vp, i64, vp, vp, i32p, vp, vp, vp, i32p, i32p, ctypes.c_int, vp]
+        lib.hjpd_autotune.restype = ctypes.c_int
+        lib.hjpd_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+        lib.hjpd_get_timing.restype = ctypes.c_int
+        lib.hjpd_destroy.argtypes = [vp]
+        lib.hjpd_destroy.restype = ctypes.c_int
+        lib.hjpd_last_error.argtypes = []
+        lib.hjpd_last_error.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    """Device pointer of a tensor (or None / int passthrough)."""
+    if a is None:
+        return None
+    if isinstance(a, int):
+        return a
+    return a.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check(rc):
+    if rc != HJPD_OK:
+        raise HjpdError(rc, load().hjpd_last_error().decode())
+
+
+def hjpd_last_error() -> str:
+    return load().hjpd_last_error().decode()
+
+
+def hjpd_create(desc: hjpd_desc) -> int:
+    ctx = ctypes.c_void_p()
+    _check(load().hjpd_create(ctypes.byref(desc), ctypes.byref(ctx)))
+    return ctx.value
+
+
+def hjpd_destroy(ctx: int) -> None:
+    _check(load().hjpd_destroy(ctx))
+
+
+def hjpd_solve_batch(ctx, n, x, t, N, h_params, g_params, phi, x_traj, p_traj, iters, status, stream=None):
+    _check(load().hjpd_solve_batch(ctx, int(n), _ptr(x), _ptr(t), _ptr(N), _ptr(h_params), _ptr(g_params),
+                                   _ptr(phi), _ptr(x_traj), _ptr(p_traj), _ptr(iters), _ptr(status),
+                                   _stream(stream)))
+
+
+def hjpd_value_grad(ctx, n, x, t, N, h_params, g_params, grad_phi, K_iters, ckpt_every, phi, dphi_dx,
+                    dh_params, dg_params, stream=None):
+    _check(load().hjpd_value_grad(ctx, int(n), _ptr(x), _ptr(t), _ptr(N), _ptr(h_params), _ptr(g_params),
+                                  _ptr(grad_phi), int(K_iters), int(ckpt_every), _ptr(phi), _ptr(dphi_dx),
+                                  _ptr(dh_params), _ptr(dg_params), _stream(stream)))
+
+
+def hjpd_autotune(ctx, n, x, t, N, h_params, g_params, phi, iters, status, probe_iters=200, stream=None):
+    _check(load().hjpd_autotune(ctx, int(n), _ptr(x), _ptr(t), _ptr(N), _ptr(h_params), _ptr(g_params),
+                                _ptr(phi), _ptr(iters), _ptr(status), int(probe_iters), _stream(stream)))
+
+
+def hjpd_get_timing(ctx):
+    ms = ctypes.c_double()
+    nl = ctypes.c_int()
+    _check(load().hjpd_get_timing(ctx, ctypes.byref(ms), ctypes.byref(nl)))
+    return ms.value, nl.value
