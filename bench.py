@@ -1,0 +1,176 @@
+"""Throughput benchmark: converged (x,t) solves per second at PDHG residual 1e-6.
+
+One step = one full solve of the workload (every point runs the primal-dual
+iteration of section 5.1, Algorithm 1, until both squared residuals are below
+1e-6 or the cap is hit) with all inputs resident in HBM.
+
+Default workload (cnorm10): d = 10, H = c(x)||p||, c = 1 + 0.5 sin(x1) cos(x2),
+g = ||x - a||^2/2 - 1, 65,536 points x ~ N(0, I), t ~ U[0.2, 1], N = 32, FP32.
+The batched path is the persistent lane-group kernel replayed from a hipGraph;
+the plain path (one point per lane, state in HBM) is timed beside it.
+
+Prints one JSON line (rank 0, one GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32_vector": 157.3e12, "fp64_vector": 78.6e12}
+
+
+def flops_per_iter_cnorm(N: int, d: int) -> int:
+    """Algorithmic flops of one iteration of one point for H = c(x)||p|| with
+    g = ||x-a||^2/2 - c0 (FMA = 2 flops; transcendentals not counted):
+      dual step,   nodes 1..N:   9d + 12  (stencil 3d, c(x) 3, ||v||^2 2d,
+                                           shrink 5, scale d, residual 3d,
+                                           grad c 4)
+      primal step, nodes 1..N-1: 8d + 6   (grad 2, update 3d + 4, difference
+                                           d, residual 2d, extrapolation 2d)
+      node 0:                    9d       (prox 4d, residual 3d, extrap. 2d)
+    plus per dual node 2 sin/cos pairs and 1 rsqrt."""
+    return N * (9 * d + 12) + (N - 1) * (8 * d + 6) + 9 * d
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run")
+    ap.add_argument("--cpu-sample", type=int, default=16384)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: points are independent, so a multi-GPU run would shard them; "
+              "only --gpus 1 is supported in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads as W
+    from paper_1803_01215_amd.solver import Solver
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    w = W.cnorm10()
+    n = w.n
+
+    def tensors(td):
+        return (torch.tensor(w.x, dtype=td, device=dev), torch.tensor(w.t, dtype=td, device=dev),
+                torch.tensor(w.N, dtype=torch.int32, device=dev), torch.tensor(w.hp, dtype=td, device=dev),
+                torch.tensor(w.gp, dtype=td, device=dev))
+
+    def make(td, **kw):
+        return Solver(d=w.d, H=w.H, g=w.g, N_max=w.N_max, sigma=w.sigma, tau=w.tau, theta=w.theta, tol=w.tol,
+                      max_iter=w.max_iter, seed=w.init_seed, dtype=td, **kw)
+
+    def timed_steps(solver, inp, out, steps, warmup):
+        for _ in range(warmup):
+            solver.solve(*inp, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            solver.solve(*inp, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    # ---- batched FP32 (the headline) ------------------------------------------------
+    td = torch.float32
+    inp = tensors(td)
+    batched = make(td, graph=True, lanes_per_point=32, nodes_per_lane=1)
+    out = batched.alloc(n)
+    ms_step = timed_steps(batched, inp, out, args.steps, args.warmup)
+    status = out.status.cpu().numpy()
+    iters = out.iters.cpu().numpy().astype(np.int64)
+    conv = int((status == 0).sum())
+    value = conv / (ms_step * 1e-3)
+
+    # dominant kernel: per-launch device time from the library's HIP events on
+    # the same stream, over the same number of steps (no graph, one launch)
+    probe = make(td, timing=True, lanes_per_point=32, nodes_per_lane=1)
+    out2 = probe.alloc(n)
+    probe.solve(*inp, out=out2)
+    torch.cuda.synchronize()
+    kms = []
+    for _ in range(args.steps):
+        probe.solve(*inp, out=out2)
+        ms, nl = probe.timing()
+        assert nl == 1
+        kms.append(ms)
+    kern_ms = float(np.mean(kms))
+    flops = float(sum(iters * flops_per_iter_cnorm(w.N_max, w.d)))
+    achieved = flops / (kern_ms * 1e-3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK["fp32_vector"] / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK["fp32_vector"], "traffic": None,
+                "kernel": "k_group_control<float, CNorm<10>, 32, 1>", "kernel_ms": kern_ms,
+                "flops_per_launch": flops}
+
+    # ---- plain FP32 -------------------------------------------------------------------
+    plain = make(td, plain=True)
+    outp = plain.alloc(n)
+    ms_plain = timed_steps(plain, inp, outp, max(1, args.plain_steps), 1)
+    conv_plain = int((outp.status.cpu().numpy() == 0).sum())
+    plain_rec = {"value": conv_plain / (ms_plain * 1e-3), "ms_per_step": ms_plain, "converged": conv_plain}
+    batched.close(); probe.close(); plain.close()
+
+    # ---- batched FP64 --------------------------------------------------------------------
+    fp64_rec = None
+    if not args.no_fp64:
+        inp64 = tensors(torch.float64)
+        b64 = make(torch.float64, graph=True, lanes_per_point=32, nodes_per_lane=1)
+        o64 = b64.alloc(n)
+        ms64 = timed_steps(b64, inp64, o64, max(1, args.steps // 2), 1)
+        c64 = int((o64.status.cpu().numpy() == 0).sum())
+        fp64_rec = {"value": c64 / (ms64 * 1e-3), "ms_per_step": ms64, "converged": c64}
+        b64.close()
+
+    # ---- CPU oracle baseline on a bounded sample ------------------------------------------
+    cpu_rec = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        O.build()
+        m = min(args.cpu_sample, n)
+        sub = w.subset(np.arange(m))
+        pb = O.Problem(sub.H, sub.g, sub.d, sub.d_y, sub.hp.astype(np.float32).astype(np.float64),
+                       sub.gp.astype(np.float32).astype(np.float64))
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        r = O.solve(pb, sub.x, sub.t, sub.N, sigma=sub.sigma, tau=sub.tau, theta=sub.theta, tol=sub.tol,
+                    max_iter=sub.max_iter, seed=sub.init_seed, N_max=sub.N_max, ids=sub.ids, threads=threads)
+        dt = time.perf_counter() - t0
+        cpu_rec = {"value": float((r.status == 0).sum() / dt), "unit": "solves/s", "cores": threads, "kind": "oracle",
+                   "sample": "first %d of the %d points, FP64 C oracle, OpenMP over points, %.1f s wall" % (m, n, dt)}
+
+    rec = {
+        "metric": "converged (x,t) solves/sec at PDHG residual 1e-6, batched vs plain kernel",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "cnorm10: d=10 state-dependent eikonal H=c(x)||p||, c=1+0.5 sin(x1)cos(x2), "
+                               "g=||x-a||^2/2-1, 65,536 points x~N(0,I), t~U[0.2,1], N=32, tol 1e-6, cap 20000",
+                   "points": n, "N": w.N_max, "d": w.d, "sigma": w.sigma, "tau": w.tau, "tile": "32 lanes x 1 node",
+                   "converged": conv, "iters_p50": float(np.median(iters)), "iters_p95": float(np.percentile(iters, 95)),
+                   "iters_max": int(iters.max())},
+        "roofline": roofline,
+        "cpu_baseline": cpu_rec,
+        "plain": plain_rec,
+        "speedup_vs_plain": value / plain_rec["value"] if plain_rec["value"] > 0 else None,
+        "fp64": fp64_rec,
+    }
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

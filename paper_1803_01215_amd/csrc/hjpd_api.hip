@@ -128,7 +128,8 @@ struct hjpd_ctx {
   int64_t queue_cap = 0;
   void* d_work = nullptr;
   size_t work_bytes = 0;
-  // graph replay
+  // graph replay (captured on an internal stream, launched on the caller's)
+  hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   std::vector<uintptr_t> gkey;
@@ -453,6 +454,7 @@ int hjpd_destroy(hjpd_ctx* c) {
   if (c->d_work) (void)hipFree(c->d_work);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->lt) hjpd::lt_destroy(c->lt);
   delete c;
   return HJPD_OK;
@@ -477,10 +479,11 @@ int hjpd_solve_batch(hjpd_ctx* c, int64_t n, const void* x, const void* t, const
   if (rc) return rc;
   const bool timed = (c->desc.flags & HJPD_TIMING) != 0;
   c->timing_valid = false;
-  auto enqueue = [&](bool inner_timed) -> int {
+  auto enqueue_on = [&](hipStream_t st) -> int {
+    const bool inner_timed = timed && st == s;
     if (c->desc.dtype == HJPD_F64)
-      return enqueue_solve<double>(c, n, x, t, N, hp, gp, phi, xtraj, ptraj, iters, status, s, inner_timed);
-    return enqueue_solve<float>(c, n, x, t, N, hp, gp, phi, xtraj, ptraj, iters, status, s, inner_timed);
+      return enqueue_solve<double>(c, n, x, t, N, hp, gp, phi, xtraj, ptraj, iters, status, st, inner_timed);
+    return enqueue_solve<float>(c, n, x, t, N, hp, gp, phi, xtraj, ptraj, iters, status, st, inner_timed);
   };
   if (c->desc.flags & HJPD_GRAPH) {
     std::vector<uintptr_t> key = {uintptr_t(n),     uintptr_t(x),     uintptr_t(t),     uintptr_t(N),
@@ -488,10 +491,13 @@ int hjpd_solve_batch(hjpd_ctx* c, int64_t n, const void* x, const void* t, const
                                   uintptr_t(ptraj), uintptr_t(iters), uintptr_t(status), uintptr_t(s)};
     if (!c->gexec || key != c->gkey) {
       drop_graph(c);
-      HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-      rc = enqueue(false);
+      if (!c->cap_stream) HIP_OK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+      // make sure earlier work on the caller's stream is not reordered: the
+      // graph itself is launched on the caller's stream below
+      HIP_OK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      rc = enqueue_on(c->cap_stream);
       hipGraph_t g = nullptr;
-      hipError_t e = hipStreamEndCapture(s, &g);
+      hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
       if (rc) {
         if (g) (void)hipGraphDestroy(g);
         return rc;
@@ -507,7 +513,7 @@ int hjpd_solve_batch(hjpd_ctx* c, int64_t n, const void* x, const void* t, const
     c->timing_valid = timed;
     return HJPD_OK;
   }
-  rc = enqueue(timed);
+  rc = enqueue_on(s);
   if (rc) return rc;
   c->timing_valid = timed;
   return HJPD_OK;

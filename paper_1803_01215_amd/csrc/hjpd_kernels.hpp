@@ -537,7 +537,7 @@ __global__ void __launch_bounds__(256) k_plain_control(KArgs<T> a) {
   constexpr int D = F::D;
   const int64_t slot = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t S = a.work_stride;
-  const int beg = a.cls_range[0], end = a.cls_range[1];
+  const int beg = a.cls_range[2 * a.cls], end = a.cls_range[2 * a.cls + 1];
   if (slot >= S || beg + slot >= end) return;
   const int64_t pt = a.queue[beg + slot];
   typename F::template Par<T> P;
@@ -694,7 +694,7 @@ __global__ void __launch_bounds__(256) k_plain_game(KArgs<T> a) {
   constexpr int DX = F::DX, DY = F::DY, D = F::D;
   const int64_t slot = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t S = a.work_stride;
-  const int beg = a.cls_range[0], end = a.cls_range[1];
+  const int beg = a.cls_range[2 * a.cls], end = a.cls_range[2 * a.cls + 1];
   if (slot >= S || beg + slot >= end) return;
   const int64_t pt = a.queue[beg + slot];
   typename F::template Par<T> P;

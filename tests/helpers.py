@@ -52,12 +52,15 @@ def gpu_solve(w: W.Workload, *, dtype="f32", plain=False, fixed_iters=None, max_
     return res
 
 
-def oracle_fixed(O, w: W.Workload, iters, *, traj=True, inputs_dtype="f64", threads=0):
+def oracle_fixed(O, w: W.Workload, iters, *, traj=True, inputs_dtype="f64", threads=0, x_scale=None):
     """Oracle run with exactly iters[i] iterations at point i (points grouped
     by count).  Inputs are first rounded to the GPU run's precision so both
-    sides see the same numbers."""
+    sides see the same numbers; x_scale (optional) then multiplies x, for the
+    conditioning screen."""
     pb = O.Problem(w.H, w.g, w.d, w.d_y, _round(w.hp, inputs_dtype), _round(w.gp, inputs_dtype))
     x, t = _round(w.x, inputs_dtype), _round(w.t, inputs_dtype)
+    if x_scale is not None:
+        x = x * x_scale
     n = w.n
     phi = np.zeros(n); status = np.zeros(n, np.int32); it = np.zeros(n, np.int32)
     xt = np.zeros((n, w.N_max + 1, w.d)) if traj else None
@@ -89,3 +92,18 @@ def oracle_tol(O, w: W.Workload, *, inputs_dtype="f64", threads=0, traj=False):
 def _round(a, dt):
     a = np.asarray(a, np.float64)
     return a.astype(np.float32).astype(np.float64) if dt == "f32" else a
+
+
+def well_conditioned(O, w: W.Workload, iters, base_phi, dtype, tol):
+    """Points whose oracle value is stable under a rounding-sized change of the
+    inputs (relative 1e-15 for FP64 runs, 1e-7 for FP32 runs, both signs): the
+    oracle's own result moves by at most tol/10 there.  Elsewhere the
+    iteration amplifies rounding differences (a non-contractive, oscillating
+    iterate), so no two implementations with different rounding order can
+    agree elementwise, and such points are screened out and counted."""
+    eps = 1e-15 if dtype == "f64" else 1e-7
+    ok = np.ones(w.n, bool)
+    for sgn in (1.0, -1.0):
+        r = oracle_fixed(O, w, iters, traj=False, inputs_dtype=dtype, x_scale=1.0 + sgn * eps)
+        ok &= rel_err(r["phi"], base_phi) <= tol / 10
+    return ok
