@@ -10,8 +10,9 @@ element:
         >= 99.9% of points;
   FP32: within 1e-4 relative, inputs rounded to FP32 on both sides.
 Points where the oracle's own result moves by more than a tenth of the
-tolerance under a rounding-sized input change are screened out and counted
-(the quadrotor workload has such points; the others have none).
+tolerance under a rounding-sized input change (1e-15 relative for FP64, 1e-6
+for FP32) are screened out and counted: the quadrotor workload has such
+points, the screen must remove none elsewhere.
 """
 import numpy as np
 import pytest
@@ -36,7 +37,7 @@ def _check(O, w, dtype, *, plain=False, max_iter=None, lanes_per_point=0, nodes_
     assert np.all(g["status"] >= 0) and np.all(g["iters"] >= 1)
     o = oracle_fixed(O, w, g["iters"], traj=traj, inputs_dtype=dtype)
     tol = TOL[dtype]
-    ok = well_conditioned(O, w, g["iters"], o["phi"], dtype, tol)
+    ok = well_conditioned(O, w, g["iters"], o, dtype, tol)
     print("  ill-conditioned points screened: %d of %d" % ((~ok).sum(), w.n), flush=True)
     assert np.mean(~ok) <= max_ill
     e = rel_err(g["phi"], o["phi"])[ok]
@@ -87,7 +88,7 @@ def test_cnorm10_tiles_match_oracle(oracle_mod, tile):
 @pytest.mark.parametrize("plain", [False, True])
 def test_quadrotor12_matches_oracle(oracle_mod, dtype, plain):
     w = W.quadrotor12().subset(np.arange(97))
-    _check(oracle_mod, w, dtype, plain=plain, max_iter=2500, check_kstop=False, max_ill=0.25)
+    _check(oracle_mod, w, dtype, plain=plain, max_iter=2500, check_kstop=False, max_ill=0.35)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
