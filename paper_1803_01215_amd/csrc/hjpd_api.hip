@@ -49,22 +49,52 @@ __global__ void k_queue_zero(int32_t* a, int n) {
   if (i < n) a[i] = 0;
 }
 
+// Per-point validation shared by the counting and scattering passes.
 template <typename T>
-__global__ void k_queue_count(int64_t n, int d, int N_max, const T* x, const T* t, const int32_t* N,
-                              int32_t* counts, T* phi, int32_t* iters, int32_t* status) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+__device__ bool point_ok(int64_t i, int d, int N_max, const T* x, const T* t, const int32_t* N) {
   const int Ni = N[i];
   const T ti = t[i];
   bool bad = !(ti > T(0)) || !__builtin_isfinite(ti) || Ni < 1 || Ni > N_max;
   for (int k = 0; k < d && !bad; k++) bad = !__builtin_isfinite(x[i * d + k]);
-  if (bad) {
-    phi[i] = T(NAN);
-    iters[i] = 0;
-    status[i] = hjpd::kBadInput;
-    return;
+  return !bad;
+}
+
+// Wave-aggregated atomic add on counter[key]: one atomic per distinct key in
+// the wavefront (all points usually share a few N values).  Returns, for each
+// participating lane, old value + its rank among the lanes with that key.
+__device__ int aggregated_add(bool part, int key, int32_t* counter) {
+  const int lane = threadIdx.x & 63;
+  uint64_t rem = __ballot(part);
+  int pos = 0;
+  while (rem) {
+    const int leader = __ffsll((unsigned long long)rem) - 1;
+    const int kl = __shfl(key, leader, 64);
+    const uint64_t m = __ballot(part && key == kl);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counter[kl], __popcll(m));
+    base = __shfl(base, leader, 64);
+    if ((m >> lane) & 1ull) pos = base + __popcll(m & ((1ull << lane) - 1ull));
+    rem &= ~m;
   }
-  atomicAdd(&counts[Ni], 1);
+  return pos;
+}
+
+template <typename T>
+__global__ void k_queue_count(int64_t n, int d, int N_max, const T* x, const T* t, const int32_t* N,
+                              int32_t* counts, T* phi, int32_t* iters, int32_t* status) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  bool ok = false;
+  int Ni = 0;
+  if (i < n) {
+    ok = point_ok(i, d, N_max, x, t, N);
+    Ni = N[i];
+    if (!ok) {
+      phi[i] = T(NAN);
+      iters[i] = 0;
+      status[i] = hjpd::kBadInput;
+    }
+  }
+  (void)aggregated_add(ok, Ni, counts);
 }
 
 // cls_bounds: [2*ncls] (lo, hi) N-range of each class, classes disjoint.
@@ -93,14 +123,14 @@ template <typename T>
 __global__ void k_queue_scatter(int64_t n, int d, int N_max, const T* x, const T* t, const int32_t* N,
                                 int32_t* cursor, int32_t* queue) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int Ni = N[i];
-  const T ti = t[i];
-  bool bad = !(ti > T(0)) || !__builtin_isfinite(ti) || Ni < 1 || Ni > N_max;
-  for (int k = 0; k < d && !bad; k++) bad = !__builtin_isfinite(x[i * d + k]);
-  if (bad) return;
-  const int pos = atomicAdd(&cursor[Ni], 1);
-  queue[pos] = int32_t(i);
+  bool ok = false;
+  int Ni = 0;
+  if (i < n) {
+    ok = point_ok(i, d, N_max, x, t, N);
+    Ni = N[i];
+  }
+  const int pos = aggregated_add(ok, Ni, cursor);
+  if (ok) queue[pos] = int32_t(i);
 }
 
 struct Cls {
