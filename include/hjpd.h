@@ -96,7 +96,8 @@ enum {
  *                        h_params = [kappa, w_P, w_E].
  *  HJPD_H_LINEAR_TANH    H = -<p, A x + eps tanh(x)> + |p|^2/2 (physical
  *                        dynamics A x + eps tanh x + u, cost |u|^2/2).
- *                        h_params = [eps, A (d*d, row-major)].  d <= 128.
+ *                        h_params = [eps, A (d*d, row-major)].  float32,
+ *                        d in {16, 32, 100, 128}, N_max <= 64.
  */
 enum { HJPD_H_CNORM = 0, HJPD_H_QUADROTOR = 1, HJPD_H_PURSUIT_EVASION = 2, HJPD_H_LINEAR_TANH = 3 };
 

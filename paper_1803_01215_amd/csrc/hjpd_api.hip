@@ -312,7 +312,8 @@ int validate_desc(const hjpd_desc* d) {
   } else if (d->H == HJPD_H_LINEAR_TANH) {
     if (!(d->g == HJPD_G_QUAD_FORM)) return fail(HJPD_EUNSUPPORTED, "LINEAR_TANH pairs with QUAD_FORM");
     if (d->dtype != HJPD_F32) return fail(HJPD_EUNSUPPORTED, "LINEAR_TANH is built for float32");
-    if (d->d > hjpd::kLtMaxD) return fail(HJPD_EUNSUPPORTED, "LINEAR_TANH is built for d <= 128");
+    if (!(d->d == 16 || d->d == 32 || d->d == 100 || d->d == 128))
+      return fail(HJPD_EUNSUPPORTED, "LINEAR_TANH is built for d in {16, 32, 100, 128}");
     if (d->N_max > hjpd::kLtMaxN) return fail(HJPD_EUNSUPPORTED, "LINEAR_TANH is built for N_max <= 64");
     if (d->flags & (HJPD_PLAIN | HJPD_GRAPH)) return fail(HJPD_EUNSUPPORTED, "LINEAR_TANH has one kernel path");
     return HJPD_OK;

@@ -1,23 +1,1006 @@
+// Linear-tanh family with quadratic initial cost, dense d (differentiation
+// workload).  H = -<p, A x + eps tanh x> + |p|^2/2 (paper convention, section
+// 2.1), g = x^T Q_s x / 2, Algorithm 1 with:
+//   dual   p_j <- (p_j + sigma (z_j - z_{j-1}) + lam (A x_j + eps tanh x_j)) / (1 + lam),
+//          lam = sigma delta                                   (closed-form prox)
+//   node 0 x_0 <- M (x_0 + tau p_1),  M = (I + tau Q_s)^{-1}
+//   primal x_j <- x_j - tau (p_j - p_{j+1}) - tau delta (A^T p_j + eps (1 - tanh^2 x_j) p_j)
+//   extrapolation z = x_new + theta (x_new - x_old).
+//
+// Forward kernel: one point per workgroup of eight wave64s, the stacked state
+// X, P, Z [(N+1) x d] in LDS (row stride d+1).  The dense products A X and
+// A^T P over all nodes of the point are matrix-core GEMMs
+// (v_mfma_f32_16x16x4_f32): wave w owns output row tile w (rows 16w .. 16w+15)
+// and keeps those rows of A and A^T as MFMA A-operand fragments in registers
+// for the whole kernel; B operands are read from LDS.  Elementwise steps run on
+// the VALU in the accumulator layout; the node-0 product with M runs on the
+// VALU.  Workgroups are persistent and pop points from a counter.
+//
+// Reverse mode (hjpd_value_grad): the forward pass stores the state every E
+// iterations; the backward kernel, per point, recomputes each segment of E
+// iterations from its checkpoint into a per-workgroup buffer (x^k and the new
+// multipliers p^{k+1}), then applies the transposed Jacobian of each iteration
+// (vector-Jacobian product) from the last iteration down to the first.  The
+// VJP's dense products A xbar and A^T vbar reuse the forward fragments; the
+// parameter gradient dA = sum of outer products over nodes is an MFMA product
+// accumulated in registers; dM and the direct dQ term are rank-1 VALU updates.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hjpd_device.hpp"
 #include "hjpd_lintanh.hpp"
 
 namespace hjpd {
 
-struct LtState {
-  int dummy;
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// tanh from the exponential, tanh|x| = 1 - 2 / (exp(2|x|) + 1), sign restored:
+// one hardware exp and one reciprocal; absolute error at FP32 rounding level.
+__device__ __forceinline__ float tanh_fast(float x) {
+  const float e = __expf(2.f * fabsf(x));
+  const float t = 1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f);
+  return copysignf(t, x);
+}
+
+constexpr int kLtThreads = 512;
+constexpr int kLtWaves = kLtThreads / 64;
+constexpr int kLtNT = 4;                                                    // 16-node column tiles: up to 64 nodes
+constexpr int kLtPart = (kLtMaxD * kLtMaxD + kLtThreads - 1) / kLtThreads;  // rank-1 entries per thread
+
+// LDS rows per array: nodes 0 .. 16*NT + 1 (NT column tiles of 16 nodes), so
+// every GEMM column read and every j+1 read stays inside the array.
+__host__ __device__ inline int lt_rows(int N_max) { return 16 * ((N_max + 15) / 16) + 2; }
+inline size_t lt_lds_forward(int d, int N_max) { return size_t(3) * lt_rows(N_max) * (d + 1) * sizeof(float); }
+inline size_t lt_lds_backward(int d, int N_max) { return size_t(5) * lt_rows(N_max) * (d + 1) * sizeof(float); }
+
+struct LtArgs {
+  const float* x;
+  const float* t;
+  const int32_t* N;
+  const float* hp;  // [eps, A (d*d)]
+  const float* Q;   // [d*d]
+  const float* M;   // (I + tau Q_s)^{-1}
+  float* phi;
+  float* xtraj;
+  float* ptraj;
+  int32_t* iters;
+  int32_t* status;
+  int32_t* head;
+  int64_t n;
+  float sigma, tau, theta, tol;
+  int max_iter, fixed, N_max;
+  uint64_t seed;
+  // checkpoints: per point n_ckpt + 1 snapshots of (X, P, Z), each 3 (N_max+1) d;
+  // snapshot c holds the state before iteration c E, the last one the final state
+  float* ckpt;
+  int ckpt_every;
+  int n_ckpt;
 };
 
-int lt_create(LtState** out, const hjpd_desc&) {
+struct LtBwdArgs {
+  LtArgs f;
+  const float* grad_phi;  // [n]
+  float* dphi_dx;         // [n][d]
+  float* seg;             // per workgroup: E snapshots of (x^k, p^{k+1}) + adjoint save area
+  float* part;            // per workgroup: dA (d*d), dM (d*d), dQ direct (d*d), deps (1)
+  int K;
+};
+
+// Per-thread constants of the accumulator layout.
+template <int D>
+struct LtLane {
+  static constexpr int KS = D / 4, RT = (D + 15) / 16, LD = D + 1;
+  int tid, wave, lr, lk;
+  bool has;
+  int ic[4];
+  bool iok[4];
+  __device__ LtLane() {
+    tid = threadIdx.x;
+    wave = tid >> 6;
+    const int lane = tid & 63;
+    lr = lane & 15;
+    lk = lane >> 4;
+    has = wave < RT;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int i = 16 * wave + 4 * lk + r;
+      iok[r] = has && i < D;
+      ic[r] = iok[r] ? i : D;  // rows past d land on the padding column
+    }
+  }
+};
+
+// Reduce a float over the workgroup (all threads get the total).
+__device__ __forceinline__ float wg_sum(float v, float* s_red) {
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
+  const int wave = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) s_red[wave] = v;
+  __syncthreads();
+  float t = 0.f;
+#pragma unroll
+  for (int w = 0; w < kLtWaves; w++) t += s_red[w];
+  return t;
+}
+
+// acc[c] = rows of this wave x nodes 16c+1 .. 16c+16:  sum_k frag[row][k] B[node][k].
+template <int D>
+__device__ __forceinline__ void gemm_nodes(const float (&frag)[D / 4], const float* sB, int lob, int NT,
+                                           f4 (&acc)[kLtNT]) {
+  constexpr int LD = D + 1;
+#pragma unroll
+  for (int c = 0; c < kLtNT; c++) acc[c] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < D / 4; s++)
+#pragma unroll
+    for (int c = 0; c < kLtNT; c++)
+      if (c < NT) acc[c] = mfma4(frag[s], sB[lob + 16 * c * LD + 4 * s], acc[c]);
+}
+
+// out[ct] += sum_{j in [jlo, jhi]} scale U[j][row] V[j][col] for this wave's 16
+// rows and column tiles ct (16 columns each): outer products summed over nodes.
+template <int D>
+__device__ __forceinline__ void gemm_outer(const LtLane<D>& L, const float* sU, const float* sV, float scale, int jlo,
+                                           int jhi, f4 (&out)[(D + 15) / 16]) {
+  constexpr int LD = D + 1, CT = (D + 15) / 16;
+  const int row = 16 * L.wave + L.lr;
+  const int rc = (L.has && row < D) ? row : D;
+  for (int j0 = jlo; j0 <= jhi; j0 += 4) {
+    const int j = j0 + L.lk;
+    const bool ok = j <= jhi;
+    const int jr = ok ? j : jlo;
+    const float a = ok ? scale * sU[jr * LD + rc] : 0.f;
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++) {
+      const int col = 16 * ct + L.lr;
+      const float b = sV[jr * LD + (col < D ? col : D)];
+      out[ct] = mfma4(a, b, out[ct]);
+    }
+  }
+}
+
+// One iteration of the splitting (dual, node 0, primal, extrapolation) on the
+// LDS state.  If sx_out / sp_out are given, x^k (before the iteration) and
+// p^{k+1} (after the dual step) are stored there ([N+1][d], row stride d).
+// Adds this thread's partial residual sums to rx, rp.
+template <int D>
+__device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af)[D / 4], const float (&atf)[D / 4],
+                           float* sX, float* sP, float* sZ, int Np, int NT, float delta, float eps, float* sx_out,
+                           float* sp_out, float& rx, float& rp) {
+  constexpr int LD = D + 1;
+  const float sigma = a.sigma, tau = a.tau, theta = a.theta;
+  const float lam = sigma * delta, c1 = 1.f / (1.f + lam), td = tau * delta;
+  int lo = (L.lr + 1) * LD;
+  asm volatile("" : "+v"(lo));
+  const int lob = lo + L.lk;
+  if (sx_out)
+    for (int e = L.tid; e < (Np + 1) * D; e += kLtThreads) {
+      const int j = e / D, i = e - j * D;
+      sx_out[e] = sX[j * LD + i];
+    }
+  // ---- dual step: p_j <- (p_j + sigma (z_j - z_{j-1}) + lam f_j) c1 ----------
+  f4 acc[kLtNT];
+  gemm_nodes<D>(af, sX, lob, NT, acc);
+#pragma unroll
+  for (int c = 0; c < kLtNT; c++) {
+    if (c >= NT) continue;
+    const int j = 16 * c + L.lr + 1;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const bool ok = L.iok[r] && j <= Np;
+      const int e = lo + 16 * c * LD + L.ic[r];
+      const float xv = sX[e], pv = sP[e];
+      const float v = pv + sigma * (sZ[e] - sZ[e - LD]);
+      const float f = acc[c][r] + eps * tanh_fast(xv);
+      const float pn = (v + lam * f) * c1;
+      const float dp = pn - pv;
+      rp += ok ? dp * dp : 0.f;
+      sP[e] = ok ? pn : pv;
+    }
+  }
+  __syncthreads();
+  if (sp_out)
+    for (int e = L.tid; e < (Np + 1) * D; e += kLtThreads) {
+      const int j = e / D, i = e - j * D;
+      sp_out[e] = sP[j * LD + i];
+    }
+  // ---- node 0 (VALU): x_0 <- M (x_0 + tau p_1), M symmetric, read by columns ----
+  float x0n = 0.f, z0n = 0.f;
+  if (L.tid < D) {
+    float acc0 = 0.f;
+    for (int kq = 0; kq < D; kq++) acc0 += a.M[kq * D + L.tid] * (sX[kq] + tau * sP[LD + kq]);
+    const float old = sX[L.tid];
+    const float dx = acc0 - old;
+    rx += dx * dx;
+    x0n = acc0;
+    z0n = acc0 + theta * dx;
+  }
+  // ---- primal step, j = 1..N-1, with G = A^T P ----------------------------------
+  gemm_nodes<D>(atf, sP, lob, NT, acc);
+#pragma unroll
+  for (int c = 0; c < kLtNT; c++) {
+    if (c >= NT) continue;
+    const int j = 16 * c + L.lr + 1;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const bool ok = L.iok[r] && j <= Np - 1;
+      const int e = lo + 16 * c * LD + L.ic[r];
+      const float xv = sX[e], pv = sP[e], pp = sP[e + LD], zv = sZ[e];
+      const float th = tanh_fast(xv);
+      const float gx = acc[c][r] + eps * (1.f - th * th) * pv;  // -grad_x H
+      const float xn = xv - tau * (pv - pp) - td * gx;
+      const float dx = xn - xv;
+      rx += ok ? dx * dx : 0.f;
+      sZ[e] = ok ? xn + theta * dx : zv;
+      sX[e] = ok ? xn : xv;
+    }
+  }
+  __syncthreads();
+  if (L.tid < D) {
+    sX[L.tid] = x0n;
+    sZ[L.tid] = z0n;
+  }
+  __syncthreads();
+}
+
+// Random start (section 6 set-up) into LDS; rows past N and the padding column zero.
+template <int D>
+__device__ void lt_init(const LtArgs& a, int64_t pt, int Np, int R, float* sX, float* sP, float* sZ) {
+  constexpr int LD = D + 1;
+  for (int e = threadIdx.x; e < R * LD; e += kLtThreads) {
+    const int j = e / LD, i = e - j * LD;
+    float xv = 0.f, pv = 0.f;
+    if (j <= Np && i < D) {
+      const float xt = a.x[pt * D + i];
+      xv = (j < Np) ? float(double(xt) + start_noise(a.seed, uint64_t(pt), kArrX, j, i)) : xt;
+      pv = (j >= 1) ? float(start_noise(a.seed, uint64_t(pt), kArrP, j, i)) : 0.f;
+    }
+    sX[e] = xv;
+    sZ[e] = xv;
+    sP[e] = pv;
+  }
+  __syncthreads();
+}
+
+// Copy LDS arrays (row stride d+1) to a compact global snapshot (row stride d).
+template <int D>
+__device__ void lt_save(const float* sX, const float* sP, const float* sZ, int Np, int N_max, float* dst) {
+  constexpr int LD = D + 1;
+  const int64_t CK = int64_t(N_max + 1) * D;
+  for (int e = threadIdx.x; e < (Np + 1) * D; e += kLtThreads) {
+    const int j = e / D, i = e - j * D;
+    dst[e] = sX[j * LD + i];
+    dst[CK + e] = sP[j * LD + i];
+    dst[2 * CK + e] = sZ[j * LD + i];
+  }
+  __syncthreads();
+}
+
+// Load up to three consecutive snapshot arrays into LDS (zero past N and in the
+// padding column); null targets are skipped.
+template <int D>
+__device__ void lt_load(float* s0, float* s1, float* s2, int Np, int N_max, int R, const float* src) {
+  constexpr int LD = D + 1;
+  const int64_t CK = int64_t(N_max + 1) * D;
+  for (int e = threadIdx.x; e < R * LD; e += kLtThreads) {
+    const int j = e / LD, i = e - j * LD;
+    const bool ok = j <= Np && i < D;
+    const int s = j * D + i;
+    s0[e] = ok ? src[s] : 0.f;
+    if (s1) s1[e] = ok ? src[CK + s] : 0.f;
+    if (s2) s2[e] = ok ? src[2 * CK + s] : 0.f;
+  }
+  __syncthreads();
+}
+
+template <int D>
+__device__ bool lt_bad_input(const LtArgs& a, int64_t pt) {
+  const int Np = a.N[pt];
+  const float tt = a.t[pt];
+  bool bad = !(tt > 0.f) || !__builtin_isfinite(tt) || Np < 1 || Np > a.N_max;
+  for (int i = 0; i < D && !bad; i++) bad = !__builtin_isfinite(a.x[pt * D + i]);
+  return bad;
+}
+
+template <int D>
+__device__ void lt_load_fragments(const float* A, int wave, int lr, int lk, float (&af)[D / 4], float (&atf)[D / 4]) {
+  const int row = 16 * wave + lr;
+#pragma unroll
+  for (int s = 0; s < D / 4; s++) {
+    const int k = 4 * s + lk;
+    af[s] = row < D ? A[row * D + k] : 0.f;
+    atf[s] = row < D ? A[k * D + row] : 0.f;
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(kLtThreads, 4) k_lt_forward(LtArgs a) {
+  static_assert(D % 4 == 0, "d must be a multiple of 4");
+  constexpr int LD = D + 1;
+  extern __shared__ float smem[];
+  __shared__ float s_red[2 * kLtWaves];
+  __shared__ int s_pt;
+  const LtLane<D> L;
+  const int R = lt_rows(a.N_max);
+  const int NT = (a.N_max + 15) / 16;
+  float* sX = smem;
+  float* sP = sX + R * LD;
+  float* sZ = sP + R * LD;
+  const float eps = a.hp[0];
+  float af[D / 4], atf[D / 4];
+  lt_load_fragments<D>(a.hp + 1, L.wave, L.lr, L.lk, af, atf);
+
+  for (;;) {
+    if (L.tid == 0) s_pt = atomicAdd(a.head, 1);
+    __syncthreads();
+    const int64_t pt = s_pt;
+    __syncthreads();
+    if (pt >= a.n) break;
+    if (lt_bad_input<D>(a, pt)) {
+      if (L.tid == 0) {
+        if (a.phi) a.phi[pt] = NAN;
+        a.iters[pt] = 0;
+        a.status[pt] = kBadInput;
+      }
+      continue;
+    }
+    const int Np = a.N[pt];
+    const float delta = a.t[pt] / float(Np);
+    lt_init<D>(a, pt, Np, R, sX, sP, sZ);
+    const int64_t slot = 3 * int64_t(a.N_max + 1) * D;
+    int k = 0, st = kMaxIter;
+    for (;;) {
+      if (a.ckpt && k % a.ckpt_every == 0 && k / a.ckpt_every < a.n_ckpt)
+        lt_save<D>(sX, sP, sZ, Np, a.N_max, a.ckpt + (pt * (a.n_ckpt + 1) + k / a.ckpt_every) * slot);
+      const bool need_res = !a.fixed || k + 1 >= a.max_iter;
+      float rx = 0.f, rp = 0.f;
+      lt_iterate<D>(L, a, af, atf, sX, sP, sZ, Np, NT, delta, eps, nullptr, nullptr, rx, rp);
+      k++;
+      bool done = k >= a.max_iter;
+      if (need_res) {
+        const float rxs = wg_sum(rx, s_red);
+        const float rps = wg_sum(rp, s_red + kLtWaves);
+        const bool fin = __builtin_isfinite(rxs + rps);
+        const bool small = rxs < a.tol && rps < a.tol;
+        if (!fin) {
+          st = kNonFinite;
+          done = true;
+        } else if (small && (!a.fixed || done)) {
+          st = kConverged;
+          done = true;
+        }
+      }
+      if (done) break;
+    }
+    if (a.ckpt) lt_save<D>(sX, sP, sZ, Np, a.N_max, a.ckpt + (pt * (a.n_ckpt + 1) + a.n_ckpt) * slot);
+
+    // ---- value: g(x_0) + sum <p_j, x_j - x_{j-1}> - delta sum H(x_j, p_j) ----------
+    int lo = (L.lr + 1) * LD;
+    asm volatile("" : "+v"(lo));
+    f4 acc[kLtNT];
+    gemm_nodes<D>(af, sX, lo + L.lk, NT, acc);
+    float val = 0.f, badf = 0.f;
+#pragma unroll
+    for (int c = 0; c < kLtNT; c++) {
+      if (c >= NT) continue;
+      const int j = 16 * c + L.lr + 1;
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const bool ok = L.iok[r] && j <= Np;
+        const int e = lo + 16 * c * LD + L.ic[r];
+        const float xv = sX[e], pv = sP[e], xm = sX[e - LD];
+        const float f = acc[c][r] + eps * tanh_fast(xv);
+        const float term = pv * (xv - xm) - delta * (0.5f * pv * pv - pv * f);
+        val += ok ? term : 0.f;
+        badf += (ok && !(__builtin_isfinite(xv) && __builtin_isfinite(pv))) ? 1.f : 0.f;
+      }
+    }
+    if (L.tid < D) {
+      float qx = 0.f;
+      for (int kq = 0; kq < D; kq++) qx += 0.5f * (a.Q[L.tid * D + kq] + a.Q[kq * D + L.tid]) * sX[kq];
+      val += 0.5f * sX[L.tid] * qx;
+      if (!__builtin_isfinite(sX[L.tid])) badf = 1.f;
+    }
+    val = wg_sum(val, s_red);
+    badf = wg_sum(badf, s_red + kLtWaves);
+    if (badf > 0.f || !__builtin_isfinite(val)) st = kNonFinite;
+    if (L.tid == 0) {
+      if (a.phi) a.phi[pt] = val;
+      a.iters[pt] = k;
+      a.status[pt] = st;
+    }
+    if (a.xtraj || a.ptraj) {
+      const int64_t base = pt * int64_t(a.N_max + 1) * D;
+      for (int e = L.tid; e < (Np + 1) * D; e += kLtThreads) {
+        const int j = e / D, i = e - j * D;
+        if (a.xtraj) a.xtraj[base + e] = sX[j * LD + i];
+        if (a.ptraj) a.ptraj[base + e] = sP[j * LD + i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reverse sweep.  Adjoint arrays XB, PB, ZB (of x, p, z after an iteration)
+// live in LDS; per iteration k (from K-1 down to 0), with x^k in S0 and
+// p^{k+1} in S1, the transposed Jacobian of the iteration is applied:
+//   z' = x' + theta (x' - x)        XB += (1+theta) ZB;  Xpre = -theta ZB   (z'_N = x_N: Xpre_N = ZB_N + XB_N)
+//   x'_0 = M w, w = x_0 + tau p'_1  wbar = M XB_0;  Xpre_0 += wbar;  PB_1 += tau wbar;  dM += XB_0 w^T
+//   x'_j = x_j - tau (p'_j - p'_{j+1}) - tau delta (A^T p'_j + eps (1 - th_j^2) p'_j),  j < N:
+//        Xpre_j += XB_j + 2 tau delta eps (1 - th_j^2) th_j p'_j XB_j
+//        PB_j += -tau XB_j - tau delta (A XB)_j - tau delta eps (1 - th_j^2) XB_j + tau XB_{j-1}
+//        dA += -tau delta p'_j XB_j^T;  deps += -tau delta sum (1 - th^2) p' XB
+//   p'_j = c1 (p_j + sigma (z_j - z_{j-1}) + lam (A x_j + eps th_j)):
+//        vbar = c1 PB;  Ppre = vbar;  Zpre_j = sigma (vbar_j - vbar_{j+1})
+//        Xpre_j += lam (A^T vbar)_j + lam eps (1 - th_j^2) vbar_j;  dA += lam vbar_j x_j^T;  deps += lam th vbar
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
+  constexpr int LD = D + 1, CT = (D + 15) / 16;
+  const LtArgs& a = b.f;
+  extern __shared__ float smem[];
+  __shared__ float s_red[2 * kLtWaves];
+  __shared__ float s_w[D], s_wb[D];
+  __shared__ int s_pt;
+  const LtLane<D> L;
+  const int R = lt_rows(a.N_max);
+  const int NT = (a.N_max + 15) / 16;
+  float* S0 = smem;
+  float* S1 = S0 + R * LD;
+  float* S2 = S1 + R * LD;
+  float* S3 = S2 + R * LD;
+  float* S4 = S3 + R * LD;
+  const float eps = a.hp[0];
+  const float sigma = a.sigma, tau = a.tau, theta = a.theta;
+  float af[D / 4], atf[D / 4];
+  lt_load_fragments<D>(a.hp + 1, L.wave, L.lr, L.lk, af, atf);
+  f4 dA[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ct++) dA[ct] = f4{0.f, 0.f, 0.f, 0.f};
+  constexpr int PT = (D * D + kLtThreads - 1) / kLtThreads;
+  float dM[PT], dQ[PT];
+#pragma unroll
+  for (int q = 0; q < PT; q++) dM[q] = dQ[q] = 0.f;
+  float deps = 0.f;
+
+  const int E = a.ckpt_every;
+  const int64_t CK = int64_t(a.N_max + 1) * D;
+  const int64_t slot = 3 * CK;
+  float* segx = b.seg + int64_t(blockIdx.x) * (int64_t(E) * 2 * CK + 3 * CK);
+  float* adjsave = segx + int64_t(E) * 2 * CK;
+
+  for (;;) {
+    if (L.tid == 0) s_pt = atomicAdd(a.head + 2, 1);
+    __syncthreads();
+    const int64_t pt = s_pt;
+    __syncthreads();
+    if (pt >= a.n) break;
+    const float w = b.grad_phi[pt];
+    if (lt_bad_input<D>(a, pt) || w == 0.f) {
+      for (int i = L.tid; i < D; i += kLtThreads) b.dphi_dx[pt * D + i] = 0.f;
+      continue;
+    }
+    const int Np = a.N[pt];
+    const float delta = a.t[pt] / float(Np), lam = sigma * delta, c1 = 1.f / (1.f + lam), td = tau * delta;
+    const float* ck_pt = a.ckpt + pt * (a.n_ckpt + 1) * slot;
+
+    // ---- adjoint of the value at the final iterate ---------------------------------
+    float* XB = S2;
+    float* PB = S3;
+    float* ZB = S4;
+    lt_load<D>(S0, S1, nullptr, Np, a.N_max, R, ck_pt + a.n_ckpt * slot);
+    {
+      int lo = (L.lr + 1) * LD;
+      asm volatile("" : "+v"(lo));
+      f4 ax[kLtNT], atp[kLtNT];
+      gemm_nodes<D>(af, S0, lo + L.lk, NT, ax);
+      gemm_nodes<D>(atf, S1, lo + L.lk, NT, atp);
+      for (int e = L.tid; e < R * LD; e += kLtThreads) {
+        XB[e] = 0.f;
+        PB[e] = 0.f;
+        ZB[e] = 0.f;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < kLtNT; c++) {
+        if (c >= NT) continue;
+        const int j = 16 * c + L.lr + 1;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const bool ok = L.iok[r] && j <= Np;
+          const int e = lo + 16 * c * LD + L.ic[r];
+          const float xv = S0[e], pv = S1[e], xm = S0[e - LD];
+          const float pn = (j < Np) ? S1[e + LD] : 0.f;
+          const float th = tanh_fast(xv);
+          const float gx = pv - pn + delta * (atp[c][r] + eps * (1.f - th * th) * pv);
+          const float gp = xv - xm + delta * (ax[c][r] + eps * th - pv);
+          if (ok) {
+            XB[e] = w * gx;
+            PB[e] = w * gp;
+          }
+          deps += ok ? w * delta * pv * th : 0.f;
+        }
+      }
+      if (L.tid < D) {
+        float qx = 0.f;
+        for (int kq = 0; kq < D; kq++) qx += 0.5f * (a.Q[L.tid * D + kq] + a.Q[kq * D + L.tid]) * S0[kq];
+        XB[L.tid] = w * (qx - S1[LD + L.tid]);
+      }
+      // dQ (direct) += w x_0 x_0^T / 2 ; dA += w delta sum_j p_j x_j^T
+#pragma unroll
+      for (int q = 0; q < PT; q++) {
+        const int e = L.tid + q * kLtThreads;
+        if (e < D * D) dQ[q] += 0.5f * w * S0[e / D] * S0[e % D];
+      }
+      gemm_outer<D>(L, S1, S0, w * delta, 1, Np, dA);
+      __syncthreads();
+    }
+
+    // ---- segments, last to first ------------------------------------------------------
+    const int nseg = (b.K + E - 1) / E;
+    for (int sg = nseg - 1; sg >= 0; sg--) {
+      const int k0 = sg * E, k1 = min(b.K, k0 + E);
+      // save the adjoint, recompute the segment forward from its checkpoint
+      lt_save<D>(XB, PB, ZB, Np, a.N_max, adjsave);
+      lt_load<D>(S0, S1, S2, Np, a.N_max, R, ck_pt + sg * slot);
+      for (int k = k0; k < k1; k++) {
+        float rx = 0.f, rp = 0.f;
+        float* so = segx + int64_t(k - k0) * 2 * CK;
+        lt_iterate<D>(L, a, af, atf, S0, S1, S2, Np, NT, delta, eps, so, so + CK, rx, rp);
+      }
+      XB = S2;
+      PB = S3;
+      ZB = S4;
+      lt_load<D>(XB, PB, ZB, Np, a.N_max, R, adjsave);
+      // reverse sweep through the segment
+      for (int k = k1 - 1; k >= k0; k--) {
+        const float* so = segx + int64_t(k - k0) * 2 * CK;
+        lt_load<D>(S0, nullptr, nullptr, Np, a.N_max, R, so);       // x^k
+        lt_load<D>(S1, nullptr, nullptr, Np, a.N_max, R, so + CK);  // p^{k+1}
+        int lo = (L.lr + 1) * LD;
+        asm volatile("" : "+v"(lo));
+        const int lob = lo + L.lk;
+        // (A) extrapolation
+        for (int e = L.tid; e < (Np + 1) * LD; e += kLtThreads) {
+          const int j = e / LD, i = e - j * LD;
+          if (i < D) {
+            const float zb = ZB[e];
+            if (j < Np) {
+              XB[e] += (1.f + theta) * zb;
+              ZB[e] = -theta * zb;
+            } else {
+              ZB[e] = zb + XB[e];
+            }
+          }
+        }
+        __syncthreads();
+        // (B1) node 0: w = x_0 + tau p'_1, wbar = M XB_0
+        if (L.tid < D) {
+          s_w[L.tid] = S0[L.tid] + tau * S1[LD + L.tid];
+          float wb = 0.f;
+          for (int kq = 0; kq < D; kq++) wb += a.M[kq * D + L.tid] * XB[kq];
+          s_wb[L.tid] = wb;
+          ZB[L.tid] += wb;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PT; q++) {
+          const int e = L.tid + q * kLtThreads;
+          if (e < D * D) dM[q] += XB[e / D] * s_w[e % D];
+        }
+        // (B2) primal step transposed
+        {
+          f4 acc[kLtNT];
+          gemm_nodes<D>(af, XB, lob, NT, acc);  // (A XB)_j
+#pragma unroll
+          for (int c = 0; c < kLtNT; c++) {
+            if (c >= NT) continue;
+            const int j = 16 * c + L.lr + 1;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+              const bool ok = L.iok[r] && j <= Np;
+              const bool prim = j <= Np - 1;
+              const int e = lo + 16 * c * LD + L.ic[r];
+              const float xb = prim ? XB[e] : 0.f;
+              const float xbm = (j >= 2) ? XB[e - LD] : 0.f;
+              const float pp = S1[e], xk = S0[e];
+              const float th = tanh_fast(xk), om = 1.f - th * th;
+              float pbd = -tau * xb - td * acc[c][r] - td * eps * om * xb + tau * xbm;
+              if (j == 1) pbd += tau * s_wb[L.ic[r] < D ? L.ic[r] : 0];
+              if (ok) {
+                PB[e] += pbd;
+                ZB[e] += xb + 2.f * td * eps * om * th * pp * xb;
+              }
+              deps += (ok && prim) ? -td * om * pp * xb : 0.f;
+            }
+          }
+          gemm_outer<D>(L, S1, XB, -td, 1, Np - 1, dA);
+        }
+        __syncthreads();
+        // (C1) vbar = c1 PB
+        for (int e = L.tid; e < (Np + 1) * LD; e += kLtThreads) PB[e] *= c1;
+        __syncthreads();
+        // (C2) dual step transposed; Zpre into the XB array
+        {
+          f4 acc[kLtNT];
+          gemm_nodes<D>(atf, PB, lob, NT, acc);  // (A^T vbar)_j
+#pragma unroll
+          for (int c = 0; c < kLtNT; c++) {
+            if (c >= NT) continue;
+            const int j = 16 * c + L.lr + 1;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+              const bool ok = L.iok[r] && j <= Np;
+              const int e = lo + 16 * c * LD + L.ic[r];
+              const float vb = PB[e], vbn = (j < Np) ? PB[e + LD] : 0.f;
+              const float xk = S0[e];
+              const float th = tanh_fast(xk);
+              if (ok) {
+                ZB[e] += lam * acc[c][r] + lam * eps * (1.f - th * th) * vb;
+                XB[e] = sigma * (vb - vbn);
+              }
+              deps += ok ? lam * th * vb : 0.f;
+            }
+          }
+          if (L.tid < D) XB[L.tid] = -sigma * PB[LD + L.tid];
+          gemm_outer<D>(L, PB, S0, lam, 1, Np, dA);
+        }
+        __syncthreads();
+        // (D) roles: x-adjoint <- Xpre (ZB array), z-adjoint <- Zpre (XB array)
+        float* tmp = XB;
+        XB = ZB;
+        ZB = tmp;
+      }
+    }
+    // d phi / d x: every x_j^0 = x + noise (j < N), x_N = x, z^0 = x^0
+    if (L.tid < D) {
+      float g = 0.f;
+      for (int j = 0; j <= Np; j++) g += XB[j * LD + L.tid] + ZB[j * LD + L.tid];
+      b.dphi_dx[pt * D + L.tid] = g;
+    }
+    __syncthreads();
+  }
+  // ---- per-workgroup partial parameter gradients ----------------------------------------
+  const int64_t DD = int64_t(D) * D;
+  float* part = b.part + int64_t(blockIdx.x) * (3 * DD + 1);
+#pragma unroll
+  for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int row = 16 * L.wave + 4 * L.lk + r, col = 16 * ct + L.lr;
+      if (L.has && row < D && col < D) part[row * D + col] = dA[ct][r];
+    }
+#pragma unroll
+  for (int q = 0; q < PT; q++) {
+    const int e = L.tid + q * kLtThreads;
+    if (e < D * D) {
+      part[DD + e] = dM[q];
+      part[2 * DD + e] = dQ[q];
+    }
+  }
+  deps = wg_sum(deps, s_red);
+  if (L.tid == 0) part[3 * DD] = deps;
+}
+
+// Sum the per-workgroup partials (fixed order: deterministic).
+__global__ void k_lt_reduce_parts(const float* part, int nwg, int d, float* out /* [3 d^2 + 1] */) {
+  const int64_t DD = int64_t(d) * d, W = 3 * DD + 1;
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= W) return;
+  float s = 0.f;
+  for (int g = 0; g < nwg; g++) s += part[g * W + e];
+  out[e] = s;
+}
+
+// C = scale A B (row-major d x d)
+__global__ void k_lt_matmul(const float* Aa, const float* Bb, int d, float* C, float scale) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= d * d) return;
+  const int r = e / d, c = e - r * d;
+  float s = 0.f;
+  for (int k = 0; k < d; k++) s += Aa[r * d + k] * Bb[k * d + c];
+  C[e] = scale * s;
+}
+
+// dh = [deps, dA]; dg = dQ_direct + sym(S) with S = -tau M dM M.
+__global__ void k_lt_grad_out(const float* sums, const float* S, int d, float* dh, float* dg) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t DD = int64_t(d) * d;
+  if (e == 0) dh[0] = sums[3 * DD];
+  if (e >= d * d) return;
+  const int r = e / d, c = e - r * d;
+  dh[1 + e] = sums[e];
+  dg[e] = sums[2 * DD + e] + 0.5f * (S[r * d + c] + S[c * d + r]);
+}
+
+// (I + tau Q_s)^{-1} by Gauss-Jordan elimination with partial pivoting in
+// double precision, one workgroup; W is a d x 2d double scratch.
+__global__ void k_lt_inverse(const float* Q, int d, double tau, double* W, float* Mout, int* fail) {
+  __shared__ int s_piv;
+  __shared__ double s_f[kLtMaxD];
+  const int tid = threadIdx.x, nt = blockDim.x, w2 = 2 * d;
+  for (int e = tid; e < d * w2; e += nt) {
+    const int r = e / w2, c = e - r * w2;
+    double v;
+    if (c < d)
+      v = (r == c ? 1.0 : 0.0) + tau * 0.5 * (double(Q[r * d + c]) + double(Q[c * d + r]));
+    else
+      v = (c - d == r) ? 1.0 : 0.0;
+    W[e] = v;
+  }
+  if (tid == 0) *fail = 0;
+  __syncthreads();
+  for (int c = 0; c < d; c++) {
+    if (tid == 0) {
+      int best = c;
+      double bv = fabs(W[c * w2 + c]);
+      for (int r = c + 1; r < d; r++) {
+        const double v = fabs(W[r * w2 + c]);
+        if (v > bv) {
+          bv = v;
+          best = r;
+        }
+      }
+      s_piv = best;
+      if (!(bv > 0.0)) *fail = 1;
+    }
+    __syncthreads();
+    const int pr = s_piv;
+    if (pr != c)
+      for (int e = tid; e < w2; e += nt) {
+        const double tmp = W[c * w2 + e];
+        W[c * w2 + e] = W[pr * w2 + e];
+        W[pr * w2 + e] = tmp;
+      }
+    __syncthreads();
+    const double inv = 1.0 / W[c * w2 + c];
+    __syncthreads();
+    for (int e = tid; e < w2; e += nt) W[c * w2 + e] *= inv;
+    __syncthreads();
+    for (int r = tid; r < d; r += nt) s_f[r] = W[r * w2 + c];
+    __syncthreads();
+    for (int e = tid; e < d * w2; e += nt) {
+      const int r = e / w2, col = e - r * w2;
+      if (r != c) W[e] -= s_f[r] * W[c * w2 + col];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < d * d; e += nt) {
+    const int r = e / d, c = e - r * d;
+    Mout[e] = float(W[r * w2 + d + c]);
+  }
+}
+
+__global__ void k_lt_zero(int32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+struct LtState {
+  int d = 0;
+  int n_cu = 0;
+  float* M = nullptr;           // d*d
+  double* W = nullptr;          // d*2d
+  int32_t* counters = nullptr;  // [0] forward head, [1] inverse failure, [2] backward head
+  int32_t* scratch_i = nullptr; // iterations and statuses of the forward pass in value_grad
+  size_t scratch_bytes = 0;
+  float* ckpt = nullptr;
+  size_t ckpt_bytes = 0;
+  float* seg = nullptr;
+  size_t seg_bytes = 0;
+  float* part = nullptr;
+  size_t part_bytes = 0;
+  float* sums = nullptr;  // 3 d^2 + 1
+  float* tmp = nullptr;   // 2 d^2
+};
+
+typedef const void* KernelPtr;
+
+static KernelPtr forward_kernel(int d) {
+  switch (d) {
+    case 16: return reinterpret_cast<KernelPtr>(&k_lt_forward<16>);
+    case 32: return reinterpret_cast<KernelPtr>(&k_lt_forward<32>);
+    case 100: return reinterpret_cast<KernelPtr>(&k_lt_forward<100>);
+    case 128: return reinterpret_cast<KernelPtr>(&k_lt_forward<128>);
+  }
+  return nullptr;
+}
+
+static KernelPtr backward_kernel(int d) {
+  switch (d) {
+    case 16: return reinterpret_cast<KernelPtr>(&k_lt_backward<16>);
+    case 32: return reinterpret_cast<KernelPtr>(&k_lt_backward<32>);
+    case 100: return reinterpret_cast<KernelPtr>(&k_lt_backward<100>);
+    case 128: return reinterpret_cast<KernelPtr>(&k_lt_backward<128>);
+  }
+  return nullptr;
+}
+
+#define LT_HIP(expr, what)                                                                                    \
+  do {                                                                                                        \
+    hipError_t e_ = (expr);                                                                                   \
+    if (e_ != hipSuccess) return hjpd_fail(HJPD_EDEVICE, (std::string(what) + ": " + hipGetErrorString(e_)).c_str()); \
+  } while (0)
+
+int lt_create(LtState** out, const hjpd_desc& desc) {
   *out = nullptr;
-  return hjpd_fail(HJPD_EUNSUPPORTED, "LINEAR_TANH not built yet");
+  if (!forward_kernel(desc.d)) return hjpd_fail(HJPD_EUNSUPPORTED, "LINEAR_TANH is built for d in {16,32,100,128}");
+  if (desc.N_max > kLtMaxN) return hjpd_fail(HJPD_EUNSUPPORTED, "LINEAR_TANH is built for N_max <= 64");
+  LtState* s = new LtState();
+  s->d = desc.d;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    delete s;
+    return hjpd_fail(HJPD_EDEVICE, "device query failed");
+  }
+  s->n_cu = prop.multiProcessorCount;
+  if (hipFuncSetAttribute(forward_kernel(desc.d), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          int(lt_lds_forward(desc.d, desc.N_max))) != hipSuccess ||
+      hipFuncSetAttribute(backward_kernel(desc.d), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          int(lt_lds_backward(desc.d, desc.N_max))) != hipSuccess) {
+    delete s;
+    return hjpd_fail(HJPD_EDEVICE, "cannot reserve LDS for the linear-tanh kernels");
+  }
+  const size_t dd = size_t(desc.d) * desc.d;
+  if (hipMalloc(&s->M, sizeof(float) * dd) != hipSuccess || hipMalloc(&s->W, sizeof(double) * 2 * dd) != hipSuccess ||
+      hipMalloc(&s->counters, sizeof(int32_t) * 8) != hipSuccess ||
+      hipMalloc(&s->sums, sizeof(float) * (3 * dd + 1)) != hipSuccess ||
+      hipMalloc(&s->tmp, sizeof(float) * 2 * dd) != hipSuccess) {
+    lt_destroy(s);
+    return hjpd_fail(HJPD_ENOMEM, "linear-tanh workspace");
+  }
+  *out = s;
+  return HJPD_OK;
 }
-void lt_destroy(LtState* s) { delete s; }
-int lt_solve(LtState*, const hjpd_desc&, int64_t, const void*, const void*, const int32_t*, const void*, const void*,
-             void*, void*, void*, int32_t*, int32_t*, hipStream_t, hipEvent_t, hipEvent_t, int*, bool*) {
-  return hjpd_fail(HJPD_EUNSUPPORTED, "LINEAR_TANH not built yet");
+
+void lt_destroy(LtState* s) {
+  if (!s) return;
+  if (s->M) (void)hipFree(s->M);
+  if (s->W) (void)hipFree(s->W);
+  if (s->counters) (void)hipFree(s->counters);
+  if (s->scratch_i) (void)hipFree(s->scratch_i);
+  if (s->ckpt) (void)hipFree(s->ckpt);
+  if (s->seg) (void)hipFree(s->seg);
+  if (s->part) (void)hipFree(s->part);
+  if (s->sums) (void)hipFree(s->sums);
+  if (s->tmp) (void)hipFree(s->tmp);
+  delete s;
 }
-int lt_value_grad(LtState*, const hjpd_desc&, int64_t, const void*, const void*, const int32_t*, const void*,
-                  const void*, const void*, int, int, void*, void*, void*, void*, hipStream_t) {
-  return hjpd_fail(HJPD_EUNSUPPORTED, "LINEAR_TANH not built yet");
+
+static int lt_grid(LtState* st, KernelPtr k, size_t lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kLtThreads, lds) != hipSuccess || nb < 1) nb = 1;
+  return nb * st->n_cu;
+}
+
+static void fill_args(LtArgs& a, LtState* st, const hjpd_desc& d, int64_t n, const void* x, const void* t,
+                      const int32_t* N, const void* hp, const void* gp, void* phi, void* xtraj, void* ptraj,
+                      int32_t* iters, int32_t* status, int max_iter, bool fixed) {
+  std::memset(&a, 0, sizeof(a));
+  a.x = (const float*)x;
+  a.t = (const float*)t;
+  a.N = N;
+  a.hp = (const float*)hp;
+  a.Q = (const float*)gp;
+  a.M = st->M;
+  a.phi = (float*)phi;
+  a.xtraj = (float*)xtraj;
+  a.ptraj = (float*)ptraj;
+  a.iters = iters;
+  a.status = status;
+  a.head = st->counters;
+  a.n = n;
+  a.sigma = float(d.sigma);
+  a.tau = float(d.tau);
+  a.theta = float(d.theta);
+  a.tol = float(d.tol);
+  a.max_iter = max_iter;
+  a.fixed = fixed ? 1 : 0;
+  a.N_max = d.N_max;
+  a.seed = d.seed;
+  a.ckpt_every = 1;
+}
+
+static int lt_setup(LtState* st, const hjpd_desc& d, const void* gp, hipStream_t s) {
+  hipLaunchKernelGGL(k_lt_zero, dim3(1), dim3(64), 0, s, st->counters, 8);
+  hipLaunchKernelGGL(k_lt_inverse, dim3(1), dim3(256), 0, s, (const float*)gp, d.d, d.tau, st->W, st->M,
+                     st->counters + 1);
+  LT_HIP(hipGetLastError(), "linear-tanh set-up kernels");
+  return HJPD_OK;
+}
+
+int lt_solve(LtState* st, const hjpd_desc& d, int64_t n, const void* x, const void* t, const int32_t* N,
+             const void* hp, const void* gp, void* phi, void* xtraj, void* ptraj, int32_t* iters, int32_t* status,
+             hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, int* launches, bool* timing_valid) {
+  int rc = lt_setup(st, d, gp, s);
+  if (rc) return rc;
+  LtArgs a;
+  fill_args(a, st, d, n, x, t, N, hp, gp, phi, xtraj, ptraj, iters, status, d.max_iter,
+            (d.flags & HJPD_FIXED_ITERS) != 0);
+  const size_t lds = lt_lds_forward(d.d, d.N_max);
+  KernelPtr k = forward_kernel(d.d);
+  void* args[] = {&a};
+  if (ev0) LT_HIP(hipEventRecord(ev0, s), "hipEventRecord");
+  LT_HIP(hipLaunchKernel(k, dim3(lt_grid(st, k, lds)), dim3(kLtThreads), args, lds, s), "linear-tanh forward");
+  if (ev1) LT_HIP(hipEventRecord(ev1, s), "hipEventRecord");
+  if (launches) *launches = 1;
+  if (timing_valid) *timing_valid = ev0 != nullptr;
+  return HJPD_OK;
+}
+
+static int grow(void** p, size_t* cap, size_t need) {
+  if (need <= *cap) return HJPD_OK;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  if (hipMalloc(p, need) != hipSuccess) return hjpd_fail(HJPD_ENOMEM, "linear-tanh reverse-mode buffers");
+  *cap = need;
+  return HJPD_OK;
+}
+
+int lt_value_grad(LtState* st, const hjpd_desc& d, int64_t n, const void* x, const void* t, const int32_t* N,
+                  const void* hp, const void* gp, const void* grad_phi, int K, int E, void* phi, void* dphi_dx,
+                  void* dh, void* dg, hipStream_t s) {
+  if (E > K) E = K;
+  const int n_ckpt = (K + E - 1) / E;
+  const size_t CK = size_t(d.N_max + 1) * d.d;
+  const size_t dd = size_t(d.d) * d.d;
+  // buffers may be reallocated: finish earlier work on this context first
+  LT_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+  int rc = grow((void**)&st->ckpt, &st->ckpt_bytes, sizeof(float) * size_t(n) * (n_ckpt + 1) * 3 * CK);
+  if (rc) return rc;
+  KernelPtr kb = backward_kernel(d.d);
+  const size_t lds_b = lt_lds_backward(d.d, d.N_max);
+  const int grid_b = lt_grid(st, kb, lds_b);
+  rc = grow((void**)&st->seg, &st->seg_bytes, sizeof(float) * size_t(grid_b) * (size_t(E) * 2 * CK + 3 * CK));
+  if (rc) return rc;
+  rc = grow((void**)&st->part, &st->part_bytes, sizeof(float) * size_t(grid_b) * (3 * dd + 1));
+  if (rc) return rc;
+  rc = grow((void**)&st->scratch_i, &st->scratch_bytes, sizeof(int32_t) * 2 * size_t(n));
+  if (rc) return rc;
+  rc = lt_setup(st, d, gp, s);
+  if (rc) return rc;
+  LtArgs a;
+  fill_args(a, st, d, n, x, t, N, hp, gp, phi, nullptr, nullptr, st->scratch_i, st->scratch_i + n, K, true);
+  a.ckpt = st->ckpt;
+  a.ckpt_every = E;
+  a.n_ckpt = n_ckpt;
+  KernelPtr kf = forward_kernel(d.d);
+  const size_t lds_f = lt_lds_forward(d.d, d.N_max);
+  void* fargs[] = {&a};
+  LT_HIP(hipLaunchKernel(kf, dim3(lt_grid(st, kf, lds_f)), dim3(kLtThreads), fargs, lds_f, s), "linear-tanh forward");
+  LtBwdArgs b;
+  b.f = a;
+  b.f.phi = nullptr;
+  b.grad_phi = (const float*)grad_phi;
+  b.dphi_dx = (float*)dphi_dx;
+  b.seg = st->seg;
+  b.part = st->part;
+  b.K = K;
+  void* bargs[] = {&b};
+  LT_HIP(hipLaunchKernel(kb, dim3(grid_b), dim3(kLtThreads), bargs, lds_b, s), "linear-tanh backward");
+  const int W = int(3 * dd + 1);
+  hipLaunchKernelGGL(k_lt_reduce_parts, dim3((W + 255) / 256), dim3(256), 0, s, st->part, grid_b, d.d, st->sums);
+  // S = -tau M (dM M)
+  const int nb = int((dd + 255) / 256);
+  hipLaunchKernelGGL(k_lt_matmul, dim3(nb), dim3(256), 0, s, st->sums + dd, st->M, d.d, st->tmp, 1.f);
+  hipLaunchKernelGGL(k_lt_matmul, dim3(nb), dim3(256), 0, s, st->M, st->tmp, d.d, st->tmp + dd, -float(d.tau));
+  hipLaunchKernelGGL(k_lt_grad_out, dim3(nb), dim3(256), 0, s, st->sums, st->tmp + dd, d.d, (float*)dh, (float*)dg);
+  LT_HIP(hipGetLastError(), "linear-tanh gradient kernels");
+  return HJPD_OK;
 }
 
 }  // namespace hjpd
