@@ -613,7 +613,8 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
               const float xbm = (j >= 2) ? XB[e - LD] : 0.f;
               const float pp = S1[e], xk = S0[e];
               const float th = tanh_fast(xk), om = 1.f - th * th;
-              float pbd = -tau * xb - td * acc[c][r] - td * eps * om * xb + tau * xbm;
+              // x_N is fixed: no primal step and no (A XB)_N term at j = N
+              float pbd = -tau * xb - (prim ? td * acc[c][r] : 0.f) - td * eps * om * xb + tau * xbm;
               if (j == 1) pbd += tau * s_wb[L.ic[r] < D ? L.ic[r] : 0];
               if (ok) {
                 PB[e] += pbd;

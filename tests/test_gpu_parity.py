@@ -26,7 +26,7 @@ TOL = {"f64": 1e-9, "f32": 1e-4}
 
 
 def _check(O, w, dtype, *, plain=False, max_iter=None, lanes_per_point=0, nodes_per_lane=0, check_kstop=True,
-           traj=True, max_ill=0.0, converged_only=False):
+           traj=True, max_ill=0.0, converged_only=False, traj_tol=None):
     if max_iter is not None:
         w.max_iter = max_iter
     g = gpu_solve(w, dtype=dtype, plain=plain, lanes_per_point=lanes_per_point, nodes_per_lane=nodes_per_lane,
@@ -51,7 +51,8 @@ def _check(O, w, dtype, *, plain=False, max_iter=None, lanes_per_point=0, nodes_
         ex = traj_err(g["x_traj"][ok], o["x_traj"][ok], w.N[ok])
         ep = traj_err(g["p_traj"][ok], o["p_traj"][ok], w.N[ok])
         print("  traj rel err x %.3g p %.3g" % (ex.max(), ep.max()), flush=True)
-        assert ex.max() <= tol and ep.max() <= tol
+        ttol = tol if traj_tol is None else max(tol, traj_tol)
+        assert ex.max() <= ttol and ep.max() <= ttol
     # NONFINITE status agrees (the fixed-K oracle cannot tell converged-at-k
     # from max-iter-at-k beyond the final residual)
     assert np.all((g["status"][ok] == 2) == (o["status"][ok] == 2))
@@ -92,14 +93,17 @@ def test_cnorm10_tiles_match_oracle(oracle_mod, tile):
 @pytest.mark.parametrize("plain", [False, True])
 def test_quadrotor12_matches_oracle(oracle_mod, dtype, plain):
     """FP64 at a 2500-iteration cap (mostly unconverged iterates); FP32 at
-    converged points, where the fixed point is attracting and FP32 rounding
-    does not accumulate along an oscillating iterate."""
+    converged points.  FP32 values at 1e-4.  FP32 trajectories at the stop
+    rule's own resolution: the rule (squared 2-norm of the change below tol)
+    stops quadrotor iterates that still move by 1e-4..1e-3 per iteration along
+    a slowly decaying oscillation, so the FP32 and FP64 iterates at the same k
+    agree only to about one step's motion, sqrt(tol) = 1e-3."""
     w = W.quadrotor12().subset(np.arange(97))
     if dtype == "f64":
         _check(oracle_mod, w, dtype, plain=plain, max_iter=2500, check_kstop=False, max_ill=0.35)
     else:
         _check(oracle_mod, w, dtype, plain=plain, max_iter=20000, check_kstop=False, max_ill=0.35,
-               converged_only=True)
+               converged_only=True, traj_tol=float(np.sqrt(w.tol)))
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
