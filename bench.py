@@ -48,7 +48,7 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run")
-    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--max-iter", type=int, default=5000,
                     help="iteration cap of the headline run (points above it count as not converged)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -95,7 +95,7 @@ def main():
     # ---- batched FP32 (the headline) ------------------------------------------------
     td = torch.float32
     inp = tensors(td)
-    batched = make(td, graph=True, lanes_per_point=32, nodes_per_lane=1)
+    batched = make(td, graph=True, lanes_per_point=16, nodes_per_lane=2)
     out = batched.alloc(n)
     ms_step = timed_steps(batched, inp, out, args.steps, args.warmup)
     status = out.status.cpu().numpy()
@@ -105,7 +105,7 @@ def main():
 
     # dominant kernel: per-launch device time from the library's HIP events on
     # the same stream, over the same number of steps (no graph, one launch)
-    probe = make(td, timing=True, lanes_per_point=32, nodes_per_lane=1)
+    probe = make(td, timing=True, lanes_per_point=16, nodes_per_lane=2)
     out2 = probe.alloc(n)
     probe.solve(*inp, out=out2)
     torch.cuda.synchronize()
@@ -120,12 +120,12 @@ def main():
     achieved = flops / (kern_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK["fp32_vector"] / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK["fp32_vector"], "traffic": None,
-                "kernel": "k_group_control<float, CNorm<10>, 32, 1>", "kernel_ms": kern_ms,
+                "kernel": "k_group_control<float, CNorm<10>, 16, 2>", "kernel_ms": kern_ms,
                 "flops_per_launch": flops}
 
     # ---- the same with the long iteration cap (20000) -----------------------------
     w.max_iter = cap_default
-    long = make(td, graph=True, lanes_per_point=32, nodes_per_lane=1)
+    long = make(td, graph=True, lanes_per_point=16, nodes_per_lane=2)
     outl = long.alloc(n)
     ms_long = timed_steps(long, inp, outl, max(1, args.steps // 2), 1)
     conv_long = int((outl.status.cpu().numpy() == 0).sum())
@@ -154,7 +154,7 @@ def main():
     fp64_rec = None
     if not args.no_fp64:
         inp64 = tensors(torch.float64)
-        b64 = make(torch.float64, graph=True, lanes_per_point=32, nodes_per_lane=1)
+        b64 = make(torch.float64, graph=True, lanes_per_point=16, nodes_per_lane=2)
         o64 = b64.alloc(n)
         ms64 = timed_steps(b64, inp64, o64, max(1, args.steps // 2), 1)
         c64 = int((o64.status.cpu().numpy() == 0).sum())
@@ -185,7 +185,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "cnorm10: d=10 state-dependent eikonal H=c(x)||p||, c=1+0.5 sin(x1)cos(x2), "
                                "g=||x-a||^2/2-1, 65,536 points x~N(0,I), t~U[0.2,1], N=32, tol 1e-6",
-                   "points": n, "N": w.N_max, "d": w.d, "sigma": w.sigma, "tau": w.tau, "tile": "32 lanes x 1 node", "max_iter": args.max_iter,
+                   "points": n, "N": w.N_max, "d": w.d, "sigma": w.sigma, "tau": w.tau, "tile": "16 lanes x 2 nodes", "max_iter": args.max_iter,
                    "converged": conv, "iters_p50": float(np.median(iters)), "iters_p95": float(np.percentile(iters, 95)),
                    "iters_max": int(iters.max())},
         "roofline": roofline,

@@ -121,7 +121,10 @@ enum {
     HJPD_PLAIN = 1u << 0,       /* one point per lane, whole batch in one launch, no refill */
     HJPD_FIXED_ITERS = 1u << 1, /* run exactly max_iter iterations (no tolerance stop) */
     HJPD_GRAPH = 1u << 2,       /* capture the solve in a hipGraph and replay it on repeat calls */
-    HJPD_TIMING = 1u << 3       /* record HIP events around the main kernels (hjpd_get_timing) */
+    HJPD_TIMING = 1u << 3,      /* record HIP events around the main kernels (hjpd_get_timing) */
+    HJPD_NO_ORDER_HINT = 1u << 4 /* queue points of one N in input order; by default points that start
+                                    far from the minimiser of g are handed out first (order only,
+                                    results are unchanged) */
 };
 
 typedef struct {
@@ -136,7 +139,7 @@ typedef struct {
     double tol;      /* tolerance on the squared residuals (> 0) */
     int max_iter;    /* iteration cap (>= 1); with HJPD_FIXED_ITERS the exact count */
     uint64_t seed;   /* random start: counter-based SplitMix64 stream */
-    unsigned flags;  /* HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_GRAPH | HJPD_TIMING */
+    unsigned flags;  /* HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_GRAPH | HJPD_TIMING | HJPD_NO_ORDER_HINT */
     int lanes_per_point; /* persistent tile override: lanes per point (8,16,32,64), 0 = tuned/default */
     int nodes_per_lane;  /* persistent tile override: time nodes per lane (1..4), 0 = tuned/default */
 } hjpd_desc;

@@ -1,12 +1,13 @@
 // C-ABI of the hjpd library (declarations and contracts in include/hjpd.h).
 //
 // A solve is a short, graph-capturable stream sequence:
-//   1. k_queue_zero     clear the per-N counters;
+//   1. k_queue_zero     clear the bucket counters;
 //   2. k_queue_count    validate each point (bad inputs get HJPD_PT_BADINPUT
-//                       and are not queued), count points per N;
-//   3. k_queue_scan     one thread: offsets of the N-buckets in descending N,
-//                       begin/end of each tile class's segment, zero the pop
-//                       counters;
+//                       and are not queued), count points per bucket: N
+//                       major, a quantised work hint minor;
+//   3. k_queue_scan     one thread: bucket offsets in descending N and, within
+//                       one N, descending hint; begin/end of each tile
+//                       class's segment; zero the pop counters;
 //   4. k_queue_scatter  write point ids into their bucket;
 //   5. one persistent kernel per tile class (or one plain kernel).
 // No host synchronisation and no allocation happen inside the sequence, so
@@ -49,6 +50,37 @@ __global__ void k_queue_zero(int32_t* a, int n) {
   if (i < n) a[i] = 0;
 }
 
+// Work hint: a point that starts far from the minimiser of g tends to need
+// more iterations (its optimal path travels farther), so within one N the
+// queue hands out far points first and the slow ones do not start last
+// (longest-expected-first scheduling; order only, results are unchanged).
+// The hint is the distance to the minimiser of g (QUAD_SHIFT: ||x - a||;
+// NORM: ||x||; PAIR_DIST: ||r_P - r_E||), quantised on a log scale into
+// kHintBuckets buckets.
+constexpr int kHintBuckets = 16;
+enum : int { kHintNone = 0, kHintShift = 1, kHintNorm = 2, kHintPair = 3 };
+
+template <typename T>
+__device__ int hint_bucket(int kind, int64_t i, int d, int d_y, const T* x, const T* gp) {
+  if (kind == kHintNone) return 0;
+  double ss = 0.0;
+  if (kind == kHintPair) {
+    const int dx = d - d_y;
+    for (int k = 0; k < 3; k++) {
+      const double r = double(x[i * d + k]) - double(x[i * d + dx + k]);
+      ss += r * r;
+    }
+  } else {
+    for (int k = 0; k < d; k++) {
+      const double r = double(x[i * d + k]) - (kind == kHintShift ? double(gp[1 + k]) : 0.0);
+      ss += r * r;
+    }
+  }
+  const int b = int(4.0 * log2(1.0 + sqrt(ss)));
+  const int q = b < 0 ? 0 : (b >= kHintBuckets ? kHintBuckets - 1 : b);
+  return kHintBuckets - 1 - q;  // bucket 0 = largest hint
+}
+
 // Per-point validation shared by the counting and scattering passes.
 template <typename T>
 __device__ bool point_ok(int64_t i, int d, int N_max, const T* x, const T* t, const int32_t* N) {
@@ -80,21 +112,21 @@ __device__ int aggregated_add(bool part, int key, int32_t* counter) {
 }
 
 template <typename T>
-__global__ void k_queue_count(int64_t n, int d, int N_max, const T* x, const T* t, const int32_t* N,
-                              int32_t* counts, T* phi, int32_t* iters, int32_t* status) {
+__global__ void k_queue_count(int64_t n, int d, int d_y, int N_max, const T* x, const T* t, const int32_t* N,
+                              int hint, const T* gp, int32_t* counts, T* phi, int32_t* iters, int32_t* status) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   bool ok = false;
-  int Ni = 0;
+  int key = 0;
   if (i < n) {
     ok = point_ok(i, d, N_max, x, t, N);
-    Ni = N[i];
+    if (ok) key = N[i] * kHintBuckets + hint_bucket(hint, i, d, d_y, x, gp);
     if (!ok) {
       phi[i] = T(NAN);
       iters[i] = 0;
       status[i] = hjpd::kBadInput;
     }
   }
-  (void)aggregated_add(ok, Ni, counts);
+  (void)aggregated_add(ok, key, counts);
 }
 
 // cls_bounds: [2*ncls] (lo, hi) N-range of each class, classes disjoint.
@@ -104,14 +136,16 @@ __global__ void k_queue_scan(int N_max, int ncls, const int32_t* cls_bounds, con
                              int32_t* cursor, int32_t* cls_range, int32_t* heads) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int off = 0;
-  for (int v = N_max; v >= 1; v--) {
-    cursor[v] = off;
-    off += counts[v];
-  }
+  for (int v = N_max; v >= 1; v--)
+    for (int b = 0; b < kHintBuckets; b++) {
+      cursor[v * kHintBuckets + b] = off;
+      off += counts[v * kHintBuckets + b];
+    }
   for (int c = 0; c < ncls; c++) {
     const int lo = cls_bounds[2 * c], hi = cls_bounds[2 * c + 1];
-    cls_range[2 * c] = cursor[hi];
-    cls_range[2 * c + 1] = cursor[lo] + counts[lo];
+    const int last = lo * kHintBuckets + kHintBuckets - 1;
+    cls_range[2 * c] = cursor[hi * kHintBuckets];
+    cls_range[2 * c + 1] = cursor[last] + counts[last];
     heads[c] = 0;
   }
   cls_range[2 * ncls] = 0;
@@ -120,16 +154,16 @@ __global__ void k_queue_scan(int N_max, int ncls, const int32_t* cls_bounds, con
 }
 
 template <typename T>
-__global__ void k_queue_scatter(int64_t n, int d, int N_max, const T* x, const T* t, const int32_t* N,
-                                int32_t* cursor, int32_t* queue) {
+__global__ void k_queue_scatter(int64_t n, int d, int d_y, int N_max, const T* x, const T* t, const int32_t* N,
+                                int hint, const T* gp, int32_t* cursor, int32_t* queue) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   bool ok = false;
-  int Ni = 0;
+  int key = 0;
   if (i < n) {
     ok = point_ok(i, d, N_max, x, t, N);
-    Ni = N[i];
+    if (ok) key = N[i] * kHintBuckets + hint_bucket(hint, i, d, d_y, x, gp);
   }
-  const int pos = aggregated_add(ok, Ni, cursor);
+  const int pos = aggregated_add(ok, key, cursor);
   if (ok) queue[pos] = int32_t(i);
 }
 
@@ -149,8 +183,8 @@ struct hjpd_ctx {
   const void* plain_kern = nullptr;
   // device workspace
   int32_t* d_cls_bounds = nullptr;  // [2*ncls]
-  int32_t* d_counts = nullptr;      // [N_max+1]
-  int32_t* d_cursor = nullptr;      // [N_max+1]
+  int32_t* d_counts = nullptr;      // [(N_max+1) * kHintBuckets]
+  int32_t* d_cursor = nullptr;      // [(N_max+1) * kHintBuckets]
   int32_t* d_cls_range = nullptr;   // [2*(ncls+1)]
   int32_t* d_heads = nullptr;       // [ncls+1]
   int ncls_alloc = 0;
@@ -197,7 +231,7 @@ hjpd::Tile default_tile(int cap) {
   switch (cap) {
     case 8: return {8, 1};
     case 16: return {16, 1};
-    case 32: return {32, 1};
+    case 32: return {16, 2};
     case 64: return {32, 2};
     case 96: return {32, 3};
     case 128: return {32, 4};
@@ -285,7 +319,7 @@ int validate_desc(const hjpd_desc* d) {
   if (d->H < 0 || d->H > 3) return fail(HJPD_EINVAL, "unknown Hamiltonian family");
   if (d->g < 0 || d->g > 3) return fail(HJPD_EINVAL, "unknown initial-cost family");
   if (d->dtype != HJPD_F32 && d->dtype != HJPD_F64) return fail(HJPD_EINVAL, "unknown dtype");
-  if (d->flags & ~unsigned(HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_GRAPH | HJPD_TIMING))
+  if (d->flags & ~unsigned(HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_GRAPH | HJPD_TIMING | HJPD_NO_ORDER_HINT))
     return fail(HJPD_EINVAL, "unknown flag bits");
   if (d->lanes_per_point != 0) {
     const int L = d->lanes_per_point, K = d->nodes_per_lane;
@@ -337,13 +371,17 @@ int enqueue_solve(hjpd_ctx* c, int64_t n, const void* x, const void* t, const in
   const hjpd_desc& D = c->desc;
   const int ncls = int(c->plan.size());
   const int nb = int((n + 255) / 256);
-  hipLaunchKernelGGL(k_queue_zero, dim3((D.N_max + 1 + 255) / 256), dim3(256), 0, s, c->d_counts, D.N_max + 1);
-  hipLaunchKernelGGL(k_queue_count<T>, dim3(nb), dim3(256), 0, s, n, D.d, D.N_max, (const T*)x, (const T*)t, N,
-                     c->d_counts, (T*)phi, iters, status);
+  const int nkeys = (D.N_max + 1) * kHintBuckets;
+  int hint = kHintNone;
+  if (!(D.flags & HJPD_NO_ORDER_HINT))
+    hint = D.g == HJPD_G_QUAD_SHIFT ? kHintShift : (D.g == HJPD_G_NORM ? kHintNorm : kHintPair);
+  hipLaunchKernelGGL(k_queue_zero, dim3((nkeys + 255) / 256), dim3(256), 0, s, c->d_counts, nkeys);
+  hipLaunchKernelGGL(k_queue_count<T>, dim3(nb), dim3(256), 0, s, n, D.d, D.d_y, D.N_max, (const T*)x, (const T*)t,
+                     N, hint, (const T*)gp, c->d_counts, (T*)phi, iters, status);
   hipLaunchKernelGGL(k_queue_scan, dim3(1), dim3(64), 0, s, D.N_max, ncls, c->d_cls_bounds, c->d_counts, c->d_cursor,
                      c->d_cls_range, c->d_heads);
-  hipLaunchKernelGGL(k_queue_scatter<T>, dim3(nb), dim3(256), 0, s, n, D.d, D.N_max, (const T*)x, (const T*)t, N,
-                     c->d_cursor, c->d_queue);
+  hipLaunchKernelGGL(k_queue_scatter<T>, dim3(nb), dim3(256), 0, s, n, D.d, D.d_y, D.N_max, (const T*)x,
+                     (const T*)t, N, hint, (const T*)gp, c->d_cursor, c->d_queue);
   HIP_OK(hipGetLastError(), "queue kernels");
 
   hjpd::KArgs<T> a;
@@ -455,8 +493,8 @@ int hjpd_create(const hjpd_desc* desc, hjpd_ctx** out) {
   } else {
     rc = build_plan(c, nullptr, nullptr);
     if (!rc) rc = upload_plan(c);
-    if (!rc && (hipMalloc(&c->d_counts, sizeof(int32_t) * (desc->N_max + 1)) != hipSuccess ||
-                hipMalloc(&c->d_cursor, sizeof(int32_t) * (desc->N_max + 1)) != hipSuccess))
+    if (!rc && (hipMalloc(&c->d_counts, sizeof(int32_t) * (desc->N_max + 1) * kHintBuckets) != hipSuccess ||
+                hipMalloc(&c->d_cursor, sizeof(int32_t) * (desc->N_max + 1) * kHintBuckets) != hipSuccess))
       rc = fail(HJPD_ENOMEM, "counter allocation");
     if (rc) {
       hjpd_destroy(c);

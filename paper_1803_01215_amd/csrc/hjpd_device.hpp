@@ -104,13 +104,67 @@ __device__ __forceinline__ double from_next(double v) {
   return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
 }
 
+// DPP controls used below (GFX9 family, kept by CDNA):
+//   row_shr:1 / row_shl:1   lane i of a 16-lane row reads lane i-1 / i+1 of the
+//                           same row; the row's first / last lane reads 0
+//                           (bound_ctrl set);
+//   quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror (lane i of each
+//   8-lane half reads lane 7-i), row_mirror (lane i of a row reads lane 15-i):
+//   the four exchanges of a 16-lane butterfly all-reduce.
+enum : int { kDppRowShl1 = 0x101, kDppRowShr1 = 0x111, kDppQuad1032 = 0xB1, kDppQuad2301 = 0x4E,
+             kDppRowHalfMirror = 0x141, kDppRowMirror = 0x140 };
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(b)), CTRL, 0xf, 0xf, true));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(b >> 32)), CTRL, 0xf, 0xf, true));
+  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+
+// Value of v held by the previous lane of the group (lane l-1 of an aligned
+// group of L lanes); the group's first lane (l = 0) gets 0.
+template <int L, typename T>
+__device__ __forceinline__ T group_prev0(T v, int l) {
+  if constexpr (L >= 32) {
+    const T s = from_prev(v);
+    return (l == 0) ? T(0) : s;
+  } else {
+    const T s = dpp_f<kDppRowShr1>(v);  // row start reads 0
+    if constexpr (L == 16) return s;
+    else return (l == 0) ? T(0) : s;
+  }
+}
+
+// Value of v held by the next lane of the group; the group's last lane gets 0.
+template <int L, typename T>
+__device__ __forceinline__ T group_next0(T v, int l) {
+  if constexpr (L >= 32) {
+    const T s = from_next(v);
+    return (l == L - 1) ? T(0) : s;
+  } else {
+    const T s = dpp_f<kDppRowShl1>(v);  // row end reads 0
+    if constexpr (L == 16) return s;
+    else return (l == L - 1) ? T(0) : s;
+  }
+}
+
 // Sum over the L lanes of an aligned group (L a power of two <= 64); every
-// lane of the group receives the total.  Butterfly over xor offsets, which
-// never leaves the group.
+// lane of the group receives the same total (each exchange adds a pair in
+// both lanes, and addition commutes).  Within a 16-lane row: DPP butterfly;
+// across rows: xor shuffles.
 template <int L, typename T>
 __device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-  for (int m = 1; m < L; m <<= 1) v += __shfl_xor(v, m, 64);
+  if constexpr (L >= 2) v += dpp_f<kDppQuad1032>(v);
+  if constexpr (L >= 4) v += dpp_f<kDppQuad2301>(v);
+  if constexpr (L >= 8) v += dpp_f<kDppRowHalfMirror>(v);
+  if constexpr (L >= 16) v += dpp_f<kDppRowMirror>(v);
+  if constexpr (L >= 32) v += __shfl_xor(v, 16, 64);
+  if constexpr (L >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 

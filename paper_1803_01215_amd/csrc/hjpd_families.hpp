@@ -32,6 +32,8 @@ template <int D_>
 struct CNorm {
   static constexpr int D = D_;
   static constexpr bool kGame = false;
+  // dual step maps v = 0 to p = 0 exactly (nodes past N stay at p = 0 without a mask)
+  static constexpr bool kZeroSafe = true;
 
   template <typename T> struct Par {
     T alpha;
@@ -41,6 +43,8 @@ struct CNorm {
     T ta[D];        // tau * a   (QUAD_SHIFT)
     T a[D];
     T inv1pt;       // 1 / (1 + tau)
+    T s1pt;         // tau / (1 + tau)
+    T sa[D];        // tau / (1 + tau) * a
   };
   template <typename T> struct Cache {
     T pn;           // ||p_new||
@@ -59,6 +63,9 @@ struct CNorm {
       P.ta[i] = tau * P.a[i];
     }
     P.inv1pt = T(1) / (T(1) + tau);
+    P.s1pt = tau / (T(1) + tau);
+#pragma unroll
+    for (int i = 0; i < D; i++) P.sa[i] = P.s1pt * P.a[i];
   }
 
   template <typename T>
@@ -71,9 +78,9 @@ struct CNorm {
 #pragma unroll
     for (int i = 0; i < D; i++) ss += v[i] * v[i];
     const T rs = M<T>::rsqrt(ss);                 // +inf at v = 0
-    const T scale = M<T>::fmax(T(1) - lam * c * rs, T(0));
-    C.pn = scale * (ss * rs);                     // = max(||v|| - lam c, 0)
-    if (!(ss > T(0))) C.pn = T(0);
+    const bool nz = ss > T(0);
+    const T scale = nz ? M<T>::fmax(T(1) - lam * c * rs, T(0)) : T(0);
+    C.pn = nz ? scale * (ss * rs) : T(0);         // = max(||v|| - lam c, 0)
 #pragma unroll
     for (int i = 0; i < D; i++) v[i] *= scale;
     C.gc0 = P.alpha * c1 * c2;
@@ -115,6 +122,23 @@ struct CNorm {
     }
   }
 
+  // Node-0 increment prox_{tau g}(x0 + tau p1) - x0.  For the shifted
+  // quadratic this is tau/(1+tau) (p1 + a - x0).
+  template <typename T>
+  __device__ static void step0(const Par<T>& P, const T (&x0)[D], const T (&p1)[D], T tau, T (&dx)[D]) {
+    if (P.gkind == kGNorm) {
+      T v[D], o[D];
+#pragma unroll
+      for (int i = 0; i < D; i++) v[i] = x0[i] + tau * p1[i];
+      prox_g(P, v, tau, o);
+#pragma unroll
+      for (int i = 0; i < D; i++) dx[i] = o[i] - x0[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < D; i++) dx[i] = P.s1pt * (p1[i] - x0[i]) + P.sa[i];
+    }
+  }
+
   template <typename T>
   __device__ static T g(const Par<T>& P, const T (&x)[D]) {
     T ss = T(0);
@@ -144,11 +168,12 @@ struct CNorm {
 struct Quad {
   static constexpr int D = 12;
   static constexpr bool kGame = false;
+  static constexpr bool kZeroSafe = false;
 
   template <typename T> struct Par {
     T m_inv, gz, clamp;
     T iJ2[3];                 // 1 / J_i^2
-    T c0, a[12], ta[12], inv1pt;
+    T c0, a[12], ta[12], inv1pt, s1pt, sa[12];
   };
   template <typename T> struct Cache {
     T b[3];                   // R e3 / m
@@ -173,6 +198,9 @@ struct Quad {
       P.ta[i] = tau * P.a[i];
     }
     P.inv1pt = T(1) / (T(1) + tau);
+    P.s1pt = tau / (T(1) + tau);
+#pragma unroll
+    for (int i = 0; i < 12; i++) P.sa[i] = P.s1pt * P.a[i];
   }
 
   template <typename T>
@@ -281,6 +309,13 @@ struct Quad {
 #pragma unroll
     for (int i = 0; i < 12; i++) o[i] = (v[i] + P.ta[i]) * P.inv1pt;
   }
+  // Node-0 increment prox_{tau g}(x0 + tau p1) - x0 = tau/(1+tau) (p1 + a - x0).
+  template <typename T>
+  __device__ static void step0(const Par<T>& P, const T (&x0)[12], const T (&p1)[12], T, T (&dx)[12]) {
+#pragma unroll
+    for (int i = 0; i < 12; i++) dx[i] = P.s1pt * (p1[i] - x0[i]) + P.sa[i];
+  }
+
 
   template <typename T>
   __device__ static T g(const Par<T>& P, const T (&x)[12]) {
@@ -311,6 +346,7 @@ struct Pursuit {
   static constexpr int D = 12;
   static constexpr int DX = 6, DY = 6;
   static constexpr bool kGame = true;
+  static constexpr bool kZeroSafe = false;
 
   template <typename T> struct Par {
     T kappa, wP, wE, r;

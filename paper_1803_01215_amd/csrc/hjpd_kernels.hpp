@@ -28,6 +28,25 @@
 
 namespace hjpd {
 
+// Occupancy target of a persistent FP32 tile (waves per SIMD, the second
+// __launch_bounds__ argument): the register state grows with K, so one node
+// per lane keeps 4 waves, two keep 3, more keep 2.  FP64 state takes twice
+// the registers; it is left to the compiler (1 = no constraint).
+template <typename T, int K>
+inline constexpr int kGroupWaves = sizeof(T) == 8 ? 1 : (K == 1 ? 4 : (K == 2 ? 3 : 2));
+
+// Issue priority of a wave (s_setprio) from the iteration count of the
+// oldest point it holds: a wave still iterating after 1,000 / 4,000 / 16,000
+// iterations holds one of the few slow points, which end the persistent
+// launch, so the SIMD arbiter is told to prefer it over waves of fresh points.
+__device__ __forceinline__ void set_wave_priority(bool active, int k) {
+  if (__any(active && k >= 16000)) __builtin_amdgcn_s_setprio(3);
+  else if (__any(active && k >= 4000)) __builtin_amdgcn_s_setprio(2);
+  else if (__any(active && k >= 1000)) __builtin_amdgcn_s_setprio(1);
+  else __builtin_amdgcn_s_setprio(0);
+}
+__device__ __forceinline__ bool priority_step(int k) { return k == 1000 || k == 4000 || k == 16000; }
+
 template <typename T>
 struct KArgs {
   const T* x;            // [n][d]
@@ -68,7 +87,7 @@ __device__ __forceinline__ T init_x(T xt, uint64_t seed, int64_t pt, int arr, in
 // Persistent lane-group kernel, optimal-control path (Algorithm 1).
 // ---------------------------------------------------------------------------
 template <typename T, class F, int L, int K>
-__global__ void __launch_bounds__(256) k_group_control(KArgs<T> a) {
+__global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArgs<T> a) {
   constexpr int D = F::D;
   const int lane = threadIdx.x & 63;
   const int l = lane & (L - 1);
@@ -81,6 +100,7 @@ __global__ void __launch_bounds__(256) k_group_control(KArgs<T> a) {
   const T sigma = a.sigma, tau = a.tau, theta = a.theta;
 
   T x[K][D], p[K][D], z[K][D], x0[D], z0[D];
+  T tj[K], tdj[K];  // per node: tau and tau*delta where the node takes a primal step, else 0
   T delta = T(0), sd = T(0), td = T(0);
   int Np = 0, k = 0;
   int64_t pt = -1;
@@ -112,10 +132,17 @@ __global__ void __launch_bounds__(256) k_group_control(KArgs<T> a) {
         z[kk][i] = x[kk][i];
       }
     }
+    // node 0 lives in the group's first lane; the other lanes keep x0 = z0 = 0
 #pragma unroll
     for (int i = 0; i < D; i++) {
-      x0[i] = init_x(xt[i], a.seed, pt, kArrX, 0, i);
+      x0[i] = (l == 0) ? init_x(xt[i], a.seed, pt, kArrX, 0, i) : T(0);
       z0[i] = x0[i];
+    }
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      const int j = 1 + l * K + kk;
+      tj[kk] = (j < Np) ? tau : T(0);
+      tdj[kk] = (j < Np) ? td : T(0);
     }
   };
 
@@ -123,66 +150,60 @@ __global__ void __launch_bounds__(256) k_group_control(KArgs<T> a) {
 
   while (__any(active)) {
     // ---- dual step -------------------------------------------------------
+    // z_{j-1} of the lane's first node: the previous lane's last node, or
+    // z_0 in the group's first lane (z0 is zero in every other lane).
     T zprev[D];
 #pragma unroll
-    for (int i = 0; i < D; i++) {
-      const T s = from_prev(z[K - 1][i]);
-      zprev[i] = (l == 0) ? z0[i] : s;
-    }
+    for (int i = 0; i < D; i++) zprev[i] = group_prev0<L>(z[K - 1][i], l) + z0[i];
     typename F::template Cache<T> C[K];
     T rp = T(0), rx = T(0);
 #pragma unroll
     for (int kk = 0; kk < K; kk++) {
-      const int j = 1 + l * K + kk;
       T v[D];
 #pragma unroll
       for (int i = 0; i < D; i++) v[i] = p[kk][i] + sigma * (z[kk][i] - (kk == 0 ? zprev[i] : z[kk - 1][i]));
       F::dual(P, x[kk], v, sd, C[kk]);
-      if (j <= Np) {
+      if constexpr (!F::kZeroSafe) {
+        // nodes past N keep p = 0
+        const int j = 1 + l * K + kk;
 #pragma unroll
-        for (int i = 0; i < D; i++) {
-          const T dp = v[i] - p[kk][i];
-          rp += dp * dp;
-          p[kk][i] = v[i];
-        }
+        for (int i = 0; i < D; i++) v[i] = (j <= Np) ? v[i] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        const T dp = v[i] - p[kk][i];
+        rp += dp * dp;
+        p[kk][i] = v[i];
       }
     }
     // ---- node 0 -----------------------------------------------------------
     T pnext[D];
 #pragma unroll
-    for (int i = 0; i < D; i++) {
-      const T s = from_next(p[0][i]);
-      pnext[i] = (l == L - 1) ? T(0) : s;
-    }
+    for (int i = 0; i < D; i++) pnext[i] = group_next0<L>(p[0][i], l);
     if (l == 0) {
-      T v0[D], xn0[D];
-#pragma unroll
-      for (int i = 0; i < D; i++) v0[i] = x0[i] + tau * p[0][i];
-      F::prox_g(P, v0, tau, xn0);
+      T dx0[D];
+      F::step0(P, x0, p[0], tau, dx0);
 #pragma unroll
       for (int i = 0; i < D; i++) {
-        const T dx = xn0[i] - x0[i];
-        rx += dx * dx;
-        z0[i] = xn0[i] + theta * dx;
-        x0[i] = xn0[i];
+        rx += dx0[i] * dx0[i];
+        z0[i] = x0[i] + (T(1) + theta) * dx0[i];
+        x0[i] += dx0[i];
       }
     }
     // ---- primal step --------------------------------------------------------
+    // Nodes j >= N take no step: their tau and tau*delta are 0 (x_N = x stays
+    // fixed, and past N nothing moves).
 #pragma unroll
     for (int kk = 0; kk < K; kk++) {
-      const int j = 1 + l * K + kk;
-      if (j < Np) {
-        T g[D];
-        F::grad(P, x[kk], p[kk], C[kk], g);
+      T g[D];
+      F::grad(P, x[kk], p[kk], C[kk], g);
 #pragma unroll
-        for (int i = 0; i < D; i++) {
-          const T pp = (kk == K - 1) ? pnext[i] : p[kk + 1][i];
-          const T xn = x[kk][i] - tau * (p[kk][i] - pp) + td * g[i];
-          const T dx = xn - x[kk][i];
-          rx += dx * dx;
-          z[kk][i] = xn + theta * dx;
-          x[kk][i] = xn;
-        }
+      for (int i = 0; i < D; i++) {
+        const T pp = (kk == K - 1) ? pnext[i] : p[kk + 1][i];
+        const T dx = tdj[kk] * g[i] - tj[kk] * (p[kk][i] - pp);
+        rx += dx * dx;
+        z[kk][i] = x[kk][i] + (T(1) + theta) * dx;
+        x[kk][i] += dx;
       }
     }
     // ---- stopping rule (section 6 set-up) ------------------------------------
@@ -195,10 +216,7 @@ __global__ void __launch_bounds__(256) k_group_control(KArgs<T> a) {
       // value: Lagrangian at the last iterate (Algorithm 1)
       T xprev[D];
 #pragma unroll
-      for (int i = 0; i < D; i++) {
-        const T s = from_prev(x[K - 1][i]);
-        xprev[i] = (l == 0) ? x0[i] : s;
-      }
+      for (int i = 0; i < D; i++) xprev[i] = group_prev0<L>(x[K - 1][i], l) + x0[i];
       T acc = T(0);
       int bad = 0;
 #pragma unroll
@@ -252,6 +270,7 @@ __global__ void __launch_bounds__(256) k_group_control(KArgs<T> a) {
       }
       pop_and_init();
     }
+    if (__any(done || (active && priority_step(k)))) set_wave_priority(active, k);
   }
 }
 
@@ -260,7 +279,7 @@ __global__ void __launch_bounds__(256) k_group_control(KArgs<T> a) {
 // Hamiltonian separates as H = Hx(x, p) + Hy(y, q): block order p, q, x, y.
 // ---------------------------------------------------------------------------
 template <typename T, class F, int L, int K>
-__global__ void __launch_bounds__(256) k_group_game(KArgs<T> a) {
+__global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_game(KArgs<T> a) {
   constexpr int DX = F::DX, DY = F::DY, D = F::D;
   const int lane = threadIdx.x & 63;
   const int l = lane & (L - 1);
@@ -274,6 +293,7 @@ __global__ void __launch_bounds__(256) k_group_game(KArgs<T> a) {
 
   T x[K][DX], p[K][DX], z[K][DX], y[K][DY], q[K][DY], w[K][DY];
   T x0[DX], z0[DX], y0[DY], w0[DY];
+  T tj[K], tdj[K];  // per node: tau and tau*delta where the node takes a primal step, else 0
   T delta = T(0), sd = T(0), td = T(0);
   int Np = 0, k = 0;
   int64_t pt = -1;
@@ -311,15 +331,22 @@ __global__ void __launch_bounds__(256) k_group_game(KArgs<T> a) {
         w[kk][i] = y[kk][i];
       }
     }
+    // node 0 lives in the group's first lane; the other lanes keep x0 = z0 = y0 = w0 = 0
 #pragma unroll
     for (int i = 0; i < DX; i++) {
-      x0[i] = init_x(xt[i], a.seed, pt, kArrX, 0, i);
+      x0[i] = (l == 0) ? init_x(xt[i], a.seed, pt, kArrX, 0, i) : T(0);
       z0[i] = x0[i];
     }
 #pragma unroll
     for (int i = 0; i < DY; i++) {
-      y0[i] = init_x(xt[DX + i], a.seed, pt, kArrY, 0, i);
+      y0[i] = (l == 0) ? init_x(xt[DX + i], a.seed, pt, kArrY, 0, i) : T(0);
       w0[i] = y0[i];
+    }
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      const int j = 1 + l * K + kk;
+      tj[kk] = (j < Np) ? tau : T(0);
+      tdj[kk] = (j < Np) ? td : T(0);
     }
   };
 
@@ -328,15 +355,9 @@ __global__ void __launch_bounds__(256) k_group_game(KArgs<T> a) {
   while (__any(active)) {
     T zprev[DX], wprev[DY];
 #pragma unroll
-    for (int i = 0; i < DX; i++) {
-      const T s = from_prev(z[K - 1][i]);
-      zprev[i] = (l == 0) ? z0[i] : s;
-    }
+    for (int i = 0; i < DX; i++) zprev[i] = group_prev0<L>(z[K - 1][i], l) + z0[i];
 #pragma unroll
-    for (int i = 0; i < DY; i++) {
-      const T s = from_prev(w[K - 1][i]);
-      wprev[i] = (l == 0) ? w0[i] : s;
-    }
+    for (int i = 0; i < DY; i++) wprev[i] = group_prev0<L>(w[K - 1][i], l) + w0[i];
     typename F::template CacheX<T> CX[K];
     typename F::template CacheY<T> CY[K];
     T rp = T(0), rq = T(0), rx = T(0), ry = T(0);
@@ -369,15 +390,9 @@ __global__ void __launch_bounds__(256) k_group_game(KArgs<T> a) {
     }
     T pnext[DX], qnext[DY];
 #pragma unroll
-    for (int i = 0; i < DX; i++) {
-      const T s = from_next(p[0][i]);
-      pnext[i] = (l == L - 1) ? T(0) : s;
-    }
+    for (int i = 0; i < DX; i++) pnext[i] = group_next0<L>(p[0][i], l);
 #pragma unroll
-    for (int i = 0; i < DY; i++) {
-      const T s = from_next(q[0][i]);
-      qnext[i] = (l == L - 1) ? T(0) : s;
-    }
+    for (int i = 0; i < DY; i++) qnext[i] = group_next0<L>(q[0][i], l);
     // ---- x block: node 0 (prox of g(., y_0^k)), then descent steps ----------
     if (l == 0) {
       T v0[DX], xn0[DX];
@@ -394,19 +409,15 @@ __global__ void __launch_bounds__(256) k_group_game(KArgs<T> a) {
     }
 #pragma unroll
     for (int kk = 0; kk < K; kk++) {
-      const int j = 1 + l * K + kk;
-      if (j < Np) {
-        T g[DX];
-        F::grad_x(P, x[kk], p[kk], CX[kk], g);
+      T g[DX];
+      F::grad_x(P, x[kk], p[kk], CX[kk], g);
 #pragma unroll
-        for (int i = 0; i < DX; i++) {
-          const T pp = (kk == K - 1) ? pnext[i] : p[kk + 1][i];
-          const T xn = x[kk][i] - tau * (p[kk][i] - pp) + td * g[i];
-          const T dx = xn - x[kk][i];
-          rx += dx * dx;
-          z[kk][i] = xn + theta * dx;
-          x[kk][i] = xn;
-        }
+      for (int i = 0; i < DX; i++) {
+        const T pp = (kk == K - 1) ? pnext[i] : p[kk + 1][i];
+        const T dx = tdj[kk] * g[i] - tj[kk] * (p[kk][i] - pp);
+        rx += dx * dx;
+        z[kk][i] = x[kk][i] + (T(1) + theta) * dx;
+        x[kk][i] += dx;
       }
     }
     // ---- y block: node 0 (prox of -g(x_0^{k+1}, .)), then ascent steps ------
@@ -425,19 +436,15 @@ __global__ void __launch_bounds__(256) k_group_game(KArgs<T> a) {
     }
 #pragma unroll
     for (int kk = 0; kk < K; kk++) {
-      const int j = 1 + l * K + kk;
-      if (j < Np) {
-        T g[DY];
-        F::grad_y(P, y[kk], q[kk], CY[kk], g);
+      T g[DY];
+      F::grad_y(P, y[kk], q[kk], CY[kk], g);
 #pragma unroll
-        for (int i = 0; i < DY; i++) {
-          const T qq = (kk == K - 1) ? qnext[i] : q[kk + 1][i];
-          const T yn = y[kk][i] - tau * (q[kk][i] - qq) - td * g[i];
-          const T dy = yn - y[kk][i];
-          ry += dy * dy;
-          w[kk][i] = yn + theta * dy;
-          y[kk][i] = yn;
-        }
+      for (int i = 0; i < DY; i++) {
+        const T qq = (kk == K - 1) ? qnext[i] : q[kk + 1][i];
+        const T dy = -tdj[kk] * g[i] - tj[kk] * (q[kk][i] - qq);
+        ry += dy * dy;
+        w[kk][i] = y[kk][i] + (T(1) + theta) * dy;
+        y[kk][i] += dy;
       }
     }
     // ---- stopping rule ------------------------------------------------------------
@@ -449,15 +456,9 @@ __global__ void __launch_bounds__(256) k_group_game(KArgs<T> a) {
     if (done) {
       T xprev[DX], yprev[DY];
 #pragma unroll
-      for (int i = 0; i < DX; i++) {
-        const T s = from_prev(x[K - 1][i]);
-        xprev[i] = (l == 0) ? x0[i] : s;
-      }
+      for (int i = 0; i < DX; i++) xprev[i] = group_prev0<L>(x[K - 1][i], l) + x0[i];
 #pragma unroll
-      for (int i = 0; i < DY; i++) {
-        const T s = from_prev(y[K - 1][i]);
-        yprev[i] = (l == 0) ? y0[i] : s;
-      }
+      for (int i = 0; i < DY; i++) yprev[i] = group_prev0<L>(y[K - 1][i], l) + y0[i];
       T acc = T(0);
       int bad = 0;
 #pragma unroll
@@ -523,6 +524,7 @@ __global__ void __launch_bounds__(256) k_group_game(KArgs<T> a) {
       }
       pop_and_init();
     }
+    if (__any(done || (active && priority_step(k)))) set_wave_priority(active, k);
   }
 }
 

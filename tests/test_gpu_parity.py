@@ -226,3 +226,23 @@ def test_autotune_then_solve_matches_oracle(oracle_mod):
     o = oracle_fixed(oracle_mod, w, it, traj=False, inputs_dtype="f32")
     assert rel_err(out.phi.cpu().numpy(), o["phi"]).max() <= 1e-4
     s.close()
+
+
+def test_order_hint_changes_schedule_only():
+    """The work-hint queue order (far points first) changes which lane group
+    takes which point, never a point's arithmetic: results are bitwise equal."""
+    w = W.cnorm10(300)
+    a = gpu_solve(w, dtype="f32", traj=True)
+    import torch
+
+    from paper_1803_01215_amd.solver import Solver
+    s = Solver(d=w.d, H=w.H, g=w.g, N_max=w.N_max, sigma=w.sigma, tau=w.tau, theta=w.theta, tol=w.tol,
+          max_iter=w.max_iter, seed=w.init_seed, dtype=torch.float32, order_hint=False)
+    dev = "cuda"
+    out = s.solve(torch.tensor(w.x, dtype=torch.float32, device=dev), torch.tensor(w.t, dtype=torch.float32, device=dev),
+                  torch.tensor(w.N, dtype=torch.int32, device=dev), torch.tensor(w.hp, dtype=torch.float32, device=dev),
+                  torch.tensor(w.gp, dtype=torch.float32, device=dev), traj=True)
+    torch.cuda.synchronize()
+    for k in ("phi", "iters", "status", "x_traj", "p_traj"):
+        assert np.array_equal(getattr(out, k).cpu().numpy(), a[k].astype(getattr(out, k).cpu().numpy().dtype)), k
+    s.close()
