@@ -24,7 +24,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp32_vector": 157.3e12, "fp64_vector": 78.6e12}
+PEAK = {"fp32_vector": 157.3e12, "fp64_vector": 78.6e12, "fp32_matrix": 157.3e12}
 
 
 def flops_per_iter_cnorm(N: int, d: int) -> int:
@@ -40,6 +40,94 @@ def flops_per_iter_cnorm(N: int, d: int) -> int:
     return N * (9 * d + 12) + (N - 1) * (8 * d + 6) + 9 * d
 
 
+# Sources of the persistent kernel: HBM traffic measured by rocprofv3 counters
+# is reported only while these files are unchanged since the measurement.
+KERNEL_SOURCES = ["paper_1803_01215_amd/csrc/hjpd_kernels.hpp", "paper_1803_01215_amd/csrc/hjpd_families.hpp",
+                  "paper_1803_01215_amd/csrc/hjpd_device.hpp", "paper_1803_01215_amd/csrc/hjpd_api.hip"]
+TRAFFIC_FILE = "profiles/traffic_cnorm10_f32_group16x2.json"
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when the summary is absent, names another kernel, or the kernel
+    sources changed after the counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel") != kernel or rec.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    return float(rec["bytes_per_launch"])
+
+
+def mfma_flops_per_iter_lintanh(N: int, d: int) -> int:
+    """Matrix-core flops of one iteration of one point for the linear-tanh
+    family: A x_j for the dual step at j = 1..N and A^T p_j for the primal
+    step at j = 1..N-1, each a d x d by d product (FMA = 2 flops)."""
+    return 2 * d * d * (2 * N - 1)
+
+
+def bench_lintanh(torch, dev, steps):
+    """Forward solves/s and MFMA throughput at K = 500 fixed iterations, and
+    the reverse-mode call (forward with checkpoints every 50 + backward +
+    reductions) on the same 16,384 points."""
+    import workloads as W
+    from paper_1803_01215_amd.autograd import LinearTanhValue
+    from paper_1803_01215_amd.solver import Solver
+
+    w = W.lintanh100()
+    K = w.max_iter
+    f32 = torch.float32
+    x = torch.tensor(w.x, dtype=f32, device=dev)
+    t = torch.tensor(w.t, dtype=f32, device=dev)
+    N = torch.tensor(w.N, dtype=torch.int32, device=dev)
+    hp = torch.tensor(w.hp, dtype=f32, device=dev)
+    Q = torch.tensor(w.gp, dtype=f32, device=dev)
+    s = Solver(d=w.d, H=w.H, g=w.g, N_max=w.N_max, sigma=w.sigma, tau=w.tau, tol=w.tol, max_iter=K,
+               seed=w.init_seed, dtype=f32, fixed_iters=True, timing=True)
+    out = s.alloc(w.n)
+    s.solve(x, t, N, hp, Q, out=out)
+    torch.cuda.synchronize()
+    kms = []
+    for _ in range(max(1, steps // 2)):
+        s.solve(x, t, N, hp, Q, out=out)
+        ms, nl = s.timing()
+        kms.append(ms)
+    fwd_ms = float(np.mean(kms))
+    s.close()
+    flops = float(w.n) * K * mfma_flops_per_iter_lintanh(w.N_max, w.d)
+    lt = LinearTanhValue(w.d, w.N_max, w.sigma, w.tau, K, ckpt_every=50, seed=w.init_seed)
+    gphi = torch.ones(w.n, dtype=f32, device=dev)
+    lt.value_grad(x, t, N, hp, Q, gphi)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(1, steps // 5)
+    e0.record()
+    for _ in range(reps):
+        lt.value_grad(x, t, N, hp, Q, gphi)
+    e1.record()
+    torch.cuda.synchronize()
+    vg_ms = e0.elapsed_time(e1) / reps
+    lt.close()
+    return {"workload": "lintanh100: d=100, H=-<p,Ax+0.1 tanh x>+|p|^2/2, g=x^T Q x/2, 16,384 points, N=50, "
+                        "K=500 fixed iterations, FP32",
+            "forward_kernel_ms": fwd_ms, "forward_solves_per_s": w.n / (fwd_ms * 1e-3),
+            "mfma": {"bound": "mfma", "achieved": flops / (fwd_ms * 1e-3) / 1e12, "peak": PEAK["fp32_matrix"] / 1e12,
+                     "unit": "TFLOP/s", "frac": flops / (fwd_ms * 1e-3) / PEAK["fp32_matrix"],
+                     "kernel": "k_lt_forward<100>", "flops_per_launch": flops},
+            "value_grad_ms": vg_ms, "value_grad_points_per_s": w.n / (vg_ms * 1e-3), "ckpt_every": 50}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,6 +139,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--max-iter", type=int, default=5000,
                     help="iteration cap of the headline run (points above it count as not converged)")
+    ap.add_argument("--no-c5", action="store_true", help="skip the linear-tanh (d=100) forward/reverse timing")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -119,7 +208,8 @@ def main():
     flops = float(sum(iters * flops_per_iter_cnorm(w.N_max, w.d)))
     achieved = flops / (kern_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK["fp32_vector"] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK["fp32_vector"], "traffic": None,
+                "frac": achieved / PEAK["fp32_vector"],
+                "traffic": measured_traffic("k_group_control<float, CNorm<10>, 16, 2>"),
                 "kernel": "k_group_control<float, CNorm<10>, 16, 2>", "kernel_ms": kern_ms,
                 "flops_per_launch": flops}
 
@@ -161,6 +251,11 @@ def main():
         fp64_rec = {"value": c64 / (ms64 * 1e-3), "ms_per_step": ms64, "converged": c64}
         b64.close()
 
+    # ---- matrix-core path (linear-tanh, d = 100): forward and reverse mode ------------------
+    c5_rec = None
+    if not args.no_c5:
+        c5_rec = bench_lintanh(torch, dev, args.steps)
+
     # ---- CPU oracle baseline on a bounded sample ------------------------------------------
     cpu_rec = None
     if not args.no_cpu:
@@ -194,6 +289,7 @@ def main():
         "speedup_vs_plain": value / plain_rec["value"] if plain_rec["value"] > 0 else None,
         "fp64": fp64_rec,
         "long_cap": long_rec,
+        "lintanh100": c5_rec,
     }
     print(json.dumps(rec))
 
