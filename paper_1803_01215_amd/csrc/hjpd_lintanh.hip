@@ -58,6 +58,12 @@ constexpr int kLtPart = (kLtMaxD * kLtMaxD + kLtThreads - 1) / kLtThreads;  // r
 __host__ __device__ inline int lt_rows(int N_max) { return 16 * ((N_max + 15) / 16) + 2; }
 inline size_t lt_lds_forward(int d, int N_max) { return size_t(3) * lt_rows(N_max) * (d + 1) * sizeof(float); }
 inline size_t lt_lds_backward(int d, int N_max) { return size_t(5) * lt_rows(N_max) * (d + 1) * sizeof(float); }
+// Per-workgroup reverse-mode buffer (floats): E recomputed steps of (x^k, p^{k+1}),
+// the saved adjoint (3 arrays), and E staged (XB_0, w) pairs for dM.
+__host__ __device__ inline int64_t lt_seg_floats(int d, int N_max, int E) {
+  const int64_t CK = int64_t(N_max + 1) * d;
+  return int64_t(E) * 2 * CK + 3 * CK + int64_t(E) * 2 * d;
+}
 
 struct LtArgs {
   const float* x;
@@ -130,18 +136,31 @@ __device__ __forceinline__ float wg_sum(float v, float* s_red) {
   return t;
 }
 
-// acc[c] = rows of this wave x nodes 16c+1 .. 16c+16:  sum_k frag[row][k] B[node][k].
+// acc[c] = rows of this wave x nodes 16c+1 .. 16c+16:  sum_k frag[row][k] B[node][k],
+// for all kLtNT column tiles (a fixed count keeps the MFMA chain free of
+// branches).  Node rows at or past R (the array's row count) read row R-1,
+// which is zero (every array is zero past N); those columns are not used.
 template <int D>
-__device__ __forceinline__ void gemm_nodes(const float (&frag)[D / 4], const float* sB, int lob, int NT,
+__device__ __forceinline__ void gemm_nodes(const float (&frag)[D / 4], const float* sB, const LtLane<D>& L, int R,
                                            f4 (&acc)[kLtNT]) {
   constexpr int LD = D + 1;
+  int base[kLtNT];
 #pragma unroll
-  for (int c = 0; c < kLtNT; c++) acc[c] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int c = 0; c < kLtNT; c++) {
+    const int row = 16 * c + L.lr + 1;
+    base[c] = (row < R ? row : R - 1) * LD + L.lk;
+    asm volatile("" : "+v"(base[c]));
+    acc[c] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+  // Scheduling fence every kGemmWindow k-steps: bounds how many B reads the
+  // scheduler hoists ahead of their MFMAs (each hoisted read holds a VGPR).
+  constexpr int kGemmWindow = 2;
 #pragma unroll
-  for (int s = 0; s < D / 4; s++)
+  for (int s = 0; s < D / 4; s++) {
 #pragma unroll
-    for (int c = 0; c < kLtNT; c++)
-      if (c < NT) acc[c] = mfma4(frag[s], sB[lob + 16 * c * LD + 4 * s], acc[c]);
+    for (int c = 0; c < kLtNT; c++) acc[c] = mfma4(frag[s], sB[base[c] + 4 * s], acc[c]);
+    if (s % kGemmWindow == kGemmWindow - 1) __builtin_amdgcn_sched_barrier(0);
+  }
 }
 
 // out[ct] += sum_{j in [jlo, jhi]} scale U[j][row] V[j][col] for this wave's 16
@@ -175,6 +194,7 @@ __device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af
                            float* sX, float* sP, float* sZ, int Np, int NT, float delta, float eps, float* sx_out,
                            float* sp_out, float& rx, float& rp) {
   constexpr int LD = D + 1;
+  const int R = lt_rows(a.N_max);
   const float sigma = a.sigma, tau = a.tau, theta = a.theta;
   const float lam = sigma * delta, c1 = 1.f / (1.f + lam), td = tau * delta;
   int lo = (L.lr + 1) * LD;
@@ -187,7 +207,7 @@ __device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af
     }
   // ---- dual step: p_j <- (p_j + sigma (z_j - z_{j-1}) + lam f_j) c1 ----------
   f4 acc[kLtNT];
-  gemm_nodes<D>(af, sX, lob, NT, acc);
+  gemm_nodes<D>(af, sX, L, R, acc);
 #pragma unroll
   for (int c = 0; c < kLtNT; c++) {
     if (c >= NT) continue;
@@ -223,7 +243,7 @@ __device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af
     z0n = acc0 + theta * dx;
   }
   // ---- primal step, j = 1..N-1, with G = A^T P ----------------------------------
-  gemm_nodes<D>(atf, sP, lob, NT, acc);
+  gemm_nodes<D>(atf, sP, L, R, acc);
 #pragma unroll
   for (int c = 0; c < kLtNT; c++) {
     if (c >= NT) continue;
@@ -385,7 +405,7 @@ __global__ void __launch_bounds__(kLtThreads, 4) k_lt_forward(LtArgs a) {
     int lo = (L.lr + 1) * LD;
     asm volatile("" : "+v"(lo));
     f4 acc[kLtNT];
-    gemm_nodes<D>(af, sX, lo + L.lk, NT, acc);
+    gemm_nodes<D>(af, sX, L, R, acc);
     float val = 0.f, badf = 0.f;
 #pragma unroll
     for (int c = 0; c < kLtNT; c++) {
@@ -465,17 +485,29 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
   f4 dA[CT];
 #pragma unroll
   for (int ct = 0; ct < CT; ct++) dA[ct] = f4{0.f, 0.f, 0.f, 0.f};
-  constexpr int PT = (D * D + kLtThreads - 1) / kLtThreads;
-  float dM[PT], dQ[PT];
-#pragma unroll
-  for (int q = 0; q < PT; q++) dM[q] = dQ[q] = 0.f;
   float deps = 0.f;
+  // dM and the direct dQ term accumulate in this workgroup's partial block in
+  // global memory, in the accumulator layout (wave rows x column tiles), so no
+  // per-thread d*d/threads arrays or index divisions stay live in registers.
+  const int64_t DD = int64_t(D) * D;
+  float* part = b.part + int64_t(blockIdx.x) * (3 * DD + 1);
+#pragma unroll
+  for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int row = 16 * L.wave + 4 * L.lk + r, col = 16 * ct + L.lr;
+      if (L.has && row < D && col < D) {
+        part[DD + row * D + col] = 0.f;
+        part[2 * DD + row * D + col] = 0.f;
+      }
+    }
 
   const int E = a.ckpt_every;
   const int64_t CK = int64_t(a.N_max + 1) * D;
   const int64_t slot = 3 * CK;
-  float* segx = b.seg + int64_t(blockIdx.x) * (int64_t(E) * 2 * CK + 3 * CK);
+  float* segx = b.seg + int64_t(blockIdx.x) * lt_seg_floats(D, a.N_max, E);
   float* adjsave = segx + int64_t(E) * 2 * CK;
+  float* stage = adjsave + 3 * CK;  // per step of a segment: XB_0 (node-0 adjoint) and w = x_0 + tau p'_1
 
   for (;;) {
     if (L.tid == 0) s_pt = atomicAdd(a.head + 2, 1);
@@ -501,8 +533,8 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
       int lo = (L.lr + 1) * LD;
       asm volatile("" : "+v"(lo));
       f4 ax[kLtNT], atp[kLtNT];
-      gemm_nodes<D>(af, S0, lo + L.lk, NT, ax);
-      gemm_nodes<D>(atf, S1, lo + L.lk, NT, atp);
+      gemm_nodes<D>(af, S0, L, R, ax);
+      gemm_nodes<D>(atf, S1, L, R, atp);
       for (int e = L.tid; e < R * LD; e += kLtThreads) {
         XB[e] = 0.f;
         PB[e] = 0.f;
@@ -535,10 +567,19 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
         XB[L.tid] = w * (qx - S1[LD + L.tid]);
       }
       // dQ (direct) += w x_0 x_0^T / 2 ; dA += w delta sum_j p_j x_j^T
+      {
+        // opaque per-lane base: keeps the 28 addresses from being hoisted
+        // out of the point loop (and held in registers for the whole kernel)
+        int rb = 16 * L.wave + 4 * L.lk;
+        asm volatile("" : "+v"(rb));
+        float* pq = part + 2 * DD + int64_t(rb) * D + L.lr;
 #pragma unroll
-      for (int q = 0; q < PT; q++) {
-        const int e = L.tid + q * kLtThreads;
-        if (e < D * D) dQ[q] += 0.5f * w * S0[e / D] * S0[e % D];
+        for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+          for (int r = 0; r < 4; r++) {
+            const int row = rb + r, col = 16 * ct + L.lr;
+            if (L.has && row < D && col < D) pq[r * D + 16 * ct] += 0.5f * w * S0[row] * S0[col];
+          }
       }
       gemm_outer<D>(L, S1, S0, w * delta, 1, Np, dA);
       __syncthreads();
@@ -582,24 +623,23 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
           }
         }
         __syncthreads();
-        // (B1) node 0: w = x_0 + tau p'_1, wbar = M XB_0
+        // (B1) node 0: w = x_0 + tau p'_1, wbar = M XB_0; dM += XB_0 w^T is
+        // applied once per segment from the staged (XB_0, w) pairs
         if (L.tid < D) {
-          s_w[L.tid] = S0[L.tid] + tau * S1[LD + L.tid];
+          const float wv = S0[L.tid] + tau * S1[LD + L.tid];
           float wb = 0.f;
           for (int kq = 0; kq < D; kq++) wb += a.M[kq * D + L.tid] * XB[kq];
           s_wb[L.tid] = wb;
-          ZB[L.tid] += wb;
+          float* st = stage + int64_t(k - k0) * 2 * D;
+          st[L.tid] = XB[L.tid];
+          st[D + L.tid] = wv;
         }
         __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PT; q++) {
-          const int e = L.tid + q * kLtThreads;
-          if (e < D * D) dM[q] += XB[e / D] * s_w[e % D];
-        }
+        if (L.tid < D) ZB[L.tid] += s_wb[L.tid];
         // (B2) primal step transposed
         {
           f4 acc[kLtNT];
-          gemm_nodes<D>(af, XB, lob, NT, acc);  // (A XB)_j
+          gemm_nodes<D>(af, XB, L, R, acc);  // (A XB)_j
 #pragma unroll
           for (int c = 0; c < kLtNT; c++) {
             if (c >= NT) continue;
@@ -632,7 +672,7 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
         // (C2) dual step transposed; Zpre into the XB array
         {
           f4 acc[kLtNT];
-          gemm_nodes<D>(atf, PB, lob, NT, acc);  // (A^T vbar)_j
+          gemm_nodes<D>(atf, PB, L, R, acc);  // (A^T vbar)_j
 #pragma unroll
           for (int c = 0; c < kLtNT; c++) {
             if (c >= NT) continue;
@@ -660,6 +700,40 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
         XB = ZB;
         ZB = tmp;
       }
+      // dM += sum over the segment's steps of XB_0 w^T: one matrix-core outer
+      // product over the staged rows (S0, S1 are free until the next segment)
+      __syncthreads();
+      for (int r0 = 0; r0 < k1 - k0; r0 += R) {
+        const int nr = min(R, k1 - k0 - r0);
+        for (int e = L.tid; e < R * LD; e += kLtThreads) {
+          const int j = e / LD, i = e - j * LD;
+          const bool ok = j < nr && i < D;
+          const float* st = stage + int64_t(r0 + j) * 2 * D;
+          S0[e] = ok ? st[i] : 0.f;
+          S1[e] = ok ? st[D + i] : 0.f;
+        }
+        __syncthreads();
+        int rb = 16 * L.wave + 4 * L.lk;
+        asm volatile("" : "+v"(rb));
+        float* pm = part + DD + int64_t(rb) * D + L.lr;
+        f4 dMf[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+          for (int r = 0; r < 4; r++) {
+            const int row = rb + r, col = 16 * ct + L.lr;
+            dMf[ct][r] = (L.has && row < D && col < D) ? pm[r * D + 16 * ct] : 0.f;
+          }
+        gemm_outer<D>(L, S0, S1, 1.f, 0, nr - 1, dMf);
+#pragma unroll
+        for (int ct = 0; ct < CT; ct++)
+#pragma unroll
+          for (int r = 0; r < 4; r++) {
+            const int row = rb + r, col = 16 * ct + L.lr;
+            if (L.has && row < D && col < D) pm[r * D + 16 * ct] = dMf[ct][r];
+          }
+        __syncthreads();
+      }
     }
     // d phi / d x: every x_j^0 = x + noise (j < N), x_N = x, z^0 = x^0
     if (L.tid < D) {
@@ -669,9 +743,7 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
     }
     __syncthreads();
   }
-  // ---- per-workgroup partial parameter gradients ----------------------------------------
-  const int64_t DD = int64_t(D) * D;
-  float* part = b.part + int64_t(blockIdx.x) * (3 * DD + 1);
+  // ---- per-workgroup partial parameter gradients (dM, dQ are already there) ----------------
 #pragma unroll
   for (int ct = 0; ct < CT; ct++)
 #pragma unroll
@@ -679,14 +751,6 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
       const int row = 16 * L.wave + 4 * L.lk + r, col = 16 * ct + L.lr;
       if (L.has && row < D && col < D) part[row * D + col] = dA[ct][r];
     }
-#pragma unroll
-  for (int q = 0; q < PT; q++) {
-    const int e = L.tid + q * kLtThreads;
-    if (e < D * D) {
-      part[DD + e] = dM[q];
-      part[2 * DD + e] = dQ[q];
-    }
-  }
   deps = wg_sum(deps, s_red);
   if (L.tid == 0) part[3 * DD] = deps;
 }
@@ -966,7 +1030,7 @@ int lt_value_grad(LtState* st, const hjpd_desc& d, int64_t n, const void* x, con
   KernelPtr kb = backward_kernel(d.d);
   const size_t lds_b = lt_lds_backward(d.d, d.N_max);
   const int grid_b = lt_grid(st, kb, lds_b);
-  rc = grow((void**)&st->seg, &st->seg_bytes, sizeof(float) * size_t(grid_b) * (size_t(E) * 2 * CK + 3 * CK));
+  rc = grow((void**)&st->seg, &st->seg_bytes, sizeof(float) * size_t(grid_b) * lt_seg_floats(d.d, d.N_max, E));
   if (rc) return rc;
   rc = grow((void**)&st->part, &st->part_bytes, sizeof(float) * size_t(grid_b) * (3 * dd + 1));
   if (rc) return rc;
