@@ -55,7 +55,7 @@ constexpr int kLtPart = (kLtMaxD * kLtMaxD + kLtThreads - 1) / kLtThreads;  // r
 
 // LDS rows per array: nodes 0 .. 16*NT + 1 (NT column tiles of 16 nodes), so
 // every GEMM column read and every j+1 read stays inside the array.
-__host__ __device__ inline int lt_rows(int N_max) { return 16 * ((N_max + 15) / 16) + 2; }
+__host__ __device__ constexpr int lt_rows(int N_max) { return 16 * ((N_max + 15) / 16) + 2; }
 inline size_t lt_lds_forward(int d, int N_max) { return size_t(3) * lt_rows(N_max) * (d + 1) * sizeof(float); }
 inline size_t lt_lds_backward(int d, int N_max) { return size_t(5) * lt_rows(N_max) * (d + 1) * sizeof(float); }
 // Per-workgroup reverse-mode buffer (floats): E recomputed steps of (x^k, p^{k+1}),
@@ -304,18 +304,36 @@ __device__ void lt_save(const float* sX, const float* sP, const float* sZ, int N
 }
 
 // Load up to three consecutive snapshot arrays into LDS (zero past N and in the
-// padding column); null targets are skipped.
+// padding column); null targets are skipped.  The loads of one array are
+// issued together before their LDS stores (one memory latency per array and
+// call, not one per element).
 template <int D>
 __device__ void lt_load(float* s0, float* s1, float* s2, int Np, int N_max, int R, const float* src) {
   constexpr int LD = D + 1;
+  constexpr int NL = (lt_rows(kLtMaxN) * LD + kLtThreads - 1) / kLtThreads;
   const int64_t CK = int64_t(N_max + 1) * D;
-  for (int e = threadIdx.x; e < R * LD; e += kLtThreads) {
-    const int j = e / LD, i = e - j * LD;
-    const bool ok = j <= Np && i < D;
-    const int s = j * D + i;
-    s0[e] = ok ? src[s] : 0.f;
-    if (s1) s1[e] = ok ? src[CK + s] : 0.f;
-    if (s2) s2[e] = ok ? src[2 * CK + s] : 0.f;
+  float* dst[3] = {s0, s1, s2};
+  // opaque thread index: the per-element row/column divisions below are
+  // recomputed per call instead of being hoisted and held for the kernel
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    if (!dst[q]) continue;
+    const float* sq = src + q * CK;
+    float v[NL];
+#pragma unroll
+    for (int u = 0; u < NL; u++) {
+      const int e = tid + u * kLtThreads;
+      const int j = e / LD, i = e - j * LD;
+      const bool ok = e < R * LD && j <= Np && i < D;
+      v[u] = ok ? sq[j * D + i] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < NL; u++) {
+      const int e = tid + u * kLtThreads;
+      if (e < R * LD) dst[q][e] = v[u];
+    }
   }
   __syncthreads();
 }
@@ -604,8 +622,7 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
       // reverse sweep through the segment
       for (int k = k1 - 1; k >= k0; k--) {
         const float* so = segx + int64_t(k - k0) * 2 * CK;
-        lt_load<D>(S0, nullptr, nullptr, Np, a.N_max, R, so);       // x^k
-        lt_load<D>(S1, nullptr, nullptr, Np, a.N_max, R, so + CK);  // p^{k+1}
+        lt_load<D>(S0, S1, nullptr, Np, a.N_max, R, so);  // x^k, p^{k+1}
         int lo = (L.lr + 1) * LD;
         asm volatile("" : "+v"(lo));
         const int lob = lo + L.lk;
