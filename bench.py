@@ -128,6 +128,47 @@ def bench_lintanh(torch, dev, steps):
             "value_grad_ms": vg_ms, "value_grad_points_per_s": w.n / (vg_ms * 1e-3), "ckpt_every": 50}
 
 
+def bench_configs(torch, dev, subset):
+    """Batched (persistent, default tiles, hipGraph) against plain (one point
+    per lane) on the other workloads: the eikonal set in full (FP64), the
+    quadrotor and pursuit-evasion sets on their first `subset` points (FP32,
+    20,000-iteration cap; the plain kernel streams each point's state through
+    HBM every iteration, so a full-size plain run would take minutes)."""
+    import workloads as W
+    from paper_1803_01215_amd.solver import Solver
+
+    out = {}
+    for name, td, m in (("eikonal2d", torch.float64, None), ("quadrotor12", torch.float32, subset),
+                        ("pursuit12", torch.float32, subset)):
+        w = W.get(name)
+        if m is not None and m < w.n:
+            w = w.subset(np.arange(m))
+        inp = (torch.tensor(w.x, dtype=td, device=dev), torch.tensor(w.t, dtype=td, device=dev),
+               torch.tensor(w.N, dtype=torch.int32, device=dev), torch.tensor(w.hp, dtype=td, device=dev),
+               torch.tensor(w.gp, dtype=td, device=dev))
+        rec = {"points": w.n, "dtype": "f64" if td == torch.float64 else "f32", "max_iter": w.max_iter}
+        for label, kw in (("batched", dict(graph=True)), ("plain", dict(plain=True))):
+            s = Solver(d=w.d, d_y=w.d_y, H=w.H, g=w.g, N_max=w.N_max, sigma=w.sigma, tau=w.tau, theta=w.theta,
+                       tol=w.tol, max_iter=w.max_iter, seed=w.init_seed, dtype=td, **kw)
+            o = s.alloc(w.n)
+            s.solve(*inp, out=o)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s.solve(*inp, out=o)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            conv = int((o.status == 0).sum())
+            rec[label] = {"ms": ms, "converged": conv, "solves_per_s": conv / (ms * 1e-3)}
+            s.close()
+        rec["speedup"] = rec["batched"]["solves_per_s"] / max(rec["plain"]["solves_per_s"], 1e-30)
+        out[name] = rec
+        print("[configs] %s: batched %.1f ms, plain %.1f ms" % (name, rec["batched"]["ms"], rec["plain"]["ms"]),
+              file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +181,9 @@ def main():
     ap.add_argument("--max-iter", type=int, default=5000,
                     help="iteration cap of the headline run (points above it count as not converged)")
     ap.add_argument("--no-c5", action="store_true", help="skip the linear-tanh (d=100) forward/reverse timing")
+    ap.add_argument("--configs", type=int, default=0, metavar="M",
+                    help="also time batched vs plain on the eikonal, quadrotor and pursuit-evasion workloads "
+                         "(the last two on their first M points)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -256,6 +300,8 @@ def main():
     if not args.no_c5:
         c5_rec = bench_lintanh(torch, dev, args.steps)
 
+    cfg_rec = bench_configs(torch, dev, args.configs) if args.configs > 0 else None
+
     # ---- CPU oracle baseline on a bounded sample ------------------------------------------
     cpu_rec = None
     if not args.no_cpu:
@@ -290,6 +336,7 @@ def main():
         "fp64": fp64_rec,
         "long_cap": long_rec,
         "lintanh100": c5_rec,
+        "configs": cfg_rec,
     }
     print(json.dumps(rec))
 
