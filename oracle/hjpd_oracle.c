@@ -23,7 +23,18 @@
  *   z     <- x_new + theta (x_new - x_old)
  *
  * (section 5.3 for "prox on the nonsmooth part, one gradient step on the
- * smooth part").  The two-player game path follows section 4.2, eq.
+ * smooth part").
+ *
+ * Hopf formulation (section 4.1, eq. dischopf; section 5.1, Algorithm 2 and
+ * Appendix A.1.2), control path, convex g:
+ *
+ *   phi(x,t) ~ max_{p_1..p_N} min_{x_1..x_{N-1}}  -g*(p_1) + <p_N, x>
+ *              + sum_{j=1..N-1} <p_j - p_{j+1}, x_j> - delta sum_{j=1..N} H(x_j,p_j,s_j)
+ *
+ * with x_N = x and no node 0; the dual step at j = 1 is the joint prox of
+ * g* + delta H(x_1,.), at j >= 2 the prox of delta H(x_j,.), both around
+ * p_j + sigma (z_j - z_{j-1}) with z_0 = 0 (the Hopf difference matrix);
+ * the x-steps are those of the Lax path.  The two-player game path follows section 4.2, eq.
  * discgenlaxhopfdg, and Algorithm 3 / Appendix A.2.1: blocks p, q, x, y in
  * that order, with the evader's costate entering H as -q.
  *
@@ -572,6 +583,52 @@ int or_prox_g(const or_problem *pb, const double *v, double tau, double *out)
     return 0;
 }
 
+/* Convex conjugate g*(p) = sup_x <x,p> - g(x) (section 4.1, derivation of
+ * eq. dischopf).  NORM: g = |x| - r gives g* = r on the unit ball, +inf
+ * outside.  QUAD_SHIFT: g = |x - a|^2/2 - c0 gives g* = |p|^2/2 + <a,p> + c0.
+ * Other initial costs: NAN (the Hopf path is not offered for them). */
+double or_gstar(const or_problem *pb, const double *p)
+{
+    int d = pb->d;
+    switch (pb->g) {
+    case OR_G_NORM: return norm2(p, d) <= 1.0 + 1e-12 ? pb->gp[0] : INFINITY;
+    case OR_G_QUAD_SHIFT: return 0.5 * dot(p, p, d) + dot(pb->gp + 1, p, d) + pb->gp[0];
+    }
+    return NAN;
+}
+
+/* Hopf dual step at j = 1 (Algorithm 2; Appendix A.1.2):
+ *   argmin_p  g*(p) + delta H(x_1, p, s_1) + |p - v|^2 / (2 sigma)
+ * for the eikonal family H = c(x)|p| (c(x_1) is a constant here):
+ *  - QUAD_SHIFT: sigma g*(p) + |p - v|^2/2 = (1+sigma)/2 |p - w|^2 + const with
+ *    w = (v - sigma a)/(1 + sigma), so p = shrink_2(w, sigma delta c/(1+sigma));
+ *  - NORM: every term is a function of |p| along the direction of v, so
+ *    p = v/|v| * clip(|v| - sigma delta c, 0, 1) (shrink, then the ball).
+ * Returns -1 when the pair (H, g) has no Hopf step here. */
+int or_hopf_prox1(const or_problem *pb, const double *x1, const double *v, double sigma, double delta,
+                  double *out)
+{
+    int d = pb->d;
+    if (pb->H != OR_H_CNORM) return -1;
+    double c = cnorm_c(pb->hp, x1);
+    if (pb->g == OR_G_QUAD_SHIFT) {
+        double *w = malloc(sizeof(double) * d);
+        for (int i = 0; i < d; i++) w[i] = (v[i] - sigma * pb->gp[1 + i]) / (1.0 + sigma);
+        or_shrink2(w, sigma * delta * c / (1.0 + sigma), d, out);
+        free(w);
+        return 0;
+    }
+    if (pb->g == OR_G_NORM) {
+        double nv = norm2(v, d);
+        double r = nv - sigma * delta * c;
+        if (r < 0.0) r = 0.0;
+        if (r > 1.0) r = 1.0;
+        for (int i = 0; i < d; i++) out[i] = nv > 0.0 ? v[i] / nv * r : 0.0;
+        return 0;
+    }
+    return -1;
+}
+
 /* Game, node 0: pursuer block x0 <- argmin tau g(x, y0) + |x - v|^2/2 for
  * g = |r_P - r_E| - r: the position moves toward r_E by shrink_2, the
  * velocity is untouched (g does not depend on it). */
@@ -690,6 +747,79 @@ static void solve_control_point(const or_problem *pb, const or_opts *o, long pt,
     if (xtraj) memcpy(xtraj, x, sz * sizeof(double));
     if (ptraj) memcpy(ptraj, p, sz * sizeof(double));
     free(x); free(p); free(z); free(xn); free(pn); free(v); free(gr); free(chol);
+}
+
+/* ------------------------------------------------------------------ */
+/* One query point: Hopf formulation (Algorithm 2, Appendix A.1.2).   */
+/* Arrays keep nodes 0..N so outputs line up with the Lax path; node  */
+/* 0 does not take part and stays zero.                               */
+/* ------------------------------------------------------------------ */
+
+static void solve_hopf_point(const or_problem *pb, const or_opts *o, long pt, const double *xt,
+                             double t, int N, double *phi, int *iters, int *status,
+                             double *xtraj, double *ptraj)
+{
+    int d = pb->d;
+    double delta = t / N;
+    size_t sz = (size_t)(N + 1) * d;
+    double *x = calloc(sz, sizeof(double)), *p = calloc(sz, sizeof(double)), *z = calloc(sz, sizeof(double));
+    double *xn = calloc(sz, sizeof(double)), *pn = calloc(sz, sizeof(double));
+    double *v = calloc(d, sizeof(double)), *gr = calloc(d, sizeof(double));
+
+    /* random start: x_j (1 <= j < N) near x, x_N = x, p_j (1 <= j <= N) near 0, z = x */
+    for (int j = 1; j < N; j++)
+        for (int i = 0; i < d; i++) x[j * d + i] = xt[i] + or_init_noise(o->seed, pt, OR_ARR_X, j, i);
+    for (int i = 0; i < d; i++) x[N * d + i] = xt[i];
+    for (int j = 1; j <= N; j++)
+        for (int i = 0; i < d; i++) p[j * d + i] = or_init_noise(o->seed, pt, OR_ARR_P, j, i);
+    memcpy(z, x, sz * sizeof(double));
+
+    int k = 0, st = OR_PT_MAXITER;
+    for (;;) {
+        /* p-update, (D^T z)_1 = z_1, (D^T z)_j = z_j - z_{j-1} */
+        for (int i = 0; i < d; i++) v[i] = p[d + i] + o->sigma * z[d + i];
+        or_hopf_prox1(pb, &x[d], v, o->sigma, delta, &pn[d]);
+        for (int j = 2; j <= N; j++) {
+            for (int i = 0; i < d; i++) v[i] = p[j * d + i] + o->sigma * (z[j * d + i] - z[(j - 1) * d + i]);
+            or_prox_p(pb, &x[j * d], v, o->sigma * delta, j * delta, &pn[j * d]);
+        }
+        /* x-update, j = 1..N-1: (D p)_j = p_j - p_{j+1}, one gradient step on -delta H */
+        for (int j = 1; j < N; j++) {
+            or_grad_x_H(pb, &x[j * d], &pn[j * d], j * delta, gr);
+            for (int i = 0; i < d; i++)
+                xn[j * d + i] = x[j * d + i] - o->tau * (pn[j * d + i] - pn[(j + 1) * d + i])
+                                + o->tau * delta * gr[i];
+        }
+        for (int i = 0; i < d; i++) xn[N * d + i] = x[N * d + i];
+
+        double rx = 0.0, rp = 0.0;
+        for (size_t a = d; a < sz; a++) {
+            rx += (xn[a] - x[a]) * (xn[a] - x[a]);
+            rp += (pn[a] - p[a]) * (pn[a] - p[a]);
+        }
+        for (size_t a = d; a < sz; a++) z[a] = xn[a] + o->theta * (xn[a] - x[a]);
+        memcpy(x, xn, sz * sizeof(double));
+        memcpy(p, pn, sz * sizeof(double));
+        k++;
+        if (!isfinite(rx + rp)) { st = OR_PT_NONFINITE; break; }
+        int small = (rx < o->tol) && (rp < o->tol);
+        if (!o->fixed_iters && small) { st = OR_PT_CONVERGED; break; }
+        if (k >= o->max_iter) { st = small ? OR_PT_CONVERGED : OR_PT_MAXITER; break; }
+    }
+
+    /* value (Algorithm 2 fval):
+       -g*(p_1) + <p_N, x> + sum_{j<N} <p_j - p_{j+1}, x_j> - delta sum_j H(x_j, p_j) */
+    double val = -or_gstar(pb, &p[d]) + dot(&p[N * d], xt, d);
+    for (int j = 1; j < N; j++)
+        for (int i = 0; i < d; i++) val += (p[j * d + i] - p[(j + 1) * d + i]) * x[j * d + i];
+    for (int j = 1; j <= N; j++) val -= delta * or_H(pb, &x[j * d], &p[j * d], j * delta);
+    if (!isfinite(val) || !all_finite(x, (int)sz) || !all_finite(p, (int)sz)) st = OR_PT_NONFINITE;
+    *phi = val;
+    *iters = k;
+    *status = st;
+    if (xtraj) memcpy(xtraj, x, sz * sizeof(double));
+    if (ptraj) memcpy(ptraj, p, sz * sizeof(double));
+    free(x); free(p); free(z); free(xn); free(pn); free(v); free(gr);
 }
 
 /* ------------------------------------------------------------------ */
@@ -821,14 +951,15 @@ static void solve_game_point(const or_problem *pb, const or_opts *o, long pt, co
  * is solved sequentially.
  * Returns 0, or -1 for an unsupported problem.
  */
-int or_solve(const or_problem *pb, long n, const double *x, const double *t, const int *N,
-             double sigma, double tau, double theta, double tol, int max_iter, int fixed_iters,
-             uint64_t seed, int N_max, const int64_t *ids, double *phi, int *iters, int *status,
-             double *x_traj, double *p_traj, int n_threads)
+static int solve_batch(const or_problem *pb, long n, const double *x, const double *t, const int *N,
+                       double sigma, double tau, double theta, double tol, int max_iter, int fixed_iters,
+                       uint64_t seed, int N_max, const int64_t *ids, double *phi, int *iters, int *status,
+                       double *x_traj, double *p_traj, int n_threads, int hopf)
 {
     int game = pb->d_y > 0;
     if (game && !(pb->H == OR_H_PURSUIT_EVASION && pb->g == OR_G_PAIR_DIST)) return -1;
     if (!game && (pb->H == OR_H_PURSUIT_EVASION || pb->g == OR_G_PAIR_DIST)) return -1;
+    if (hopf && (game || pb->H != OR_H_CNORM || !(pb->g == OR_G_NORM || pb->g == OR_G_QUAD_SHIFT))) return -1;
     or_opts o = { sigma, tau, theta, tol, max_iter, fixed_iters, seed, N_max };
     int d = pb->d;
 #ifdef _OPENMP
@@ -854,8 +985,30 @@ int or_solve(const or_problem *pb, long n, const double *x, const double *t, con
         long id = ids ? (long)ids[i] : i;
         if (game)
             solve_game_point(pb, &o, id, &x[i * d], ti, Ni, &phi[i], &iters[i], &status[i], xt_out, pt_out);
+        else if (hopf)
+            solve_hopf_point(pb, &o, id, &x[i * d], ti, Ni, &phi[i], &iters[i], &status[i], xt_out, pt_out);
         else
             solve_control_point(pb, &o, id, &x[i * d], ti, Ni, &phi[i], &iters[i], &status[i], xt_out, pt_out);
     }
     return 0;
+}
+
+/* Lax formulation (Algorithm 1; Algorithm 3 for games). */
+int or_solve(const or_problem *pb, long n, const double *x, const double *t, const int *N,
+             double sigma, double tau, double theta, double tol, int max_iter, int fixed_iters,
+             uint64_t seed, int N_max, const int64_t *ids, double *phi, int *iters, int *status,
+             double *x_traj, double *p_traj, int n_threads)
+{
+    return solve_batch(pb, n, x, t, N, sigma, tau, theta, tol, max_iter, fixed_iters, seed, N_max, ids, phi, iters,
+                       status, x_traj, p_traj, n_threads, 0);
+}
+
+/* Hopf formulation (Algorithm 2), eikonal family with NORM or QUAD_SHIFT g. */
+int or_solve_hopf(const or_problem *pb, long n, const double *x, const double *t, const int *N,
+                  double sigma, double tau, double theta, double tol, int max_iter, int fixed_iters,
+                  uint64_t seed, int N_max, const int64_t *ids, double *phi, int *iters, int *status,
+                  double *x_traj, double *p_traj, int n_threads)
+{
+    return solve_batch(pb, n, x, t, N, sigma, tau, theta, tol, max_iter, fixed_iters, seed, N_max, ids, phi, iters,
+                       status, x_traj, p_traj, n_threads, 1);
 }

@@ -55,6 +55,12 @@ def lib():
                                   ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
                                   D, I, I, D, D, ctypes.c_int]
         _lib.or_solve.restype = ctypes.c_int
+        _lib.or_solve_hopf.argtypes = _lib.or_solve.argtypes
+        _lib.or_solve_hopf.restype = ctypes.c_int
+        _lib.or_gstar.argtypes = [P, D]
+        _lib.or_gstar.restype = ctypes.c_double
+        _lib.or_hopf_prox1.argtypes = [P, D, D, ctypes.c_double, ctypes.c_double, D]
+        _lib.or_hopf_prox1.restype = ctypes.c_int
         _lib.or_splitmix64_mix.argtypes = [ctypes.c_uint64]
         _lib.or_splitmix64_mix.restype = ctypes.c_uint64
         _lib.or_splitmix64_at.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
@@ -131,6 +137,16 @@ class Problem:
         assert lib().or_prox_g(self.c, _dp(v), tau, _dp(out)) == 0
         return out
 
+    def gstar(self, p):
+        p = np.ascontiguousarray(p, np.float64)
+        return lib().or_gstar(self.c, _dp(p))
+
+    def hopf_prox1(self, x1, v, sigma, delta):
+        x1 = np.ascontiguousarray(x1, np.float64); v = np.ascontiguousarray(v, np.float64)
+        out = np.zeros(self.d)
+        assert lib().or_hopf_prox1(self.c, _dp(x1), _dp(v), sigma, delta, _dp(out)) == 0
+        return out
+
     def game_H(self, x, y, p, q):
         a = [np.ascontiguousarray(z, np.float64) for z in (x, y, p, q)]
         return lib().or_game_H(self.c, *[_dp(z) for z in a])
@@ -171,13 +187,15 @@ class Result:
 
 
 def solve(pb: Problem, x, t, N, *, sigma, tau, theta=1.0, tol=1e-8, max_iter=5000, fixed_iters=False,
-          seed=0, N_max=None, ids=None, traj=False, threads=0) -> Result:
+          seed=0, N_max=None, ids=None, traj=False, threads=0, hopf=False) -> Result:
     """Run the oracle over a batch of points.
 
     x: [n, d]; t: [n]; N: [n] (intervals per point).  ids: each point's
     index in the full workload (selects its random start), default 0..n-1.
     In fixed-iteration mode exactly max_iter iterations are run (unless a
-    non-finite value stops the point first).
+    non-finite value stops the point first).  hopf=True runs the Hopf
+    formulation (Algorithm 2; eikonal family with NORM or QUAD_SHIFT g); its
+    trajectories have node 0 = 0.
     """
     x = np.ascontiguousarray(x, np.float64).reshape(-1, pb.d)
     n = x.shape[0]
@@ -193,7 +211,8 @@ def solve(pb: Problem, x, t, N, *, sigma, tau, theta=1.0, tol=1e-8, max_iter=500
         ids = np.ascontiguousarray(ids, np.int64)
         idp = ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     I = ctypes.POINTER(ctypes.c_int)
-    rc = lib().or_solve(pb.c, n, _dp(x), _dp(t), N.ctypes.data_as(I), sigma, tau, theta, tol, int(max_iter),
+    fn = lib().or_solve_hopf if hopf else lib().or_solve
+    rc = fn(pb.c, n, _dp(x), _dp(t), N.ctypes.data_as(I), sigma, tau, theta, tol, int(max_iter),
                         int(bool(fixed_iters)), int(seed) & (2**64 - 1), int(N_max), idp, _dp(phi),
                         iters.ctypes.data_as(I), status.ctypes.data_as(I),
                         _dp(xt) if traj else None, _dp(pt) if traj else None, int(threads))

@@ -618,3 +618,115 @@ def test_statuses(oracle_mod):
     pq = oracle_mod.Problem(q.H, q.g, q.d, q.d_y, q.hp, q.gp)
     r = oracle_mod.solve(pq, q.x, q.t, q.N, sigma=0.05, tau=5.0, tol=1e-6, max_iter=20000, seed=0, N_max=60)
     assert np.all(r.status == 2)
+
+
+# --------------------------------------------------------------------------
+# Hopf formulation (section 4.1 eq. dischopf; Algorithm 2; Appendix A.1.2)
+# --------------------------------------------------------------------------
+
+def test_gstar_is_the_convex_conjugate(oracle_mod):
+    """g*(p) = sup_x <x,p> - g(x), evaluated by numerical maximisation."""
+    rng = _rng(40)
+    d = 3
+    a = np.array([0.3, -0.2, 0.5])
+    pq = oracle_mod.Problem(W.H_CNORM, W.G_QUAD_SHIFT, d, 0, [0.5], np.concatenate([[0.7], a]))
+    pn = oracle_mod.Problem(W.H_CNORM, W.G_NORM, d, 0, [0.5], [0.8])
+    for _ in range(4):
+        p = rng.standard_normal(d)
+        r = minimize(lambda x: -(x @ p - pq.g_val(x)), np.zeros(d), method="BFGS", options={"gtol": 1e-12})
+        assert abs(pq.gstar(p) - (-r.fun)) < 1e-9
+        q = p / np.linalg.norm(p) * rng.uniform(0.1, 0.95)  # inside the unit ball: sup attained at x = 0
+        xs = rng.standard_normal((2000, d)) * rng.uniform(0, 5, (2000, 1))
+        best = np.max(xs @ q - np.array([pn.g_val(x) for x in xs]))
+        assert best <= pn.gstar(q) + 1e-12 and pn.gstar(q) - best < 0.35
+        assert abs(pn.gstar(q) - (-pn.g_val(np.zeros(d)))) < 1e-12  # <x,q> - |x| <= 0, equality at x = 0
+        assert np.isinf(pn.gstar(p / np.linalg.norm(p) * 1.5))
+
+
+@pytest.mark.parametrize("g", ["shift", "norm"])
+def test_hopf_first_dual_step_is_argmin(oracle_mod, g):
+    """p_1 = argmin_p g*(p) + delta H(x_1, p) + |p - v|^2/(2 sigma) (Appendix
+    A.1.2, j = 1), minimised directly (NORM: constrained to the unit ball)."""
+    rng = _rng(41)
+    d, alpha = 3, 0.5
+    a = np.array([0.3, -0.2, 0.5])
+    pb = (oracle_mod.Problem(W.H_CNORM, W.G_QUAD_SHIFT, d, 0, [alpha], np.concatenate([[0.7], a])) if g == "shift"
+          else oracle_mod.Problem(W.H_CNORM, W.G_NORM, d, 0, [alpha], [0.8]))
+    for k in range(6):
+        x1 = rng.standard_normal(d)
+        v = rng.standard_normal(d) * (0.3 if k % 2 else 2.0)
+        sigma, delta = rng.uniform(0.5, 4.0), rng.uniform(0.02, 0.2)
+        out = pb.hopf_prox1(x1, v, sigma, delta)
+        c = 1 + alpha * np.sin(x1[0]) * np.cos(x1[1])
+        if g == "shift":
+            f = lambda p: 0.5 * p @ p + a @ p + 0.7 + delta * c * np.linalg.norm(p) + np.sum((p - v) ** 2) / (2 * sigma)
+            r = minimize(f, v * 0.5 + 0.01, method="Nelder-Mead", options={"xatol": 1e-12, "fatol": 1e-15, "maxiter": 40000})
+            ref = r.x
+        else:
+            f = lambda p: 0.8 + delta * c * np.linalg.norm(p) + np.sum((p - v) ** 2) / (2 * sigma)
+            cons = [{"type": "ineq", "fun": lambda p: 1.0 - p @ p}]
+            r = minimize(f, np.zeros(d) + 0.01, method="SLSQP", constraints=cons, options={"ftol": 1e-15, "maxiter": 500})
+            ref = r.x
+        assert f(out) <= f(ref) + 1e-10
+        assert np.max(np.abs(out - ref)) < 1e-4
+
+
+def test_hopf_eikonal_matches_closed_form(oracle_mod):
+    """H = ||p||, g = ||x|| - 1: with a state-independent H the discrete Hopf
+    problem forces p_1 = .. = p_N and is the classical Hopf formula
+    max_{|p|<=1} <x,p> - t|p| - 1 = max(|x| - t, 0) - 1 (section 2.1)."""
+    w = W.eikonal2d(64)
+    pb = oracle_mod.Problem(w.H, w.g, w.d, w.d_y, w.hp, w.gp)
+    r = oracle_mod.solve(pb, w.x, w.t, w.N, sigma=w.sigma, tau=w.tau, tol=1e-26, max_iter=60000,
+                         seed=w.init_seed, traj=True, hopf=True)
+    nx = np.linalg.norm(w.x, axis=1)
+    exact = np.maximum(nx - w.t, 0) - 1
+    assert np.max(np.abs(r.phi - exact)) < 1e-9
+    far = nx > w.t + 0.05
+    # every multiplier equals the unit vector x/|x|; x_N = x; node 0 is unused
+    assert np.max(np.abs(r.p_traj[far, 1:, :] - (w.x / nx[:, None])[far][:, None, :])) < 1e-6
+    assert np.array_equal(r.x_traj[:, -1, :], w.x) and np.all(r.x_traj[:, 0, :] == 0)
+
+
+def test_hopf_constant_speed_matches_closed_form(oracle_mod):
+    """alpha = 0, g = ||x-a||^2/2 - 1: Hopf formula max_p <x-a,p> - |p|^2/2 - t|p| - 1
+    = max(||x - a|| - t, 0)^2/2 - 1."""
+    w = W.cnorm10(48, alpha=0.0)
+    pb = oracle_mod.Problem(w.H, w.g, w.d, w.d_y, w.hp, w.gp)
+    r = oracle_mod.solve(pb, w.x, w.t, w.N, sigma=w.sigma, tau=w.tau, tol=1e-26, max_iter=40000,
+                         seed=w.init_seed, hopf=True)
+    a = w.gp[1:]
+    exact = 0.5 * np.maximum(np.linalg.norm(w.x - a, axis=1) - w.t, 0) ** 2 - 1
+    assert np.max(np.abs(r.phi - exact)) < 1e-9
+
+
+def test_hopf_and_lax_values_agree_state_dependent(oracle_mod):
+    """alpha != 0: the discrete Hopf saddle is the Lax saddle with x_0
+    minimised out analytically (the derivation of eq. dischopf), so both
+    formulations reach the same value, by different iterations."""
+    w = W.cnorm10(24)
+    pb = oracle_mod.Problem(w.H, w.g, w.d, w.d_y, w.hp, w.gp)
+    kw = dict(sigma=w.sigma, tau=w.tau, tol=1e-24, max_iter=60000, seed=w.init_seed)
+    rl = oracle_mod.solve(pb, w.x, w.t, w.N, **kw)
+    rh = oracle_mod.solve(pb, w.x, w.t, w.N, hopf=True, **kw)
+    ok = (rl.status == 0) & (rh.status == 0)
+    assert ok.sum() >= 20
+    assert np.max(np.abs(rl.phi - rh.phi)[ok]) < 1e-8
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_hopf_state_dependent_eikonal_matches_direct_shooting(oracle_mod, N):
+    rng = _rng(44 + N)
+    alpha, d = 0.5, 2
+    a = np.array([0.4, -0.3])
+    pb = oracle_mod.Problem(W.H_CNORM, W.G_QUAD_SHIFT, d, 0, [alpha], np.concatenate([[1.0], a]))
+    c = lambda z: 1 + alpha * np.sin(z[0]) * np.cos(z[1])
+    g = lambda z: 0.5 * np.sum((z - a) ** 2) - 1.0
+    step = lambda s, u: (c(s) * u, 0.0)
+    for _ in range(3):
+        x = rng.uniform(-1.5, 1.5, d)
+        t = rng.uniform(0.2, 0.8)
+        r = oracle_mod.solve(pb, x[None], t, N, sigma=1.0, tau=0.25, tol=1e-26, max_iter=40000, seed=1, hopf=True)
+        assert r.status[0] == 0
+        brute = _shoot_min(step, g, x, N, t, d, rng, bounds_unit_ball=True)
+        assert abs(r.phi[0] - brute) < 1e-6, (r.phi[0], brute)
