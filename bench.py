@@ -276,6 +276,15 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # ---- Hopf formulation (Algorithm 2) on the same workload, same tile and cap ---------
+    hopf = make(td, graph=True, lanes_per_point=16, nodes_per_lane=2, hopf=True)
+    outh = hopf.alloc(n)
+    ms_hopf = timed_steps(hopf, inp, outh, max(1, args.steps // 2), 1)
+    conv_hopf = int((outh.status.cpu().numpy() == 0).sum())
+    hopf_rec = {"value": conv_hopf / (ms_hopf * 1e-3), "ms_per_step": ms_hopf, "converged": conv_hopf,
+                "iters_p50": float(np.median(outh.iters.cpu().numpy()))}
+    hopf.close()
+
     # ---- plain FP32 -------------------------------------------------------------------
     plain = make(td, plain=True)
     outp = plain.alloc(n)
@@ -335,6 +344,7 @@ def main():
         "speedup_vs_plain": value / plain_rec["value"] if plain_rec["value"] > 0 else None,
         "fp64": fp64_rec,
         "long_cap": long_rec,
+        "hopf": hopf_rec,
         "lintanh100": c5_rec,
         "configs": cfg_rec,
     }

@@ -122,9 +122,15 @@ enum {
     HJPD_FIXED_ITERS = 1u << 1, /* run exactly max_iter iterations (no tolerance stop) */
     HJPD_GRAPH = 1u << 2,       /* capture the solve in a hipGraph and replay it on repeat calls */
     HJPD_TIMING = 1u << 3,      /* record HIP events around the main kernels (hjpd_get_timing) */
-    HJPD_NO_ORDER_HINT = 1u << 4 /* queue points of one N in input order; by default points that start
+    HJPD_NO_ORDER_HINT = 1u << 4, /* queue points of one N in input order; by default points that start
                                     far from the minimiser of g are handed out first (order only,
                                     results are unchanged) */
+    HJPD_HOPF = 1u << 5          /* Hopf formulation (section 4.1 eq. dischopf, Algorithm 2) instead of
+                                    Lax (Algorithm 1): nodes 1..N, no x_0; the dual step at j = 1 is the
+                                    joint prox of g* + delta H(x_1,.) (Appendix A.1.2); the value is
+                                    -g*(p_1) + <p_N,x> + sum_{j<N} <p_j - p_{j+1}, x_j> - delta sum H.
+                                    Built for H = CNORM with g = NORM or QUAD_SHIFT (control path);
+                                    other pairs return HJPD_EUNSUPPORTED.  Trajectory node 0 is zero. */
 };
 
 typedef struct {
@@ -139,7 +145,7 @@ typedef struct {
     double tol;      /* tolerance on the squared residuals (> 0) */
     int max_iter;    /* iteration cap (>= 1); with HJPD_FIXED_ITERS the exact count */
     uint64_t seed;   /* random start: counter-based SplitMix64 stream */
-    unsigned flags;  /* HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_GRAPH | HJPD_TIMING | HJPD_NO_ORDER_HINT */
+    unsigned flags;  /* HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_GRAPH | HJPD_TIMING | HJPD_NO_ORDER_HINT | HJPD_HOPF */
     int lanes_per_point; /* persistent tile override: lanes per point (8,16,32,64), 0 = tuned/default */
     int nodes_per_lane;  /* persistent tile override: time nodes per lane (1..4), 0 = tuned/default */
 } hjpd_desc;

@@ -319,7 +319,7 @@ int validate_desc(const hjpd_desc* d) {
   if (d->H < 0 || d->H > 3) return fail(HJPD_EINVAL, "unknown Hamiltonian family");
   if (d->g < 0 || d->g > 3) return fail(HJPD_EINVAL, "unknown initial-cost family");
   if (d->dtype != HJPD_F32 && d->dtype != HJPD_F64) return fail(HJPD_EINVAL, "unknown dtype");
-  if (d->flags & ~unsigned(HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_GRAPH | HJPD_TIMING | HJPD_NO_ORDER_HINT))
+  if (d->flags & ~unsigned(HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_GRAPH | HJPD_TIMING | HJPD_NO_ORDER_HINT | HJPD_HOPF))
     return fail(HJPD_EINVAL, "unknown flag bits");
   if (d->lanes_per_point != 0) {
     const int L = d->lanes_per_point, K = d->nodes_per_lane;
@@ -331,6 +331,8 @@ int validate_desc(const hjpd_desc* d) {
   if (d->d > 1023) return fail(HJPD_EINVAL, "d must be <= 1023");
   // supported pairs
   const bool game = d->d_y > 0;
+  if ((d->flags & HJPD_HOPF) && !(d->H == HJPD_H_CNORM && !game && (d->g == HJPD_G_NORM || d->g == HJPD_G_QUAD_SHIFT)))
+    return fail(HJPD_EUNSUPPORTED, "the Hopf formulation is built for CNORM with NORM or QUAD_SHIFT");
   if (d->H == HJPD_H_PURSUIT_EVASION) {
     if (!(game && d->g == HJPD_G_PAIR_DIST && d->d == 12 && d->d_y == 6))
       return fail(HJPD_EUNSUPPORTED, "pursuit-evasion needs d = 12, d_y = 6, g = PAIR_DIST");
@@ -409,6 +411,7 @@ int enqueue_solve(hjpd_ctx* c, int64_t n, const void* x, const void* t, const in
   a.N_max = D.N_max;
   a.d = D.d;
   a.gkind = D.g;
+  a.hopf = (D.flags & HJPD_HOPF) ? 1 : 0;
   a.seed = D.seed;
   void* args[] = {&a};
   if (timed) HIP_OK(hipEventRecord(c->ev0, s), "hipEventRecord");

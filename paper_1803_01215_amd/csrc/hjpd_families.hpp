@@ -34,6 +34,8 @@ struct CNorm {
   static constexpr bool kGame = false;
   // dual step maps v = 0 to p = 0 exactly (nodes past N stay at p = 0 without a mask)
   static constexpr bool kZeroSafe = true;
+  // Hopf formulation (Algorithm 2) available: closed-form conjugates of both g
+  static constexpr bool kHopf = true;
 
   template <typename T> struct Par {
     T alpha;
@@ -85,6 +87,49 @@ struct CNorm {
     for (int i = 0; i < D; i++) v[i] *= scale;
     C.gc0 = P.alpha * c1 * c2;
     C.gc1 = -P.alpha * s1 * s2;
+  }
+
+  // Hopf formulation, dual step at j = 1 (Algorithm 2): the joint prox
+  //   argmin_p g*(p) + lam/sigma c(x)|p| + |p - v|^2/(2 sigma),  lam = sigma delta.
+  // Shifted quadratic g: g*(p) = |p|^2/2 + <a,p> + c0, so completing the square
+  // gives p = shrink_2((v - sigma a)/(1 + sigma), lam c/(1 + sigma)).
+  // Norm g: g* = r on the unit ball, so p = v/|v| min(max(|v| - lam c, 0), 1).
+  template <typename T>
+  __device__ static void dual_hopf1(const Par<T>& P, const T (&x)[D], T (&v)[D], T lam, T sigma, Cache<T>& C) {
+    T s1, c1, s2, c2;
+    M<T>::sincos(x[0], &s1, &c1);
+    M<T>::sincos(x[1], &s2, &c2);
+    const T c = T(1) + P.alpha * s1 * c2;
+    T mu = lam * c;
+    if (P.gkind != kGNorm) {
+      const T r1 = T(1) / (T(1) + sigma);
+#pragma unroll
+      for (int i = 0; i < D; i++) v[i] = (v[i] - sigma * P.a[i]) * r1;
+      mu *= r1;
+    }
+    T ss = T(0);
+#pragma unroll
+    for (int i = 0; i < D; i++) ss += v[i] * v[i];
+    const bool nz = ss > T(0);
+    const T rs = M<T>::rsqrt(ss);
+    T len = nz ? M<T>::fmax(ss * rs - mu, T(0)) : T(0);  // shrunk length
+    if (P.gkind == kGNorm) len = len < T(1) ? len : T(1);
+    const T scale = nz ? len * rs : T(0);
+    C.pn = len;
+#pragma unroll
+    for (int i = 0; i < D; i++) v[i] *= scale;
+    C.gc0 = P.alpha * c1 * c2;
+    C.gc1 = -P.alpha * s1 * s2;
+  }
+
+  // Convex conjugate of g at p (finite branch: the Hopf iterates keep |p| <= 1 for the norm g).
+  template <typename T>
+  __device__ static T gstar(const Par<T>& P, const T (&p)[D]) {
+    if (P.gkind == kGNorm) return P.r;
+    T s = T(0);
+#pragma unroll
+    for (int i = 0; i < D; i++) s += p[i] * (T(0.5) * p[i] + P.a[i]);
+    return s + P.c0;
   }
 
   // Only the first two coordinates of grad_x H are non-zero.
@@ -169,6 +214,7 @@ struct Quad {
   static constexpr int D = 12;
   static constexpr bool kGame = false;
   static constexpr bool kZeroSafe = false;
+  static constexpr bool kHopf = false;
 
   template <typename T> struct Par {
     T m_inv, gz, clamp;
@@ -347,6 +393,7 @@ struct Pursuit {
   static constexpr int DX = 6, DY = 6;
   static constexpr bool kGame = true;
   static constexpr bool kZeroSafe = false;
+  static constexpr bool kHopf = false;
 
   template <typename T> struct Par {
     T kappa, wP, wE, r;

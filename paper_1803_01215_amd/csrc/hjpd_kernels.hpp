@@ -67,6 +67,7 @@ struct KArgs {
   int cls;
   T sigma, tau, theta, tol;
   int max_iter, fixed, N_max, d, gkind;
+  int hopf;                  // 1: Hopf formulation (Algorithm 2), no node 0
   uint64_t seed;
 };
 
@@ -133,9 +134,10 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
       }
     }
     // node 0 lives in the group's first lane; the other lanes keep x0 = z0 = 0
+    // (and every lane in the Hopf formulation, which has no node 0)
 #pragma unroll
     for (int i = 0; i < D; i++) {
-      x0[i] = (l == 0) ? init_x(xt[i], a.seed, pt, kArrX, 0, i) : T(0);
+      x0[i] = (l == 0 && !a.hopf) ? init_x(xt[i], a.seed, pt, kArrX, 0, i) : T(0);
       z0[i] = x0[i];
     }
 #pragma unroll
@@ -151,7 +153,8 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
   while (__any(active)) {
     // ---- dual step -------------------------------------------------------
     // z_{j-1} of the lane's first node: the previous lane's last node, or
-    // z_0 in the group's first lane (z0 is zero in every other lane).
+    // z_0 in the group's first lane (z0 is zero in every other lane; the
+    // Hopf difference operator has z_0 = 0).
     T zprev[D];
 #pragma unroll
     for (int i = 0; i < D; i++) zprev[i] = group_prev0<L>(z[K - 1][i], l) + z0[i];
@@ -162,7 +165,15 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
       T v[D];
 #pragma unroll
       for (int i = 0; i < D; i++) v[i] = p[kk][i] + sigma * (z[kk][i] - (kk == 0 ? zprev[i] : z[kk - 1][i]));
-      F::dual(P, x[kk], v, sd, C[kk]);
+      if constexpr (F::kHopf) {
+        // Hopf: node 1 (first lane, first slot) takes the joint prox with g*
+        if (kk == 0 && a.hopf && l == 0)
+          F::dual_hopf1(P, x[kk], v, sd, sigma, C[kk]);
+        else
+          F::dual(P, x[kk], v, sd, C[kk]);
+      } else {
+        F::dual(P, x[kk], v, sd, C[kk]);
+      }
       if constexpr (!F::kZeroSafe) {
         // nodes past N keep p = 0
         const int j = 1 + l * K + kk;
@@ -180,7 +191,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
     T pnext[D];
 #pragma unroll
     for (int i = 0; i < D; i++) pnext[i] = group_next0<L>(p[0][i], l);
-    if (l == 0) {
+    if (l == 0 && !a.hopf) {
       T dx0[D];
       F::step0(P, x0, p[0], tau, dx0);
 #pragma unroll
@@ -231,7 +242,9 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
         }
       }
       if (l == 0) {
-        acc += F::g(P, x0);
+        // Lax: + g(x_0); Hopf (x_0 = 0 in the sum above): - g*(p_1)
+        if constexpr (F::kHopf) acc += a.hopf ? -F::gstar(P, p[0]) : F::g(P, x0);
+        else acc += F::g(P, x0);
         bad |= !all_finite<T, D>(x0);
       }
       acc = group_sum<L>(acc);
@@ -559,7 +572,8 @@ __global__ void __launch_bounds__(256) k_plain_control(KArgs<T> a) {
   for (int j = 0; j <= Np; j++) {
 #pragma unroll
     for (int i = 0; i < D; i++) {
-      const T xv = (j < Np) ? init_x(xt[i], a.seed, pt, kArrX, j, i) : xt[i];
+      // the Hopf formulation has no node 0 (kept at zero)
+      const T xv = (j == 0 && a.hopf) ? T(0) : ((j < Np) ? init_x(xt[i], a.seed, pt, kArrX, j, i) : xt[i]);
       WX[at(j, i)] = xv;
       WZ[at(j, i)] = xv;
       WP[at(j, i)] = (j >= 1) ? T(start_noise(a.seed, uint64_t(pt), kArrP, j, i)) : T(0);
@@ -585,15 +599,20 @@ __global__ void __launch_bounds__(256) k_plain_control(KArgs<T> a) {
       T pold[D];
 #pragma unroll
       for (int i = 0; i < D; i++) pold[i] = WP[at(1, i)];
-      F::dual(P, xj, pj, sd, Cj);
+      if constexpr (F::kHopf) {
+        if (a.hopf) F::dual_hopf1(P, xj, pj, sd, sigma, Cj);
+        else F::dual(P, xj, pj, sd, Cj);
+      } else {
+        F::dual(P, xj, pj, sd, Cj);
+      }
 #pragma unroll
       for (int i = 0; i < D; i++) {
         const T dp = pj[i] - pold[i];
         rp += dp * dp;
       }
     }
-    // node 0
-    {
+    // node 0 (Lax formulation only)
+    if (!a.hopf) {
       T x0[D], v0[D], xn0[D];
 #pragma unroll
       for (int i = 0; i < D; i++) {
@@ -666,7 +685,15 @@ __global__ void __launch_bounds__(256) k_plain_control(KArgs<T> a) {
     if (a.xtraj) a.xtraj[base + i] = xprev[i];
     if (a.ptraj) a.ptraj[base + i] = T(0);
   }
-  acc = F::g(P, xprev);
+  // Lax: g(x_0); Hopf (node 0 is zero): -g*(p_1)
+  if constexpr (F::kHopf) {
+    T p1[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) p1[i] = WP[at(1, i)];
+    acc = a.hopf ? -F::gstar(P, p1) : F::g(P, xprev);
+  } else {
+    acc = F::g(P, xprev);
+  }
   for (int j = 1; j <= Np; j++) {
     T xv[D], pv[D], s = T(0);
 #pragma unroll

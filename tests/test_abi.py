@@ -71,6 +71,8 @@ def test_create_rejects_invalid_descriptors(lib, bad):
     dict(H=2, d=12, d_y=0, g=2),                         # pursuit needs d_y = 6
     dict(H=3, d=100, g=3, dtype=1),                      # linear-tanh float32 only
     dict(N_max=300),                                     # beyond the largest tile
+    dict(H=1, d=12, flags=32),                           # Hopf: built for CNORM only
+    dict(H=2, d=12, d_y=6, g=2, flags=32),               # no Hopf for the game path
 ])
 def test_create_reports_unsupported(lib, unsup):
     from paper_1803_01215_amd import hjpd
@@ -95,3 +97,13 @@ def test_valid_descriptor_without_gpu_reports_device_error(lib):
     from paper_1803_01215_amd import hjpd
     ctx = ctypes.c_void_p()
     assert lib.hjpd_create(ctypes.byref(_desc()), ctypes.byref(ctx)) == hjpd.HJPD_EDEVICE
+
+
+def test_flag_values_match_header():
+    """The binding's flag constants are the header's (shift expressions parsed)."""
+    from paper_1803_01215_amd import hjpd
+    src = open(HEADER).read()
+    for name in ["HJPD_PLAIN", "HJPD_FIXED_ITERS", "HJPD_GRAPH", "HJPD_TIMING", "HJPD_NO_ORDER_HINT", "HJPD_HOPF"]:
+        m = re.search(name + r"\s*=\s*1u\s*<<\s*(\d+)", src)
+        assert m, name
+        assert getattr(hjpd, name) == 1 << int(m.group(1)), name
