@@ -34,7 +34,17 @@
  * with x_N = x and no node 0; the dual step at j = 1 is the joint prox of
  * g* + delta H(x_1,.), at j >= 2 the prox of delta H(x_j,.), both around
  * p_j + sigma (z_j - z_{j-1}) with z_0 = 0 (the Hopf difference matrix);
- * the x-steps are those of the Lax path.  The two-player game path follows section 4.2, eq.
+ * the x-steps are those of the Lax path.
+ *
+ * Robustness recipes (section 6, remarks on slow points), control path:
+ *  - on reaching the iteration cap, continue from the current iterate with
+ *    sigma raised by sigma_inc and tau = sigma0 tau0 / sigma, at most
+ *    `restarts` times (sigma_inc = 0 is the plain rerun);
+ *  - after the first cap, also stop when the value changes by at most
+ *    value_tol max(|value|, 1) between consecutive iterations;
+ *  - `starts` random starts (seed, seed+1, ...); the reported point is the
+ *    lowest value among the starts that stopped by a tolerance rule, else
+ *    the lowest finite value, ties to the earlier start.  The two-player game path follows section 4.2, eq.
  * discgenlaxhopfdg, and Algorithm 3 / Appendix A.2.1: blocks p, q, x, y in
  * that order, with the evader's costate entering H as -q.
  *
@@ -70,7 +80,7 @@
 /* Family ids: identical numbering to the public header, restated here. */
 enum { OR_H_CNORM = 0, OR_H_QUADROTOR = 1, OR_H_PURSUIT_EVASION = 2, OR_H_LINEAR_TANH = 3 };
 enum { OR_G_NORM = 0, OR_G_QUAD_SHIFT = 1, OR_G_PAIR_DIST = 2, OR_G_QUAD_FORM = 3 };
-enum { OR_PT_CONVERGED = 0, OR_PT_MAXITER = 1, OR_PT_NONFINITE = 2, OR_PT_BADINPUT = 3 };
+enum { OR_PT_CONVERGED = 0, OR_PT_MAXITER = 1, OR_PT_NONFINITE = 2, OR_PT_BADINPUT = 3, OR_PT_VALUE_STALLED = 4 };
 enum { OR_ARR_X = 0, OR_ARR_P = 1, OR_ARR_Y = 2, OR_ARR_Q = 3 };
 
 typedef struct {
@@ -666,6 +676,8 @@ typedef struct {
     int max_iter, fixed_iters;
     uint64_t seed;
     int N_max;
+    int starts, restarts;        /* recipes (see the header comment); 1 and 0 = plain Algorithm 1 */
+    double sigma_inc, value_tol;
 } or_opts;
 
 static int all_finite(const double *a, int n)
@@ -675,47 +687,63 @@ static int all_finite(const double *a, int n)
     return 1;
 }
 
-static void solve_control_point(const or_problem *pb, const or_opts *o, long pt, const double *xt,
-                                double t, int N, double *phi, int *iters, int *status,
-                                double *xtraj, double *ptraj)
+/* The value: the Lagrangian g(x_0) + sum_j <p_j, x_j - x_{j-1}> - delta sum_j H(x_j, p_j). */
+static double control_value(const or_problem *pb, const double *x, const double *p, int N, double delta)
+{
+    int d = pb->d;
+    double val = or_g(pb, x);
+    for (int j = 1; j <= N; j++) {
+        for (int i = 0; i < d; i++) val += p[j * d + i] * (x[j * d + i] - x[(j - 1) * d + i]);
+        val -= delta * or_H(pb, &x[j * d], &p[j * d], j * delta);
+    }
+    return val;
+}
+
+/* One random start (seed) of Algorithm 1 with the cap/sigma recipe; x, p
+ * (N+1 x d) receive the last iterate. */
+static void control_run(const or_problem *pb, const or_opts *o, long pt, const double *xt, double t, int N,
+                        uint64_t seed, double *x, double *p, double *phi, int *iters, int *status)
 {
     int d = pb->d;
     double delta = t / N;
     size_t sz = (size_t)(N + 1) * d;
-    double *x = calloc(sz, sizeof(double)), *p = calloc(sz, sizeof(double)), *z = calloc(sz, sizeof(double));
-    double *xn = calloc(sz, sizeof(double)), *pn = calloc(sz, sizeof(double));
+    double *z = calloc(sz, sizeof(double)), *xn = calloc(sz, sizeof(double)), *pn = calloc(sz, sizeof(double));
     double *v = calloc(d, sizeof(double)), *gr = calloc(d, sizeof(double));
+    double sigma = o->sigma, tau = o->tau;
+    const double st_product = o->sigma * o->tau;
     double *chol = NULL;
     if (pb->g == OR_G_QUAD_FORM) {
         chol = malloc(sizeof(double) * d * d);
-        chol_I_tauQ(pb->gp, d, o->tau, chol);
+        chol_I_tauQ(pb->gp, d, tau, chol);
     }
 
     /* random start (section 6 set-up) */
+    memset(x, 0, sz * sizeof(double));
+    memset(p, 0, sz * sizeof(double));
     for (int j = 0; j < N; j++)
-        for (int i = 0; i < d; i++) x[j * d + i] = xt[i] + or_init_noise(o->seed, pt, OR_ARR_X, j, i);
+        for (int i = 0; i < d; i++) x[j * d + i] = xt[i] + or_init_noise(seed, pt, OR_ARR_X, j, i);
     for (int i = 0; i < d; i++) x[N * d + i] = xt[i];
     for (int j = 1; j <= N; j++)
-        for (int i = 0; i < d; i++) p[j * d + i] = or_init_noise(o->seed, pt, OR_ARR_P, j, i);
+        for (int i = 0; i < d; i++) p[j * d + i] = or_init_noise(seed, pt, OR_ARR_P, j, i);
     memcpy(z, x, sz * sizeof(double));
 
-    int k = 0, st = OR_PT_MAXITER;
+    int k = 0, kp = 0, phase = 0, st = OR_PT_MAXITER;
+    double prev_val = NAN;
     for (;;) {
         /* dual step: p_j <- prox_{sigma delta H(x_j,.)}(p_j + sigma (z_j - z_{j-1})) */
         for (int i = 0; i < d; i++) pn[i] = 0.0;
         for (int j = 1; j <= N; j++) {
-            for (int i = 0; i < d; i++) v[i] = p[j * d + i] + o->sigma * (z[j * d + i] - z[(j - 1) * d + i]);
-            or_prox_p(pb, &x[j * d], v, o->sigma * delta, j * delta, &pn[j * d]);
+            for (int i = 0; i < d; i++) v[i] = p[j * d + i] + sigma * (z[j * d + i] - z[(j - 1) * d + i]);
+            or_prox_p(pb, &x[j * d], v, sigma * delta, j * delta, &pn[j * d]);
         }
         /* node 0: x_0 <- prox_{tau g}(x_0 - tau (D^T p)_0), (D^T p)_0 = -p_1 */
-        for (int i = 0; i < d; i++) v[i] = x[i] + o->tau * pn[d + i];
-        prox_g(pb, v, o->tau, chol, xn);
+        for (int i = 0; i < d; i++) v[i] = x[i] + tau * pn[d + i];
+        prox_g(pb, v, tau, chol, xn);
         /* nodes 1..N-1: one gradient step on -delta H plus the coupling term */
         for (int j = 1; j < N; j++) {
             or_grad_x_H(pb, &x[j * d], &pn[j * d], j * delta, gr);
             for (int i = 0; i < d; i++)
-                xn[j * d + i] = x[j * d + i] - o->tau * (pn[j * d + i] - pn[(j + 1) * d + i])
-                                + o->tau * delta * gr[i];
+                xn[j * d + i] = x[j * d + i] - tau * (pn[j * d + i] - pn[(j + 1) * d + i]) + tau * delta * gr[i];
         }
         for (int i = 0; i < d; i++) xn[N * d + i] = x[N * d + i];
 
@@ -728,25 +756,78 @@ static void solve_control_point(const or_problem *pb, const or_opts *o, long pt,
         memcpy(x, xn, sz * sizeof(double));
         memcpy(p, pn, sz * sizeof(double));
         k++;
+        kp++;
         if (!isfinite(rx + rp)) { st = OR_PT_NONFINITE; break; }
         int small = (rx < o->tol) && (rp < o->tol);
         if (!o->fixed_iters && small) { st = OR_PT_CONVERGED; break; }
-        if (k >= o->max_iter) { st = small ? OR_PT_CONVERGED : OR_PT_MAXITER; break; }
+        if (o->fixed_iters) {
+            if (k >= o->max_iter) { st = small ? OR_PT_CONVERGED : OR_PT_MAXITER; break; }
+            continue;
+        }
+        /* value-change rule, after the first cap */
+        if (phase >= 1 && o->value_tol > 0.0) {
+            double val = control_value(pb, x, p, N, delta);
+            if (isfinite(prev_val) && fabs(val - prev_val) <= o->value_tol * fmax(fabs(val), 1.0)) {
+                st = OR_PT_VALUE_STALLED;
+                break;
+            }
+            prev_val = val;
+        }
+        if (kp >= o->max_iter) {
+            if (phase < o->restarts) {
+                /* cap reached: raise sigma, keep sigma tau, continue from this iterate */
+                phase++;
+                kp = 0;
+                sigma += o->sigma_inc;
+                tau = st_product / sigma;
+                prev_val = NAN;
+                if (chol) chol_I_tauQ(pb->gp, d, tau, chol);
+                continue;
+            }
+            st = OR_PT_MAXITER;
+            break;
+        }
     }
-
-    /* value: the Lagrangian at the last iterate */
-    double val = or_g(pb, x);
-    for (int j = 1; j <= N; j++) {
-        for (int i = 0; i < d; i++) val += p[j * d + i] * (x[j * d + i] - x[(j - 1) * d + i]);
-        val -= delta * or_H(pb, &x[j * d], &p[j * d], j * delta);
-    }
+    double val = control_value(pb, x, p, N, delta);
     if (!isfinite(val) || !all_finite(x, (int)sz) || !all_finite(p, (int)sz)) st = OR_PT_NONFINITE;
     *phi = val;
     *iters = k;
     *status = st;
-    if (xtraj) memcpy(xtraj, x, sz * sizeof(double));
-    if (ptraj) memcpy(ptraj, p, sz * sizeof(double));
-    free(x); free(p); free(z); free(xn); free(pn); free(v); free(gr); free(chol);
+    free(z); free(xn); free(pn); free(v); free(gr); free(chol);
+}
+
+static int rank_of(int st, double phi)
+{
+    if (st == OR_PT_CONVERGED || st == OR_PT_VALUE_STALLED) return 0;
+    return isfinite(phi) ? 1 : 2;
+}
+
+static void solve_control_point(const or_problem *pb, const or_opts *o, long pt, const double *xt,
+                                double t, int N, double *phi, int *iters, int *status,
+                                double *xtraj, double *ptraj)
+{
+    int d = pb->d;
+    size_t sz = (size_t)(N + 1) * d;
+    double *x = calloc(sz, sizeof(double)), *p = calloc(sz, sizeof(double));
+    int starts = o->starts > 1 ? o->starts : 1;
+    int best_rank = 3;
+    double best_phi = NAN;
+    for (int s = 0; s < starts; s++) {
+        double ph;
+        int it, st;
+        control_run(pb, o, pt, xt, t, N, o->seed + (uint64_t)s, x, p, &ph, &it, &st);
+        int r = rank_of(st, ph);
+        if (r < best_rank || (r == best_rank && r < 2 && ph < best_phi)) {
+            best_rank = r;
+            best_phi = ph;
+            *phi = ph;
+            *iters = it;
+            *status = st;
+            if (xtraj) memcpy(xtraj, x, sz * sizeof(double));
+            if (ptraj) memcpy(ptraj, p, sz * sizeof(double));
+        }
+    }
+    free(x); free(p);
 }
 
 /* ------------------------------------------------------------------ */
@@ -951,16 +1032,28 @@ static void solve_game_point(const or_problem *pb, const or_opts *o, long pt, co
  * is solved sequentially.
  * Returns 0, or -1 for an unsupported problem.
  */
+typedef struct {
+    int starts, restarts;
+    double sigma_inc, value_tol;
+} or_recipe;
+
 static int solve_batch(const or_problem *pb, long n, const double *x, const double *t, const int *N,
                        double sigma, double tau, double theta, double tol, int max_iter, int fixed_iters,
                        uint64_t seed, int N_max, const int64_t *ids, double *phi, int *iters, int *status,
-                       double *x_traj, double *p_traj, int n_threads, int hopf)
+                       double *x_traj, double *p_traj, int n_threads, int hopf, const or_recipe *recipe)
 {
     int game = pb->d_y > 0;
     if (game && !(pb->H == OR_H_PURSUIT_EVASION && pb->g == OR_G_PAIR_DIST)) return -1;
     if (!game && (pb->H == OR_H_PURSUIT_EVASION || pb->g == OR_G_PAIR_DIST)) return -1;
     if (hopf && (game || pb->H != OR_H_CNORM || !(pb->g == OR_G_NORM || pb->g == OR_G_QUAD_SHIFT))) return -1;
-    or_opts o = { sigma, tau, theta, tol, max_iter, fixed_iters, seed, N_max };
+    or_opts o = { sigma, tau, theta, tol, max_iter, fixed_iters, seed, N_max, 1, 0, 0.0, 0.0 };
+    if (recipe) {
+        o.starts = recipe->starts;
+        o.restarts = recipe->restarts;
+        o.sigma_inc = recipe->sigma_inc;
+        o.value_tol = recipe->value_tol;
+        if (game || hopf || fixed_iters || o.restarts < 0 || o.sigma_inc < 0.0 || o.value_tol < 0.0) return -1;
+    }
     int d = pb->d;
 #ifdef _OPENMP
     int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
@@ -1000,7 +1093,7 @@ int or_solve(const or_problem *pb, long n, const double *x, const double *t, con
              double *x_traj, double *p_traj, int n_threads)
 {
     return solve_batch(pb, n, x, t, N, sigma, tau, theta, tol, max_iter, fixed_iters, seed, N_max, ids, phi, iters,
-                       status, x_traj, p_traj, n_threads, 0);
+                       status, x_traj, p_traj, n_threads, 0, NULL);
 }
 
 /* Hopf formulation (Algorithm 2), eikonal family with NORM or QUAD_SHIFT g. */
@@ -1010,5 +1103,16 @@ int or_solve_hopf(const or_problem *pb, long n, const double *x, const double *t
                   double *x_traj, double *p_traj, int n_threads)
 {
     return solve_batch(pb, n, x, t, N, sigma, tau, theta, tol, max_iter, fixed_iters, seed, N_max, ids, phi, iters,
-                       status, x_traj, p_traj, n_threads, 1);
+                       status, x_traj, p_traj, n_threads, 1, NULL);
+}
+
+/* Algorithm 1 with the robustness recipes (control path, tolerance mode). */
+int or_solve_recipe(const or_problem *pb, long n, const double *x, const double *t, const int *N,
+                    double sigma, double tau, double theta, double tol, int max_iter, uint64_t seed, int N_max,
+                    const int64_t *ids, int starts, int restarts, double sigma_inc, double value_tol,
+                    double *phi, int *iters, int *status, double *x_traj, double *p_traj, int n_threads)
+{
+    or_recipe r = { starts, restarts, sigma_inc, value_tol };
+    return solve_batch(pb, n, x, t, N, sigma, tau, theta, tol, max_iter, 0, seed, N_max, ids, phi, iters,
+                       status, x_traj, p_traj, n_threads, 0, &r);
 }

@@ -57,6 +57,11 @@ def lib():
         _lib.or_solve.restype = ctypes.c_int
         _lib.or_solve_hopf.argtypes = _lib.or_solve.argtypes
         _lib.or_solve_hopf.restype = ctypes.c_int
+        _lib.or_solve_recipe.argtypes = [P, ctypes.c_long, D, D, I, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_uint64,
+                                         ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_double, ctypes.c_double, D, I, I, D, D, ctypes.c_int]
+        _lib.or_solve_recipe.restype = ctypes.c_int
         _lib.or_gstar.argtypes = [P, D]
         _lib.or_gstar.restype = ctypes.c_double
         _lib.or_hopf_prox1.argtypes = [P, D, D, ctypes.c_double, ctypes.c_double, D]
@@ -187,7 +192,8 @@ class Result:
 
 
 def solve(pb: Problem, x, t, N, *, sigma, tau, theta=1.0, tol=1e-8, max_iter=5000, fixed_iters=False,
-          seed=0, N_max=None, ids=None, traj=False, threads=0, hopf=False) -> Result:
+          seed=0, N_max=None, ids=None, traj=False, threads=0, hopf=False, starts=1, restarts=0, sigma_inc=0.0,
+          value_tol=0.0) -> Result:
     """Run the oracle over a batch of points.
 
     x: [n, d]; t: [n]; N: [n] (intervals per point).  ids: each point's
@@ -195,7 +201,9 @@ def solve(pb: Problem, x, t, N, *, sigma, tau, theta=1.0, tol=1e-8, max_iter=500
     In fixed-iteration mode exactly max_iter iterations are run (unless a
     non-finite value stops the point first).  hopf=True runs the Hopf
     formulation (Algorithm 2; eikonal family with NORM or QUAD_SHIFT g); its
-    trajectories have node 0 = 0.
+    trajectories have node 0 = 0.  starts / restarts / sigma_inc / value_tol
+    select the robustness recipes (control path, tolerance mode): see the
+    C source's header comment.
     """
     x = np.ascontiguousarray(x, np.float64).reshape(-1, pb.d)
     n = x.shape[0]
@@ -211,11 +219,20 @@ def solve(pb: Problem, x, t, N, *, sigma, tau, theta=1.0, tol=1e-8, max_iter=500
         ids = np.ascontiguousarray(ids, np.int64)
         idp = ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     I = ctypes.POINTER(ctypes.c_int)
-    fn = lib().or_solve_hopf if hopf else lib().or_solve
-    rc = fn(pb.c, n, _dp(x), _dp(t), N.ctypes.data_as(I), sigma, tau, theta, tol, int(max_iter),
-                        int(bool(fixed_iters)), int(seed) & (2**64 - 1), int(N_max), idp, _dp(phi),
-                        iters.ctypes.data_as(I), status.ctypes.data_as(I),
-                        _dp(xt) if traj else None, _dp(pt) if traj else None, int(threads))
+    if starts > 1 or restarts > 0 or value_tol > 0.0:
+        if hopf or fixed_iters:
+            raise ValueError("oracle: recipes are for the Lax control path in tolerance mode")
+        rc = lib().or_solve_recipe(pb.c, n, _dp(x), _dp(t), N.ctypes.data_as(I), sigma, tau, theta, tol,
+                                   int(max_iter), int(seed) & (2**64 - 1), int(N_max), idp, int(starts),
+                                   int(restarts), float(sigma_inc), float(value_tol), _dp(phi),
+                                   iters.ctypes.data_as(I), status.ctypes.data_as(I),
+                                   _dp(xt) if traj else None, _dp(pt) if traj else None, int(threads))
+    else:
+        fn = lib().or_solve_hopf if hopf else lib().or_solve
+        rc = fn(pb.c, n, _dp(x), _dp(t), N.ctypes.data_as(I), sigma, tau, theta, tol, int(max_iter),
+                int(bool(fixed_iters)), int(seed) & (2**64 - 1), int(N_max), idp, _dp(phi),
+                iters.ctypes.data_as(I), status.ctypes.data_as(I),
+                _dp(xt) if traj else None, _dp(pt) if traj else None, int(threads))
     if rc != 0:
         raise ValueError("oracle: unsupported problem")
     return Result(phi, iters, status, xt, pt)

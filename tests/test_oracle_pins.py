@@ -730,3 +730,81 @@ def test_hopf_state_dependent_eikonal_matches_direct_shooting(oracle_mod, N):
         assert r.status[0] == 0
         brute = _shoot_min(step, g, x, N, t, d, rng, bounds_unit_ball=True)
         assert abs(r.phi[0] - brute) < 1e-6, (r.phi[0], brute)
+
+
+# --------------------------------------------------------------------------
+# Robustness recipes (section 6: sigma raised at the cap, value-change stop,
+# several random starts)
+# --------------------------------------------------------------------------
+
+def test_recipes_off_reproduce_algorithm_1(oracle_mod):
+    w = W.cnorm10(16)
+    pb = oracle_mod.Problem(w.H, w.g, w.d, w.d_y, w.hp, w.gp)
+    kw = dict(sigma=w.sigma, tau=w.tau, tol=w.tol, max_iter=3000, seed=w.init_seed, traj=True)
+    a = oracle_mod.solve(pb, w.x, w.t, w.N, **kw)
+    b = oracle_mod.solve(pb, w.x, w.t, w.N, starts=1, restarts=0, value_tol=0.0, **kw)
+    # value_tol = 0 and starts = 1 take the plain path; force the recipe path with a no-op restart budget
+    c = oracle_mod.solve(pb, w.x, w.t, w.N, restarts=1, sigma_inc=0.0, **dict(kw, max_iter=100000))
+    assert np.array_equal(a.phi, b.phi) and np.array_equal(a.iters, b.iters)
+    conv = a.status == 0
+    assert np.array_equal(a.phi[conv], c.phi[conv]) and np.array_equal(a.x_traj[conv], c.x_traj[conv])
+
+
+def test_sigma_raise_continues_to_the_closed_form(oracle_mod):
+    """Eikonal at a small sigma and a short cap: Algorithm 1 stops at the cap;
+    raising sigma by 20 (tau = 0.25/sigma) and continuing from the iterate
+    reaches the exact value max(|x| - t, 0) - 1."""
+    w = W.eikonal2d(24)
+    pb = oracle_mod.Problem(w.H, w.g, w.d, w.d_y, w.hp, w.gp)
+    kw = dict(sigma=0.5, tau=0.5, tol=1e-14, max_iter=400, seed=w.init_seed)
+    plain = oracle_mod.solve(pb, w.x, w.t, w.N, **kw)
+    assert np.mean(plain.status == 1) > 0.5
+    r = oracle_mod.solve(pb, w.x, w.t, w.N, restarts=40, sigma_inc=20.0, **kw)
+    exact = np.maximum(np.linalg.norm(w.x, axis=1) - w.t, 0) - 1
+    assert np.all(r.status == 0)
+    assert np.max(np.abs(r.phi - exact)) < 1e-6
+    assert np.all(r.iters[plain.status == 1] > 400)  # those continued past the first cap
+
+
+def test_value_change_stop_after_the_cap(oracle_mod):
+    """After the first cap the value-change rule stops a slowly settling
+    eikonal iterate; the value it returns is the exact one to well within the
+    residual rule's own accuracy."""
+    w = W.eikonal2d(24)
+    pb = oracle_mod.Problem(w.H, w.g, w.d, w.d_y, w.hp, w.gp)
+    kw = dict(sigma=w.sigma, tau=w.tau, tol=1e-30, max_iter=1500, seed=w.init_seed)
+    r = oracle_mod.solve(pb, w.x, w.t, w.N, restarts=3, sigma_inc=0.0, value_tol=1e-10, **kw)
+    exact = np.maximum(np.linalg.norm(w.x, axis=1) - w.t, 0) - 1
+    assert np.any(r.status == 4)
+    assert np.all(r.iters[r.status == 4] > 1500)
+    # a stalled value is not a converged iterate: accuracy of order sqrt(value_tol)
+    assert np.max(np.abs(r.phi - exact)) < 1e-5
+    # before the first cap the rule is off: one long phase equals Algorithm 1
+    long = dict(kw, max_iter=6000)
+    a = oracle_mod.solve(pb, w.x, w.t, w.N, **long)
+    b = oracle_mod.solve(pb, w.x, w.t, w.N, restarts=0, value_tol=1e-10, **long)
+    assert np.array_equal(a.phi, b.phi) and np.array_equal(a.status, b.status)
+
+
+def test_multi_start_keeps_the_lowest_converged_value(oracle_mod):
+    """Several random starts (seed, seed+1, ...): the reported value is the
+    lowest among the starts that met a stopping rule, and it matches direct
+    shooting of the discretised problem (nonconvex speed, alpha = 0.9)."""
+    rng = _rng(60)
+    alpha, d, N = 0.9, 2, 3
+    a = np.array([1.2, -0.9])
+    pb = oracle_mod.Problem(W.H_CNORM, W.G_QUAD_SHIFT, d, 0, [alpha], np.concatenate([[1.0], a]))
+    c = lambda z: 1 + alpha * np.sin(z[0]) * np.cos(z[1])
+    g = lambda z: 0.5 * np.sum((z - a) ** 2) - 1.0
+    step = lambda s, u: (c(s) * u, 0.0)
+    xs = rng.uniform(-2.0, 2.0, (6, d))
+    t = 0.9
+    kw = dict(sigma=1.0, tau=0.25, tol=1e-24, max_iter=40000)
+    singles = np.stack([oracle_mod.solve(pb, xs, t, N, seed=7 + s, **kw).phi for s in range(5)])
+    multi = oracle_mod.solve(pb, xs, t, N, seed=7, starts=5, **kw)
+    assert np.all(multi.status == 0)
+    assert np.array_equal(multi.phi, singles.min(axis=0))
+    for i in range(len(xs)):
+        brute = _shoot_min(step, g, xs[i], N, t, d, rng, starts=6, bounds_unit_ball=True)
+        assert multi.phi[i] <= brute + 1e-6
+        assert abs(multi.phi[i] - brute) < 1e-5
