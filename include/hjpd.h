@@ -67,7 +67,8 @@ enum {
     HJPD_PT_CONVERGED = 0, /* ||x^{k+1}-x^k||^2 < tol and ||p^{k+1}-p^k||^2 < tol (games: also y, q) */
     HJPD_PT_MAXITER = 1,   /* max_iter iterations done without meeting the rule */
     HJPD_PT_NONFINITE = 2, /* a residual, the value or an output became Inf/NaN */
-    HJPD_PT_BADINPUT = 3   /* t <= 0 or not finite, N < 1 or N > N_max, or x not finite */
+    HJPD_PT_BADINPUT = 3,  /* t <= 0 or not finite, N < 1 or N > N_max, or x not finite */
+    HJPD_PT_VALUE_STALLED = 4 /* recipes: stopped by the value-change rule after the cap */
 };
 
 /*
@@ -148,6 +149,24 @@ typedef struct {
     unsigned flags;  /* HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_GRAPH | HJPD_TIMING | HJPD_NO_ORDER_HINT | HJPD_HOPF */
     int lanes_per_point; /* persistent tile override: lanes per point (8,16,32,64), 0 = tuned/default */
     int nodes_per_lane;  /* persistent tile override: time nodes per lane (1..4), 0 = tuned/default */
+    /* Robustness recipes (section 6, remarks on slow points); all zero = plain
+     * Algorithm 1.  Control path, persistent kernels, tolerance mode, Lax
+     * formulation only (else HJPD_EUNSUPPORTED).
+     *  starts:    random starts per point (seed, seed+1, ...); the reported
+     *             point is the lowest value among the starts that met a
+     *             stopping rule, else the lowest finite value, ties to the
+     *             earlier start (0 or 1 = one start);
+     *  restarts:  times the iteration may continue past the cap max_iter with
+     *             sigma raised by sigma_inc and tau = sigma0 tau0 / sigma
+     *             (sigma_inc = 0: continue with the same steps);
+     *  value_tol: after the first cap, also stop (HJPD_PT_VALUE_STALLED) when
+     *             the value changes by at most value_tol max(|value|, 1)
+     *             between consecutive iterations (0 = off).
+     * iters reports the chosen start's iterations over all its phases. */
+    int starts;
+    int restarts;
+    double sigma_inc;
+    double value_tol;
 } hjpd_desc;
 
 /*

@@ -35,6 +35,8 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+bool has_recipe(const hjpd_desc& d) { return d.starts > 1 || d.restarts > 0 || d.value_tol > 0.0; }
+
 #define HIP_OK(expr, what)                                                                 \
   do {                                                                                     \
     hipError_t e_ = (expr);                                                                \
@@ -207,7 +209,7 @@ struct hjpd_ctx {
 
 namespace {
 
-typedef const void* (*Lookup)(int, int, int);
+typedef const void* (*Lookup)(int, int, int, int);
 
 Lookup lookup_for(const hjpd_desc& d) {
   const bool f64 = d.dtype == HJPD_F64;
@@ -266,7 +268,7 @@ int build_plan(hjpd_ctx* c, const int* tile_override_L, const int* tile_override
     }
     cl.L = t.L;
     cl.K = t.K;
-    cl.kern = lk(0, t.L, t.K);
+    cl.kern = lk(0, t.L, t.K, has_recipe(c->desc));
     if (!cl.kern) return fail(HJPD_EUNSUPPORTED, "tile not built");
     cl.grid = persistent_grid(c, cl.kern);
     c->plan.push_back(cl);
@@ -277,7 +279,7 @@ int build_plan(hjpd_ctx* c, const int* tile_override_L, const int* tile_override
       break;
     }
   }
-  c->plain_kern = lk(1, 0, 0);
+  c->plain_kern = lk(1, 0, 0, 0);
   return HJPD_OK;
 }
 
@@ -329,8 +331,13 @@ int validate_desc(const hjpd_desc* d) {
     return fail(HJPD_EINVAL, "nodes_per_lane given without lanes_per_point");
   }
   if (d->d > 1023) return fail(HJPD_EINVAL, "d must be <= 1023");
+  if (d->starts < 0 || d->starts > 1024 || d->restarts < 0 || !(d->sigma_inc >= 0.0) || !std::isfinite(d->sigma_inc) ||
+      !(d->value_tol >= 0.0) || !std::isfinite(d->value_tol))
+    return fail(HJPD_EINVAL, "recipes: starts in 0..1024, restarts >= 0, sigma_inc >= 0, value_tol >= 0");
   // supported pairs
   const bool game = d->d_y > 0;
+  if (has_recipe(*d) && (game || d->H == HJPD_H_LINEAR_TANH || (d->flags & (HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_HOPF))))
+    return fail(HJPD_EUNSUPPORTED, "recipes are built for the persistent Lax control path in tolerance mode");
   if ((d->flags & HJPD_HOPF) && !(d->H == HJPD_H_CNORM && !game && (d->g == HJPD_G_NORM || d->g == HJPD_G_QUAD_SHIFT)))
     return fail(HJPD_EUNSUPPORTED, "the Hopf formulation is built for CNORM with NORM or QUAD_SHIFT");
   if (d->H == HJPD_H_PURSUIT_EVASION) {
@@ -412,6 +419,10 @@ int enqueue_solve(hjpd_ctx* c, int64_t n, const void* x, const void* t, const in
   a.d = D.d;
   a.gkind = D.g;
   a.hopf = (D.flags & HJPD_HOPF) ? 1 : 0;
+  a.starts = D.starts > 1 ? D.starts : 1;
+  a.restarts = D.restarts;
+  a.sigma_inc = T(D.sigma_inc);
+  a.value_tol = T(D.value_tol);
   a.seed = D.seed;
   void* args[] = {&a};
   if (timed) HIP_OK(hipEventRecord(c->ev0, s), "hipEventRecord");
@@ -638,7 +649,7 @@ int hjpd_autotune(hjpd_ctx* c, int64_t n, const void* x, const void* t, const in
       std::vector<Cls> saved_plan = c->plan;
       c->plan[ci].L = tl.L;
       c->plan[ci].K = tl.K;
-      c->plan[ci].kern = lk(0, tl.L, tl.K);
+      c->plan[ci].kern = lk(0, tl.L, tl.K, has_recipe(c->desc));
       c->plan[ci].grid = persistent_grid(c, c->plan[ci].kern);
       double ms_total = 0;
       for (int rep = 0; rep < 2 && !rc; rep++) {

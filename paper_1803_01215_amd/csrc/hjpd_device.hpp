@@ -19,7 +19,7 @@
 namespace hjpd {
 
 enum : int { kArrX = 0, kArrP = 1, kArrY = 2, kArrQ = 3 };
-enum : int { kConverged = 0, kMaxIter = 1, kNonFinite = 2, kBadInput = 3 };
+enum : int { kConverged = 0, kMaxIter = 1, kNonFinite = 2, kBadInput = 3, kValueStalled = 4 };
 
 // ---------------------------------------------------------------------------
 // Random start
@@ -58,6 +58,7 @@ template <> struct M<float> {
   static __device__ __forceinline__ float rcp(float a) { return __builtin_amdgcn_rcpf(a); }
   static __device__ __forceinline__ float tanh(float a) { return ::tanhf(a); }
   static __device__ __forceinline__ float fmax(float a, float b) { return ::fmaxf(a, b); }
+  static __device__ __forceinline__ float fabs_(float a) { return ::fabsf(a); }
   static __device__ __forceinline__ bool finite(float a) { return __builtin_isfinite(a); }
 };
 
@@ -68,6 +69,7 @@ template <> struct M<double> {
   static __device__ __forceinline__ double rcp(double a) { return 1.0 / a; }
   static __device__ __forceinline__ double tanh(double a) { return ::tanh(a); }
   static __device__ __forceinline__ double fmax(double a, double b) { return ::fmax(a, b); }
+  static __device__ __forceinline__ double fabs_(double a) { return ::fabs(a); }
   static __device__ __forceinline__ bool finite(double a) { return __builtin_isfinite(a); }
 };
 

@@ -60,10 +60,16 @@ struct CNorm {
     P.r = gp[0];
     P.c0 = gp[0];
 #pragma unroll
-    for (int i = 0; i < D; i++) {
-      P.a[i] = (gkind == kGQuadShift) ? gp[1 + i] : T(0);
-      P.ta[i] = tau * P.a[i];
-    }
+    for (int i = 0; i < D; i++) P.a[i] = (gkind == kGQuadShift) ? gp[1 + i] : T(0);
+    set_tau(P, tau, gkind);
+  }
+
+  // Parameters that depend on the primal step tau (recomputed when a recipe
+  // raises sigma and lowers tau).
+  template <typename T>
+  __device__ static void set_tau(Par<T>& P, T tau, int) {
+#pragma unroll
+    for (int i = 0; i < D; i++) P.ta[i] = tau * P.a[i];
     P.inv1pt = T(1) / (T(1) + tau);
     P.s1pt = tau / (T(1) + tau);
 #pragma unroll
@@ -239,10 +245,15 @@ struct Quad {
     P.clamp = hp[5];
     P.c0 = gp[0];
 #pragma unroll
-    for (int i = 0; i < 12; i++) {
-      P.a[i] = gp[1 + i];
-      P.ta[i] = tau * P.a[i];
-    }
+    for (int i = 0; i < 12; i++) P.a[i] = gp[1 + i];
+    set_tau(P, tau, 0);
+  }
+
+  // Parameters that depend on the primal step tau.
+  template <typename T>
+  __device__ static void set_tau(Par<T>& P, T tau, int) {
+#pragma unroll
+    for (int i = 0; i < 12; i++) P.ta[i] = tau * P.a[i];
     P.inv1pt = T(1) / (T(1) + tau);
     P.s1pt = tau / (T(1) + tau);
 #pragma unroll

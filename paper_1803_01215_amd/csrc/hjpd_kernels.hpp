@@ -69,6 +69,9 @@ struct KArgs {
   int max_iter, fixed, N_max, d, gkind;
   int hopf;                  // 1: Hopf formulation (Algorithm 2), no node 0
   uint64_t seed;
+  // robustness recipes (kernels compiled with them only)
+  int starts, restarts;
+  T sigma_inc, value_tol;
 };
 
 template <typename T, int D>
@@ -85,7 +88,8 @@ __device__ __forceinline__ T init_x(T xt, uint64_t seed, int64_t pt, int arr, in
 }
 
 // ---------------------------------------------------------------------------
-// Persistent lane-group kernel, optimal-control path (Algorithm 1).
+// Persistent lane-group kernel, optimal-control path (Algorithm 1; Hopf:
+// Algorithm 2).
 // ---------------------------------------------------------------------------
 template <typename T, class F, int L, int K>
 __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArgs<T> a) {
@@ -282,6 +286,306 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
           for (int i = 0; i < D; i++) a.ptraj[base + i] = T(0);
       }
       pop_and_init();
+    }
+    if (__any(done || (active && priority_step(k)))) set_wave_priority(active, k);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent lane-group kernel with the robustness recipes of section 6
+// (several random starts, sigma raised at the iteration cap, value-change
+// stop after the first cap), control path.  A separate kernel: the recipe
+// state and the per-point step sizes would otherwise cost the plain kernel
+// registers.  Launched with kRec = true; kRec = false reduces it to the plain
+// iteration (the same arithmetic as k_group_control).
+// ---------------------------------------------------------------------------
+template <typename T, class F, int L, int K, bool kRec = true>
+__global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_rec(KArgs<T> a) {
+  constexpr int D = F::D;
+  const int lane = threadIdx.x & 63;
+  const int l = lane & (L - 1);
+  const int leader = lane - l;
+
+  typename F::template Par<T> P;
+  F::load(P, a.hp, a.gp, a.gkind, a.tau);
+  const int beg = a.cls_range[2 * a.cls], end = a.cls_range[2 * a.cls + 1];
+  int32_t* head = a.heads + a.cls;
+  const T theta = a.theta;
+  // step sizes: kernel constants, or per point when the recipes may raise sigma
+  T sigma = a.sigma, tau = a.tau;
+
+  T x[K][D], p[K][D], z[K][D], x0[D], z0[D];
+  T tj[K], tdj[K];  // per node: tau and tau*delta where the node takes a primal step, else 0
+  T delta = T(0), sd = T(0), td = T(0);
+  int Np = 0, k = 0;
+  int64_t pt = -1;
+  bool active = false;
+  // recipe state (dead code without kRec)
+  int start = 0, phase = 0, kp = 0, best_rank = 3;
+  T prev_val = T(0), best_phi = T(0);
+  bool have_prev = false;
+
+  auto set_steps = [&]() __attribute__((always_inline)) {
+    sd = sigma * delta;
+    td = tau * delta;
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      const int j = 1 + l * K + kk;
+      tj[kk] = (j < Np) ? tau : T(0);
+      tdj[kk] = (j < Np) ? td : T(0);
+    }
+    if constexpr (kRec) F::set_tau(P, tau, a.gkind);
+  };
+
+  // random start number `s` of the current point (seed + s; s = 0 without recipes)
+  auto init_start = [&](int s) __attribute__((always_inline)) {
+    const uint64_t seed = a.seed + uint64_t(s);
+    k = 0;
+    if constexpr (kRec) {
+      start = s;
+      phase = 0;
+      kp = 0;
+      have_prev = false;
+      sigma = a.sigma;
+      tau = a.tau;
+    }
+    T xt[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) xt[i] = a.x[pt * a.d + i];
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      const int j = 1 + l * K + kk;
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        x[kk][i] = (j < Np) ? init_x(xt[i], seed, pt, kArrX, j, i) : xt[i];
+        p[kk][i] = (j <= Np) ? T(start_noise(seed, uint64_t(pt), kArrP, j, i)) : T(0);
+        z[kk][i] = x[kk][i];
+      }
+    }
+    // node 0 lives in the group's first lane; the other lanes keep x0 = z0 = 0
+    // (and every lane in the Hopf formulation, which has no node 0)
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      x0[i] = (l == 0 && !a.hopf) ? init_x(xt[i], seed, pt, kArrX, 0, i) : T(0);
+      z0[i] = x0[i];
+    }
+    set_steps();
+  };
+
+  auto pop_and_init = [&]() __attribute__((always_inline)) {
+    int idx = 0;
+    if (l == 0) idx = atomicAdd(head, 1);
+    idx = __shfl(idx, leader, 64);
+    const int qi = beg + idx;
+    active = qi < end;
+    if (!active) return;
+    pt = a.queue[qi];
+    Np = a.N[pt];
+    delta = a.t[pt] / T(Np);
+    if constexpr (kRec) best_rank = 3;
+    init_start(0);
+  };
+
+  // The value: the Lagrangian at the current iterate (Algorithm 1 fval; Hopf:
+  // Algorithm 2 fval), summed over the group; `bad` flags a non-finite entry.
+  auto lagrangian = [&](int& bad) __attribute__((always_inline)) {
+    T xprev[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) xprev[i] = group_prev0<L>(x[K - 1][i], l) + x0[i];
+    T acc = T(0);
+    bad = 0;
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      const int j = 1 + l * K + kk;
+      if (j <= Np) {
+        T s = T(0);
+#pragma unroll
+        for (int i = 0; i < D; i++) s += p[kk][i] * (x[kk][i] - (kk == 0 ? xprev[i] : x[kk - 1][i]));
+        acc += s - delta * F::H(P, x[kk], p[kk]);
+        bad |= !(all_finite<T, D>(x[kk]) && all_finite<T, D>(p[kk]));
+      }
+    }
+    if (l == 0) {
+      // Lax: + g(x_0); Hopf (x_0 = 0 in the sum above): - g*(p_1)
+      if constexpr (F::kHopf) acc += a.hopf ? -F::gstar(P, p[0]) : F::g(P, x0);
+      else acc += F::g(P, x0);
+      bad |= !all_finite<T, D>(x0);
+    }
+    bad = group_or<L>(bad);
+    return group_sum<L>(acc);
+  };
+
+  pop_and_init();
+
+  while (__any(active)) {
+    // ---- dual step -------------------------------------------------------
+    // z_{j-1} of the lane's first node: the previous lane's last node, or
+    // z_0 in the group's first lane (z0 is zero in every other lane; the
+    // Hopf difference operator has z_0 = 0).
+    T zprev[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) zprev[i] = group_prev0<L>(z[K - 1][i], l) + z0[i];
+    typename F::template Cache<T> C[K];
+    T rp = T(0), rx = T(0);
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      T v[D];
+#pragma unroll
+      for (int i = 0; i < D; i++) v[i] = p[kk][i] + sigma * (z[kk][i] - (kk == 0 ? zprev[i] : z[kk - 1][i]));
+      if constexpr (F::kHopf) {
+        // Hopf: node 1 (first lane, first slot) takes the joint prox with g*
+        if (kk == 0 && a.hopf && l == 0)
+          F::dual_hopf1(P, x[kk], v, sd, sigma, C[kk]);
+        else
+          F::dual(P, x[kk], v, sd, C[kk]);
+      } else {
+        F::dual(P, x[kk], v, sd, C[kk]);
+      }
+      if constexpr (!F::kZeroSafe) {
+        // nodes past N keep p = 0
+        const int j = 1 + l * K + kk;
+#pragma unroll
+        for (int i = 0; i < D; i++) v[i] = (j <= Np) ? v[i] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        const T dp = v[i] - p[kk][i];
+        rp += dp * dp;
+        p[kk][i] = v[i];
+      }
+    }
+    // ---- node 0 -----------------------------------------------------------
+    T pnext[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) pnext[i] = group_next0<L>(p[0][i], l);
+    if (l == 0 && !a.hopf) {
+      T dx0[D];
+      F::step0(P, x0, p[0], tau, dx0);
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        rx += dx0[i] * dx0[i];
+        z0[i] = x0[i] + (T(1) + theta) * dx0[i];
+        x0[i] += dx0[i];
+      }
+    }
+    // ---- primal step --------------------------------------------------------
+    // Nodes j >= N take no step: their tau and tau*delta are 0 (x_N = x stays
+    // fixed, and past N nothing moves).
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      T g[D];
+      F::grad(P, x[kk], p[kk], C[kk], g);
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        const T pp = (kk == K - 1) ? pnext[i] : p[kk + 1][i];
+        const T dx = tdj[kk] * g[i] - tj[kk] * (p[kk][i] - pp);
+        rx += dx * dx;
+        z[kk][i] = x[kk][i] + (T(1) + theta) * dx;
+        x[kk][i] += dx;
+      }
+    }
+    // ---- stopping rule (section 6 set-up) ------------------------------------
+    k++;
+    const T rxs = group_sum<L>(rx), rps = group_sum<L>(rp);
+    const bool fin = M<T>::finite(rxs + rps);
+    const bool small = (rxs < a.tol) && (rps < a.tol);
+    bool done;
+    int st = kMaxIter;
+    if constexpr (!kRec) {
+      done = active && (!fin || (!a.fixed && small) || k >= a.max_iter);
+      st = !fin ? kNonFinite : (small ? kConverged : kMaxIter);
+    } else {
+      // recipes (tolerance mode only): cap -> raise sigma and continue, up to
+      // a.restarts times; after the first cap also stop on a stalled value
+      kp++;
+      done = false;
+      if (active) {
+        if (!fin) {
+          done = true;
+          st = kNonFinite;
+        } else if (small) {
+          done = true;
+          st = kConverged;
+        } else {
+          if (phase >= 1 && a.value_tol > T(0)) {
+            int bad_v = 0;
+            const T val = lagrangian(bad_v);
+            if (have_prev && M<T>::fabs_(val - prev_val) <= a.value_tol * M<T>::fmax(M<T>::fabs_(val), T(1))) {
+              done = true;
+              st = kValueStalled;
+            }
+            prev_val = val;
+            have_prev = true;
+          }
+          if (!done && kp >= a.max_iter) {
+            if (phase < a.restarts) {
+              phase++;
+              kp = 0;
+              have_prev = false;
+              sigma += a.sigma_inc;
+              tau = a.sigma * a.tau / sigma;
+              set_steps();
+            } else {
+              done = true;
+              st = kMaxIter;
+            }
+          }
+        }
+      }
+    }
+    if (done) {
+      int bad = 0;
+      const T acc = lagrangian(bad);
+      if (bad || !M<T>::finite(acc)) st = kNonFinite;
+      bool write = true;
+      if constexpr (kRec) {
+        // several starts: keep the lowest value among those that met a stopping
+        // rule, else the lowest finite value; ties keep the earlier start
+        const int rank = (st == kConverged || st == kValueStalled) ? 0 : (M<T>::finite(acc) ? 1 : 2);
+        write = rank < best_rank || (rank == best_rank && rank < 2 && acc < best_phi);
+        if (write) {
+          best_rank = rank;
+          best_phi = acc;
+        }
+      }
+      if (write) {
+        if (l == 0) {
+          a.phi[pt] = acc;
+          a.iters[pt] = k;
+          a.status[pt] = st;
+        }
+        const int64_t base = pt * int64_t(a.N_max + 1) * a.d;
+        if (a.xtraj) {
+#pragma unroll
+          for (int kk = 0; kk < K; kk++) {
+            const int j = 1 + l * K + kk;
+            if (j <= Np)
+#pragma unroll
+              for (int i = 0; i < D; i++) a.xtraj[base + j * D + i] = x[kk][i];
+          }
+          if (l == 0)
+#pragma unroll
+            for (int i = 0; i < D; i++) a.xtraj[base + i] = x0[i];
+        }
+        if (a.ptraj) {
+#pragma unroll
+          for (int kk = 0; kk < K; kk++) {
+            const int j = 1 + l * K + kk;
+            if (j <= Np)
+#pragma unroll
+              for (int i = 0; i < D; i++) a.ptraj[base + j * D + i] = p[kk][i];
+          }
+          if (l == 0)
+#pragma unroll
+            for (int i = 0; i < D; i++) a.ptraj[base + i] = T(0);
+        }
+      }
+      if constexpr (kRec) {
+        if (start + 1 < a.starts) init_start(start + 1);
+        else pop_and_init();
+      } else {
+        pop_and_init();
+      }
     }
     if (__any(done || (active && priority_step(k)))) set_wave_priority(active, k);
   }

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libhjpd.so")
 
 HJPD_OK, HJPD_EINVAL, HJPD_ENOMEM, HJPD_EDEVICE, HJPD_EUNSUPPORTED = 0, 1, 2, 3, 4
-HJPD_PT_CONVERGED, HJPD_PT_MAXITER, HJPD_PT_NONFINITE, HJPD_PT_BADINPUT = 0, 1, 2, 3
+HJPD_PT_CONVERGED, HJPD_PT_MAXITER, HJPD_PT_NONFINITE, HJPD_PT_BADINPUT, HJPD_PT_VALUE_STALLED = 0, 1, 2, 3, 4
 HJPD_H_CNORM, HJPD_H_QUADROTOR, HJPD_H_PURSUIT_EVASION, HJPD_H_LINEAR_TANH = 0, 1, 2, 3
 HJPD_G_NORM, HJPD_G_QUAD_SHIFT, HJPD_G_PAIR_DIST, HJPD_G_QUAD_FORM = 0, 1, 2, 3
 HJPD_F32, HJPD_F64 = 0, 1
@@ -36,7 +36,8 @@ class hjpd_desc(ctypes.Structure):
                 ("dtype", ctypes.c_int), ("N_max", ctypes.c_int), ("sigma", ctypes.c_double),
                 ("tau", ctypes.c_double), ("theta", ctypes.c_double), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint),
-                ("lanes_per_point", ctypes.c_int), ("nodes_per_lane", ctypes.c_int)]
+                ("lanes_per_point", ctypes.c_int), ("nodes_per_lane", ctypes.c_int), ("starts", ctypes.c_int),
+                ("restarts", ctypes.c_int), ("sigma_inc", ctypes.c_double), ("value_tol", ctypes.c_double)]
 
 
 _lib = None

@@ -38,7 +38,8 @@ class Solver:
 
     def __init__(self, *, d, H, g, N_max, sigma, tau, theta=1.0, tol=1e-6, max_iter=20000, seed=0, d_y=0,
                  dtype=torch.float32, plain=False, fixed_iters=False, graph=False, timing=False,
-                 lanes_per_point=0, nodes_per_lane=0, order_hint=True, hopf=False):
+                 lanes_per_point=0, nodes_per_lane=0, order_hint=True, hopf=False, starts=1, restarts=0,
+                 sigma_inc=0.0, value_tol=0.0):
         self.dtype = dtype
         self.d, self.N_max = d, N_max
         flags = ((C.HJPD_PLAIN if plain else 0) | (C.HJPD_FIXED_ITERS if fixed_iters else 0)
@@ -47,7 +48,8 @@ class Solver:
         self.desc = C.hjpd_desc(d=d, d_y=d_y, H=H, g=g, dtype=C.HJPD_F64 if dtype == torch.float64 else C.HJPD_F32,
                                 N_max=N_max, sigma=sigma, tau=tau, theta=theta, tol=tol, max_iter=max_iter,
                                 seed=seed & (2**64 - 1), flags=flags, lanes_per_point=lanes_per_point,
-                                nodes_per_lane=nodes_per_lane)
+                                nodes_per_lane=nodes_per_lane, starts=starts, restarts=restarts, sigma_inc=sigma_inc,
+                                value_tol=value_tol)
         self.ctx = C.hjpd_create(self.desc)
 
     def close(self):
