@@ -164,6 +164,29 @@ def bench_configs(torch, dev, subset):
             s.close()
         rec["speedup"] = rec["batched"]["solves_per_s"] / max(rec["plain"]["solves_per_s"], 1e-30)
         out[name] = rec
+        if name == "quadrotor12":
+            # robustness recipes (section 6): cap 5,000, then up to three more
+            # phases, stopping also on a stalled value (rel. change <= 1e-7)
+            rw = w.subset(np.arange(w.n))
+            rw.max_iter = 5000
+            s = Solver(d=rw.d, d_y=rw.d_y, H=rw.H, g=rw.g, N_max=rw.N_max, sigma=rw.sigma, tau=rw.tau,
+                       theta=rw.theta, tol=rw.tol, max_iter=rw.max_iter, seed=rw.init_seed, dtype=td, graph=True,
+                       restarts=3, sigma_inc=0.0, value_tol=1e-7)
+            o = s.alloc(rw.n)
+            s.solve(*inp, out=o)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s.solve(*inp, out=o)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            st = np.bincount(o.status.cpu().numpy(), minlength=5)
+            out["quadrotor12_recipes"] = {
+                "points": rw.n, "recipe": "max_iter 5000, restarts 3, sigma_inc 0, value_tol 1e-7", "ms": ms,
+                "converged": int(st[0]), "value_stalled": int(st[4]), "max_iter": int(st[1]),
+                "solves_per_s": float(st[0] + st[4]) / (ms * 1e-3)}
+            s.close()
         print("[configs] %s: batched %.1f ms, plain %.1f ms" % (name, rec["batched"]["ms"], rec["plain"]["ms"]),
               file=sys.stderr, flush=True)
     return out
