@@ -36,6 +36,28 @@
  * p_j + sigma (z_j - z_{j-1}) with z_0 = 0 (the Hopf difference matrix);
  * the x-steps are those of the Lax path.
  *
+ * Forward Euler and trapezoidal discretisations (section 4.1, eq.
+ * disclaxFE; the remark after Algorithm 1 that averaging the forward and
+ * backward Euler approximations gives a trapezoidal rule), eikonal family.
+ * Writing p_j for the costate of the interval (j-1, j), j = 1..N, all three
+ * discretisations are one saddle problem
+ *
+ *   g(x_0) + sum_{j=1..N} <p_j, x_j - x_{j-1}>
+ *          - delta sum_{j=1..N} [ wl H(x_{j-1},p_j,s_{j-1}) + wr H(x_j,p_j,s_j) ]
+ *
+ * with weights (wl, wr) = (0, 1) backward Euler (eq. disclaxBE), (1, 0)
+ * forward Euler (eq. disclaxFE, whose p_j is p_{j+1} here) and (1/2, 1/2)
+ * trapezoid (the average of the two Hamiltonian sums).  The iteration keeps
+ * Algorithm 1's pattern; x_0, which now meets both g and H, takes a
+ * proximal-gradient step (section 5.3: gradient step on the smooth part,
+ * prox on the nonsmooth part):
+ *
+ *   p_j <- argmin_p sigma delta (wl H(x_{j-1},p) + wr H(x_j,p)) + |p - (p_j + sigma (z_j - z_{j-1}))|^2/2
+ *   x_0 <- prox_{tau g}( x_0 + tau p_1 + tau delta wl grad_x H(x_0, p_1) )
+ *   x_j <- x_j - tau (p_j - p_{j+1}) + tau delta (wr grad_x H(x_j,p_j) + wl grad_x H(x_j,p_{j+1}))
+ *
+ * For H = c(x)|p| the p-step is a shrink by sigma delta (wl c(x_{j-1}) + wr c(x_j)).
+ *
  * Robustness recipes (section 6, remarks on slow points), control path:
  *  - on reaching the iteration cap, continue from the current iterate with
  *    sigma raised by sigma_inc and tau = sigma0 tau0 / sigma, at most
@@ -904,6 +926,91 @@ static void solve_hopf_point(const or_problem *pb, const or_opts *o, long pt, co
 }
 
 /* ------------------------------------------------------------------ */
+/* One query point: weighted Euler discretisations (forward Euler,     */
+/* trapezoid; backward Euler at wl = 0, wr = 1), eikonal family.       */
+/* ------------------------------------------------------------------ */
+
+/* The Lagrangian of the weighted saddle at (x, p). */
+static double mix_value(const or_problem *pb, const double *x, const double *p, int N, double delta, double wl,
+                        double wr)
+{
+    int d = pb->d;
+    double val = or_g(pb, x);
+    for (int j = 1; j <= N; j++) {
+        for (int i = 0; i < d; i++) val += p[j * d + i] * (x[j * d + i] - x[(j - 1) * d + i]);
+        val -= delta * (wl * or_H(pb, &x[(j - 1) * d], &p[j * d], (j - 1) * delta)
+                        + wr * or_H(pb, &x[j * d], &p[j * d], j * delta));
+    }
+    return val;
+}
+
+static void solve_mix_point(const or_problem *pb, const or_opts *o, long pt, const double *xt, double t, int N,
+                            double wl, double wr, double *phi, int *iters, int *status, double *xtraj, double *ptraj)
+{
+    int d = pb->d;
+    double delta = t / N;
+    size_t sz = (size_t)(N + 1) * d;
+    double *x = calloc(sz, sizeof(double)), *p = calloc(sz, sizeof(double)), *z = calloc(sz, sizeof(double));
+    double *xn = calloc(sz, sizeof(double)), *pn = calloc(sz, sizeof(double));
+    double *v = calloc(d, sizeof(double)), *ga = calloc(d, sizeof(double)), *gb = calloc(d, sizeof(double));
+
+    /* random start, as in Algorithm 1: x_j (j < N) near x, x_N = x, p_j (j >= 1) near 0, z = x */
+    for (int j = 0; j < N; j++)
+        for (int i = 0; i < d; i++) x[j * d + i] = xt[i] + or_init_noise(o->seed, pt, OR_ARR_X, j, i);
+    for (int i = 0; i < d; i++) x[N * d + i] = xt[i];
+    for (int j = 1; j <= N; j++)
+        for (int i = 0; i < d; i++) p[j * d + i] = or_init_noise(o->seed, pt, OR_ARR_P, j, i);
+    memcpy(z, x, sz * sizeof(double));
+
+    int k = 0, st = OR_PT_MAXITER;
+    for (;;) {
+        /* p-step: shrink by sigma delta times the interval's weighted speed */
+        for (int i = 0; i < d; i++) pn[i] = 0.0;
+        for (int j = 1; j <= N; j++) {
+            double c_eff = wl * cnorm_c(pb->hp, &x[(j - 1) * d]) + wr * cnorm_c(pb->hp, &x[j * d]);
+            for (int i = 0; i < d; i++) v[i] = p[j * d + i] + o->sigma * (z[j * d + i] - z[(j - 1) * d + i]);
+            or_shrink2(v, o->sigma * delta * c_eff, d, &pn[j * d]);
+        }
+        /* node 0: proximal-gradient step (gradient of -delta wl H(x_0, p_1), prox of g) */
+        or_grad_x_H(pb, &x[0], &pn[d], 0.0, ga);
+        for (int i = 0; i < d; i++) v[i] = x[i] + o->tau * pn[d + i] + o->tau * delta * wl * ga[i];
+        prox_g(pb, v, o->tau, NULL, xn);
+        /* nodes 1..N-1: x_j is the right end of interval j (weight wr, costate p_j)
+           and the left end of interval j+1 (weight wl, costate p_{j+1}) */
+        for (int j = 1; j < N; j++) {
+            or_grad_x_H(pb, &x[j * d], &pn[j * d], j * delta, ga);
+            or_grad_x_H(pb, &x[j * d], &pn[(j + 1) * d], j * delta, gb);
+            for (int i = 0; i < d; i++)
+                xn[j * d + i] = x[j * d + i] - o->tau * (pn[j * d + i] - pn[(j + 1) * d + i])
+                                + o->tau * delta * (wr * ga[i] + wl * gb[i]);
+        }
+        for (int i = 0; i < d; i++) xn[N * d + i] = x[N * d + i];
+
+        double rx = 0.0, rp = 0.0;
+        for (size_t a = 0; a < sz; a++) {
+            rx += (xn[a] - x[a]) * (xn[a] - x[a]);
+            rp += (pn[a] - p[a]) * (pn[a] - p[a]);
+        }
+        for (size_t a = 0; a < sz; a++) z[a] = xn[a] + o->theta * (xn[a] - x[a]);
+        memcpy(x, xn, sz * sizeof(double));
+        memcpy(p, pn, sz * sizeof(double));
+        k++;
+        if (!isfinite(rx + rp)) { st = OR_PT_NONFINITE; break; }
+        int small = (rx < o->tol) && (rp < o->tol);
+        if (!o->fixed_iters && small) { st = OR_PT_CONVERGED; break; }
+        if (k >= o->max_iter) { st = small ? OR_PT_CONVERGED : OR_PT_MAXITER; break; }
+    }
+    double val = mix_value(pb, x, p, N, delta, wl, wr);
+    if (!isfinite(val) || !all_finite(x, (int)sz) || !all_finite(p, (int)sz)) st = OR_PT_NONFINITE;
+    *phi = val;
+    *iters = k;
+    *status = st;
+    if (xtraj) memcpy(xtraj, x, sz * sizeof(double));
+    if (ptraj) memcpy(ptraj, p, sz * sizeof(double));
+    free(x); free(p); free(z); free(xn); free(pn); free(v); free(ga); free(gb);
+}
+
+/* ------------------------------------------------------------------ */
 /* One query point: game path (Algorithm 3, Appendix A.2.1).          */
 /* ------------------------------------------------------------------ */
 
@@ -1040,12 +1147,15 @@ typedef struct {
 static int solve_batch(const or_problem *pb, long n, const double *x, const double *t, const int *N,
                        double sigma, double tau, double theta, double tol, int max_iter, int fixed_iters,
                        uint64_t seed, int N_max, const int64_t *ids, double *phi, int *iters, int *status,
-                       double *x_traj, double *p_traj, int n_threads, int hopf, const or_recipe *recipe)
+                       double *x_traj, double *p_traj, int n_threads, int hopf, const or_recipe *recipe,
+                       const double *mix)
 {
     int game = pb->d_y > 0;
     if (game && !(pb->H == OR_H_PURSUIT_EVASION && pb->g == OR_G_PAIR_DIST)) return -1;
     if (!game && (pb->H == OR_H_PURSUIT_EVASION || pb->g == OR_G_PAIR_DIST)) return -1;
     if (hopf && (game || pb->H != OR_H_CNORM || !(pb->g == OR_G_NORM || pb->g == OR_G_QUAD_SHIFT))) return -1;
+    if (mix && (game || hopf || recipe || pb->H != OR_H_CNORM || !(pb->g == OR_G_NORM || pb->g == OR_G_QUAD_SHIFT)))
+        return -1;
     or_opts o = { sigma, tau, theta, tol, max_iter, fixed_iters, seed, N_max, 1, 0, 0.0, 0.0 };
     if (recipe) {
         o.starts = recipe->starts;
@@ -1080,6 +1190,9 @@ static int solve_batch(const or_problem *pb, long n, const double *x, const doub
             solve_game_point(pb, &o, id, &x[i * d], ti, Ni, &phi[i], &iters[i], &status[i], xt_out, pt_out);
         else if (hopf)
             solve_hopf_point(pb, &o, id, &x[i * d], ti, Ni, &phi[i], &iters[i], &status[i], xt_out, pt_out);
+        else if (mix)
+            solve_mix_point(pb, &o, id, &x[i * d], ti, Ni, mix[0], mix[1], &phi[i], &iters[i], &status[i], xt_out,
+                            pt_out);
         else
             solve_control_point(pb, &o, id, &x[i * d], ti, Ni, &phi[i], &iters[i], &status[i], xt_out, pt_out);
     }
@@ -1093,7 +1206,7 @@ int or_solve(const or_problem *pb, long n, const double *x, const double *t, con
              double *x_traj, double *p_traj, int n_threads)
 {
     return solve_batch(pb, n, x, t, N, sigma, tau, theta, tol, max_iter, fixed_iters, seed, N_max, ids, phi, iters,
-                       status, x_traj, p_traj, n_threads, 0, NULL);
+                       status, x_traj, p_traj, n_threads, 0, NULL, NULL);
 }
 
 /* Hopf formulation (Algorithm 2), eikonal family with NORM or QUAD_SHIFT g. */
@@ -1103,7 +1216,7 @@ int or_solve_hopf(const or_problem *pb, long n, const double *x, const double *t
                   double *x_traj, double *p_traj, int n_threads)
 {
     return solve_batch(pb, n, x, t, N, sigma, tau, theta, tol, max_iter, fixed_iters, seed, N_max, ids, phi, iters,
-                       status, x_traj, p_traj, n_threads, 1, NULL);
+                       status, x_traj, p_traj, n_threads, 1, NULL, NULL);
 }
 
 /* Algorithm 1 with the robustness recipes (control path, tolerance mode). */
@@ -1114,5 +1227,17 @@ int or_solve_recipe(const or_problem *pb, long n, const double *x, const double 
 {
     or_recipe r = { starts, restarts, sigma_inc, value_tol };
     return solve_batch(pb, n, x, t, N, sigma, tau, theta, tol, max_iter, 0, seed, N_max, ids, phi, iters,
-                       status, x_traj, p_traj, n_threads, 0, &r);
+                       status, x_traj, p_traj, n_threads, 0, &r, NULL);
+}
+
+/* Weighted Euler discretisations (forward Euler wl = 1, wr = 0; trapezoid
+ * wl = wr = 1/2; backward Euler wl = 0, wr = 1), eikonal family. */
+int or_solve_mix(const or_problem *pb, long n, const double *x, const double *t, const int *N,
+                 double sigma, double tau, double theta, double tol, int max_iter, int fixed_iters,
+                 uint64_t seed, int N_max, const int64_t *ids, double wl, double wr, double *phi, int *iters,
+                 int *status, double *x_traj, double *p_traj, int n_threads)
+{
+    double w[2] = { wl, wr };
+    return solve_batch(pb, n, x, t, N, sigma, tau, theta, tol, max_iter, fixed_iters, seed, N_max, ids, phi, iters,
+                       status, x_traj, p_traj, n_threads, 0, NULL, w);
 }

@@ -62,6 +62,11 @@ def lib():
                                          ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
                                          ctypes.c_double, ctypes.c_double, D, I, I, D, D, ctypes.c_int]
         _lib.or_solve_recipe.restype = ctypes.c_int
+        _lib.or_solve_mix.argtypes = [P, ctypes.c_long, D, D, I, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.c_double, ctypes.c_double, D, I, I, D, D, ctypes.c_int]
+        _lib.or_solve_mix.restype = ctypes.c_int
         _lib.or_gstar.argtypes = [P, D]
         _lib.or_gstar.restype = ctypes.c_double
         _lib.or_hopf_prox1.argtypes = [P, D, D, ctypes.c_double, ctypes.c_double, D]
@@ -191,9 +196,13 @@ class Result:
     p_traj: np.ndarray | None
 
 
+# Hamiltonian weights (wl, wr) of the interval (j-1, j): H at its left and right node.
+DISC_WEIGHTS = {"be": (0.0, 1.0), "fe": (1.0, 0.0), "trap": (0.5, 0.5)}
+
+
 def solve(pb: Problem, x, t, N, *, sigma, tau, theta=1.0, tol=1e-8, max_iter=5000, fixed_iters=False,
           seed=0, N_max=None, ids=None, traj=False, threads=0, hopf=False, starts=1, restarts=0, sigma_inc=0.0,
-          value_tol=0.0) -> Result:
+          value_tol=0.0, disc="be") -> Result:
     """Run the oracle over a batch of points.
 
     x: [n, d]; t: [n]; N: [n] (intervals per point).  ids: each point's
@@ -203,7 +212,11 @@ def solve(pb: Problem, x, t, N, *, sigma, tau, theta=1.0, tol=1e-8, max_iter=500
     formulation (Algorithm 2; eikonal family with NORM or QUAD_SHIFT g); its
     trajectories have node 0 = 0.  starts / restarts / sigma_inc / value_tol
     select the robustness recipes (control path, tolerance mode): see the
-    C source's header comment.
+    C source's header comment.  disc selects the time discretisation of the
+    Lax path: "be" backward Euler (Algorithm 1), "fe" forward Euler,
+    "trap" the trapezoidal average of the two (eikonal family), or a pair
+    (wl, wr) of Hamiltonian weights; "be" is Algorithm 1 itself, any other
+    value runs the weighted-discretisation solver.
     """
     x = np.ascontiguousarray(x, np.float64).reshape(-1, pb.d)
     n = x.shape[0]
@@ -219,7 +232,16 @@ def solve(pb: Problem, x, t, N, *, sigma, tau, theta=1.0, tol=1e-8, max_iter=500
         ids = np.ascontiguousarray(ids, np.int64)
         idp = ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     I = ctypes.POINTER(ctypes.c_int)
-    if starts > 1 or restarts > 0 or value_tol > 0.0:
+    weights = DISC_WEIGHTS.get(disc, disc) if isinstance(disc, str) else tuple(disc)
+    if disc != "be":
+        if hopf or starts > 1 or restarts > 0 or value_tol > 0.0:
+            raise ValueError("oracle: the weighted discretisations are for the plain Lax control path")
+        wl, wr = (float(w) for w in weights)
+        rc = lib().or_solve_mix(pb.c, n, _dp(x), _dp(t), N.ctypes.data_as(I), sigma, tau, theta, tol,
+                                int(max_iter), int(bool(fixed_iters)), int(seed) & (2**64 - 1), int(N_max), idp,
+                                wl, wr, _dp(phi), iters.ctypes.data_as(I), status.ctypes.data_as(I),
+                                _dp(xt) if traj else None, _dp(pt) if traj else None, int(threads))
+    elif starts > 1 or restarts > 0 or value_tol > 0.0:
         if hopf or fixed_iters:
             raise ValueError("oracle: recipes are for the Lax control path in tolerance mode")
         rc = lib().or_solve_recipe(pb.c, n, _dp(x), _dp(t), N.ctypes.data_as(I), sigma, tau, theta, tol,

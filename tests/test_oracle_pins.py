@@ -808,3 +808,155 @@ def test_multi_start_keeps_the_lowest_converged_value(oracle_mod):
         brute = _shoot_min(step, g, xs[i], N, t, d, rng, starts=6, bounds_unit_ball=True)
         assert multi.phi[i] <= brute + 1e-6
         assert abs(multi.phi[i] - brute) < 1e-5
+
+
+# --------------------------------------------------------------------------
+# Forward Euler and trapezoidal discretisations (section 4.1, eq. disclaxFE;
+# the remark after Algorithm 1 on averaging the two Euler approximations)
+# --------------------------------------------------------------------------
+
+def _eik2(oracle_mod, alpha, a=(0.4, -0.3)):
+    a = np.asarray(a, float)
+    pb = oracle_mod.Problem(W.H_CNORM, W.G_QUAD_SHIFT, 2, 0, [alpha], np.concatenate([[1.0], a]))
+    c = lambda z: 1 + alpha * np.sin(z[0]) * np.cos(z[1])
+    g = lambda z: 0.5 * np.sum((z - a) ** 2) - 1.0
+    return pb, c, g, a
+
+
+def test_disc_backward_weights_reproduce_algorithm_1(oracle_mod):
+    """Weights (0, 1) are the backward-Euler saddle: the weighted solver
+    then reproduces Algorithm 1 bit for bit (values, stop iterations and
+    both trajectories)."""
+    w = W.cnorm10(16)
+    pb = oracle_mod.Problem(w.H, w.g, w.d, w.d_y, w.hp, w.gp)
+    kw = dict(sigma=w.sigma, tau=w.tau, tol=w.tol, max_iter=w.max_iter, seed=w.init_seed, traj=True)
+    a = oracle_mod.solve(pb, w.x, w.t, w.N, **kw)
+    b = oracle_mod.solve(pb, w.x, w.t, w.N, disc=(0.0, 1.0), **kw)
+    for u, v in [(a.phi, b.phi), (a.iters, b.iters), (a.x_traj, b.x_traj), (a.p_traj, b.p_traj)]:
+        assert np.array_equal(u, v)
+
+
+@pytest.mark.parametrize("disc", ["fe", "trap"])
+def test_disc_constant_speed_matches_closed_forms(oracle_mod, disc):
+    """c = 1: H does not depend on x, so every discretisation has the
+    Hopf-Lax value exactly: max(||x-a|| - t, 0)^2/2 - 1 for the shifted
+    quadratic g and max(||x|| - t, 0) - 1 for the norm g."""
+    w = W.cnorm10(24, alpha=0.0)
+    pb = oracle_mod.Problem(w.H, w.g, w.d, w.d_y, w.hp, w.gp)
+    r = oracle_mod.solve(pb, w.x, w.t, w.N, sigma=w.sigma, tau=w.tau, tol=1e-26, max_iter=40000,
+                         seed=w.init_seed, disc=disc)
+    exact = 0.5 * np.maximum(np.linalg.norm(w.x - w.gp[1:], axis=1) - w.t, 0) ** 2 - 1
+    assert np.all(r.status == 0)
+    assert np.max(np.abs(r.phi - exact)) < 1e-9
+    e = W.eikonal2d(32)
+    pe = oracle_mod.Problem(e.H, e.g, e.d, e.d_y, e.hp, e.gp)
+    r = oracle_mod.solve(pe, e.x, e.t, e.N, sigma=e.sigma, tau=e.tau, tol=1e-26, max_iter=30000,
+                         seed=e.init_seed, disc=disc)
+    assert np.max(np.abs(r.phi - (np.maximum(np.linalg.norm(e.x, axis=1) - e.t, 0) - 1))) < 1e-9
+
+
+def _transcription_min(c_eff, g, x, N, t, d, rng, starts=4):
+    """min g(x_0) over node positions x_0..x_{N-1} (x_N = x) with every step
+    inside its speed ball: ||x_j - x_{j-1}|| <= delta c_eff(x_{j-1}, x_j).
+    The p-maximisation of the eikonal saddle is exactly this constraint."""
+    delta = t / N
+
+    def nodes(Z):
+        return np.vstack([Z.reshape(N, d), x])
+    cons = [{"type": "ineq",
+             "fun": (lambda Z, j=j: delta * c_eff(nodes(Z)[j - 1], nodes(Z)[j])
+                     - np.linalg.norm(nodes(Z)[j] - nodes(Z)[j - 1]))} for j in range(1, N + 1)]
+    best = None
+    for _ in range(starts):
+        Z0 = np.tile(x, N) + 0.05 * rng.standard_normal(N * d)
+        r = minimize(lambda Z: g(nodes(Z)[0]), Z0, method="SLSQP", constraints=cons,
+                     options={"ftol": 1e-15, "maxiter": 3000})
+        if r.success and (best is None or r.fun < best):
+            best = r.fun
+    return best
+
+
+@pytest.mark.parametrize("disc", ["fe", "trap"])
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_disc_state_dependent_matches_direct_transcription(oracle_mod, disc, N):
+    """alpha != 0: the forward-Euler (trapezoid) value is the least g(x_0)
+    over discrete paths whose step j has length at most delta c(x_{j-1})
+    (delta (c(x_{j-1}) + c(x_j))/2), found by SLSQP over the node positions."""
+    rng = _rng(70 + N + (10 if disc == "trap" else 0))
+    pb, c, g, _ = _eik2(oracle_mod, 0.5)
+    wl, wr = oracle_mod.DISC_WEIGHTS[disc]
+    c_eff = lambda u, v: wl * c(u) + wr * c(v)
+    for _ in range(3):
+        x = rng.uniform(-1.5, 1.5, 2)
+        t = rng.uniform(0.2, 0.8)
+        r = oracle_mod.solve(pb, x[None], t, N, sigma=1.0, tau=0.25, tol=1e-26, max_iter=40000, seed=1, disc=disc)
+        assert r.status[0] == 0
+        best = _transcription_min(c_eff, g, x, N, t, 2, rng)
+        assert abs(r.phi[0] - best) < 1e-6, (r.phi[0], best)
+
+
+def _mix_lagrangian(xs, ps, c, g, delta, wl, wr):
+    """The weighted saddle's Lagrangian, written here from its definition:
+    g(x_0) + sum_j <p_j, x_j - x_{j-1}> - delta sum_j (wl c(x_{j-1}) + wr c(x_j)) |p_j|."""
+    L = g(xs[0])
+    for j in range(1, len(xs)):
+        L += ps[j] @ (xs[j] - xs[j - 1]) - delta * (wl * c(xs[j - 1]) + wr * c(xs[j])) * np.linalg.norm(ps[j])
+    return L
+
+
+@pytest.mark.parametrize("disc", ["fe", "trap"])
+def test_disc_fixed_point_is_stationary_for_independent_lagrangian(oracle_mod, disc):
+    """At convergence the free nodes x_0..x_{N-1} are stationary points of the
+    Lagrangian above (central differences), and every step x_j - x_{j-1}
+    equals delta c_eff p_j/|p_j| (optimality of the p_j with |p_j| > 0)."""
+    pb, c, g, a = _eik2(oracle_mod, 0.5)
+    wl, wr = oracle_mod.DISC_WEIGHTS[disc]
+    rng = _rng(80)
+    N, t, h = 6, 0.7, 1e-6
+    delta = t / N
+    for _ in range(2):
+        # far enough from the minimiser of g that every step is at full speed (p_j != 0)
+        u = rng.standard_normal(2)
+        x = a + 1.6 * u / np.linalg.norm(u)
+        r = oracle_mod.solve(pb, x[None], t, N, sigma=1.0, tau=0.25, tol=1e-28, max_iter=60000, seed=2,
+                             disc=disc, traj=True)
+        assert r.status[0] == 0
+        xs, ps = r.x_traj[0].copy(), r.p_traj[0]
+        assert np.array_equal(xs[N], x)
+        for j in range(N):
+            for i in range(2):
+                xp = xs.copy(); xp[j, i] += h
+                xm = xs.copy(); xm[j, i] -= h
+                dL = (_mix_lagrangian(xp, ps, c, g, delta, wl, wr) - _mix_lagrangian(xm, ps, c, g, delta, wl, wr)) / (2 * h)
+                assert abs(dL) < 1e-7, (j, i, dL)
+        for j in range(1, N + 1):
+            npj = np.linalg.norm(ps[j])
+            assert npj > 1e-3
+            step = delta * (wl * c(xs[j - 1]) + wr * c(xs[j])) * ps[j] / npj
+            assert np.max(np.abs((xs[j] - xs[j - 1]) - step)) < 1e-9
+
+
+def test_trapezoid_is_second_order_and_euler_first_order(oracle_mod):
+    """The trapezoid (average of the two Euler Hamiltonian sums) is the more
+    accurate rule: halving delta divides its error by about 4, while the
+    backward- and forward-Euler errors halve and bracket the limit from
+    opposite sides.  The limit is estimated by Richardson extrapolation of the
+    trapezoid at N = 64 and 128."""
+    pb, _, _, a = _eik2(oracle_mod, 0.5)
+    rng = _rng(90)
+    u = rng.standard_normal((3, 2))
+    x = a + 1.5 * u / np.linalg.norm(u, axis=1, keepdims=True)   # out of reach: the value depends on delta
+    t = 0.6
+    kw = dict(sigma=1.0, tau=0.25, tol=1e-26, max_iter=200000, seed=1)
+    v = {(dz, N): oracle_mod.solve(pb, x, t, N, disc=dz, **kw).phi for dz in ["be", "fe", "trap"] for N in [8, 16, 32]}
+    t64 = oracle_mod.solve(pb, x, t, 64, disc="trap", **kw).phi
+    t128 = oracle_mod.solve(pb, x, t, 128, disc="trap", **kw).phi
+    ref = t128 + (t128 - t64) / 3
+    moving = np.abs(v["be", 8] - ref) > 1e-4
+    assert moving.sum() == 3
+    for dz, lo, hi in [("be", 1.7, 2.3), ("fe", 1.7, 2.3), ("trap", 3.5, 4.5)]:
+        e = [np.abs(v[dz, N] - ref)[moving] for N in [8, 16, 32]]
+        assert np.all(lo < e[0] / e[1]) and np.all(e[0] / e[1] < hi), (dz, e)
+        assert np.all(lo < e[1] / e[2]) and np.all(e[1] / e[2] < hi), (dz, e)
+    assert np.all(np.sign(v["be", 16] - ref)[moving] == -np.sign(v["fe", 16] - ref)[moving])
+    assert np.all(np.abs(v["trap", 16] - ref)[moving] < 0.1 * np.abs(v["be", 16] - ref)[moving])
