@@ -126,12 +126,26 @@ enum {
     HJPD_NO_ORDER_HINT = 1u << 4, /* queue points of one N in input order; by default points that start
                                     far from the minimiser of g are handed out first (order only,
                                     results are unchanged) */
-    HJPD_HOPF = 1u << 5          /* Hopf formulation (section 4.1 eq. dischopf, Algorithm 2) instead of
+    HJPD_HOPF = 1u << 5,         /* Hopf formulation (section 4.1 eq. dischopf, Algorithm 2) instead of
                                     Lax (Algorithm 1): nodes 1..N, no x_0; the dual step at j = 1 is the
                                     joint prox of g* + delta H(x_1,.) (Appendix A.1.2); the value is
                                     -g*(p_1) + <p_N,x> + sum_{j<N} <p_j - p_{j+1}, x_j> - delta sum H.
                                     Built for H = CNORM with g = NORM or QUAD_SHIFT (control path);
                                     other pairs return HJPD_EUNSUPPORTED.  Trajectory node 0 is zero. */
+    HJPD_FORWARD_EULER = 1u << 6, /* forward-Euler discretisation of the Lax saddle (section 4.1, eq.
+                                    disclaxFE) instead of backward Euler.  With p_j the costate of the
+                                    interval (j-1, j), j = 1..N (eq. disclaxFE's p_{j-1}), the saddle is
+                                    g(x_0) + sum_j <p_j, x_j - x_{j-1}> - delta sum_j H(x_{j-1}, p_j):
+                                    H meets g at x_0, which takes a proximal-gradient step
+                                    prox_{tau g}(x_0 + tau p_1 + tau delta grad_x H(x_0, p_1)) (section 5.3).
+                                    Trajectories keep the layout of the backward-Euler path (p_0 = 0). */
+    HJPD_TRAPEZOID = 1u << 7      /* trapezoidal rule: the average of the backward- and forward-Euler
+                                    Hamiltonian sums (the remark after Algorithm 1), i.e.
+                                    - delta sum_j (H(x_{j-1}, p_j) + H(x_j, p_j)) / 2, second-order in
+                                    delta where both Euler rules are first-order.  HJPD_FORWARD_EULER and
+                                    HJPD_TRAPEZOID are built for H = CNORM with g = NORM or QUAD_SHIFT on the
+                                    persistent control path (not with HJPD_PLAIN, HJPD_HOPF or the recipes:
+                                    HJPD_EUNSUPPORTED); setting both is HJPD_EINVAL. */
 };
 
 typedef struct {
@@ -146,7 +160,8 @@ typedef struct {
     double tol;      /* tolerance on the squared residuals (> 0) */
     int max_iter;    /* iteration cap (>= 1); with HJPD_FIXED_ITERS the exact count */
     uint64_t seed;   /* random start: counter-based SplitMix64 stream */
-    unsigned flags;  /* HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_GRAPH | HJPD_TIMING | HJPD_NO_ORDER_HINT | HJPD_HOPF */
+    unsigned flags;  /* HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_GRAPH | HJPD_TIMING | HJPD_NO_ORDER_HINT | HJPD_HOPF
+                        | HJPD_FORWARD_EULER | HJPD_TRAPEZOID */
     int lanes_per_point; /* persistent tile override: lanes per point (8,16,32,64), 0 = tuned/default */
     int nodes_per_lane;  /* persistent tile override: time nodes per lane (1..4), 0 = tuned/default */
     /* Robustness recipes (section 6, remarks on slow points); all zero = plain

@@ -36,6 +36,12 @@ int fail(int code, const std::string& msg) {
 }
 
 bool has_recipe(const hjpd_desc& d) { return d.starts > 1 || d.restarts > 0 || d.value_tol > 0.0; }
+bool has_mix(const hjpd_desc& d) { return (d.flags & (HJPD_FORWARD_EULER | HJPD_TRAPEZOID)) != 0; }
+// Persistent kernel variant of a descriptor (validated: recipes and weighted
+// discretisations exclude each other).
+int kernel_variant(const hjpd_desc& d) {
+  return has_recipe(d) ? hjpd::kVarRecipe : (has_mix(d) ? hjpd::kVarMix : hjpd::kVarPlain);
+}
 
 #define HIP_OK(expr, what)                                                                 \
   do {                                                                                     \
@@ -268,7 +274,7 @@ int build_plan(hjpd_ctx* c, const int* tile_override_L, const int* tile_override
     }
     cl.L = t.L;
     cl.K = t.K;
-    cl.kern = lk(0, t.L, t.K, has_recipe(c->desc));
+    cl.kern = lk(0, t.L, t.K, kernel_variant(c->desc));
     if (!cl.kern) return fail(HJPD_EUNSUPPORTED, "tile not built");
     cl.grid = persistent_grid(c, cl.kern);
     c->plan.push_back(cl);
@@ -321,8 +327,11 @@ int validate_desc(const hjpd_desc* d) {
   if (d->H < 0 || d->H > 3) return fail(HJPD_EINVAL, "unknown Hamiltonian family");
   if (d->g < 0 || d->g > 3) return fail(HJPD_EINVAL, "unknown initial-cost family");
   if (d->dtype != HJPD_F32 && d->dtype != HJPD_F64) return fail(HJPD_EINVAL, "unknown dtype");
-  if (d->flags & ~unsigned(HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_GRAPH | HJPD_TIMING | HJPD_NO_ORDER_HINT | HJPD_HOPF))
+  if (d->flags & ~unsigned(HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_GRAPH | HJPD_TIMING | HJPD_NO_ORDER_HINT | HJPD_HOPF |
+                          HJPD_FORWARD_EULER | HJPD_TRAPEZOID))
     return fail(HJPD_EINVAL, "unknown flag bits");
+  if ((d->flags & HJPD_FORWARD_EULER) && (d->flags & HJPD_TRAPEZOID))
+    return fail(HJPD_EINVAL, "HJPD_FORWARD_EULER and HJPD_TRAPEZOID exclude each other");
   if (d->lanes_per_point != 0) {
     const int L = d->lanes_per_point, K = d->nodes_per_lane;
     if (!(L == 8 || L == 16 || L == 32 || L == 64) || K < 1 || K > 4)
@@ -340,6 +349,10 @@ int validate_desc(const hjpd_desc* d) {
     return fail(HJPD_EUNSUPPORTED, "recipes are built for the persistent Lax control path in tolerance mode");
   if ((d->flags & HJPD_HOPF) && !(d->H == HJPD_H_CNORM && !game && (d->g == HJPD_G_NORM || d->g == HJPD_G_QUAD_SHIFT)))
     return fail(HJPD_EUNSUPPORTED, "the Hopf formulation is built for CNORM with NORM or QUAD_SHIFT");
+  if (has_mix(*d) && (game || d->H != HJPD_H_CNORM || !(d->g == HJPD_G_NORM || d->g == HJPD_G_QUAD_SHIFT) ||
+                      (d->flags & (HJPD_PLAIN | HJPD_HOPF)) || has_recipe(*d)))
+    return fail(HJPD_EUNSUPPORTED,
+                "forward Euler and trapezoid are built for CNORM with NORM or QUAD_SHIFT on the persistent Lax path");
   if (d->H == HJPD_H_PURSUIT_EVASION) {
     if (!(game && d->g == HJPD_G_PAIR_DIST && d->d == 12 && d->d_y == 6))
       return fail(HJPD_EUNSUPPORTED, "pursuit-evasion needs d = 12, d_y = 6, g = PAIR_DIST");
@@ -419,6 +432,8 @@ int enqueue_solve(hjpd_ctx* c, int64_t n, const void* x, const void* t, const in
   a.d = D.d;
   a.gkind = D.g;
   a.hopf = (D.flags & HJPD_HOPF) ? 1 : 0;
+  a.wl = (D.flags & HJPD_FORWARD_EULER) ? T(1) : ((D.flags & HJPD_TRAPEZOID) ? T(0.5) : T(0));
+  a.wr = (D.flags & HJPD_FORWARD_EULER) ? T(0) : ((D.flags & HJPD_TRAPEZOID) ? T(0.5) : T(1));
   a.starts = D.starts > 1 ? D.starts : 1;
   a.restarts = D.restarts;
   a.sigma_inc = T(D.sigma_inc);
@@ -649,7 +664,7 @@ int hjpd_autotune(hjpd_ctx* c, int64_t n, const void* x, const void* t, const in
       std::vector<Cls> saved_plan = c->plan;
       c->plan[ci].L = tl.L;
       c->plan[ci].K = tl.K;
-      c->plan[ci].kern = lk(0, tl.L, tl.K, has_recipe(c->desc));
+      c->plan[ci].kern = lk(0, tl.L, tl.K, kernel_variant(c->desc));
       c->plan[ci].grid = persistent_grid(c, c->plan[ci].kern);
       double ms_total = 0;
       for (int rep = 0; rep < 2 && !rc; rep++) {

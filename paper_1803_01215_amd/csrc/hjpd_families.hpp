@@ -36,6 +36,10 @@ struct CNorm {
   static constexpr bool kZeroSafe = true;
   // Hopf formulation (Algorithm 2) available: closed-form conjugates of both g
   static constexpr bool kHopf = true;
+  // Weighted Euler discretisations (forward Euler, trapezoid) available: a
+  // weighted sum of c(x_{j-1})|p| and c(x_j)|p| is again a multiple of |p|,
+  // so its prox stays a shrink
+  static constexpr bool kMix = true;
 
   template <typename T> struct Par {
     T alpha;
@@ -93,6 +97,32 @@ struct CNorm {
     for (int i = 0; i < D; i++) v[i] *= scale;
     C.gc0 = P.alpha * c1 * c2;
     C.gc1 = -P.alpha * s1 * s2;
+  }
+
+  // Speed c(x) = 1 + alpha sin(x_1) cos(x_2) and the two non-zero
+  // components of its gradient.
+  template <typename T>
+  __device__ static void speed(const Par<T>& P, const T (&x)[D], T& c, T& gc0, T& gc1) {
+    T s1, c1, s2, c2;
+    M<T>::sincos(x[0], &s1, &c1);
+    M<T>::sincos(x[1], &s2, &c2);
+    c = T(1) + P.alpha * s1 * c2;
+    gc0 = P.alpha * c1 * c2;
+    gc1 = -P.alpha * s1 * s2;
+  }
+
+  // v <- shrink_2(v, mu) = v max(1 - mu/|v|, 0) (shrink_2(0) = 0); returns |v| after.
+  template <typename T>
+  __device__ static T shrink(T (&v)[D], T mu) {
+    T ss = T(0);
+#pragma unroll
+    for (int i = 0; i < D; i++) ss += v[i] * v[i];
+    const T rs = M<T>::rsqrt(ss);
+    const bool nz = ss > T(0);
+    const T scale = nz ? M<T>::fmax(T(1) - mu * rs, T(0)) : T(0);
+#pragma unroll
+    for (int i = 0; i < D; i++) v[i] *= scale;
+    return nz ? scale * (ss * rs) : T(0);
   }
 
   // Hopf formulation, dual step at j = 1 (Algorithm 2): the joint prox
@@ -221,6 +251,7 @@ struct Quad {
   static constexpr bool kGame = false;
   static constexpr bool kZeroSafe = false;
   static constexpr bool kHopf = false;
+  static constexpr bool kMix = false;
 
   template <typename T> struct Par {
     T m_inv, gz, clamp;
@@ -405,6 +436,7 @@ struct Pursuit {
   static constexpr bool kGame = true;
   static constexpr bool kZeroSafe = false;
   static constexpr bool kHopf = false;
+  static constexpr bool kMix = false;
 
   template <typename T> struct Par {
     T kappa, wP, wE, r;

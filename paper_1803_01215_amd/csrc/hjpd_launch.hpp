@@ -13,18 +13,27 @@ inline constexpr Tile kTiles[] = {{8, 1},  {16, 1}, {8, 2},  {32, 1}, {16, 2}, {
 inline constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 inline constexpr int kMaxCapacity = 256;
 
+// Persistent kernel variants.
+enum Variant { kVarPlain = 0, kVarRecipe = 1, kVarMix = 2 };
+
 template <typename T, class F, int L, int K>
-const void* group_ptr(int recipe) {
-  if constexpr (F::kGame)
-    return recipe ? nullptr : reinterpret_cast<const void*>(&k_group_game<T, F, L, K>);
-  else
-    return recipe ? reinterpret_cast<const void*>(&k_group_control_rec<T, F, L, K, true>)
-                  : reinterpret_cast<const void*>(&k_group_control<T, F, L, K>);
+const void* group_ptr(int variant) {
+  if constexpr (F::kGame) {
+    return variant == kVarPlain ? reinterpret_cast<const void*>(&k_group_game<T, F, L, K>) : nullptr;
+  } else {
+    if (variant == kVarRecipe) return reinterpret_cast<const void*>(&k_group_control_rec<T, F, L, K, true>);
+    if (variant == kVarMix) {
+      if constexpr (F::kMix) return reinterpret_cast<const void*>(&k_group_control_mix<T, F, L, K>);
+      else return nullptr;
+    }
+    return reinterpret_cast<const void*>(&k_group_control<T, F, L, K>);
+  }
 }
 
-// recipe != 0 selects the control kernel compiled with the robustness recipes.
+// variant: kVarPlain (Algorithm 1 / 2 / 3), kVarRecipe (control kernel with
+// the robustness recipes), kVarMix (weighted Euler discretisations).
 template <typename T, class F>
-const void* pick_kernel(int plain, int L, int K, int recipe) {
+const void* pick_kernel(int plain, int L, int K, int variant) {
   if (plain) {
     if constexpr (F::kGame)
       return reinterpret_cast<const void*>(&k_plain_game<T, F>);
@@ -32,7 +41,7 @@ const void* pick_kernel(int plain, int L, int K, int recipe) {
       return reinterpret_cast<const void*>(&k_plain_control<T, F>);
   }
 #define HJPD_TILE_CASE(LL, KK) \
-  if (L == LL && K == KK) return group_ptr<T, F, LL, KK>(recipe);
+  if (L == LL && K == KK) return group_ptr<T, F, LL, KK>(variant);
   HJPD_TILE_CASE(8, 1) HJPD_TILE_CASE(16, 1) HJPD_TILE_CASE(8, 2) HJPD_TILE_CASE(32, 1) HJPD_TILE_CASE(16, 2) HJPD_TILE_CASE(8, 4) HJPD_TILE_CASE(64, 1)
   HJPD_TILE_CASE(32, 2) HJPD_TILE_CASE(16, 4) HJPD_TILE_CASE(32, 3) HJPD_TILE_CASE(64, 2) HJPD_TILE_CASE(32, 4) HJPD_TILE_CASE(64, 3) HJPD_TILE_CASE(64, 4)
 #undef HJPD_TILE_CASE
@@ -43,7 +52,7 @@ const void* pick_kernel(int plain, int L, int K, int recipe) {
 
 // One lookup function per (family shape, dtype), defined in its own
 // translation unit so the instantiations compile in parallel.
-#define HJPD_DECLARE_LOOKUP(name) const void* hjpd_lookup_##name(int plain, int L, int K, int recipe);
+#define HJPD_DECLARE_LOOKUP(name) const void* hjpd_lookup_##name(int plain, int L, int K, int variant);
 HJPD_DECLARE_LOOKUP(cnorm2_f32)
 HJPD_DECLARE_LOOKUP(cnorm2_f64)
 HJPD_DECLARE_LOOKUP(cnorm3_f32)

@@ -20,6 +20,7 @@ HJPD_G_NORM, HJPD_G_QUAD_SHIFT, HJPD_G_PAIR_DIST, HJPD_G_QUAD_FORM = 0, 1, 2, 3
 HJPD_F32, HJPD_F64 = 0, 1
 HJPD_PERSISTENT, HJPD_PLAIN, HJPD_FIXED_ITERS, HJPD_GRAPH, HJPD_TIMING, HJPD_NO_ORDER_HINT, HJPD_HOPF = (
     0, 1, 2, 4, 8, 16, 32)
+HJPD_FORWARD_EULER, HJPD_TRAPEZOID = 64, 128
 
 EXPORTED = ["hjpd_create", "hjpd_solve_batch", "hjpd_value_grad", "hjpd_autotune", "hjpd_get_timing",
             "hjpd_destroy", "hjpd_last_error"]

@@ -33,18 +33,26 @@ def _need(t, name, dtype, numel=None):
         raise ValueError("%s must have %d elements, got %d" % (name, numel, t.numel()))
 
 
+_DISC_FLAGS = {"be": 0, "fe": C.HJPD_FORWARD_EULER, "trap": C.HJPD_TRAPEZOID}
+
+
 class Solver:
     """One hjpd context (problem families, dimension, dtype, step sizes)."""
 
     def __init__(self, *, d, H, g, N_max, sigma, tau, theta=1.0, tol=1e-6, max_iter=20000, seed=0, d_y=0,
                  dtype=torch.float32, plain=False, fixed_iters=False, graph=False, timing=False,
                  lanes_per_point=0, nodes_per_lane=0, order_hint=True, hopf=False, starts=1, restarts=0,
-                 sigma_inc=0.0, value_tol=0.0):
+                 sigma_inc=0.0, value_tol=0.0, disc="be"):
+        # disc: time discretisation of the Lax saddle, "be" backward Euler (Algorithm 1),
+        # "fe" forward Euler, "trap" trapezoid (eikonal family)
+        if disc not in _DISC_FLAGS:
+            raise ValueError("disc must be one of %s" % sorted(_DISC_FLAGS))
         self.dtype = dtype
         self.d, self.N_max = d, N_max
         flags = ((C.HJPD_PLAIN if plain else 0) | (C.HJPD_FIXED_ITERS if fixed_iters else 0)
                  | (C.HJPD_GRAPH if graph else 0) | (C.HJPD_TIMING if timing else 0)
-                 | (0 if order_hint else C.HJPD_NO_ORDER_HINT) | (C.HJPD_HOPF if hopf else 0))
+                 | (0 if order_hint else C.HJPD_NO_ORDER_HINT) | (C.HJPD_HOPF if hopf else 0)
+                 | _DISC_FLAGS[disc])
         self.desc = C.hjpd_desc(d=d, d_y=d_y, H=H, g=g, dtype=C.HJPD_F64 if dtype == torch.float64 else C.HJPD_F32,
                                 N_max=N_max, sigma=sigma, tau=tau, theta=theta, tol=tol, max_iter=max_iter,
                                 seed=seed & (2**64 - 1), flags=flags, lanes_per_point=lanes_per_point,

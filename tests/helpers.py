@@ -26,7 +26,8 @@ def traj_err(a, b, N):
 
 
 def gpu_solve(w: W.Workload, *, dtype="f32", plain=False, fixed_iters=None, max_iter=None, tol=None, traj=True,
-              graph=False, lanes_per_point=0, nodes_per_lane=0, x=None, t=None, N=None, timing=False, hopf=False):
+              graph=False, lanes_per_point=0, nodes_per_lane=0, x=None, t=None, N=None, timing=False, hopf=False,
+              disc="be"):
     import torch
 
     from paper_1803_01215_amd.solver import Solver
@@ -36,7 +37,7 @@ def gpu_solve(w: W.Workload, *, dtype="f32", plain=False, fixed_iters=None, max_
                tol=w.tol if tol is None else tol, max_iter=w.max_iter if max_iter is None else max_iter,
                seed=w.init_seed, dtype=td, plain=plain,
                fixed_iters=w.fixed_iters if fixed_iters is None else fixed_iters, graph=graph,
-               lanes_per_point=lanes_per_point, nodes_per_lane=nodes_per_lane, timing=timing, hopf=hopf)
+               lanes_per_point=lanes_per_point, nodes_per_lane=nodes_per_lane, timing=timing, hopf=hopf, disc=disc)
     dev = "cuda"
     xs = torch.tensor(w.x if x is None else x, dtype=td, device=dev).contiguous()
     ts = torch.tensor(w.t if t is None else t, dtype=td, device=dev).contiguous()
@@ -52,7 +53,8 @@ def gpu_solve(w: W.Workload, *, dtype="f32", plain=False, fixed_iters=None, max_
     return res
 
 
-def oracle_fixed(O, w: W.Workload, iters, *, traj=True, inputs_dtype="f64", threads=0, x_scale=None, hopf=False):
+def oracle_fixed(O, w: W.Workload, iters, *, traj=True, inputs_dtype="f64", threads=0, x_scale=None, hopf=False,
+                 disc="be"):
     """Oracle run with exactly iters[i] iterations at point i (points grouped
     by count).  Inputs are first rounded to the GPU run's precision so both
     sides see the same numbers; x_scale (optional) then multiplies x, for the
@@ -73,19 +75,19 @@ def oracle_fixed(O, w: W.Workload, iters, *, traj=True, inputs_dtype="f64", thre
         r = O.solve(pb, x[sel], t[sel], w.N[sel], sigma=float(_round(w.sigma, inputs_dtype)),
                     tau=float(_round(w.tau, inputs_dtype)), theta=w.theta, tol=float(_round(w.tol, inputs_dtype)),
                     max_iter=int(K), fixed_iters=True, seed=w.init_seed, N_max=w.N_max, ids=ids[sel], traj=traj,
-                    threads=threads, hopf=hopf)
+                    threads=threads, hopf=hopf, disc=disc)
         phi[sel] = r.phi; status[sel] = r.status; it[sel] = r.iters
         if traj:
             xt[sel] = r.x_traj; pt[sel] = r.p_traj
     return {"phi": phi, "iters": it, "status": status, "x_traj": xt, "p_traj": pt}
 
 
-def oracle_tol(O, w: W.Workload, *, inputs_dtype="f64", threads=0, traj=False, hopf=False):
+def oracle_tol(O, w: W.Workload, *, inputs_dtype="f64", threads=0, traj=False, hopf=False, disc="be"):
     pb = O.Problem(w.H, w.g, w.d, w.d_y, _round(w.hp, inputs_dtype), _round(w.gp, inputs_dtype))
     r = O.solve(pb, _round(w.x, inputs_dtype), _round(w.t, inputs_dtype), w.N,
                 sigma=float(_round(w.sigma, inputs_dtype)), tau=float(_round(w.tau, inputs_dtype)), theta=w.theta,
                 tol=float(_round(w.tol, inputs_dtype)), max_iter=w.max_iter, fixed_iters=w.fixed_iters,
-                seed=w.init_seed, N_max=w.N_max, ids=w.ids, traj=traj, threads=threads, hopf=hopf)
+                seed=w.init_seed, N_max=w.N_max, ids=w.ids, traj=traj, threads=threads, hopf=hopf, disc=disc)
     return {"phi": r.phi, "iters": r.iters, "status": r.status, "x_traj": r.x_traj, "p_traj": r.p_traj}
 
 
@@ -94,7 +96,7 @@ def _round(a, dt):
     return a.astype(np.float32).astype(np.float64) if dt == "f32" else a
 
 
-def well_conditioned(O, w: W.Workload, iters, base, dtype, tol, hopf=False):
+def well_conditioned(O, w: W.Workload, iters, base, dtype, tol, hopf=False, disc="be"):
     """Points whose oracle result is stable under a rounding-sized change of
     the inputs: relative 1e-15 for FP64 runs; 1e-6 for FP32 runs (FP32 unit
     roundoff 6e-8 accumulated over thousands of iterations), both signs.  A
@@ -107,7 +109,7 @@ def well_conditioned(O, w: W.Workload, iters, base, dtype, tol, hopf=False):
     traj = base.get("x_traj") is not None
     ok = np.ones(w.n, bool)
     for sgn in (1.0, -1.0):
-        r = oracle_fixed(O, w, iters, traj=traj, inputs_dtype=dtype, x_scale=1.0 + sgn * eps, hopf=hopf)
+        r = oracle_fixed(O, w, iters, traj=traj, inputs_dtype=dtype, x_scale=1.0 + sgn * eps, hopf=hopf, disc=disc)
         ok &= rel_err(r["phi"], base["phi"]) <= tol / 10
         if traj:
             ok &= traj_err(r["x_traj"], base["x_traj"], w.N) <= tol / 10

@@ -54,6 +54,7 @@ def _desc(**kw):
     dict(tol=0.0), dict(max_iter=0), dict(d=0), dict(N_max=0), dict(d_y=-1), dict(d_y=10), dict(dtype=7),
     dict(H=9), dict(g=9), dict(flags=1 << 10), dict(lanes_per_point=12, nodes_per_lane=1),
     dict(lanes_per_point=32, nodes_per_lane=5), dict(nodes_per_lane=2),
+    dict(flags=64 | 128),                                # forward Euler and trapezoid together
 ])
 def test_create_rejects_invalid_descriptors(lib, bad):
     from paper_1803_01215_amd import hjpd
@@ -73,6 +74,11 @@ def test_create_rejects_invalid_descriptors(lib, bad):
     dict(N_max=300),                                     # beyond the largest tile
     dict(H=1, d=12, flags=32),                           # Hopf: built for CNORM only
     dict(H=2, d=12, d_y=6, g=2, flags=32),               # no Hopf for the game path
+    dict(H=1, d=12, flags=64),                           # forward Euler: built for CNORM only
+    dict(H=2, d=12, d_y=6, g=2, flags=128),              # no trapezoid for the game path
+    dict(flags=64 | 1),                                  # no weighted discretisation on the plain kernel
+    dict(flags=128 | 32),                                # nor with the Hopf formulation
+    dict(flags=64, starts=3),                            # nor with the recipes
 ])
 def test_create_reports_unsupported(lib, unsup):
     from paper_1803_01215_amd import hjpd
@@ -103,7 +109,8 @@ def test_flag_values_match_header():
     """The binding's flag constants are the header's (shift expressions parsed)."""
     from paper_1803_01215_amd import hjpd
     src = open(HEADER).read()
-    for name in ["HJPD_PLAIN", "HJPD_FIXED_ITERS", "HJPD_GRAPH", "HJPD_TIMING", "HJPD_NO_ORDER_HINT", "HJPD_HOPF"]:
+    for name in ["HJPD_PLAIN", "HJPD_FIXED_ITERS", "HJPD_GRAPH", "HJPD_TIMING", "HJPD_NO_ORDER_HINT", "HJPD_HOPF",
+                 "HJPD_FORWARD_EULER", "HJPD_TRAPEZOID"]:
         m = re.search(name + r"\s*=\s*1u\s*<<\s*(\d+)", src)
         assert m, name
         assert getattr(hjpd, name) == 1 << int(m.group(1)), name

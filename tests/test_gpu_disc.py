@@ -1,0 +1,77 @@
+"""GPU parity of the forward-Euler and trapezoidal discretisations (section
+4.1, eq. disclaxFE, and the trapezoidal average of the two Euler rules)
+against the oracle's weighted-discretisation path, with the protocol of the
+Lax parity tests: the oracle is rerun for exactly the GPU's stop iteration per
+point and compared element by element (FP64 1e-9, FP32 1e-4 relative)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from helpers import gpu_solve
+from test_gpu_parity import _check
+
+pytestmark = pytest.mark.gpu
+
+DISCS = ["fe", "trap"]
+
+
+@pytest.mark.parametrize("disc", DISCS)
+def test_disc_eikonal2d_f64_matches_oracle_and_closed_form(oracle_mod, disc):
+    """c = 1: every discretisation has the Hopf-Lax value exactly."""
+    w = W.eikonal2d()
+    g = _check(oracle_mod, w, "f64", disc=disc)
+    assert np.all(g["status"] == 0)
+    exact = np.maximum(np.linalg.norm(w.x, axis=1) - w.t, 0) - 1
+    assert np.max(np.abs(g["phi"] - exact)) < 1e-6
+    assert np.all(g["p_traj"][:, 0, :] == 0)
+    assert np.array_equal(g["x_traj"][np.arange(w.n), w.N], w.x)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("disc", DISCS)
+def test_disc_cnorm10_matches_oracle(oracle_mod, disc, dtype):
+    w = W.cnorm10(300)  # several waves and a ragged last one
+    _check(oracle_mod, w, dtype, disc=disc)
+
+
+@pytest.mark.parametrize("tile", [(8, 4), (32, 1), (64, 1), (32, 3)])
+@pytest.mark.parametrize("disc", DISCS)
+def test_disc_cnorm10_tiles_match_oracle(oracle_mod, disc, tile):
+    """Tiles whose lane groups span a whole row or more (32, 64 lanes) move the
+    left node's speed and the right node's costate norm across rows."""
+    w = W.cnorm10(130)
+    _check(oracle_mod, w, "f32", lanes_per_point=tile[0], nodes_per_lane=tile[1], check_kstop=False, disc=disc)
+
+
+@pytest.mark.parametrize("disc", DISCS)
+def test_disc_small_and_ragged_N(oracle_mod, disc):
+    """N = 1 (node 0 is the only free node and meets H), N = 2, 3, and N
+    filling the tile exactly."""
+    w = W.cnorm10(64)
+    w.N = np.array([1, 2, 3, 17, 31, 32] * 10 + [32] * 4, dtype=np.int32)
+    _check(oracle_mod, w, "f64", check_kstop=False, disc=disc)
+
+
+@pytest.mark.parametrize("disc", DISCS)
+def test_disc_fixed_iterations(oracle_mod, disc):
+    """HJPD_FIXED_ITERS: exactly max_iter iterations at every point."""
+    w = W.cnorm10(96)
+    w.fixed_iters = True
+    g = _check(oracle_mod, w, "f64", max_iter=700, check_kstop=False, disc=disc)
+    assert np.all(g["iters"] == 700)
+
+
+def test_trapezoid_lies_between_the_euler_values_at_convergence():
+    """The three discretisations solve different saddles: at the same N the
+    converged backward- and forward-Euler values differ by O(delta), and the
+    trapezoid value, the average of their Hamiltonian sums, falls between them
+    at almost every point."""
+    w = W.cnorm10(512)
+    r = {d: gpu_solve(w, dtype="f64", traj=False, tol=1e-16, max_iter=20000, disc=d) for d in ["be", "fe", "trap"]}
+    ok = np.all([r[d]["status"] == 0 for d in r], axis=0)
+    assert ok.mean() > 0.95
+    lo = np.minimum(r["be"]["phi"], r["fe"]["phi"]) - 1e-7
+    hi = np.maximum(r["be"]["phi"], r["fe"]["phi"]) + 1e-7
+    between = (r["trap"]["phi"] >= lo) & (r["trap"]["phi"] <= hi)
+    assert between[ok].mean() > 0.98
+    assert np.median(np.abs(r["be"]["phi"] - r["fe"]["phi"])[ok]) > 1e-4

@@ -26,18 +26,18 @@ TOL = {"f64": 1e-9, "f32": 1e-4}
 
 
 def _check(O, w, dtype, *, plain=False, max_iter=None, lanes_per_point=0, nodes_per_lane=0, check_kstop=True,
-           traj=True, max_ill=0.0, converged_only=False, traj_tol=None, hopf=False):
+           traj=True, max_ill=0.0, converged_only=False, traj_tol=None, hopf=False, disc="be"):
     if max_iter is not None:
         w.max_iter = max_iter
     g = gpu_solve(w, dtype=dtype, plain=plain, lanes_per_point=lanes_per_point, nodes_per_lane=nodes_per_lane,
-                  traj=traj, hopf=hopf)
+                  traj=traj, hopf=hopf, disc=disc)
     print("[%s %s plain=%s tile=%s,%s] n=%d iters p50=%d max=%d status=%s" % (
         w.name, dtype, plain, lanes_per_point, nodes_per_lane, w.n, np.median(g["iters"]), g["iters"].max(),
         np.bincount(g["status"], minlength=4)), flush=True)
     assert np.all(g["status"] >= 0) and np.all(g["iters"] >= 1)
-    o = oracle_fixed(O, w, g["iters"], traj=traj, inputs_dtype=dtype, hopf=hopf)
+    o = oracle_fixed(O, w, g["iters"], traj=traj, inputs_dtype=dtype, hopf=hopf, disc=disc)
     tol = TOL[dtype]
-    ok = well_conditioned(O, w, g["iters"], o, dtype, tol, hopf=hopf)
+    ok = well_conditioned(O, w, g["iters"], o, dtype, tol, hopf=hopf, disc=disc)
     print("  ill-conditioned points screened: %d of %d" % ((~ok).sum(), w.n), flush=True)
     assert np.mean(~ok) <= max_ill
     if converged_only:
@@ -57,7 +57,7 @@ def _check(O, w, dtype, *, plain=False, max_iter=None, lanes_per_point=0, nodes_
     # from max-iter-at-k beyond the final residual)
     assert np.all((g["status"][ok] == 2) == (o["status"][ok] == 2))
     if check_kstop:
-        ot = oracle_tol(O, w, inputs_dtype=dtype, hopf=hopf)
+        ot = oracle_tol(O, w, inputs_dtype=dtype, hopf=hopf, disc=disc)
         dk = np.abs(ot["iters"].astype(np.int64) - g["iters"])
         frac = np.mean(dk <= 1)
         print("  k_stop |dk|<=1 fraction %.4f, max |dk| %d" % (frac, dk.max()), flush=True)
