@@ -308,6 +308,17 @@ def main():
                 "iters_p50": float(np.median(outh.iters.cpu().numpy()))}
     hopf.close()
 
+    # ---- forward-Euler and trapezoidal discretisations, same workload, tile and cap --------
+    disc_rec = {}
+    for disc in ("fe", "trap"):
+        sd = make(td, graph=True, lanes_per_point=16, nodes_per_lane=2, disc=disc)
+        outd = sd.alloc(n)
+        ms_d = timed_steps(sd, inp, outd, max(1, args.steps // 2), 1)
+        conv_d = int((outd.status.cpu().numpy() == 0).sum())
+        disc_rec[disc] = {"value": conv_d / (ms_d * 1e-3), "ms_per_step": ms_d, "converged": conv_d,
+                          "iters_p50": float(np.median(outd.iters.cpu().numpy()))}
+        sd.close()
+
     # ---- plain FP32 -------------------------------------------------------------------
     plain = make(td, plain=True)
     outp = plain.alloc(n)
@@ -368,6 +379,8 @@ def main():
         "fp64": fp64_rec,
         "long_cap": long_rec,
         "hopf": hopf_rec,
+        "forward_euler": disc_rec["fe"],
+        "trapezoid": disc_rec["trap"],
         "lintanh100": c5_rec,
         "configs": cfg_rec,
     }
