@@ -58,6 +58,21 @@
  *
  * For H = c(x)|p| the p-step is a shrink by sigma delta (wl c(x_{j-1}) + wr c(x_j)).
  *
+ * Game Hopf formulation (section 4.2, eq. discgenlaxhopfdghopf; Algorithm 4)
+ * for a separable convex-concave g(x,y) = e(x) + h(y), with e* the convex
+ * and h_* the concave conjugate:
+ *
+ *   phi ~ min_q max_p min_{x_1..x_{N-1}} max_{y_1..y_{N-1}}  -e*(p_1) - h_*(-q_1)
+ *         + <p_N, x> - <q_N, y> + sum_{j<N} (<p_j - p_{j+1}, x_j> - <q_j - q_{j+1}, y_j>)
+ *         - delta sum_j H(x_j, y_j, p_j, -q_j)
+ *
+ * built for Isaacs' game of section 6.3 (see the family's block below),
+ * together with Algorithm 3 for the same game so that the two formulations
+ * can be compared.  The costate updates follow section 6.3: a shrink for p
+ * after a gradient step on the smooth part, a gradient step for q (the
+ * linear and quadratic parts are kept exact); x and y take one descent /
+ * ascent step each, y after x.
+ *
  * Robustness recipes (section 6, remarks on slow points), control path:
  *  - on reaching the iteration cap, continue from the current iterate with
  *    sigma raised by sigma_inc and tau = sigma0 tau0 / sigma, at most
@@ -100,8 +115,8 @@
 #endif
 
 /* Family ids: identical numbering to the public header, restated here. */
-enum { OR_H_CNORM = 0, OR_H_QUADROTOR = 1, OR_H_PURSUIT_EVASION = 2, OR_H_LINEAR_TANH = 3 };
-enum { OR_G_NORM = 0, OR_G_QUAD_SHIFT = 1, OR_G_PAIR_DIST = 2, OR_G_QUAD_FORM = 3 };
+enum { OR_H_CNORM = 0, OR_H_QUADROTOR = 1, OR_H_PURSUIT_EVASION = 2, OR_H_LINEAR_TANH = 3, OR_H_ISAACS = 4 };
+enum { OR_G_NORM = 0, OR_G_QUAD_SHIFT = 1, OR_G_PAIR_DIST = 2, OR_G_QUAD_FORM = 3, OR_G_SADDLE_QUAD = 4 };
 enum { OR_PT_CONVERGED = 0, OR_PT_MAXITER = 1, OR_PT_NONFINITE = 2, OR_PT_BADINPUT = 3, OR_PT_VALUE_STALLED = 4 };
 enum { OR_ARR_X = 0, OR_ARR_P = 1, OR_ARR_Y = 2, OR_ARR_Q = 3 };
 
@@ -429,6 +444,78 @@ static void lt_grad_x(const double *hp, int d, const double *x, const double *p,
         double th = tanh(x[c]);
         g[c] = -(s + hp[0] * (1.0 - th * th) * p[c]);
     }
+}
+
+/* ------------------------------------------------------------------ */
+/* Isaacs' game (section 6.3, an unnamed example of Isaacs), d = 2:    */
+/* scalar x (first player) and y (second player), dynamics             */
+/* x' = 2 beta + sin(alpha), y' = -c(x,y) + cos(alpha), running cost 1, */
+/* so that H(x,y,p,q) = -c(x,y) q + 2|p| - sqrt(p^2 + q^2) - 1 (the    */
+/* section's closed form of the min-max over the controls).  Bump speed */
+/* c(x,y) = b0 (1 + b1 exp(-b2 ((x - cx)^2 + (y - cy)^2)));            */
+/* hp = [b0, b1, b2, cx, cy] (section 6.3: 2, 3, 4, 1, 1).  Initial    */
+/* cost g = e(x) + h(y), e(x) = (a x)^2/2 - c0 convex, h(y) = -(b y)^2/2 */
+/* concave; gp = [c0, a, b] (section 6.3: 1/2, 2.5, 1).                 */
+/* ------------------------------------------------------------------ */
+
+static double isaacs_c(const double *hp, double x, double y, double *cx, double *cy)
+{
+    double rx = x - hp[3], ry = y - hp[4];
+    double e = exp(-hp[2] * (rx * rx + ry * ry));
+    if (cx) *cx = hp[0] * hp[1] * e * (-2.0 * hp[2] * rx);
+    if (cy) *cy = hp[0] * hp[1] * e * (-2.0 * hp[2] * ry);
+    return hp[0] * (1.0 + hp[1] * e);
+}
+
+/* H(x, y, p, q) as defined above (callers pass the costate pair (p, -q)). */
+double or_isaacs_H(const double *hp, double x, double y, double p, double q)
+{
+    return -isaacs_c(hp, x, y, NULL, NULL) * q + 2.0 * fabs(p) - sqrt(p * p + q * q) - 1.0;
+}
+
+/* e*(p) = sup_x p x - e(x) = p^2/(2 a^2) + c0. */
+double or_saddle_estar(const double *gp, double p) { return p * p / (2.0 * gp[1] * gp[1]) + gp[0]; }
+
+/* h_*(q) = inf_y q y - h(y) = -q^2/(2 b^2). */
+double or_saddle_hstar(const double *gp, double q) { return -q * q / (2.0 * gp[2] * gp[2]); }
+
+double or_saddle_g(const double *gp, double x, double y)
+{
+    return 0.5 * gp[1] * gp[1] * x * x - gp[0] - 0.5 * gp[2] * gp[2] * y * y;
+}
+
+static double shrink1(double v, double lam)
+{
+    double a = fabs(v) - lam;
+    return a > 0.0 ? (v > 0.0 ? a : -a) : 0.0;
+}
+
+/* p-step at one node (maximisation over p of -delta H(x,y,p,-q) [- e*(p) at
+ * the Hopf node 1] - |p - v|^2/(2 sigma)): the term +delta sqrt(p^2 + q^2)
+ * is linearised at the current p (its gradient is taken as 0 at p = q = 0),
+ * then the rest is solved exactly: a shrink by 2 sigma delta, scaled by
+ * 1/(1 + sigma/a^2) when e* takes part. */
+double or_isaacs_dual_p(const double *gp, double p_old, double q_old, double v, double sigma, double delta,
+                        int first_hopf)
+{
+    double s = sqrt(p_old * p_old + q_old * q_old);
+    double vv = v + sigma * delta * (s > 0.0 ? p_old / s : 0.0);
+    if (!first_hopf) return shrink1(vv, 2.0 * sigma * delta);
+    double r = 1.0 / (1.0 + sigma / (gp[1] * gp[1]));
+    return shrink1(vv * r, 2.0 * sigma * delta * r);
+}
+
+/* q-step at one node (minimisation over q of -delta H(x,y,p,-q) [- h_*(-q)
+ * at the Hopf node 1] + |q - u|^2/(2 sigma), with the new p): -delta H is
+ * -delta c q + delta sqrt(p^2 + q^2) + const; the root term is linearised
+ * at the current q, the linear and quadratic terms are exact. */
+double or_isaacs_dual_q(const double *hp, const double *gp, double x, double y, double p_new, double q_old,
+                        double u, double sigma, double delta, int first_hopf)
+{
+    double s = sqrt(p_new * p_new + q_old * q_old);
+    double c = isaacs_c(hp, x, y, NULL, NULL);
+    double uu = u + sigma * delta * c - sigma * delta * (s > 0.0 ? q_old / s : 0.0);
+    return first_hopf ? uu / (1.0 + sigma / (gp[2] * gp[2])) : uu;
 }
 
 /* ------------------------------------------------------------------ */
@@ -1126,6 +1213,107 @@ static void solve_game_point(const or_problem *pb, const or_opts *o, long pt, co
 }
 
 /* ------------------------------------------------------------------ */
+/* One query point of Isaacs' game: Algorithm 4 (hopf = 1; no node 0,   */
+/* z_0 = w_0 = 0) or Algorithm 3 (hopf = 0; node 0 by the prox of e and */
+/* the prox of -h).  Blocks p, q, x, y in that order.                  */
+/* ------------------------------------------------------------------ */
+
+static void solve_isaacs_point(const or_problem *pb, const or_opts *o, long pt, const double *xt, double t, int N,
+                               int hopf, double *phi, int *iters, int *status, double *xtraj, double *ptraj)
+{
+    const double *hp = pb->hp, *gp = pb->gp;
+    double delta = t / N, sg = o->sigma, ta = o->tau, th = o->theta;
+    size_t n1 = (size_t)N + 1;
+    double *x = calloc(n1, 8), *y = calloc(n1, 8), *p = calloc(n1, 8), *q = calloc(n1, 8);
+    double *z = calloc(n1, 8), *w = calloc(n1, 8), *xn = calloc(n1, 8), *yn = calloc(n1, 8);
+    double *pn = calloc(n1, 8), *qn = calloc(n1, 8);
+    int j0 = hopf ? 1 : 0;
+
+    /* random start: free nodes near (x, y), costates near 0, node N = (x, y) */
+    for (int j = j0; j < N; j++) {
+        x[j] = xt[0] + or_init_noise(o->seed, pt, OR_ARR_X, j, 0);
+        y[j] = xt[1] + or_init_noise(o->seed, pt, OR_ARR_Y, j, 0);
+    }
+    x[N] = xt[0];
+    y[N] = xt[1];
+    for (int j = 1; j <= N; j++) {
+        p[j] = or_init_noise(o->seed, pt, OR_ARR_P, j, 0);
+        q[j] = or_init_noise(o->seed, pt, OR_ARR_Q, j, 0);
+    }
+    memcpy(z, x, n1 * 8);
+    memcpy(w, y, n1 * 8);
+
+    int k = 0, st = OR_PT_MAXITER;
+    for (;;) {
+        /* p and q, node by node (q uses the new p of its node) */
+        for (int j = 1; j <= N; j++) {
+            int first = hopf && j == 1;
+            double v = p[j] + sg * (z[j] - z[j - 1]);
+            pn[j] = or_isaacs_dual_p(gp, p[j], q[j], v, sg, delta, first);
+            double u = q[j] + sg * (w[j] - w[j - 1]);
+            qn[j] = or_isaacs_dual_q(hp, gp, x[j], y[j], pn[j], q[j], u, sg, delta, first);
+        }
+        /* x: descent; with H(x,y,p,-q) = c(x,y) q + ..., grad_x H = q dc/dx */
+        if (!hopf) xn[0] = (x[0] + ta * pn[1]) / (1.0 + ta * gp[1] * gp[1]);
+        for (int j = 1; j < N; j++) {
+            double cx;
+            isaacs_c(hp, x[j], y[j], &cx, NULL);
+            xn[j] = x[j] - ta * (pn[j] - pn[j + 1]) + ta * delta * qn[j] * cx;
+        }
+        xn[N] = x[N];
+        /* y: ascent, at the new x */
+        if (!hopf) yn[0] = (y[0] + ta * qn[1]) / (1.0 + ta * gp[2] * gp[2]);
+        for (int j = 1; j < N; j++) {
+            double cy;
+            isaacs_c(hp, xn[j], y[j], NULL, &cy);
+            yn[j] = y[j] - ta * (qn[j] - qn[j + 1]) - ta * delta * qn[j] * cy;
+        }
+        yn[N] = y[N];
+
+        double rx = 0, ry = 0, rp = 0, rq = 0;
+        for (int j = 0; j <= N; j++) {
+            rx += (xn[j] - x[j]) * (xn[j] - x[j]);
+            ry += (yn[j] - y[j]) * (yn[j] - y[j]);
+            rp += (pn[j] - p[j]) * (pn[j] - p[j]);
+            rq += (qn[j] - q[j]) * (qn[j] - q[j]);
+        }
+        for (int j = j0; j <= N; j++) {
+            z[j] = xn[j] + th * (xn[j] - x[j]);
+            w[j] = yn[j] + th * (yn[j] - y[j]);
+        }
+        memcpy(x, xn, n1 * 8); memcpy(y, yn, n1 * 8);
+        memcpy(p, pn, n1 * 8); memcpy(q, qn, n1 * 8);
+        k++;
+        if (!isfinite(rx + ry + rp + rq)) { st = OR_PT_NONFINITE; break; }
+        int small = rx < o->tol && ry < o->tol && rp < o->tol && rq < o->tol;
+        if (!o->fixed_iters && small) { st = OR_PT_CONVERGED; break; }
+        if (k >= o->max_iter) { st = small ? OR_PT_CONVERGED : OR_PT_MAXITER; break; }
+    }
+
+    double val;
+    if (hopf) {
+        /* -e*(p_1) - h_*(-q_1) + <p_N,x> - <q_N,y> + sum_{j<N} ((p_j - p_{j+1}) x_j - (q_j - q_{j+1}) y_j) */
+        val = -or_saddle_estar(gp, p[1]) - or_saddle_hstar(gp, -q[1]) + p[N] * xt[0] - q[N] * xt[1];
+        for (int j = 1; j < N; j++) val += (p[j] - p[j + 1]) * x[j] - (q[j] - q[j + 1]) * y[j];
+    } else {
+        val = or_saddle_g(gp, x[0], y[0]);
+        for (int j = 1; j <= N; j++) val += p[j] * (x[j] - x[j - 1]) - q[j] * (y[j] - y[j - 1]);
+    }
+    for (int j = 1; j <= N; j++) val -= delta * or_isaacs_H(hp, x[j], y[j], p[j], -q[j]);
+    if (!isfinite(val) || !all_finite(x, (int)n1) || !all_finite(y, (int)n1) || !all_finite(p, (int)n1) ||
+        !all_finite(q, (int)n1))
+        st = OR_PT_NONFINITE;
+    *phi = val;
+    *iters = k;
+    *status = st;
+    for (int j = 0; j <= N; j++) {
+        if (xtraj) { xtraj[2 * j] = x[j]; xtraj[2 * j + 1] = y[j]; }
+        if (ptraj) { ptraj[2 * j] = p[j]; ptraj[2 * j + 1] = q[j]; }
+    }
+    free(x); free(y); free(p); free(q); free(z); free(w); free(xn); free(yn); free(pn); free(qn);
+}
+
+/* ------------------------------------------------------------------ */
 /* Batch driver.                                                       */
 /* ------------------------------------------------------------------ */
 
@@ -1151,9 +1339,12 @@ static int solve_batch(const or_problem *pb, long n, const double *x, const doub
                        const double *mix)
 {
     int game = pb->d_y > 0;
-    if (game && !(pb->H == OR_H_PURSUIT_EVASION && pb->g == OR_G_PAIR_DIST)) return -1;
+    int isaacs = game && pb->H == OR_H_ISAACS && pb->g == OR_G_SADDLE_QUAD && pb->d == 2 && pb->d_y == 1;
+    if (game && !isaacs && !(pb->H == OR_H_PURSUIT_EVASION && pb->g == OR_G_PAIR_DIST)) return -1;
+    if (!game && (pb->H == OR_H_ISAACS || pb->g == OR_G_SADDLE_QUAD)) return -1;
     if (!game && (pb->H == OR_H_PURSUIT_EVASION || pb->g == OR_G_PAIR_DIST)) return -1;
-    if (hopf && (game || pb->H != OR_H_CNORM || !(pb->g == OR_G_NORM || pb->g == OR_G_QUAD_SHIFT))) return -1;
+    if (hopf && !isaacs && (game || pb->H != OR_H_CNORM || !(pb->g == OR_G_NORM || pb->g == OR_G_QUAD_SHIFT)))
+        return -1;
     if (mix && (game || hopf || recipe || pb->H != OR_H_CNORM || !(pb->g == OR_G_NORM || pb->g == OR_G_QUAD_SHIFT)))
         return -1;
     or_opts o = { sigma, tau, theta, tol, max_iter, fixed_iters, seed, N_max, 1, 0, 0.0, 0.0 };
@@ -1186,7 +1377,9 @@ static int solve_batch(const or_problem *pb, long n, const double *x, const doub
         double *xt_out = x_traj ? &x_traj[(size_t)i * (N_max + 1) * d] : NULL;
         double *pt_out = p_traj ? &p_traj[(size_t)i * (N_max + 1) * d] : NULL;
         long id = ids ? (long)ids[i] : i;
-        if (game)
+        if (isaacs)
+            solve_isaacs_point(pb, &o, id, &x[i * d], ti, Ni, hopf, &phi[i], &iters[i], &status[i], xt_out, pt_out);
+        else if (game)
             solve_game_point(pb, &o, id, &x[i * d], ti, Ni, &phi[i], &iters[i], &status[i], xt_out, pt_out);
         else if (hopf)
             solve_hopf_point(pb, &o, id, &x[i * d], ti, Ni, &phi[i], &iters[i], &status[i], xt_out, pt_out);

@@ -67,6 +67,16 @@ def lib():
                                       ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
                                       ctypes.c_double, ctypes.c_double, D, I, I, D, D, ctypes.c_int]
         _lib.or_solve_mix.restype = ctypes.c_int
+        for nm, at in [("or_isaacs_H", [D, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+                       ("or_saddle_estar", [D, ctypes.c_double]), ("or_saddle_hstar", [D, ctypes.c_double]),
+                       ("or_saddle_g", [D, ctypes.c_double, ctypes.c_double]),
+                       ("or_isaacs_dual_p", [D, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_int]),
+                       ("or_isaacs_dual_q", [D, D, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_int])]:
+            getattr(_lib, nm).argtypes = at
+            getattr(_lib, nm).restype = ctypes.c_double
         _lib.or_gstar.argtypes = [P, D]
         _lib.or_gstar.restype = ctypes.c_double
         _lib.or_hopf_prox1.argtypes = [P, D, D, ctypes.c_double, ctypes.c_double, D]

@@ -960,3 +960,208 @@ def test_trapezoid_is_second_order_and_euler_first_order(oracle_mod):
         assert np.all(lo < e[1] / e[2]) and np.all(e[1] / e[2] < hi), (dz, e)
     assert np.all(np.sign(v["be", 16] - ref)[moving] == -np.sign(v["fe", 16] - ref)[moving])
     assert np.all(np.abs(v["trap", 16] - ref)[moving] < 0.1 * np.abs(v["be", 16] - ref)[moving])
+
+
+# --------------------------------------------------------------------------
+# Game Hopf formulation (section 4.2, eq. discgenlaxhopfdghopf; Algorithm 4)
+# on Isaacs' game of section 6.3
+# --------------------------------------------------------------------------
+
+def _isaacs_pb(oracle_mod, hp=None, gp=None):
+    hp = W.ISAACS_PARAMS if hp is None else np.asarray(hp, float)
+    gp = W.ISAACS_G if gp is None else np.asarray(gp, float)
+    return oracle_mod.Problem(W.H_ISAACS, W.G_SADDLE_QUAD, 2, 1, hp, gp), hp, gp
+
+
+def _isaacs_c(hp, x, y):
+    return hp[0] * (1 + hp[1] * np.exp(-hp[2] * ((x - hp[3]) ** 2 + (y - hp[4]) ** 2)))
+
+
+def test_isaacs_H_is_the_min_max_over_controls(oracle_mod):
+    """H(x,y,p,q) = min over alpha in [0, 2 pi] of max over beta in [-1, 1] of
+    <(2 beta + sin alpha, -c(x,y) + cos alpha), (p, q)> - 1, evaluated by
+    brute force on the dynamics written here (section 6.3)."""
+    hp = W.ISAACS_PARAMS
+    lib = oracle_mod.lib()
+    rng = _rng(100)
+    al = np.linspace(0, 2 * np.pi, 200001)
+    for _ in range(20):
+        x, y, p, q = rng.uniform(-2, 2, 4)
+        c = _isaacs_c(hp, x, y)
+        inner = np.maximum(2 * p, -2 * p) + np.sin(al) * p + (-c + np.cos(al)) * q - 1   # max over beta = +-1
+        brute = inner.min()
+        assert abs(lib.or_isaacs_H(np.ascontiguousarray(hp).ctypes.data_as(oracle_mod.ctypes.POINTER(oracle_mod.ctypes.c_double)), x, y, p, q) - brute) < 1e-9
+
+
+def _dp_arr(oracle_mod, a):
+    return np.ascontiguousarray(a, float).ctypes.data_as(oracle_mod.ctypes.POINTER(oracle_mod.ctypes.c_double))
+
+
+def test_isaacs_conjugates_match_numerical_sup_and_inf(oracle_mod):
+    """e*(p) = sup_x p x - e(x) (convex conjugate), h_*(q) = inf_y q y - h(y)
+    (concave conjugate) for e(x) = (a x)^2/2 - c0, h(y) = -(b y)^2/2."""
+    from scipy.optimize import minimize_scalar
+    lib = oracle_mod.lib()
+    gp = np.array([0.5, 2.5, 1.3])
+    c0, a, b = gp
+    for v in np.linspace(-3, 3, 13):
+        sup = -minimize_scalar(lambda x: -(v * x - (0.5 * (a * x) ** 2 - c0))).fun
+        inf = minimize_scalar(lambda y: v * y + 0.5 * (b * y) ** 2).fun
+        assert abs(lib.or_saddle_estar(_dp_arr(oracle_mod, gp), v) - sup) < 1e-9
+        assert abs(lib.or_saddle_hstar(_dp_arr(oracle_mod, gp), v) - inf) < 1e-9
+
+
+def test_isaacs_costate_steps_solve_their_subproblems(oracle_mod):
+    """The p-step maximises -2 delta |p| + delta (the root term linearised at
+    the current p) [- e*(p) at the Hopf node 1] - |p - v|^2/(2 sigma); the
+    q-step minimises -delta c q + delta (root term linearised at the current
+    q) [+ q^2/(2 b^2) at node 1] + |q - u|^2/(2 sigma).  Both checked against
+    a dense grid search of those objectives, written here."""
+    lib = oracle_mod.lib()
+    hp, gp = W.ISAACS_PARAMS, W.ISAACS_G
+    a, b = gp[1], gp[2]
+    rng = _rng(101)
+    grid = np.linspace(-6, 6, 1200001)
+    for _ in range(12):
+        po, qo, v, u = rng.uniform(-1.5, 1.5, 4)
+        x, y = rng.uniform(-2, 2, 2)
+        sigma, delta = rng.choice([2.0, 10.0]), 0.005 * rng.integers(1, 4)
+        s = np.hypot(po, qo)
+        for first in (0, 1):
+            f = (-2 * delta * np.abs(grid) + delta * grid * po / s - (first * grid ** 2 / (2 * a * a))
+                 - (grid - v) ** 2 / (2 * sigma))
+            pg = grid[np.argmax(f)]
+            pn = lib.or_isaacs_dual_p(_dp_arr(oracle_mod, gp), po, qo, v, sigma, delta, first)
+            assert abs(pn - pg) < 2e-5
+            s2 = np.hypot(pn, qo)
+            c = _isaacs_c(hp, x, y)
+            fq = (-delta * c * grid + delta * grid * qo / s2 + first * grid ** 2 / (2 * b * b)
+                  + (grid - u) ** 2 / (2 * sigma))
+            qg = grid[np.argmin(fq)]
+            qn = lib.or_isaacs_dual_q(_dp_arr(oracle_mod, hp), _dp_arr(oracle_mod, gp), x, y, pn, qo, u, sigma,
+                                     delta, first)
+            assert abs(qn - qg) < 2e-5
+
+
+def test_isaacs_hopf_and_lax_reach_the_same_value(oracle_mod):
+    """Algorithm 4's saddle is Algorithm 3's with x_0 minimised and y_0
+    maximised out through e* and h_* (the derivation of eq.
+    discgenlaxhopfdghopf): the two iterations, which differ at node 0 and
+    node 1, converge to the same value."""
+    w = W.isaacs2(200)
+    pb = oracle_mod.Problem(w.H, w.g, w.d, w.d_y, w.hp, w.gp)
+    kw = dict(sigma=w.sigma, tau=w.tau, tol=1e-22, max_iter=60000, seed=w.init_seed, ids=w.ids)
+    h = oracle_mod.solve(pb, w.x, w.t, w.N, hopf=True, **kw)
+    l = oracle_mod.solve(pb, w.x, w.t, w.N, **kw)
+    ok = (h.status == 0) & (l.status == 0)
+    assert ok.mean() > 0.97
+    assert np.max(np.abs(h.phi - l.phi)[ok]) < 1e-9
+
+
+def _minmax_pq(f, lo=-20.0, hi=20.0):
+    """min over q of max over p of f(p, q) for scalar p, q: dense grids, then
+    bounded refinement around the grid optimum at each level.  The range
+    covers the optimal costates of the grid (|p| <= a^2 |x| ~ 19)."""
+    from scipy.optimize import minimize_scalar
+    pg = np.linspace(lo, hi, 16001)
+
+    def inner(q):
+        k = int(np.argmax(f(pg, q)))
+        a, b = pg[max(k - 1, 0)], pg[min(k + 1, len(pg) - 1)]
+        r = minimize_scalar(lambda p: -f(p, q), bounds=(a, b), method="bounded", options={"xatol": 1e-12})
+        return -r.fun
+    qg = np.linspace(lo, hi, 1601)
+    vals = np.array([inner(q) for q in qg])
+    k = int(np.argmin(vals))
+    r = minimize_scalar(inner, bounds=(qg[max(k - 1, 0)], qg[min(k + 1, len(qg) - 1)]), method="bounded",
+                        options={"xatol": 1e-12})
+    return r.fun
+
+
+def test_isaacs_single_interval_matches_brute_force_min_max(oracle_mod):
+    """N = 1: no free nodes, and the value is min over q of max over p of
+    -e*(p) - h_*(-q) + p x - q y - delta H(x, y, p, -q), found here by nested
+    scalar searches."""
+    pb, hp, gp = _isaacs_pb(oracle_mod)
+    c0, a, b = gp
+    rng = _rng(102)
+    for _ in range(6):
+        x, y = rng.uniform(-2.5, 2.5, 2)
+        t = float(rng.choice([0.025, 0.05, 0.1]))
+        c = _isaacs_c(hp, x, y)
+        f = lambda p, q: (-(p * p / (2 * a * a) + c0) + q * q / (2 * b * b) + p * x - q * y
+                          - t * (c * q + 2 * np.abs(p) - np.sqrt(p * p + q * q) - 1))
+        r = oracle_mod.solve(pb, np.array([[x, y]]), t, 1, sigma=2.0, tau=0.125, tol=1e-26, max_iter=60000, seed=3,
+                             hopf=True)
+        assert r.status[0] == 0
+        assert abs(r.phi[0] - _minmax_pq(f)) < 1e-7, (x, y, t)
+
+
+def test_isaacs_state_independent_speed_matches_the_hopf_formula(oracle_mod):
+    """Constant speed (b1 = 0): stationarity in every free x_j and y_j makes
+    all p_j and all q_j equal, so the discrete value is the game Hopf formula
+    min_q max_p -e*(p) - h_*(-q) + p x - q y - t H(p, -q) for any N."""
+    pb, hp, gp = _isaacs_pb(oracle_mod, hp=[2.0, 0.0, 4.0, 1.0, 1.0])
+    c0, a, b = gp
+    rng = _rng(103)
+    for _ in range(4):
+        x, y = rng.uniform(-2.5, 2.5, 2)
+        t, N = 0.1, 10
+        f = lambda p, q: (-(p * p / (2 * a * a) + c0) + q * q / (2 * b * b) + p * x - q * y
+                          - t * (2.0 * q + 2 * np.abs(p) - np.sqrt(p * p + q * q) - 1))
+        r = oracle_mod.solve(pb, np.array([[x, y]]), t, N, sigma=2.0, tau=0.125, tol=1e-26, max_iter=80000, seed=4,
+                             hopf=True, traj=True)
+        assert r.status[0] == 0
+        assert abs(r.phi[0] - _minmax_pq(f)) < 1e-7
+        assert np.ptp(r.p_traj[0, 1:, 0]) < 1e-9 and np.ptp(r.p_traj[0, 1:, 1]) < 1e-9
+
+
+def _isaacs_lagrangian(xs, ys, ps, qs, x, y, hp, gp, delta):
+    """Eq. discgenlaxhopfdghopf's objective, written here: nodes 1..N-1 free,
+    costates 1..N."""
+    c0, a, b = gp
+    N = len(ps) - 1
+    L = -(ps[1] ** 2 / (2 * a * a) + c0) + qs[1] ** 2 / (2 * b * b) + ps[N] * x - qs[N] * y
+    for j in range(1, N):
+        L += (ps[j] - ps[j + 1]) * xs[j] - (qs[j] - qs[j + 1]) * ys[j]
+    for j in range(1, N + 1):
+        c = _isaacs_c(hp, xs[j], ys[j])
+        L -= delta * (c * qs[j] + 2 * abs(ps[j]) - np.hypot(ps[j], qs[j]) - 1)
+    return L
+
+
+def test_isaacs_fixed_point_is_stationary_for_independent_lagrangian(oracle_mod):
+    """At convergence every free node and every q_j is a stationary point of
+    the objective above, and every p_j either is (p_j != 0) or satisfies the
+    subgradient condition of the 2 delta |p| kink (p_j = 0)."""
+    pb, hp, gp = _isaacs_pb(oracle_mod)
+    rng = _rng(104)
+    N, t, h = 10, 0.05, 1e-6
+    delta = t / N
+    for _ in range(3):
+        x, y = rng.uniform(-2.5, 2.5, 2)
+        r = oracle_mod.solve(pb, np.array([[x, y]]), t, N, sigma=2.0, tau=0.125, tol=1e-28, max_iter=80000, seed=5,
+                             hopf=True, traj=True)
+        assert r.status[0] == 0
+        xs, ys = r.x_traj[0, :, 0].copy(), r.x_traj[0, :, 1].copy()
+        ps, qs = r.p_traj[0, :, 0].copy(), r.p_traj[0, :, 1].copy()
+        assert xs[N] == x and ys[N] == y
+
+        def d(arr, j):
+            a0 = arr[j]
+            arr[j] = a0 + h; fp = _isaacs_lagrangian(xs, ys, ps, qs, x, y, hp, gp, delta)
+            arr[j] = a0 - h; fm = _isaacs_lagrangian(xs, ys, ps, qs, x, y, hp, gp, delta)
+            arr[j] = a0
+            return (fp - fm) / (2 * h)
+        for j in range(1, N):
+            assert abs(d(xs, j)) < 1e-7 and abs(d(ys, j)) < 1e-7
+        for j in range(1, N + 1):
+            assert abs(d(qs, j)) < 1e-7
+            if abs(ps[j]) > 1e-6:
+                assert abs(d(ps, j)) < 1e-7
+            else:
+                # the smooth part's slope lies inside the kink's subdifferential [-2 delta, 2 delta]
+                p0 = ps[j]; ps[j] = 0.0
+                smooth = d(ps, j)  # central difference across the kink cancels the |p| term
+                ps[j] = p0
+                assert abs(smooth) <= 2 * delta + 1e-7

@@ -4,7 +4,7 @@ This module only draws inputs (query points, horizons, step counts and
 problem parameters) from NumPy's PCG64 generator.  It holds none of the
 method's arithmetic, so both the GPU path and the oracle may use it.
 
-Five workloads:
+Six workloads:
   eikonal2d   2-D eikonal H = ||p||, g = ||x|| - 1, t = 1, N = 16, 256 points,
               x ~ U[-2,2]^2 (section 6.1 family, closed form known).
   cnorm10     d = 10, H = c(x)||p||, c = 1 + 0.5 sin(x1) cos(x2),
@@ -20,6 +20,11 @@ Five workloads:
   lintanh100  d = 100, H_c = <p, Ax + 0.1 tanh x> - ||p||^2/2, A ~ N(0,1/d),
               g = x^T Q x / 2, Q = M M^T/d + 0.5 I, x ~ N(0,I), t = 1, N = 50,
               16,384 points, 500 fixed iterations (differentiation workload).
+  isaacs2     Isaacs' game of section 6.3 with the convex-concave initial cost:
+              x, y scalars, H = -c(x,y) q + 2|p| - sqrt(p^2+q^2) - 1, bump
+              speed c, g = (2.5 x)^2/2 - 1/2 - y^2/2; the section's 73 x 73 grid
+              on [-3,3]^2 at t = 0.025, 0.05, 0.075, 0.1 (delta = 0.005),
+              21,316 points (game Hopf formulation, Algorithm 4).
 """
 from __future__ import annotations
 
@@ -29,8 +34,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 # Family ids (same numbering as the public C header).
-H_CNORM, H_QUADROTOR, H_PURSUIT_EVASION, H_LINEAR_TANH = 0, 1, 2, 3
-G_NORM, G_QUAD_SHIFT, G_PAIR_DIST, G_QUAD_FORM = 0, 1, 2, 3
+H_CNORM, H_QUADROTOR, H_PURSUIT_EVASION, H_LINEAR_TANH, H_ISAACS = 0, 1, 2, 3, 4
+G_NORM, G_QUAD_SHIFT, G_PAIR_DIST, G_QUAD_FORM, G_SADDLE_QUAD = 0, 1, 2, 3, 4
 
 SEED_BASE = 1803 * 10
 
@@ -144,8 +149,36 @@ def lintanh100(n: int = 16384, eps: float = 0.1) -> Workload:
                     init_seed=SEED_BASE + 104, extra={"A": A, "Q": Q})
 
 
+# Isaacs' game of section 6.3: bump speed c = b0 (1 + b1 exp(-b2 |(x,y) - (cx,cy)|^2)) and the
+# convex-concave initial cost (a x)^2/2 - c0 - (b y)^2/2.
+ISAACS_PARAMS = np.array([2.0, 3.0, 4.0, 1.0, 1.0])   # b0, b1, b2, cx, cy
+ISAACS_G = np.array([0.5, 2.5, 1.0])                   # c0, a, b
+
+
+def isaacs2(n: int | None = None, mesh: float = 1.0 / 12.0) -> Workload:
+    """Section 6.3's grid: [-3,3]^2 with spacing 1/12 (73 x 73 points) at the
+    four times 0.025, 0.05, 0.075, 0.1 with delta = 0.005 (N = 5, 10, 15, 20),
+    times major.  n (optional) keeps a seeded random subset of that many
+    points, in grid order."""
+    g = np.arange(-3.0, 3.0 + 0.5 * mesh, mesh)
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1)
+    times = np.array([0.025, 0.05, 0.075, 0.1])
+    x = np.tile(xy, (len(times), 1))
+    t = np.repeat(times, len(xy))
+    N = np.round(t / 0.005).astype(np.int32)
+    ids = np.arange(len(x))
+    if n is not None and n < len(x):
+        keep = np.sort(_rng(5).choice(len(x), n, replace=False))
+        x, t, N, ids = x[keep], t[keep], N[keep], ids[keep]
+    sigma = 2.0
+    return Workload("isaacs2", 5, H_ISAACS, G_SADDLE_QUAD, 2, 1, len(x), 20, "f32", sigma, 0.25 / sigma, 1.0,
+                    1e-8, 20000, False, x, t, N, ISAACS_PARAMS.copy(), ISAACS_G.copy(), init_seed=SEED_BASE + 105,
+                    extra={"ids": ids})
+
+
 ALL = {"eikonal2d": eikonal2d, "cnorm10": cnorm10, "quadrotor12": quadrotor12, "pursuit12": pursuit12,
-       "lintanh100": lintanh100}
+       "lintanh100": lintanh100, "isaacs2": isaacs2}
 
 
 def get(name: str, n: int | None = None) -> Workload:
