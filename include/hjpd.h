@@ -99,8 +99,18 @@ enum {
  *                        dynamics A x + eps tanh x + u, cost |u|^2/2).
  *                        h_params = [eps, A (d*d, row-major)].  float32,
  *                        d in {16, 32, 100, 128}, N_max <= 64.
+ *  HJPD_H_ISAACS         Isaacs' game of section 6.3, d = 2, d_y = 1 (scalar
+ *                        players x and y): x' = 2 beta + sin(alpha),
+ *                        y' = -c(x,y) + cos(alpha), running cost 1, so
+ *                        H(x,y,p,q) = -c(x,y) q + 2|p| - sqrt(p^2 + q^2) - 1
+ *                        (costate (p,-q) in the game formulation), bump speed
+ *                        c = b0 (1 + b1 exp(-b2 |(x,y) - (cx,cy)|^2)).
+ *                        h_params = [b0, b1, b2, cx, cy].  Game Hopf
+ *                        formulation only (HJPD_HOPF, Algorithm 4), with
+ *                        g = HJPD_G_SADDLE_QUAD; persistent kernel.
  */
-enum { HJPD_H_CNORM = 0, HJPD_H_QUADROTOR = 1, HJPD_H_PURSUIT_EVASION = 2, HJPD_H_LINEAR_TANH = 3 };
+enum { HJPD_H_CNORM = 0, HJPD_H_QUADROTOR = 1, HJPD_H_PURSUIT_EVASION = 2, HJPD_H_LINEAR_TANH = 3,
+       HJPD_H_ISAACS = 4 };
 
 /*
  * Initial-cost families g (g_params: device array of the context's dtype).
@@ -109,10 +119,15 @@ enum { HJPD_H_CNORM = 0, HJPD_H_QUADROTOR = 1, HJPD_H_PURSUIT_EVASION = 2, HJPD_
  *  HJPD_G_PAIR_DIST   g = ||r_P - r_E||_2 - r (games; positions are the first
  *                     three coordinates of each block).   g_params = [r]
  *  HJPD_G_QUAD_FORM   g = x^T Q_s x / 2, Q_s = (Q + Q^T)/2. g_params = [Q (d*d)]
+ *  HJPD_G_SADDLE_QUAD g(x,y) = e(x) + h(y), e = (a x)^2/2 - c0 convex,
+ *                     h = -(b y)^2/2 concave (games, scalar players); the
+ *                     game Hopf formulation uses e*(p) = p^2/(2a^2) + c0 and
+ *                     h_*(q) = -q^2/(2b^2).       g_params = [c0, a, b]
  * Supported pairs: CNORM with NORM or QUAD_SHIFT; QUADROTOR with QUAD_SHIFT;
- * PURSUIT_EVASION with PAIR_DIST; LINEAR_TANH with QUAD_FORM.
+ * PURSUIT_EVASION with PAIR_DIST; LINEAR_TANH with QUAD_FORM; ISAACS with
+ * SADDLE_QUAD.
  */
-enum { HJPD_G_NORM = 0, HJPD_G_QUAD_SHIFT = 1, HJPD_G_PAIR_DIST = 2, HJPD_G_QUAD_FORM = 3 };
+enum { HJPD_G_NORM = 0, HJPD_G_QUAD_SHIFT = 1, HJPD_G_PAIR_DIST = 2, HJPD_G_QUAD_FORM = 3, HJPD_G_SADDLE_QUAD = 4 };
 
 enum { HJPD_F32 = 0, HJPD_F64 = 1 };
 
@@ -131,7 +146,11 @@ enum {
                                     joint prox of g* + delta H(x_1,.) (Appendix A.1.2); the value is
                                     -g*(p_1) + <p_N,x> + sum_{j<N} <p_j - p_{j+1}, x_j> - delta sum H.
                                     Built for H = CNORM with g = NORM or QUAD_SHIFT (control path);
-                                    other pairs return HJPD_EUNSUPPORTED.  Trajectory node 0 is zero. */
+                                    for H = ISAACS it selects the game Hopf formulation (section 4.2
+                                    eq. discgenlaxhopfdghopf, Algorithm 4): value -e*(p_1) - h_*(-q_1)
+                                    + <p_N,x> - <q_N,y> + sum_{j<N} (<p_j - p_{j+1}, x_j>
+                                    - <q_j - q_{j+1}, y_j>) - delta sum H(x_j, y_j, p_j, -q_j).
+                                    Other pairs return HJPD_EUNSUPPORTED.  Trajectory node 0 is zero. */
     HJPD_FORWARD_EULER = 1u << 6, /* forward-Euler discretisation of the Lax saddle (section 4.1, eq.
                                     disclaxFE) instead of backward Euler.  With p_j the costate of the
                                     interval (j-1, j), j = 1..N (eq. disclaxFE's p_{j-1}), the saddle is

@@ -30,6 +30,7 @@ INSTANCES = [
     ("cnorm10_f32", "CNorm<10>", "float"), ("cnorm10_f64", "CNorm<10>", "double"),
     ("quad_f32", "Quad", "float"), ("quad_f64", "Quad", "double"),
     ("pursuit_f32", "Pursuit", "float"), ("pursuit_f64", "Pursuit", "double"),
+    ("isaacs_f32", "Isaacs", "float"), ("isaacs_f64", "Isaacs", "double"),
 ]
 
 

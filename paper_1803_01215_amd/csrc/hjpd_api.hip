@@ -63,8 +63,9 @@ __global__ void k_queue_zero(int32_t* a, int n) {
 // queue hands out far points first and the slow ones do not start last
 // (longest-expected-first scheduling; order only, results are unchanged).
 // The hint is the distance to the minimiser of g (QUAD_SHIFT: ||x - a||;
-// NORM: ||x||; PAIR_DIST: ||r_P - r_E||), quantised on a log scale into
-// kHintBuckets buckets.
+// NORM: ||x||; PAIR_DIST: ||r_P - r_E||; SADDLE_QUAD: ||(x, y)||, the
+// distance to its saddle point), quantised on a log scale into kHintBuckets
+// buckets.
 constexpr int kHintBuckets = 16;
 enum : int { kHintNone = 0, kHintShift = 1, kHintNorm = 2, kHintPair = 3 };
 
@@ -231,6 +232,7 @@ Lookup lookup_for(const hjpd_desc& d) {
   if (d.H == HJPD_H_QUADROTOR && d.d == 12 && d.d_y == 0) return f64 ? hjpd_lookup_quad_f64 : hjpd_lookup_quad_f32;
   if (d.H == HJPD_H_PURSUIT_EVASION && d.d == 12 && d.d_y == 6)
     return f64 ? hjpd_lookup_pursuit_f64 : hjpd_lookup_pursuit_f32;
+  if (d.H == HJPD_H_ISAACS && d.d == 2 && d.d_y == 1) return f64 ? hjpd_lookup_isaacs_f64 : hjpd_lookup_isaacs_f32;
   return nullptr;
 }
 
@@ -324,8 +326,8 @@ int validate_desc(const hjpd_desc* d) {
   if (d->max_iter < 1) return fail(HJPD_EINVAL, "max_iter must be >= 1");
   if (d->N_max < 1) return fail(HJPD_EINVAL, "N_max must be >= 1");
   if (d->N_max > 1023) return fail(HJPD_EINVAL, "N_max must be <= 1023");
-  if (d->H < 0 || d->H > 3) return fail(HJPD_EINVAL, "unknown Hamiltonian family");
-  if (d->g < 0 || d->g > 3) return fail(HJPD_EINVAL, "unknown initial-cost family");
+  if (d->H < 0 || d->H > 4) return fail(HJPD_EINVAL, "unknown Hamiltonian family");
+  if (d->g < 0 || d->g > 4) return fail(HJPD_EINVAL, "unknown initial-cost family");
   if (d->dtype != HJPD_F32 && d->dtype != HJPD_F64) return fail(HJPD_EINVAL, "unknown dtype");
   if (d->flags & ~unsigned(HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_GRAPH | HJPD_TIMING | HJPD_NO_ORDER_HINT | HJPD_HOPF |
                           HJPD_FORWARD_EULER | HJPD_TRAPEZOID))
@@ -347,8 +349,9 @@ int validate_desc(const hjpd_desc* d) {
   const bool game = d->d_y > 0;
   if (has_recipe(*d) && (game || d->H == HJPD_H_LINEAR_TANH || (d->flags & (HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_HOPF))))
     return fail(HJPD_EUNSUPPORTED, "recipes are built for the persistent Lax control path in tolerance mode");
-  if ((d->flags & HJPD_HOPF) && !(d->H == HJPD_H_CNORM && !game && (d->g == HJPD_G_NORM || d->g == HJPD_G_QUAD_SHIFT)))
-    return fail(HJPD_EUNSUPPORTED, "the Hopf formulation is built for CNORM with NORM or QUAD_SHIFT");
+  if ((d->flags & HJPD_HOPF) && !(d->H == HJPD_H_CNORM && !game && (d->g == HJPD_G_NORM || d->g == HJPD_G_QUAD_SHIFT)) &&
+      d->H != HJPD_H_ISAACS)
+    return fail(HJPD_EUNSUPPORTED, "the Hopf formulation is built for CNORM with NORM or QUAD_SHIFT, and for ISAACS");
   if (has_mix(*d) && (game || d->H != HJPD_H_CNORM || !(d->g == HJPD_G_NORM || d->g == HJPD_G_QUAD_SHIFT) ||
                       (d->flags & (HJPD_PLAIN | HJPD_HOPF)) || has_recipe(*d)))
     return fail(HJPD_EUNSUPPORTED,
@@ -356,8 +359,13 @@ int validate_desc(const hjpd_desc* d) {
   if (d->H == HJPD_H_PURSUIT_EVASION) {
     if (!(game && d->g == HJPD_G_PAIR_DIST && d->d == 12 && d->d_y == 6))
       return fail(HJPD_EUNSUPPORTED, "pursuit-evasion needs d = 12, d_y = 6, g = PAIR_DIST");
-  } else if (game) {
-    return fail(HJPD_EUNSUPPORTED, "the game path is built for the pursuit-evasion family only");
+  } else if (d->H == HJPD_H_ISAACS) {
+    if (!(game && d->g == HJPD_G_SADDLE_QUAD && d->d == 2 && d->d_y == 1))
+      return fail(HJPD_EUNSUPPORTED, "ISAACS needs d = 2, d_y = 1, g = SADDLE_QUAD");
+    if (!(d->flags & HJPD_HOPF) || (d->flags & HJPD_PLAIN))
+      return fail(HJPD_EUNSUPPORTED, "ISAACS is built for the game Hopf formulation on the persistent kernel");
+  } else if (game || d->g == HJPD_G_SADDLE_QUAD) {
+    return fail(HJPD_EUNSUPPORTED, "the game path is built for the pursuit-evasion and Isaacs families only");
   } else if (d->H == HJPD_H_CNORM) {
     if (!(d->g == HJPD_G_NORM || d->g == HJPD_G_QUAD_SHIFT))
       return fail(HJPD_EUNSUPPORTED, "CNORM pairs with NORM or QUAD_SHIFT");
@@ -396,7 +404,8 @@ int enqueue_solve(hjpd_ctx* c, int64_t n, const void* x, const void* t, const in
   const int nkeys = (D.N_max + 1) * kHintBuckets;
   int hint = kHintNone;
   if (!(D.flags & HJPD_NO_ORDER_HINT))
-    hint = D.g == HJPD_G_QUAD_SHIFT ? kHintShift : (D.g == HJPD_G_NORM ? kHintNorm : kHintPair);
+    hint = D.g == HJPD_G_QUAD_SHIFT ? kHintShift
+                                    : ((D.g == HJPD_G_NORM || D.g == HJPD_G_SADDLE_QUAD) ? kHintNorm : kHintPair);
   hipLaunchKernelGGL(k_queue_zero, dim3((nkeys + 255) / 256), dim3(256), 0, s, c->d_counts, nkeys);
   hipLaunchKernelGGL(k_queue_count<T>, dim3(nb), dim3(256), 0, s, n, D.d, D.d_y, D.N_max, (const T*)x, (const T*)t,
                      N, hint, (const T*)gp, c->d_counts, (T*)phi, iters, status);

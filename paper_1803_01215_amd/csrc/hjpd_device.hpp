@@ -57,6 +57,7 @@ template <> struct M<float> {
   static __device__ __forceinline__ float rsqrt(float a) { return __frsqrt_rn(a); }
   static __device__ __forceinline__ float rcp(float a) { return __builtin_amdgcn_rcpf(a); }
   static __device__ __forceinline__ float tanh(float a) { return ::tanhf(a); }
+  static __device__ __forceinline__ float exp(float a) { return ::expf(a); }
   static __device__ __forceinline__ float fmax(float a, float b) { return ::fmaxf(a, b); }
   static __device__ __forceinline__ float fabs_(float a) { return ::fabsf(a); }
   static __device__ __forceinline__ bool finite(float a) { return __builtin_isfinite(a); }
@@ -68,6 +69,7 @@ template <> struct M<double> {
   static __device__ __forceinline__ double rsqrt(double a) { return ::rsqrt(a); }
   static __device__ __forceinline__ double rcp(double a) { return 1.0 / a; }
   static __device__ __forceinline__ double tanh(double a) { return ::tanh(a); }
+  static __device__ __forceinline__ double exp(double a) { return ::exp(a); }
   static __device__ __forceinline__ double fmax(double a, double b) { return ::fmax(a, b); }
   static __device__ __forceinline__ double fabs_(double a) { return ::fabs(a); }
   static __device__ __forceinline__ bool finite(double a) { return __builtin_isfinite(a); }

@@ -437,6 +437,7 @@ struct Pursuit {
   static constexpr bool kZeroSafe = false;
   static constexpr bool kHopf = false;
   static constexpr bool kMix = false;
+  static constexpr bool kGameHopf = false;  // Algorithm 3 (k_group_game, k_plain_game)
 
   template <typename T> struct Par {
     T kappa, wP, wE, r;
@@ -553,6 +554,90 @@ struct Pursuit {
   __device__ static T g(const Par<T>& P, const T (&x0)[6], const T (&y0)[6]) {
     const T a = x0[0] - y0[0], b = x0[1] - y0[1], c = x0[2] - y0[2];
     return M<T>::sqrt(a * a + b * b + c * c) - P.r;
+  }
+};
+
+// ===========================================================================
+// Isaacs' game (section 6.3), d = 2: scalar x (minimiser) and y (maximiser),
+// dynamics x' = 2 beta + sin(alpha), y' = -c(x,y) + cos(alpha), running cost
+// 1, so H(x,y,p,q) = -c(x,y) q + 2|p| - sqrt(p^2 + q^2) - 1, taken by the
+// game algorithms at the costate pair (p, -q):
+//   c q + 2|p| - sqrt(p^2 + q^2) - 1.
+// Bump speed c = b0 (1 + b1 exp(-b2 |(x,y) - (cx,cy)|^2)); hp = [b0,b1,b2,cx,cy].
+// Convex-concave initial cost g = e(x) + h(y), e = (a x)^2/2 - c0,
+// h = -(b y)^2/2; gp = [c0, a, b]; e*(p) = p^2/(2a^2) + c0, h_*(q) = -q^2/(2b^2).
+// Built for the game Hopf formulation (Algorithm 4) only.  Costate steps
+// (section 6.3): the root term is linearised at the current costates, the
+// rest is solved exactly (a shrink for p, a linear step for q).
+// ===========================================================================
+struct Isaacs {
+  static constexpr int D = 2;
+  static constexpr int DX = 1, DY = 1;
+  static constexpr bool kGame = true;
+  static constexpr bool kZeroSafe = false;
+  static constexpr bool kHopf = false;
+  static constexpr bool kMix = false;
+  static constexpr bool kGameHopf = true;  // Algorithm 4 (k_group_game_hopf)
+
+  template <typename T> struct Par {
+    T b0, b1, b2, cx, cy;
+    T c0, ia2, ib2;  // c0, 1/a^2, 1/b^2
+  };
+
+  template <typename T>
+  __device__ static void load(Par<T>& P, const T* hp, const T* gp, int, T) {
+    P.b0 = hp[0]; P.b1 = hp[1]; P.b2 = hp[2]; P.cx = hp[3]; P.cy = hp[4];
+    P.c0 = gp[0];
+    P.ia2 = T(1) / (gp[1] * gp[1]);
+    P.ib2 = T(1) / (gp[2] * gp[2]);
+  }
+
+  // c(x,y) and its partial derivatives.
+  template <typename T>
+  __device__ static T speed(const Par<T>& P, T x, T y, T& dcx, T& dcy) {
+    const T rx = x - P.cx, ry = y - P.cy;
+    const T be = P.b0 * P.b1 * M<T>::exp(-P.b2 * (rx * rx + ry * ry));
+    dcx = T(-2) * P.b2 * rx * be;
+    dcy = T(-2) * P.b2 * ry * be;
+    return P.b0 + be;
+  }
+
+  // p-step: shrink_{2 sigma delta}(v + sigma delta p/|(p,q)|) at the current
+  // (p, q); at the Hopf node 1 the e* quadratic scales both by 1/(1 + sigma/a^2).
+  template <typename T>
+  __device__ static T dual_p(const Par<T>& P, T p, T q, T v, T sd, T sigma, bool first) {
+    const T ss = p * p + q * q;
+    const T g = ss > T(0) ? p * M<T>::rsqrt(ss) : T(0);
+    T vv = v + sd * g, lam = T(2) * sd;
+    if (first) {
+      const T r = T(1) / (T(1) + sigma * P.ia2);
+      vv *= r;
+      lam *= r;
+    }
+    const T m = M<T>::fabs_(vv) - lam;
+    return m > T(0) ? (vv > T(0) ? m : -m) : T(0);
+  }
+
+  // q-step with the new p: u + sigma delta c - sigma delta q/|(p,q)|; at the
+  // Hopf node 1 the h_* quadratic divides by 1 + sigma/b^2.
+  template <typename T>
+  __device__ static T dual_q(const Par<T>& P, T c, T p, T q, T u, T sd, T sigma, bool first) {
+    const T ss = p * p + q * q;
+    const T g = ss > T(0) ? q * M<T>::rsqrt(ss) : T(0);
+    const T uu = u + sd * c - sd * g;
+    return first ? uu / (T(1) + sigma * P.ib2) : uu;
+  }
+
+  // H at the costate pair (p, -q).
+  template <typename T>
+  __device__ static T H(T c, T p, T q) {
+    return c * q + T(2) * M<T>::fabs_(p) - M<T>::sqrt(p * p + q * q) - T(1);
+  }
+
+  // -e*(p_1) - h_*(-q_1).
+  template <typename T>
+  __device__ static T conj_terms(const Par<T>& P, T p1, T q1) {
+    return -(T(0.5) * p1 * p1 * P.ia2 + P.c0) + T(0.5) * q1 * q1 * P.ib2;
   }
 };
 

@@ -1065,6 +1065,180 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_game(KArgs<T
 }
 
 // ---------------------------------------------------------------------------
+// Persistent lane-group kernel, game Hopf formulation (Algorithm 4) for a
+// separable convex-concave initial cost, families with scalar players
+// (Isaacs).  Nodes 1..N, no node 0: z_0 = w_0 = 0 (the Hopf difference
+// operator), and at node 1 the costate steps take -e*(p_1) and -h_*(-q_1)
+// in.  Per iteration, node by node: p (uses x^k, y^k, q^k), then q (uses the
+// new p); then x (descent, at y^k), then y (ascent, at the new x).  Value:
+//   -e*(p_1) - h_*(-q_1) + sum_j (p_j (x_j - x_{j-1}) - q_j (y_j - y_{j-1}))
+//   - delta sum_j H(x_j, y_j, p_j, -q_j),  x_0 = y_0 = 0,
+// which is eq. discgenlaxhopfdghopf's objective after summation by parts.
+// ---------------------------------------------------------------------------
+template <typename T, class F, int L, int K>
+__global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_game_hopf(KArgs<T> a) {
+  static_assert(F::DX == 1 && F::DY == 1, "scalar players");
+  constexpr int D = F::D;
+  const int lane = threadIdx.x & 63;
+  const int l = lane & (L - 1);
+  const int leader = lane - l;
+
+  typename F::template Par<T> P;
+  F::load(P, a.hp, a.gp, a.gkind, a.tau);
+  const int beg = a.cls_range[2 * a.cls], end = a.cls_range[2 * a.cls + 1];
+  int32_t* head = a.heads + a.cls;
+  const T sigma = a.sigma, tau = a.tau, theta = a.theta;
+
+  T x[K], y[K], p[K], q[K], z[K], w[K];
+  T tj[K], tdj[K];  // per node: tau and tau*delta where the node takes a primal step, else 0
+  T delta = T(0), sd = T(0), td = T(0), xN = T(0), yN = T(0);
+  int Np = 0, k = 0;
+  int64_t pt = -1;
+  bool active = false;
+
+  auto pop_and_init = [&]() {
+    int idx = 0;
+    if (l == 0) idx = atomicAdd(head, 1);
+    idx = __shfl(idx, leader, 64);
+    const int qi = beg + idx;
+    active = qi < end;
+    if (!active) return;
+    pt = a.queue[qi];
+    Np = a.N[pt];
+    delta = a.t[pt] / T(Np);
+    sd = sigma * delta;
+    td = tau * delta;
+    k = 0;
+    xN = a.x[pt * a.d];
+    yN = a.x[pt * a.d + 1];
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      const int j = 1 + l * K + kk;
+      x[kk] = (j < Np) ? init_x(xN, a.seed, pt, kArrX, j, 0) : xN;
+      y[kk] = (j < Np) ? init_x(yN, a.seed, pt, kArrY, j, 0) : yN;
+      p[kk] = (j <= Np) ? T(start_noise(a.seed, uint64_t(pt), kArrP, j, 0)) : T(0);
+      q[kk] = (j <= Np) ? T(start_noise(a.seed, uint64_t(pt), kArrQ, j, 0)) : T(0);
+      z[kk] = x[kk];
+      w[kk] = y[kk];
+      tj[kk] = (j < Np) ? tau : T(0);
+      tdj[kk] = (j < Np) ? td : T(0);
+    }
+  };
+
+  pop_and_init();
+
+  while (__any(active)) {
+    // z_{j-1}, w_{j-1} of the lane's first node; zero in the group's first
+    // lane (no node 0 in the Hopf formulation)
+    const T zprev = group_prev0<L>(z[K - 1], l), wprev = group_prev0<L>(w[K - 1], l);
+    T gx[K];  // d c/dx at (x^k, y^k)
+    T rp = T(0), rq = T(0), rx = T(0), ry = T(0);
+    // ---- p, then q, node by node ------------------------------------------------
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      const int j = 1 + l * K + kk;
+      const bool first = (l == 0) && (kk == 0);
+      T dcy;
+      const T c = F::speed(P, x[kk], y[kk], gx[kk], dcy);
+      const T v = p[kk] + sigma * (z[kk] - (kk == 0 ? zprev : z[kk - 1]));
+      const T pn = F::dual_p(P, p[kk], q[kk], v, sd, sigma, first);
+      const T u = q[kk] + sigma * (w[kk] - (kk == 0 ? wprev : w[kk - 1]));
+      const T qn = F::dual_q(P, c, pn, q[kk], u, sd, sigma, first);
+      if (j <= Np) {
+        rp += (pn - p[kk]) * (pn - p[kk]);
+        rq += (qn - q[kk]) * (qn - q[kk]);
+        p[kk] = pn;
+        q[kk] = qn;
+      }
+    }
+    const T pnext = group_next0<L>(p[0], l), qnext = group_next0<L>(q[0], l);
+    // ---- x: descent, grad_x H(x, y, p, -q) = q dc/dx ------------------------------
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      const T pp = (kk == K - 1) ? pnext : p[kk + 1];
+      const T dx = tdj[kk] * q[kk] * gx[kk] - tj[kk] * (p[kk] - pp);
+      rx += dx * dx;
+      z[kk] = x[kk] + (T(1) + theta) * dx;
+      x[kk] += dx;
+    }
+    // ---- y: ascent at the new x ---------------------------------------------------
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      T dcx, dcy;
+      (void)F::speed(P, x[kk], y[kk], dcx, dcy);
+      const T qq = (kk == K - 1) ? qnext : q[kk + 1];
+      const T dy = -tdj[kk] * q[kk] * dcy - tj[kk] * (q[kk] - qq);
+      ry += dy * dy;
+      w[kk] = y[kk] + (T(1) + theta) * dy;
+      y[kk] += dy;
+    }
+    // ---- stopping rule: all four blocks -------------------------------------------
+    k++;
+    const T rxs = group_sum<L>(rx), rps = group_sum<L>(rp), rys = group_sum<L>(ry), rqs = group_sum<L>(rq);
+    const bool fin = M<T>::finite(rxs + rps + rys + rqs);
+    const bool small = (rxs < a.tol) && (rps < a.tol) && (rys < a.tol) && (rqs < a.tol);
+    const bool done = active && (!fin || (!a.fixed && small) || k >= a.max_iter);
+    if (done) {
+      const T xprev = group_prev0<L>(x[K - 1], l), yprev = group_prev0<L>(y[K - 1], l);
+      T acc = T(0);
+      int bad = 0;
+#pragma unroll
+      for (int kk = 0; kk < K; kk++) {
+        const int j = 1 + l * K + kk;
+        if (j <= Np) {
+          T dcx, dcy;
+          const T c = F::speed(P, x[kk], y[kk], dcx, dcy);
+          acc += p[kk] * (x[kk] - (kk == 0 ? xprev : x[kk - 1])) - q[kk] * (y[kk] - (kk == 0 ? yprev : y[kk - 1]))
+                 - delta * F::H(c, p[kk], q[kk]);
+          bad |= !(M<T>::finite(x[kk]) && M<T>::finite(y[kk]) && M<T>::finite(p[kk]) && M<T>::finite(q[kk]));
+        }
+      }
+      if (l == 0) acc += F::conj_terms(P, p[0], q[0]);
+      acc = group_sum<L>(acc);
+      bad = group_or<L>(bad);
+      int st = !fin ? kNonFinite : (small ? kConverged : kMaxIter);
+      if (bad || !M<T>::finite(acc)) st = kNonFinite;
+      if (l == 0) {
+        a.phi[pt] = acc;
+        a.iters[pt] = k;
+        a.status[pt] = st;
+      }
+      const int64_t base = pt * int64_t(a.N_max + 1) * a.d;
+      if (a.xtraj) {
+#pragma unroll
+        for (int kk = 0; kk < K; kk++) {
+          const int j = 1 + l * K + kk;
+          if (j <= Np) {
+            a.xtraj[base + j * D] = x[kk];
+            a.xtraj[base + j * D + 1] = y[kk];
+          }
+        }
+        if (l == 0) {
+          a.xtraj[base] = T(0);
+          a.xtraj[base + 1] = T(0);
+        }
+      }
+      if (a.ptraj) {
+#pragma unroll
+        for (int kk = 0; kk < K; kk++) {
+          const int j = 1 + l * K + kk;
+          if (j <= Np) {
+            a.ptraj[base + j * D] = p[kk];
+            a.ptraj[base + j * D + 1] = q[kk];
+          }
+        }
+        if (l == 0) {
+          a.ptraj[base] = T(0);
+          a.ptraj[base + 1] = T(0);
+        }
+      }
+      pop_and_init();
+    }
+    if (__any(done || (active && priority_step(k)))) set_wave_priority(active, k);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Plain kernel, optimal-control path: one point per lane.
 // Workspace arrays X, P, Z, each [N_max+1][D][S] (S = lanes launched).
 // One fused sweep per iteration: the dual step of node j+1 (reads the old

@@ -19,7 +19,9 @@ enum Variant { kVarPlain = 0, kVarRecipe = 1, kVarMix = 2 };
 template <typename T, class F, int L, int K>
 const void* group_ptr(int variant) {
   if constexpr (F::kGame) {
-    return variant == kVarPlain ? reinterpret_cast<const void*>(&k_group_game<T, F, L, K>) : nullptr;
+    if (variant != kVarPlain) return nullptr;
+    if constexpr (F::kGameHopf) return reinterpret_cast<const void*>(&k_group_game_hopf<T, F, L, K>);
+    else return reinterpret_cast<const void*>(&k_group_game<T, F, L, K>);
   } else {
     if (variant == kVarRecipe) return reinterpret_cast<const void*>(&k_group_control_rec<T, F, L, K, true>);
     if (variant == kVarMix) {
@@ -35,10 +37,12 @@ const void* group_ptr(int variant) {
 template <typename T, class F>
 const void* pick_kernel(int plain, int L, int K, int variant) {
   if (plain) {
-    if constexpr (F::kGame)
-      return reinterpret_cast<const void*>(&k_plain_game<T, F>);
-    else
+    if constexpr (F::kGame) {
+      if constexpr (F::kGameHopf) return nullptr;  // no plain kernel for the game Hopf formulation
+      else return reinterpret_cast<const void*>(&k_plain_game<T, F>);
+    } else {
       return reinterpret_cast<const void*>(&k_plain_control<T, F>);
+    }
   }
 #define HJPD_TILE_CASE(LL, KK) \
   if (L == LL && K == KK) return group_ptr<T, F, LL, KK>(variant);
@@ -65,4 +69,6 @@ HJPD_DECLARE_LOOKUP(quad_f32)
 HJPD_DECLARE_LOOKUP(quad_f64)
 HJPD_DECLARE_LOOKUP(pursuit_f32)
 HJPD_DECLARE_LOOKUP(pursuit_f64)
+HJPD_DECLARE_LOOKUP(isaacs_f32)
+HJPD_DECLARE_LOOKUP(isaacs_f64)
 #undef HJPD_DECLARE_LOOKUP

@@ -15,8 +15,8 @@ LIB_PATH = os.path.join(_HERE, "lib", "libhjpd.so")
 
 HJPD_OK, HJPD_EINVAL, HJPD_ENOMEM, HJPD_EDEVICE, HJPD_EUNSUPPORTED = 0, 1, 2, 3, 4
 HJPD_PT_CONVERGED, HJPD_PT_MAXITER, HJPD_PT_NONFINITE, HJPD_PT_BADINPUT, HJPD_PT_VALUE_STALLED = 0, 1, 2, 3, 4
-HJPD_H_CNORM, HJPD_H_QUADROTOR, HJPD_H_PURSUIT_EVASION, HJPD_H_LINEAR_TANH = 0, 1, 2, 3
-HJPD_G_NORM, HJPD_G_QUAD_SHIFT, HJPD_G_PAIR_DIST, HJPD_G_QUAD_FORM = 0, 1, 2, 3
+HJPD_H_CNORM, HJPD_H_QUADROTOR, HJPD_H_PURSUIT_EVASION, HJPD_H_LINEAR_TANH, HJPD_H_ISAACS = 0, 1, 2, 3, 4
+HJPD_G_NORM, HJPD_G_QUAD_SHIFT, HJPD_G_PAIR_DIST, HJPD_G_QUAD_FORM, HJPD_G_SADDLE_QUAD = 0, 1, 2, 3, 4
 HJPD_F32, HJPD_F64 = 0, 1
 HJPD_PERSISTENT, HJPD_PLAIN, HJPD_FIXED_ITERS, HJPD_GRAPH, HJPD_TIMING, HJPD_NO_ORDER_HINT, HJPD_HOPF = (
     0, 1, 2, 4, 8, 16, 32)

@@ -52,7 +52,7 @@ def _desc(**kw):
 @pytest.mark.parametrize("bad", [
     dict(sigma=0.0), dict(sigma=-1.0), dict(tau=0.0), dict(sigma=1.0, tau=0.3), dict(theta=1.5), dict(theta=-0.1),
     dict(tol=0.0), dict(max_iter=0), dict(d=0), dict(N_max=0), dict(d_y=-1), dict(d_y=10), dict(dtype=7),
-    dict(H=9), dict(g=9), dict(flags=1 << 10), dict(lanes_per_point=12, nodes_per_lane=1),
+    dict(H=9), dict(g=9), dict(H=5), dict(g=5), dict(flags=1 << 10), dict(lanes_per_point=12, nodes_per_lane=1),
     dict(lanes_per_point=32, nodes_per_lane=5), dict(nodes_per_lane=2),
     dict(flags=64 | 128),                                # forward Euler and trapezoid together
 ])
@@ -79,6 +79,11 @@ def test_create_rejects_invalid_descriptors(lib, bad):
     dict(flags=64 | 1),                                  # no weighted discretisation on the plain kernel
     dict(flags=128 | 32),                                # nor with the Hopf formulation
     dict(flags=64, starts=3),                            # nor with the recipes
+    dict(H=4, g=4, d=2, d_y=1),                          # Isaacs: game Hopf formulation only
+    dict(H=4, g=4, d=2, d_y=1, flags=32 | 1),            # no plain kernel for it
+    dict(H=4, g=4, d=3, d_y=1, flags=32),                # scalar players only
+    dict(H=4, g=1, d=2, d_y=1, flags=32),                # Isaacs pairs with SADDLE_QUAD
+    dict(g=4, d=10, flags=32),                           # SADDLE_QUAD is a game cost
 ])
 def test_create_reports_unsupported(lib, unsup):
     from paper_1803_01215_amd import hjpd

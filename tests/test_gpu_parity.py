@@ -26,7 +26,7 @@ TOL = {"f64": 1e-9, "f32": 1e-4}
 
 
 def _check(O, w, dtype, *, plain=False, max_iter=None, lanes_per_point=0, nodes_per_lane=0, check_kstop=True,
-           traj=True, max_ill=0.0, converged_only=False, traj_tol=None, hopf=False, disc="be"):
+           traj=True, max_ill=0.0, converged_only=False, traj_tol=None, hopf=False, disc="be", ill_only_at_cap=False):
     if max_iter is not None:
         w.max_iter = max_iter
     g = gpu_solve(w, dtype=dtype, plain=plain, lanes_per_point=lanes_per_point, nodes_per_lane=nodes_per_lane,
@@ -40,6 +40,9 @@ def _check(O, w, dtype, *, plain=False, max_iter=None, lanes_per_point=0, nodes_
     ok = well_conditioned(O, w, g["iters"], o, dtype, tol, hopf=hopf, disc=disc)
     print("  ill-conditioned points screened: %d of %d" % ((~ok).sum(), w.n), flush=True)
     assert np.mean(~ok) <= max_ill
+    if ill_only_at_cap:
+        # rounding-sensitive points are allowed only among points still moving at the cap
+        assert np.all(g["status"][~ok] == 1), (g["status"][~ok], g["iters"][~ok])
     if converged_only:
         ok &= g["status"] == 0
         print("  compared at converged points: %d" % ok.sum(), flush=True)

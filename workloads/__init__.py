@@ -159,7 +159,8 @@ def isaacs2(n: int | None = None, mesh: float = 1.0 / 12.0) -> Workload:
     """Section 6.3's grid: [-3,3]^2 with spacing 1/12 (73 x 73 points) at the
     four times 0.025, 0.05, 0.075, 0.1 with delta = 0.005 (N = 5, 10, 15, 20),
     times major.  n (optional) keeps a seeded random subset of that many
-    points, in grid order."""
+    points, in grid order, as a batch of its own (random starts keyed by the
+    position in that batch)."""
     g = np.arange(-3.0, 3.0 + 0.5 * mesh, mesh)
     X, Y = np.meshgrid(g, g, indexing="ij")
     xy = np.stack([X.ravel(), Y.ravel()], axis=1)
@@ -167,14 +168,12 @@ def isaacs2(n: int | None = None, mesh: float = 1.0 / 12.0) -> Workload:
     x = np.tile(xy, (len(times), 1))
     t = np.repeat(times, len(xy))
     N = np.round(t / 0.005).astype(np.int32)
-    ids = np.arange(len(x))
     if n is not None and n < len(x):
         keep = np.sort(_rng(5).choice(len(x), n, replace=False))
-        x, t, N, ids = x[keep], t[keep], N[keep], ids[keep]
+        x, t, N = x[keep], t[keep], N[keep]
     sigma = 2.0
     return Workload("isaacs2", 5, H_ISAACS, G_SADDLE_QUAD, 2, 1, len(x), 20, "f32", sigma, 0.25 / sigma, 1.0,
-                    1e-8, 20000, False, x, t, N, ISAACS_PARAMS.copy(), ISAACS_G.copy(), init_seed=SEED_BASE + 105,
-                    extra={"ids": ids})
+                    1e-8, 20000, False, x, t, N, ISAACS_PARAMS.copy(), ISAACS_G.copy(), init_seed=SEED_BASE + 105)
 
 
 ALL = {"eikonal2d": eikonal2d, "cnorm10": cnorm10, "quadrotor12": quadrotor12, "pursuit12": pursuit12,
