@@ -40,7 +40,11 @@ bool has_mix(const hjpd_desc& d) { return (d.flags & (HJPD_FORWARD_EULER | HJPD_
 // Persistent kernel variant of a descriptor (validated: recipes and weighted
 // discretisations exclude each other).
 int kernel_variant(const hjpd_desc& d) {
-  return has_recipe(d) ? hjpd::kVarRecipe : (has_mix(d) ? hjpd::kVarMix : hjpd::kVarPlain);
+  if (has_recipe(d)) return hjpd::kVarRecipe;
+  if (has_mix(d)) return hjpd::kVarMix;
+  // Algorithm 1 for the eikonal family runs in the shifted layout (node 0 is an ordinary slot)
+  if (d.H == HJPD_H_CNORM && d.d_y == 0 && !(d.flags & HJPD_HOPF)) return hjpd::kVarShift;
+  return hjpd::kVarPlain;
 }
 
 #define HIP_OK(expr, what)                                                                 \

@@ -111,6 +111,27 @@ struct CNorm {
     gc1 = -P.alpha * s1 * s2;
   }
 
+  // Node-0 prox in the shifted layout: v <- prox_{tau g}(v) in the group's
+  // first lane, v unchanged elsewhere (first = false).
+  template <typename T>
+  __device__ static void prox0(const Par<T>& P, T (&v)[D], T tau, bool first) {
+    if (P.gkind == kGNorm) {
+      T ss = T(0);
+#pragma unroll
+      for (int i = 0; i < D; i++) ss += v[i] * v[i];
+      const T sc = M<T>::fmax(T(1) - tau * M<T>::rsqrt(ss), T(0));
+      const T m = first ? sc : T(1);
+#pragma unroll
+      for (int i = 0; i < D; i++) v[i] *= m;
+    } else {
+      // (v + tau a)/(1 + tau) = v/(1 + tau) + sa
+      const T m = first ? P.inv1pt : T(1);
+      const T f = first ? T(1) : T(0);
+#pragma unroll
+      for (int i = 0; i < D; i++) v[i] = m * v[i] + f * P.sa[i];
+    }
+  }
+
   // v <- shrink_2(v, mu) = v max(1 - mu/|v|, 0) (shrink_2(0) = 0); returns |v| after.
   template <typename T>
   __device__ static T shrink(T (&v)[D], T mu) {

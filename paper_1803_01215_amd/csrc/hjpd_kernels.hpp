@@ -811,6 +811,214 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_mix(
 }
 
 // ---------------------------------------------------------------------------
+// Persistent lane-group kernel for the eikonal family, Lax formulation, with
+// the node layout shifted by one: slot kk of lane l holds the primal node
+// j = lK + kk (x_j, z_j) and the dual node j + 1 (p_{j+1}).  Node 0 is the
+// first lane's slot 0, an ordinary primal slot whose step is followed by the
+// prox of g (the first lane only); node L*K, when N fills the tile, is the
+// query point, supplied by the group's last lane.  No lane carries a separate
+// node-0 state.  Per iteration (Algorithm 1):
+//   p_{j+1} <- shrink_2(p_{j+1} + sigma (z_{j+1} - z_j), sigma delta c(x_{j+1}))
+//   x_j <- x_j - tau (p_j - p_{j+1}) + tau delta |p_j| grad c(x_j)
+//   x_0 <- prox_{tau g}(that step)            (p_0 = 0)
+// z_{j+1} and c(x_{j+1}) of a lane's last slot come from the next lane, p_j
+// and |p_j| of its first slot from the previous lane: two D-wide and two
+// scalar DPP row shifts.  Against k_group_control this removes the node-0
+// block that every lane issued for one lane per group, and the x_0, z_0
+// registers of every lane.
+// ---------------------------------------------------------------------------
+template <typename T, class F, int L, int K>
+__global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shift(KArgs<T> a) {
+  constexpr int D = F::D;
+  const int lane = threadIdx.x & 63;
+  const int l = lane & (L - 1);
+  const int leader = lane - l;
+  const bool first = (l == 0), last = (l == L - 1);
+
+  typename F::template Par<T> P;
+  F::load(P, a.hp, a.gp, a.gkind, a.tau);
+  const int beg = a.cls_range[2 * a.cls], end = a.cls_range[2 * a.cls + 1];
+  int32_t* head = a.heads + a.cls;
+  const T sigma = a.sigma, tau = a.tau, theta = a.theta;
+
+  T x[K][D], p[K][D], z[K][D];
+  T xe[D], ce;      // the query point x and c(x) in the group's last lane, 0 elsewhere
+  T tj[K], tdj[K];  // per primal slot: tau and tau*delta where the node moves (j < N), else 0
+  T delta = T(0), sd = T(0), td = T(0);
+  int Np = 0, k = 0;
+  int64_t pt = -1;
+  bool active = false;
+
+  auto pop_and_init = [&]() {
+    int idx = 0;
+    if (l == 0) idx = atomicAdd(head, 1);
+    idx = __shfl(idx, leader, 64);
+    const int qi = beg + idx;
+    active = qi < end;
+    if (!active) return;
+    pt = a.queue[qi];
+    Np = a.N[pt];
+    delta = a.t[pt] / T(Np);
+    sd = sigma * delta;
+    td = tau * delta;
+    k = 0;
+    T xt[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) xt[i] = a.x[pt * a.d + i];
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      const int j = l * K + kk;
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        x[kk][i] = (j < Np) ? init_x(xt[i], a.seed, pt, kArrX, j, i) : xt[i];
+        p[kk][i] = (j + 1 <= Np) ? T(start_noise(a.seed, uint64_t(pt), kArrP, j + 1, i)) : T(0);
+        z[kk][i] = x[kk][i];
+      }
+      tj[kk] = (j < Np) ? tau : T(0);
+      tdj[kk] = (j < Np) ? td : T(0);
+    }
+    T cq, g0, g1;
+    F::speed(P, xt, cq, g0, g1);
+    ce = last ? cq : T(0);
+#pragma unroll
+    for (int i = 0; i < D; i++) xe[i] = last ? xt[i] : T(0);
+  };
+
+  pop_and_init();
+
+  while (__any(active)) {
+    // ---- speeds at the current iterate (own primal slots) --------------------
+    T cj[K], gc0[K], gc1[K];
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) F::speed(P, x[kk], cj[kk], gc0[kk], gc1[kk]);
+    // right neighbour of the last slot: next lane's slot 0, or x in the last lane
+    T znext[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) znext[i] = group_next0<L>(z[0][i], l) + xe[i];
+    const T cnext = group_next0<L>(cj[0], l) + ce;
+    // ---- dual step: p_{j+1} in slot kk -----------------------------------------
+    T pn[K];
+    T rp = T(0), rx = T(0);
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      T v[D];
+#pragma unroll
+      for (int i = 0; i < D; i++) v[i] = p[kk][i] + sigma * ((kk == K - 1 ? znext[i] : z[kk + 1][i]) - z[kk][i]);
+      const T cr = (kk == K - 1) ? cnext : cj[kk + 1];
+      pn[kk] = F::shrink(v, sd * cr);
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        const T dp = v[i] - p[kk][i];
+        rp += dp * dp;
+        p[kk][i] = v[i];
+      }
+    }
+    // ---- primal step: x_j in slot kk; p_j of the first slot from the previous
+    //      lane (p_0 = 0 in the first lane) --------------------------------------
+    T pprev[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) pprev[i] = group_prev0<L>(p[K - 1][i], l);
+    const T pnprev = group_prev0<L>(pn[K - 1], l);
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      const T coef = tdj[kk] * ((kk == 0) ? pnprev : pn[kk - 1]);
+      T dx[D];
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        const T pl = (kk == 0) ? pprev[i] : p[kk - 1][i];
+        dx[i] = -tj[kk] * (pl - p[kk][i]);
+      }
+      dx[0] += coef * gc0[kk];
+      dx[1] += coef * gc1[kk];
+      if (kk == 0) {
+        // node 0 (first lane): the prox of g after the step
+        T v[D];
+#pragma unroll
+        for (int i = 0; i < D; i++) v[i] = x[0][i] + dx[i];
+        F::prox0(P, v, tau, first);
+#pragma unroll
+        for (int i = 0; i < D; i++) dx[i] = v[i] - x[0][i];
+      }
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        rx += dx[i] * dx[i];
+        z[kk][i] = x[kk][i] + (T(1) + theta) * dx[i];
+        x[kk][i] += dx[i];
+      }
+    }
+    // ---- stopping rule (section 6 set-up) ------------------------------------
+    k++;
+    const T rxs = group_sum<L>(rx), rps = group_sum<L>(rp);
+    const bool fin = M<T>::finite(rxs + rps);
+    const bool small = (rxs < a.tol) && (rps < a.tol);
+    const bool done = active && (!fin || (!a.fixed && small) || k >= a.max_iter);
+    if (done) {
+      // value: g(x_0) + sum_j <p_j, x_j - x_{j-1}> - delta sum_j c(x_j) |p_j|
+#pragma unroll
+      for (int kk = 0; kk < K; kk++) F::speed(P, x[kk], cj[kk], gc0[kk], gc1[kk]);
+      const T cn2 = group_next0<L>(cj[0], l) + ce;
+      T xnext[D];
+#pragma unroll
+      for (int i = 0; i < D; i++) xnext[i] = group_next0<L>(x[0][i], l) + xe[i];
+      T acc = T(0);
+      int bad = 0;
+#pragma unroll
+      for (int kk = 0; kk < K; kk++) {
+        const int j = l * K + kk + 1;  // dual node of the slot
+        if (j <= Np) {
+          T s = T(0), ss = T(0);
+#pragma unroll
+          for (int i = 0; i < D; i++) {
+            s += p[kk][i] * ((kk == K - 1 ? xnext[i] : x[kk + 1][i]) - x[kk][i]);
+            ss += p[kk][i] * p[kk][i];
+          }
+          const T cr = (kk == K - 1) ? cn2 : cj[kk + 1];
+          acc += s - delta * cr * M<T>::sqrt(ss);
+          bad |= !(all_finite<T, D>(x[kk]) && all_finite<T, D>(p[kk]));
+        }
+      }
+      if (first) acc += F::g(P, x[0]);
+      acc = group_sum<L>(acc);
+      bad = group_or<L>(bad);
+      int st = !fin ? kNonFinite : (small ? kConverged : kMaxIter);
+      if (bad || !M<T>::finite(acc)) st = kNonFinite;
+      if (first) {
+        a.phi[pt] = acc;
+        a.iters[pt] = k;
+        a.status[pt] = st;
+      }
+      const int64_t base = pt * int64_t(a.N_max + 1) * a.d;
+      if (a.xtraj) {
+#pragma unroll
+        for (int kk = 0; kk < K; kk++) {
+          const int j = l * K + kk;
+          if (j <= Np)
+#pragma unroll
+            for (int i = 0; i < D; i++) a.xtraj[base + j * D + i] = x[kk][i];
+        }
+        if (first && Np == L * K)  // node N lies past the tile: the query point
+#pragma unroll
+          for (int i = 0; i < D; i++) a.xtraj[base + Np * D + i] = a.x[pt * a.d + i];
+      }
+      if (a.ptraj) {
+#pragma unroll
+        for (int kk = 0; kk < K; kk++) {
+          const int j = l * K + kk + 1;
+          if (j <= Np)
+#pragma unroll
+            for (int i = 0; i < D; i++) a.ptraj[base + j * D + i] = p[kk][i];
+        }
+        if (first)
+#pragma unroll
+          for (int i = 0; i < D; i++) a.ptraj[base + i] = T(0);
+      }
+      pop_and_init();
+    }
+    if (__any(done || (active && priority_step(k)))) set_wave_priority(active, k);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Persistent lane-group kernel, game path (Algorithm 3) for games whose
 // Hamiltonian separates as H = Hx(x, p) + Hy(y, q): block order p, q, x, y.
 // ---------------------------------------------------------------------------
