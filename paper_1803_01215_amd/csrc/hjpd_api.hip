@@ -42,8 +42,8 @@ bool has_mix(const hjpd_desc& d) { return (d.flags & (HJPD_FORWARD_EULER | HJPD_
 int kernel_variant(const hjpd_desc& d) {
   if (has_recipe(d)) return hjpd::kVarRecipe;
   if (has_mix(d)) return hjpd::kVarMix;
-  // Algorithm 1 for the eikonal family runs in the shifted layout (node 0 is an ordinary slot)
-  if (d.H == HJPD_H_CNORM && d.d_y == 0 && !(d.flags & HJPD_HOPF)) return hjpd::kVarShift;
+  // Algorithms 1 and 2 for the eikonal family run in the shifted layout (node 0 is an ordinary slot)
+  if (d.H == HJPD_H_CNORM && d.d_y == 0) return (d.flags & HJPD_HOPF) ? hjpd::kVarShiftHopf : hjpd::kVarShift;
   return hjpd::kVarPlain;
 }
 

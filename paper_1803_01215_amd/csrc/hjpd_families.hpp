@@ -146,6 +146,32 @@ struct CNorm {
     return nz ? scale * (ss * rs) : T(0);
   }
 
+  // Dual step of the shifted layout's slot 0 in the Hopf formulation, given
+  // the threshold mu = sigma delta c(x_1): in the group's first lane (node 1)
+  // the joint prox with g* (see dual_hopf1), elsewhere the plain shrink.
+  // Returns |p| after.
+  template <typename T>
+  __device__ static T shrink_hopf1(const Par<T>& P, T (&v)[D], T mu, T sigma, bool first) {
+    if (P.gkind != kGNorm) {
+      const T r1 = first ? T(1) / (T(1) + sigma) : T(1);
+      const T sg = first ? sigma : T(0);
+#pragma unroll
+      for (int i = 0; i < D; i++) v[i] = (v[i] - sg * P.a[i]) * r1;
+      mu *= r1;
+    }
+    T ss = T(0);
+#pragma unroll
+    for (int i = 0; i < D; i++) ss += v[i] * v[i];
+    const bool nz = ss > T(0);
+    const T rs = M<T>::rsqrt(ss);
+    T len = nz ? M<T>::fmax(ss * rs - mu, T(0)) : T(0);
+    if (P.gkind == kGNorm && first) len = len < T(1) ? len : T(1);
+    const T scale = nz ? len * rs : T(0);
+#pragma unroll
+    for (int i = 0; i < D; i++) v[i] *= scale;
+    return len;
+  }
+
   // Hopf formulation, dual step at j = 1 (Algorithm 2): the joint prox
   //   argmin_p g*(p) + lam/sigma c(x)|p| + |p - v|^2/(2 sigma),  lam = sigma delta.
   // Shifted quadratic g: g*(p) = |p|^2/2 + <a,p> + c0, so completing the square

@@ -11,7 +11,9 @@
 //     extrapolate z = x_new + theta (x_new - x_old)
 //     residuals   ||x^{k+1}-x^k||^2, ||p^{k+1}-p^k||^2 summed over the group.
 //   z_{j-1} and p_{j+1} cross a lane boundary once per lane per iteration
-//   (DPP wavefront shifts).  Groups pop point ids from a device queue
+//   (DPP wavefront shifts).  The eikonal family uses the same scheme with the
+//   node layout shifted by one, so that node 0 is an ordinary slot
+//   (k_group_control_shift).  Groups pop point ids from a device queue
 //   (sorted by N, one segment per tile class); a group whose point meets the
 //   stopping rule writes its outputs and immediately pops the next point
 //   (retire and refill), so waves stay full until the queue drains.
@@ -89,8 +91,9 @@ __device__ __forceinline__ T init_x(T xt, uint64_t seed, int64_t pt, int arr, in
 }
 
 // ---------------------------------------------------------------------------
-// Persistent lane-group kernel, optimal-control path (Algorithm 1; Hopf:
-// Algorithm 2).
+// Persistent lane-group kernel, optimal-control path (Algorithm 1), for the
+// families whose dual step needs the whole neighbouring state (quadrotor).
+// The eikonal family runs k_group_control_shift below.
 // ---------------------------------------------------------------------------
 template <typename T, class F, int L, int K>
 __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArgs<T> a) {
@@ -139,10 +142,9 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
       }
     }
     // node 0 lives in the group's first lane; the other lanes keep x0 = z0 = 0
-    // (and every lane in the Hopf formulation, which has no node 0)
 #pragma unroll
     for (int i = 0; i < D; i++) {
-      x0[i] = (l == 0 && !a.hopf) ? init_x(xt[i], a.seed, pt, kArrX, 0, i) : T(0);
+      x0[i] = (l == 0) ? init_x(xt[i], a.seed, pt, kArrX, 0, i) : T(0);
       z0[i] = x0[i];
     }
 #pragma unroll
@@ -170,15 +172,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
       T v[D];
 #pragma unroll
       for (int i = 0; i < D; i++) v[i] = p[kk][i] + sigma * (z[kk][i] - (kk == 0 ? zprev[i] : z[kk - 1][i]));
-      if constexpr (F::kHopf) {
-        // Hopf: node 1 (first lane, first slot) takes the joint prox with g*
-        if (kk == 0 && a.hopf && l == 0)
-          F::dual_hopf1(P, x[kk], v, sd, sigma, C[kk]);
-        else
-          F::dual(P, x[kk], v, sd, C[kk]);
-      } else {
-        F::dual(P, x[kk], v, sd, C[kk]);
-      }
+      F::dual(P, x[kk], v, sd, C[kk]);
       if constexpr (!F::kZeroSafe) {
         // nodes past N keep p = 0
         const int j = 1 + l * K + kk;
@@ -196,7 +190,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
     T pnext[D];
 #pragma unroll
     for (int i = 0; i < D; i++) pnext[i] = group_next0<L>(p[0][i], l);
-    if (l == 0 && !a.hopf) {
+    if (l == 0) {
       T dx0[D];
       F::step0(P, x0, p[0], tau, dx0);
 #pragma unroll
@@ -247,9 +241,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
         }
       }
       if (l == 0) {
-        // Lax: + g(x_0); Hopf (x_0 = 0 in the sum above): - g*(p_1)
-        if constexpr (F::kHopf) acc += a.hopf ? -F::gstar(P, p[0]) : F::g(P, x0);
-        else acc += F::g(P, x0);
+        acc += F::g(P, x0);
         bad |= !all_finite<T, D>(x0);
       }
       acc = group_sum<L>(acc);
@@ -364,10 +356,9 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_rec(
       }
     }
     // node 0 lives in the group's first lane; the other lanes keep x0 = z0 = 0
-    // (and every lane in the Hopf formulation, which has no node 0)
 #pragma unroll
     for (int i = 0; i < D; i++) {
-      x0[i] = (l == 0 && !a.hopf) ? init_x(xt[i], seed, pt, kArrX, 0, i) : T(0);
+      x0[i] = (l == 0) ? init_x(xt[i], seed, pt, kArrX, 0, i) : T(0);
       z0[i] = x0[i];
     }
     set_steps();
@@ -407,9 +398,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_rec(
       }
     }
     if (l == 0) {
-      // Lax: + g(x_0); Hopf (x_0 = 0 in the sum above): - g*(p_1)
-      if constexpr (F::kHopf) acc += a.hopf ? -F::gstar(P, p[0]) : F::g(P, x0);
-      else acc += F::g(P, x0);
+      acc += F::g(P, x0);
       bad |= !all_finite<T, D>(x0);
     }
     bad = group_or<L>(bad);
@@ -433,15 +422,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_rec(
       T v[D];
 #pragma unroll
       for (int i = 0; i < D; i++) v[i] = p[kk][i] + sigma * (z[kk][i] - (kk == 0 ? zprev[i] : z[kk - 1][i]));
-      if constexpr (F::kHopf) {
-        // Hopf: node 1 (first lane, first slot) takes the joint prox with g*
-        if (kk == 0 && a.hopf && l == 0)
-          F::dual_hopf1(P, x[kk], v, sd, sigma, C[kk]);
-        else
-          F::dual(P, x[kk], v, sd, C[kk]);
-      } else {
-        F::dual(P, x[kk], v, sd, C[kk]);
-      }
+      F::dual(P, x[kk], v, sd, C[kk]);
       if constexpr (!F::kZeroSafe) {
         // nodes past N keep p = 0
         const int j = 1 + l * K + kk;
@@ -459,7 +440,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_rec(
     T pnext[D];
 #pragma unroll
     for (int i = 0; i < D; i++) pnext[i] = group_next0<L>(p[0][i], l);
-    if (l == 0 && !a.hopf) {
+    if (l == 0) {
       T dx0[D];
       F::step0(P, x0, p[0], tau, dx0);
 #pragma unroll
@@ -826,8 +807,12 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_mix(
 // scalar DPP row shifts.  Against k_group_control this removes the node-0
 // block that every lane issued for one lane per group, and the x_0, z_0
 // registers of every lane.
+// Hopf formulation (Algorithm 2, kHopf): node 0 does not exist; its slot
+// keeps x_0 = z_0 = 0 (the Hopf difference operator) and takes no step, node
+// 1's dual step is the joint prox with g*, and the value has -g*(p_1) in
+// place of g(x_0).
 // ---------------------------------------------------------------------------
-template <typename T, class F, int L, int K>
+template <typename T, class F, int L, int K, bool kHopf>
 __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shift(KArgs<T> a) {
   constexpr int D = F::D;
   const int lane = threadIdx.x & 63;
@@ -868,14 +853,15 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
 #pragma unroll
     for (int kk = 0; kk < K; kk++) {
       const int j = l * K + kk;
+      const bool moves = (j < Np) && !(kHopf && j == 0);  // Hopf: no node 0
 #pragma unroll
       for (int i = 0; i < D; i++) {
-        x[kk][i] = (j < Np) ? init_x(xt[i], a.seed, pt, kArrX, j, i) : xt[i];
+        x[kk][i] = moves ? init_x(xt[i], a.seed, pt, kArrX, j, i) : ((j < Np) ? T(0) : xt[i]);
         p[kk][i] = (j + 1 <= Np) ? T(start_noise(a.seed, uint64_t(pt), kArrP, j + 1, i)) : T(0);
         z[kk][i] = x[kk][i];
       }
-      tj[kk] = (j < Np) ? tau : T(0);
-      tdj[kk] = (j < Np) ? td : T(0);
+      tj[kk] = moves ? tau : T(0);
+      tdj[kk] = moves ? td : T(0);
     }
     T cq, g0, g1;
     F::speed(P, xt, cq, g0, g1);
@@ -905,7 +891,12 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
 #pragma unroll
       for (int i = 0; i < D; i++) v[i] = p[kk][i] + sigma * ((kk == K - 1 ? znext[i] : z[kk + 1][i]) - z[kk][i]);
       const T cr = (kk == K - 1) ? cnext : cj[kk + 1];
-      pn[kk] = F::shrink(v, sd * cr);
+      if constexpr (kHopf) {
+        if (kk == 0) pn[kk] = F::shrink_hopf1(P, v, sd * cr, sigma, first);  // node 1: with g*
+        else pn[kk] = F::shrink(v, sd * cr);
+      } else {
+        pn[kk] = F::shrink(v, sd * cr);
+      }
 #pragma unroll
       for (int i = 0; i < D; i++) {
         const T dp = v[i] - p[kk][i];
@@ -935,7 +926,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
         T v[D];
 #pragma unroll
         for (int i = 0; i < D; i++) v[i] = x[0][i] + dx[i];
-        F::prox0(P, v, tau, first);
+        F::prox0(P, v, tau, first && !kHopf);  // Hopf: node 0 stays at 0
 #pragma unroll
         for (int i = 0; i < D; i++) dx[i] = v[i] - x[0][i];
       }
@@ -977,7 +968,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
           bad |= !(all_finite<T, D>(x[kk]) && all_finite<T, D>(p[kk]));
         }
       }
-      if (first) acc += F::g(P, x[0]);
+      if (first) acc += kHopf ? -F::gstar(P, p[0]) : F::g(P, x[0]);  // Hopf: -g*(p_1), x_0 = 0
       acc = group_sum<L>(acc);
       bad = group_or<L>(bad);
       int st = !fin ? kNonFinite : (small ? kConverged : kMaxIter);

@@ -13,11 +13,12 @@ inline constexpr Tile kTiles[] = {{8, 1},  {16, 1}, {8, 2},  {32, 1}, {16, 2}, {
 inline constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 inline constexpr int kMaxCapacity = 256;
 
-// Persistent kernel variants: the general control kernel (Algorithms 1 and 2,
-// and the game kernels), the control kernel with the robustness recipes, the
-// eikonal family's weighted discretisations (forward Euler, trapezoid), and
-// the eikonal family's shifted-layout kernel for Algorithm 1.
-enum Variant { kVarPlain = 0, kVarRecipe = 1, kVarMix = 2, kVarShift = 3 };
+// Persistent kernel variants: the general kernels (k_group_control for the
+// quadrotor, the game kernels), the control kernel with the robustness
+// recipes, the eikonal family's weighted discretisations (forward Euler,
+// trapezoid), and the eikonal family's shifted-layout kernel for Algorithms 1
+// and 2 (which kVarPlain also selects for that family).
+enum Variant { kVarPlain = 0, kVarRecipe = 1, kVarMix = 2, kVarShift = 3, kVarShiftHopf = 4 };
 
 template <typename T, class F, int L, int K>
 const void* group_ptr(int variant) {
@@ -27,21 +28,22 @@ const void* group_ptr(int variant) {
     else return reinterpret_cast<const void*>(&k_group_game<T, F, L, K>);
   } else {
     if (variant == kVarRecipe) return reinterpret_cast<const void*>(&k_group_control_rec<T, F, L, K, true>);
-    if (variant == kVarMix || variant == kVarShift) {
-      if constexpr (F::kMix) {
-        return variant == kVarMix ? reinterpret_cast<const void*>(&k_group_control_mix<T, F, L, K>)
-                                  : reinterpret_cast<const void*>(&k_group_control_shift<T, F, L, K>);
-      } else {
-        return nullptr;
-      }
+    if constexpr (F::kMix) {
+      // eikonal family: the shifted layout (Algorithms 1 and 2) or the weighted rules
+      if (variant == kVarMix) return reinterpret_cast<const void*>(&k_group_control_mix<T, F, L, K>);
+      if (variant == kVarShiftHopf) return reinterpret_cast<const void*>(&k_group_control_shift<T, F, L, K, true>);
+      return reinterpret_cast<const void*>(&k_group_control_shift<T, F, L, K, false>);
+    } else {
+      if (variant != kVarPlain) return nullptr;
+      return reinterpret_cast<const void*>(&k_group_control<T, F, L, K>);
     }
-    return reinterpret_cast<const void*>(&k_group_control<T, F, L, K>);
   }
 }
 
 // variant: kVarPlain (Algorithm 1 / 2 / 3), kVarRecipe (control kernel with
 // the robustness recipes), kVarMix (weighted Euler discretisations),
-// kVarShift (Algorithm 1 in the shifted layout, eikonal family).
+// kVarShift / kVarShiftHopf (Algorithm 1 / 2 in the shifted layout, eikonal
+// family).
 template <typename T, class F>
 const void* pick_kernel(int plain, int L, int K, int variant) {
   if (plain) {

@@ -122,6 +122,20 @@ def test_eikonal_small_N_and_max_N(oracle_mod):
     _check(oracle_mod, w, "f64", check_kstop=False)
 
 
+@pytest.mark.parametrize("variant", [dict(), dict(hopf=True), dict(disc="fe")])
+def test_largest_tile_N_256(oracle_mod, variant):
+    """N_max = 256 (the 64 x 4 tile): N = 256 fills the tile, so node N
+    comes from the group's last lane; N = 255, 129 and 1 leave it inside.
+    Fixed iteration count (1,500), FP64, trajectories compared."""
+    w = W.cnorm10(12)
+    w.N = np.array([256, 255, 129, 1] * 3, dtype=np.int32)
+    w.N_max = 256
+    w.t = np.full(w.n, 0.8)
+    w.fixed_iters = True
+    g = _check(oracle_mod, w, "f64", max_iter=1500, check_kstop=False, **variant)
+    assert np.all(g["iters"] == 1500)
+
+
 def test_statuses_and_bad_inputs(oracle_mod):
     w = W.cnorm10(40)
     x = w.x.copy(); t = w.t.copy(); N = w.N.copy()

@@ -165,3 +165,14 @@ def test_recipes_off_match_plain_solve():
     assert conv.all()
     assert np.array_equal(a["iters"], b["iters"].astype(a["iters"].dtype))
     assert np.max(rel_err(b["phi"], a["phi"])) < 1e-12
+
+
+def test_recipes_largest_tile_f64(oracle_mod):
+    """N_max = 256 (the 64 x 4 tile, and 64 x 3 for N = 129) in FP64: three
+    phases of 400 iterations with sigma raised by 1 at each cap."""
+    w = W.cnorm10(12)
+    w.N = np.array([256, 255, 129, 1] * 3, dtype=np.int32)
+    w.N_max = 256
+    w.t = np.full(w.n, 0.8)
+    w.max_iter = 400
+    _compare(oracle_mod, w, "f64", 0.99, restarts=2, sigma_inc=1.0)
