@@ -136,6 +136,20 @@ def test_largest_tile_N_256(oracle_mod, variant):
     assert np.all(g["iters"] == 1500)
 
 
+@pytest.mark.parametrize("name", ["quadrotor12", "pursuit12"])
+def test_largest_tile_N_256_other_families(oracle_mod, name):
+    """The quadrotor (general control kernel) and the pursuit-evasion game at
+    N_max = 256: N = 256 and 255 run the 64 x 4 tile, 129 the 64 x 3 tile.
+    FP64, 300 fixed iterations, trajectories compared."""
+    w = W.get(name).subset(np.arange(9))
+    w.N = np.array([256, 255, 129] * 3, dtype=np.int32)
+    w.N_max = 256
+    w.t = np.full(w.n, 3.0)
+    w.fixed_iters = True
+    g = _check(oracle_mod, w, "f64", max_iter=300, check_kstop=False, max_ill=0.35 if name == "quadrotor12" else 0.0)
+    assert np.all(g["iters"] == 300)
+
+
 def test_statuses_and_bad_inputs(oracle_mod):
     w = W.cnorm10(40)
     x = w.x.copy(); t = w.t.copy(); N = w.N.copy()
