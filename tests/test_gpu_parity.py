@@ -124,11 +124,12 @@ def test_eikonal_small_N_and_max_N(oracle_mod):
 
 @pytest.mark.parametrize("variant", [dict(), dict(hopf=True), dict(disc="fe")])
 def test_largest_tile_N_256(oracle_mod, variant):
-    """N_max = 256 (the 64 x 4 tile): N = 256 fills the tile, so node N
-    comes from the group's last lane; N = 255, 129 and 1 leave it inside.
-    Fixed iteration count (1,500), FP64, trajectories compared."""
-    w = W.cnorm10(12)
-    w.N = np.array([256, 255, 129, 1] * 3, dtype=np.int32)
+    """N_max = 256: one point in every capacity class of the default plan
+    (8 x 1 up to 64 x 4), with N at a class's top (the tile is full, so node
+    N comes from the group's last lane) and inside it.  Fixed iteration count
+    (1,500), FP64, trajectories compared."""
+    w = W.cnorm10(14)
+    w.N = np.array([256, 255, 192, 129, 128, 100, 96, 70, 64, 40, 32, 17, 9, 1], dtype=np.int32)
     w.N_max = 256
     w.t = np.full(w.n, 0.8)
     w.fixed_iters = True
