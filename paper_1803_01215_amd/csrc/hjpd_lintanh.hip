@@ -231,7 +231,10 @@ __device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af
       const int j = e / D, i = e - j * D;
       sp_out[e] = sP[j * LD + i];
     }
-  // ---- node 0 (VALU): x_0 <- M (x_0 + tau p_1), M symmetric, read by columns ----
+  // ---- node 0 (VALU): x_0 <- M (x_0 + tau p_1), M symmetric, read by columns.
+  // Waves 0 and 1 compute it while the other waves start the primal product
+  // (the forward kernel and the reverse kernel's recompute use this same
+  // summation order, so the recompute reproduces the forward bit for bit).
   float x0n = 0.f, z0n = 0.f;
   if (L.tid < D) {
     float acc0 = 0.f;
@@ -486,7 +489,8 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
   const LtArgs& a = b.f;
   extern __shared__ float smem[];
   __shared__ float s_red[2 * kLtWaves];
-  __shared__ float s_w[D], s_wb[D];
+  __shared__ float s_wb[4 * 128];  // quarters of wbar = M XB_0 (B1)
+  auto wbar = [&](int i) { return (s_wb[i] + s_wb[128 + i]) + (s_wb[256 + i] + s_wb[384 + i]); };
   __shared__ int s_pt;
   const LtLane<D> L;
   const int R = lt_rows(a.N_max);
@@ -640,19 +644,27 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
           }
         }
         __syncthreads();
-        // (B1) node 0: w = x_0 + tau p'_1, wbar = M XB_0; dM += XB_0 w^T is
+        // (B1) node 0: w = x_0 + tau p'_1, wbar = M XB_0 (quarters of each row's
+        // terms summed by the eight waves, added below); dM += XB_0 w^T is
         // applied once per segment from the staged (XB_0, w) pairs
+        {
+          const int i = L.tid & 127, g = L.tid >> 7;
+          if (i < D) {
+            constexpr int KQ = (D + 3) / 4;
+            const int k1 = (g + 1) * KQ < D ? (g + 1) * KQ : D;
+            float part = 0.f;
+            for (int kq = g * KQ; kq < k1; kq++) part += a.M[kq * D + i] * XB[kq];
+            s_wb[g * 128 + i] = part;
+          }
+        }
         if (L.tid < D) {
           const float wv = S0[L.tid] + tau * S1[LD + L.tid];
-          float wb = 0.f;
-          for (int kq = 0; kq < D; kq++) wb += a.M[kq * D + L.tid] * XB[kq];
-          s_wb[L.tid] = wb;
           float* st = stage + int64_t(k - k0) * 2 * D;
           st[L.tid] = XB[L.tid];
           st[D + L.tid] = wv;
         }
         __syncthreads();
-        if (L.tid < D) ZB[L.tid] += s_wb[L.tid];
+        if (L.tid < D) ZB[L.tid] += wbar(L.tid);
         // (B2) primal step transposed
         {
           f4 acc[kLtNT];
@@ -672,7 +684,7 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
               const float th = tanh_fast(xk), om = 1.f - th * th;
               // x_N is fixed: no primal step and no (A XB)_N term at j = N
               float pbd = -tau * xb - (prim ? td * acc[c][r] : 0.f) - td * eps * om * xb + tau * xbm;
-              if (j == 1) pbd += tau * s_wb[L.ic[r] < D ? L.ic[r] : 0];
+              if (j == 1) pbd += tau * wbar(L.ic[r] < D ? L.ic[r] : 0);
               if (ok) {
                 PB[e] += pbd;
                 ZB[e] += xb + 2.f * td * eps * om * th * pp * xb;
