@@ -276,8 +276,8 @@ def main():
     achieved = flops / (kern_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK["fp32_vector"] / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK["fp32_vector"],
-                "traffic": measured_traffic("k_group_control_shift<float, CNorm<10>, 16, 2>"),
-                "kernel": "k_group_control_shift<float, CNorm<10>, 16, 2>", "kernel_ms": kern_ms,
+                "traffic": measured_traffic("k_group_control_shift<float, CNorm<10>, 16, 2, false>"),
+                "kernel": "k_group_control_shift<float, CNorm<10>, 16, 2, false>", "kernel_ms": kern_ms,
                 "flops_per_launch": flops}
 
     # ---- the same with the long iteration cap (20000) -----------------------------
