@@ -256,9 +256,17 @@ hjpd::Tile default_tile(int cap) {
 
 const int kCaps[] = {8, 16, 32, 64, 96, 128, 192, 256};
 
+// Persistent grid: resident blocks per CU, at most kMaxBlocksPerCU (two
+// waves per SIMD).  A launch ends with its slowest points, which run their
+// iterations one after another; every extra wave on a SIMD takes issue slots
+// from them (a wave alone issues about twice as fast as one of three), while
+// two waves already keep the SIMD's issue slots busy on the bulk of points.
+constexpr int kMaxBlocksPerCU = 2;
+
 int persistent_grid(hjpd_ctx* c, const void* kern) {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, 0) != hipSuccess || nb < 1) nb = 1;
+  if (nb > kMaxBlocksPerCU) nb = kMaxBlocksPerCU;
   return nb * c->n_cu;
 }
 

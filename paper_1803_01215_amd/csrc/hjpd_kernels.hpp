@@ -38,16 +38,27 @@ template <typename T, int K>
 inline constexpr int kGroupWaves = sizeof(T) == 8 ? 1 : (K == 1 ? 4 : (K == 2 ? 3 : 2));
 
 // Issue priority of a wave (s_setprio) from the iteration count of the
-// oldest point it holds: a wave still iterating after 1,000 / 4,000 / 16,000
-// iterations holds one of the few slow points, which end the persistent
-// launch, so the SIMD arbiter is told to prefer it over waves of fresh points.
-__device__ __forceinline__ void set_wave_priority(bool active, int k) {
-  if (__any(active && k >= 16000)) __builtin_amdgcn_s_setprio(3);
-  else if (__any(active && k >= 4000)) __builtin_amdgcn_s_setprio(2);
-  else if (__any(active && k >= 1000)) __builtin_amdgcn_s_setprio(1);
+// oldest point it holds.  A point still iterating after a tenth, a fifth and
+// two fifths of the iteration cap is in the slow tail of the batch: the few
+// slowest points run their iterations one after another and end the
+// persistent launch, so the SIMD arbiter is told to prefer their waves over
+// waves of faster points from early on (levels 1, 2, 3).  Order of issue
+// only; results are unchanged.
+struct WavePrio {
+  int t1, t2, t3;
+  __device__ explicit WavePrio(int max_iter) {
+    t1 = max_iter / 10 > 1 ? max_iter / 10 : 1;
+    t2 = max_iter / 5 > t1 ? max_iter / 5 : t1 + 1;
+    t3 = 2 * (max_iter / 5) > t2 ? 2 * (max_iter / 5) : t2 + 1;
+  }
+  __device__ bool step(int k) const { return k == t1 || k == t2 || k == t3; }
+};
+__device__ __forceinline__ void set_wave_priority(bool active, int k, const WavePrio& pr) {
+  if (__any(active && k >= pr.t3)) __builtin_amdgcn_s_setprio(3);
+  else if (__any(active && k >= pr.t2)) __builtin_amdgcn_s_setprio(2);
+  else if (__any(active && k >= pr.t1)) __builtin_amdgcn_s_setprio(1);
   else __builtin_amdgcn_s_setprio(0);
 }
-__device__ __forceinline__ bool priority_step(int k) { return k == 1000 || k == 4000 || k == 16000; }
 
 template <typename T>
 struct KArgs {
@@ -104,6 +115,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
 
   typename F::template Par<T> P;
   F::load(P, a.hp, a.gp, a.gkind, a.tau);
+  const WavePrio prio(a.max_iter);
   const int beg = a.cls_range[2 * a.cls], end = a.cls_range[2 * a.cls + 1];
   int32_t* head = a.heads + a.cls;
   const T sigma = a.sigma, tau = a.tau, theta = a.theta;
@@ -280,7 +292,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
       }
       pop_and_init();
     }
-    if (__any(done || (active && priority_step(k)))) set_wave_priority(active, k);
+    if (__any(done || (active && prio.step(k)))) set_wave_priority(active, k, prio);
   }
 }
 
@@ -301,6 +313,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_rec(
 
   typename F::template Par<T> P;
   F::load(P, a.hp, a.gp, a.gkind, a.tau);
+  const WavePrio prio(a.max_iter);
   const int beg = a.cls_range[2 * a.cls], end = a.cls_range[2 * a.cls + 1];
   int32_t* head = a.heads + a.cls;
   const T theta = a.theta;
@@ -569,7 +582,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_rec(
         pop_and_init();
       }
     }
-    if (__any(done || (active && priority_step(k)))) set_wave_priority(active, k);
+    if (__any(done || (active && prio.step(k)))) set_wave_priority(active, k, prio);
   }
 }
 
@@ -596,6 +609,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_mix(
 
   typename F::template Par<T> P;
   F::load(P, a.hp, a.gp, a.gkind, a.tau);
+  const WavePrio prio(a.max_iter);
   const int beg = a.cls_range[2 * a.cls], end = a.cls_range[2 * a.cls + 1];
   int32_t* head = a.heads + a.cls;
   const T sigma = a.sigma, tau = a.tau, theta = a.theta, wl = a.wl, wr = a.wr;
@@ -787,7 +801,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_mix(
       }
       pop_and_init();
     }
-    if (__any(done || (active && priority_step(k)))) set_wave_priority(active, k);
+    if (__any(done || (active && prio.step(k)))) set_wave_priority(active, k, prio);
   }
 }
 
@@ -822,6 +836,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
 
   typename F::template Par<T> P;
   F::load(P, a.hp, a.gp, a.gkind, a.tau);
+  const WavePrio prio(a.max_iter);
   const int beg = a.cls_range[2 * a.cls], end = a.cls_range[2 * a.cls + 1];
   int32_t* head = a.heads + a.cls;
   const T sigma = a.sigma, tau = a.tau, theta = a.theta;
@@ -1005,7 +1020,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
       }
       pop_and_init();
     }
-    if (__any(done || (active && priority_step(k)))) set_wave_priority(active, k);
+    if (__any(done || (active && prio.step(k)))) set_wave_priority(active, k, prio);
   }
 }
 
@@ -1022,6 +1037,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_game(KArgs<T
 
   typename F::template Par<T> P;
   F::load(P, a.hp, a.gp, a.gkind, a.tau);
+  const WavePrio prio(a.max_iter);
   const int beg = a.cls_range[2 * a.cls], end = a.cls_range[2 * a.cls + 1];
   int32_t* head = a.heads + a.cls;
   const T sigma = a.sigma, tau = a.tau, theta = a.theta;
@@ -1259,7 +1275,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_game(KArgs<T
       }
       pop_and_init();
     }
-    if (__any(done || (active && priority_step(k)))) set_wave_priority(active, k);
+    if (__any(done || (active && prio.step(k)))) set_wave_priority(active, k, prio);
   }
 }
 
@@ -1284,6 +1300,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_game_hopf(KA
 
   typename F::template Par<T> P;
   F::load(P, a.hp, a.gp, a.gkind, a.tau);
+  const WavePrio prio(a.max_iter);
   const int beg = a.cls_range[2 * a.cls], end = a.cls_range[2 * a.cls + 1];
   int32_t* head = a.heads + a.cls;
   const T sigma = a.sigma, tau = a.tau, theta = a.theta;
@@ -1433,7 +1450,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_game_hopf(KA
       }
       pop_and_init();
     }
-    if (__any(done || (active && priority_step(k)))) set_wave_priority(active, k);
+    if (__any(done || (active && prio.step(k)))) set_wave_priority(active, k, prio);
   }
 }
 
