@@ -153,12 +153,15 @@ def bench_configs(torch, dev, subset):
             o = s.alloc(w.n)
             s.solve(*inp, out=o)
             torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            s.solve(*inp, out=o)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1)
+            times = []
+            for _ in range(3 if label == "batched" else 1):  # median of 3: one launch can be an outlier
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                s.solve(*inp, out=o)
+                e1.record()
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            ms = float(np.median(times))
             conv = int((o.status == 0).sum())
             rec[label] = {"ms": ms, "converged": conv, "solves_per_s": conv / (ms * 1e-3)}
             s.close()

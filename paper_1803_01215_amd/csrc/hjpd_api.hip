@@ -256,18 +256,36 @@ hjpd::Tile default_tile(int cap) {
 
 const int kCaps[] = {8, 16, 32, 64, 96, 128, 192, 256};
 
-// Persistent grid: resident blocks per CU, at most kMaxBlocksPerCU (two
-// waves per SIMD).  A launch ends with its slowest points, which run their
-// iterations one after another; every extra wave on a SIMD takes issue slots
-// from them (a wave alone issues about twice as fast as one of three), while
-// two waves already keep the SIMD's issue slots busy on the bulk of points.
-constexpr int kMaxBlocksPerCU = 2;
-
+// Persistent grid at full occupancy: resident blocks per CU times CUs.
 int persistent_grid(hjpd_ctx* c, const void* kern) {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, 0) != hipSuccess || nb < 1) nb = 1;
-  if (nb > kMaxBlocksPerCU) nb = kMaxBlocksPerCU;
   return nb * c->n_cu;
+}
+
+// Grid of one class launch.  A persistent launch ends when its slowest points
+// have run all their iterations, one after another; every extra wave on their
+// SIMD takes issue slots from them (a wave alone issues about twice as fast as
+// one of three).  Unless the batch is many times what the grid holds at once,
+// when the bulk of points sets the launch time and a third wave per SIMD hides
+// more latency, the grid keeps at most kTailBlocksPerCU blocks per CU.  It
+// never has more blocks than the batch fills: with a small batch the waves
+// that would find the queue empty are not launched, so the busy waves spread
+// over the SIMDs instead of sharing some of them.
+constexpr int kTailBlocksPerCU = 2;
+constexpr int64_t kBulkFactor = 8;
+
+int launch_grid(const hjpd_ctx* c, const Cls& cl, int64_t n) {
+  const int per_block = 256 / cl.L;                          // points one block holds at once
+  const int64_t resident = int64_t(cl.grid) * per_block;     // points held at once, full occupancy
+  int64_t grid = cl.grid;
+  if (n <= kBulkFactor * resident) {
+    const int nb = cl.grid / c->n_cu;
+    grid = int64_t(nb < kTailBlocksPerCU ? nb : kTailBlocksPerCU) * c->n_cu;
+  }
+  const int64_t fill = (n + per_block - 1) / per_block;
+  if (grid > fill) grid = fill > 0 ? fill : 1;
+  return int(grid);
 }
 
 int build_plan(hjpd_ctx* c, const int* tile_override_L, const int* tile_override_K) {
@@ -470,7 +488,7 @@ int enqueue_solve(hjpd_ctx* c, int64_t n, const void* x, const void* t, const in
   } else {
     for (int ci = 0; ci < ncls; ci++) {
       a.cls = ci;
-      HIP_OK(hipLaunchKernel(c->plan[ci].kern, dim3(c->plan[ci].grid), dim3(256), args, 0, s),
+      HIP_OK(hipLaunchKernel(c->plan[ci].kern, dim3(launch_grid(c, c->plan[ci], n)), dim3(256), args, 0, s),
              "persistent kernel launch");
       launches++;
     }
