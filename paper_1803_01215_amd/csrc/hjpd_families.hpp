@@ -132,6 +132,18 @@ struct CNorm {
     }
   }
 
+  // The node-0 prox of the shifted layout when it is affine, prox(v) = m v + f:
+  // true for the shifted quadratic g, with (m, f) = (1/(1 + tau), tau a/(1 + tau))
+  // in the group's first lane and (1, 0) elsewhere; false for the norm g, whose
+  // prox (prox0) is not affine.
+  template <typename T>
+  __device__ static bool prox0_affine(const Par<T>& P, bool first, T& m, T (&f)[D]) {
+    m = first ? P.inv1pt : T(1);
+#pragma unroll
+    for (int i = 0; i < D; i++) f[i] = first ? P.sa[i] : T(0);
+    return P.gkind != kGNorm;
+  }
+
   // v <- shrink_2(v, mu) = v max(1 - mu/|v|, 0) (shrink_2(0) = 0); returns |v| after.
   template <typename T>
   __device__ static T shrink(T (&v)[D], T mu) {
@@ -149,12 +161,14 @@ struct CNorm {
   // Dual step of the shifted layout's slot 0 in the Hopf formulation, given
   // the threshold mu = sigma delta c(x_1): in the group's first lane (node 1)
   // the joint prox with g* (see dual_hopf1), elsewhere the plain shrink.
-  // Returns |p| after.
+  // v and mu are in units of `unit` (the kernel keeps the dual scaled by tau):
+  // the prox commutes with that scaling once a and the unit ball of g* are
+  // scaled too.  Returns |p| after, in the same units.
   template <typename T>
-  __device__ static T shrink_hopf1(const Par<T>& P, T (&v)[D], T mu, T sigma, bool first) {
+  __device__ static T shrink_hopf1(const Par<T>& P, T (&v)[D], T mu, T sigma, bool first, T unit) {
     if (P.gkind != kGNorm) {
       const T r1 = first ? T(1) / (T(1) + sigma) : T(1);
-      const T sg = first ? sigma : T(0);
+      const T sg = first ? sigma * unit : T(0);
 #pragma unroll
       for (int i = 0; i < D; i++) v[i] = (v[i] - sg * P.a[i]) * r1;
       mu *= r1;
@@ -165,7 +179,7 @@ struct CNorm {
     const bool nz = ss > T(0);
     const T rs = M<T>::rsqrt(ss);
     T len = nz ? M<T>::fmax(ss * rs - mu, T(0)) : T(0);
-    if (P.gkind == kGNorm && first) len = len < T(1) ? len : T(1);
+    if (P.gkind == kGNorm && first) len = len < unit ? len : unit;
     const T scale = nz ? len * rs : T(0);
 #pragma unroll
     for (int i = 0; i < D; i++) v[i] *= scale;

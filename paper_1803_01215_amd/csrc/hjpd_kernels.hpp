@@ -821,6 +821,15 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_mix(
 // scalar DPP row shifts.  Against k_group_control this removes the node-0
 // block that every lane issued for one lane per group, and the x_0, z_0
 // registers of every lane.
+// The dual is held scaled by tau (registers ps = tau p): the shrink commutes
+// with the scaling, so the dual step is unchanged in form, and the primal
+// difference term becomes ps_{j+1} - ps_j with no multiply.  Slots that do not
+// move (past N, and node 0 in the Hopf formulation) are masked where x and z
+// are updated, by a 0/1 factor per slot, instead of in every coordinate of the
+// step.  For the shifted quadratic g the node-0 prox is affine,
+// m (x_0 + dx) + f, and is applied to the step as m dx + ((m - 1) x_0 + f).
+// The p residual is tau^2 times the unscaled one and is tested against
+// tau^2 tol; the value and p outputs are scaled back by 1/tau.
 // Hopf formulation (Algorithm 2, kHopf): node 0 does not exist; its slot
 // keeps x_0 = z_0 = 0 (the Hopf difference operator) and takes no step, node
 // 1's dual step is the joint prox with g*, and the value has -g*(p_1) in
@@ -840,11 +849,16 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
   const int beg = a.cls_range[2 * a.cls], end = a.cls_range[2 * a.cls + 1];
   int32_t* head = a.heads + a.cls;
   const T sigma = a.sigma, tau = a.tau, theta = a.theta;
+  const T ts = tau * sigma, itau = T(1) / tau, tolp = a.tol * tau * tau;
+  // node-0 prox as m v + f (first lane; identity elsewhere) when it is affine
+  T m0, f0[D];
+  const bool aff0 = F::prox0_affine(P, first, m0, f0);
+  const T mm0 = m0 - T(1);
 
-  T x[K][D], p[K][D], z[K][D];
+  T x[K][D], ps[K][D], z[K][D];
   T xe[D], ce;      // the query point x and c(x) in the group's last lane, 0 elsewhere
-  T tj[K], tdj[K];  // per primal slot: tau and tau*delta where the node moves (j < N), else 0
-  T delta = T(0), sd = T(0), td = T(0);
+  T mv[K], mz[K];   // per primal slot: 1 and theta where the node moves, else 0
+  T delta = T(0), tsd = T(0);
   int Np = 0, k = 0;
   int64_t pt = -1;
   bool active = false;
@@ -859,8 +873,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
     pt = a.queue[qi];
     Np = a.N[pt];
     delta = a.t[pt] / T(Np);
-    sd = sigma * delta;
-    td = tau * delta;
+    tsd = ts * delta;
     k = 0;
     T xt[D];
 #pragma unroll
@@ -872,11 +885,11 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
 #pragma unroll
       for (int i = 0; i < D; i++) {
         x[kk][i] = moves ? init_x(xt[i], a.seed, pt, kArrX, j, i) : ((j < Np) ? T(0) : xt[i]);
-        p[kk][i] = (j + 1 <= Np) ? T(start_noise(a.seed, uint64_t(pt), kArrP, j + 1, i)) : T(0);
+        ps[kk][i] = (j + 1 <= Np) ? tau * T(start_noise(a.seed, uint64_t(pt), kArrP, j + 1, i)) : T(0);
         z[kk][i] = x[kk][i];
       }
-      tj[kk] = moves ? tau : T(0);
-      tdj[kk] = moves ? td : T(0);
+      mv[kk] = moves ? T(1) : T(0);
+      mz[kk] = moves ? theta : T(0);
     }
     T cq, g0, g1;
     F::speed(P, xt, cq, g0, g1);
@@ -897,69 +910,76 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
 #pragma unroll
     for (int i = 0; i < D; i++) znext[i] = group_next0<L>(z[0][i], l) + xe[i];
     const T cnext = group_next0<L>(cj[0], l) + ce;
-    // ---- dual step: p_{j+1} in slot kk -----------------------------------------
-    T pn[K];
+    // ---- dual step: tau p_{j+1} in slot kk -------------------------------------
+    T pn[K];  // tau |p_{j+1}|
     T rp = T(0), rx = T(0);
 #pragma unroll
     for (int kk = 0; kk < K; kk++) {
       T v[D];
 #pragma unroll
-      for (int i = 0; i < D; i++) v[i] = p[kk][i] + sigma * ((kk == K - 1 ? znext[i] : z[kk + 1][i]) - z[kk][i]);
+      for (int i = 0; i < D; i++) v[i] = ps[kk][i] + ts * ((kk == K - 1 ? znext[i] : z[kk + 1][i]) - z[kk][i]);
       const T cr = (kk == K - 1) ? cnext : cj[kk + 1];
       if constexpr (kHopf) {
-        if (kk == 0) pn[kk] = F::shrink_hopf1(P, v, sd * cr, sigma, first);  // node 1: with g*
-        else pn[kk] = F::shrink(v, sd * cr);
+        if (kk == 0) pn[kk] = F::shrink_hopf1(P, v, tsd * cr, sigma, first, tau);  // node 1: with g*
+        else pn[kk] = F::shrink(v, tsd * cr);
       } else {
-        pn[kk] = F::shrink(v, sd * cr);
+        pn[kk] = F::shrink(v, tsd * cr);
       }
 #pragma unroll
       for (int i = 0; i < D; i++) {
-        const T dp = v[i] - p[kk][i];
+        const T dp = v[i] - ps[kk][i];
         rp += dp * dp;
-        p[kk][i] = v[i];
+        ps[kk][i] = v[i];
       }
     }
     // ---- primal step: x_j in slot kk; p_j of the first slot from the previous
     //      lane (p_0 = 0 in the first lane) --------------------------------------
     T pprev[D];
 #pragma unroll
-    for (int i = 0; i < D; i++) pprev[i] = group_prev0<L>(p[K - 1][i], l);
+    for (int i = 0; i < D; i++) pprev[i] = group_prev0<L>(ps[K - 1][i], l);
     const T pnprev = group_prev0<L>(pn[K - 1], l);
 #pragma unroll
     for (int kk = 0; kk < K; kk++) {
-      const T coef = tdj[kk] * ((kk == 0) ? pnprev : pn[kk - 1]);
+      const T coef = delta * ((kk == 0) ? pnprev : pn[kk - 1]);  // tau delta |p_j|
       T dx[D];
 #pragma unroll
-      for (int i = 0; i < D; i++) {
-        const T pl = (kk == 0) ? pprev[i] : p[kk - 1][i];
-        dx[i] = -tj[kk] * (pl - p[kk][i]);
-      }
+      for (int i = 0; i < D; i++) dx[i] = ps[kk][i] - ((kk == 0) ? pprev[i] : ps[kk - 1][i]);
       dx[0] += coef * gc0[kk];
       dx[1] += coef * gc1[kk];
-      if (kk == 0) {
-        // node 0 (first lane): the prox of g after the step
-        T v[D];
+      if constexpr (!kHopf) {
+        if (kk == 0) {
+          // node 0 (first lane): the prox of g after the step
+          if (aff0) {
 #pragma unroll
-        for (int i = 0; i < D; i++) v[i] = x[0][i] + dx[i];
-        F::prox0(P, v, tau, first && !kHopf);  // Hopf: node 0 stays at 0
+            for (int i = 0; i < D; i++) dx[i] = m0 * dx[i] + (mm0 * x[0][i] + f0[i]);
+          } else {
+            T v[D];
 #pragma unroll
-        for (int i = 0; i < D; i++) dx[i] = v[i] - x[0][i];
+            for (int i = 0; i < D; i++) v[i] = x[0][i] + dx[i];
+            F::prox0(P, v, tau, first);
+#pragma unroll
+            for (int i = 0; i < D; i++) dx[i] = v[i] - x[0][i];
+          }
+        }
       }
+      T sx = T(0);
 #pragma unroll
       for (int i = 0; i < D; i++) {
-        rx += dx[i] * dx[i];
-        z[kk][i] = x[kk][i] + (T(1) + theta) * dx[i];
-        x[kk][i] += dx[i];
+        sx += dx[i] * dx[i];
+        x[kk][i] += mv[kk] * dx[i];
+        z[kk][i] = x[kk][i] + mz[kk] * dx[i];
       }
+      rx += mv[kk] * sx;
     }
     // ---- stopping rule (section 6 set-up) ------------------------------------
     k++;
     const T rxs = group_sum<L>(rx), rps = group_sum<L>(rp);
     const bool fin = M<T>::finite(rxs + rps);
-    const bool small = (rxs < a.tol) && (rps < a.tol);
+    const bool small = (rxs < a.tol) && (rps < tolp);
     const bool done = active && (!fin || (!a.fixed && small) || k >= a.max_iter);
     if (done) {
-      // value: g(x_0) + sum_j <p_j, x_j - x_{j-1}> - delta sum_j c(x_j) |p_j|
+      // value: g(x_0) + sum_j <p_j, x_j - x_{j-1}> - delta sum_j c(x_j) |p_j|,
+      // the sum taken over tau p and scaled back
 #pragma unroll
       for (int kk = 0; kk < K; kk++) F::speed(P, x[kk], cj[kk], gc0[kk], gc1[kk]);
       const T cn2 = group_next0<L>(cj[0], l) + ce;
@@ -975,15 +995,25 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
           T s = T(0), ss = T(0);
 #pragma unroll
           for (int i = 0; i < D; i++) {
-            s += p[kk][i] * ((kk == K - 1 ? xnext[i] : x[kk + 1][i]) - x[kk][i]);
-            ss += p[kk][i] * p[kk][i];
+            s += ps[kk][i] * ((kk == K - 1 ? xnext[i] : x[kk + 1][i]) - x[kk][i]);
+            ss += ps[kk][i] * ps[kk][i];
           }
           const T cr = (kk == K - 1) ? cn2 : cj[kk + 1];
           acc += s - delta * cr * M<T>::sqrt(ss);
-          bad |= !(all_finite<T, D>(x[kk]) && all_finite<T, D>(p[kk]));
+          bad |= !(all_finite<T, D>(x[kk]) && all_finite<T, D>(ps[kk]));
         }
       }
-      if (first) acc += kHopf ? -F::gstar(P, p[0]) : F::g(P, x[0]);  // Hopf: -g*(p_1), x_0 = 0
+      acc *= itau;
+      if (first) {
+        if constexpr (kHopf) {  // -g*(p_1), x_0 = 0
+          T p1[D];
+#pragma unroll
+          for (int i = 0; i < D; i++) p1[i] = ps[0][i] * itau;
+          acc -= F::gstar(P, p1);
+        } else {
+          acc += F::g(P, x[0]);
+        }
+      }
       acc = group_sum<L>(acc);
       bad = group_or<L>(bad);
       int st = !fin ? kNonFinite : (small ? kConverged : kMaxIter);
@@ -1012,7 +1042,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
           const int j = l * K + kk + 1;
           if (j <= Np)
 #pragma unroll
-            for (int i = 0; i < D; i++) a.ptraj[base + j * D + i] = p[kk][i];
+            for (int i = 0; i < D; i++) a.ptraj[base + j * D + i] = ps[kk][i] * itau;
         }
         if (first)
 #pragma unroll
