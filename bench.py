@@ -77,7 +77,30 @@ def mfma_flops_per_iter_lintanh(N: int, d: int) -> int:
     return 2 * d * d * (2 * N - 1)
 
 
-def bench_lintanh(torch, dev, steps):
+def oracle_sample(w, m):
+    """The FP64 oracle on the first m points of a workload (FP32-rounded
+    parameters, the GPU's stopping rule), OpenMP over points on the host's
+    cores: converged solves/s of the sample (fixed-iteration workloads count
+    every finished point), with the sample and thread count stated."""
+    from oracle import oracle as O
+    O.build()
+    m = min(m, w.n)
+    sub = w.subset(np.arange(m))
+    pb = O.Problem(sub.H, sub.g, sub.d, sub.d_y, sub.hp.astype(np.float32).astype(np.float64),
+                   sub.gp.astype(np.float32).astype(np.float64))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    r = O.solve(pb, sub.x, sub.t, sub.N, sigma=sub.sigma, tau=sub.tau, theta=sub.theta, tol=sub.tol,
+                max_iter=sub.max_iter, seed=sub.init_seed, N_max=sub.N_max, ids=sub.ids, threads=threads,
+                fixed_iters=sub.fixed_iters)
+    dt = time.perf_counter() - t0
+    done = m if sub.fixed_iters else int((r.status == 0).sum())
+    return {"value": done / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d of the %d points, FP64 C oracle, OpenMP over points, %.1f s wall, %d %s" % (
+                m, w.n, dt, done, "finished" if sub.fixed_iters else "converged")}
+
+
+def bench_lintanh(torch, dev, steps, cpu=False):
     """Forward solves/s and MFMA throughput at K = 500 fixed iterations, and
     the reverse-mode call (forward with checkpoints every 50 + backward +
     reductions) on the same 16,384 points."""
@@ -125,10 +148,11 @@ def bench_lintanh(torch, dev, steps):
             "mfma": {"bound": "mfma", "achieved": flops / (fwd_ms * 1e-3) / 1e12, "peak": PEAK["fp32_matrix"] / 1e12,
                      "unit": "TFLOP/s", "frac": flops / (fwd_ms * 1e-3) / PEAK["fp32_matrix"],
                      "kernel": "k_lt_forward<100>", "flops_per_launch": flops},
-            "value_grad_ms": vg_ms, "value_grad_points_per_s": w.n / (vg_ms * 1e-3), "ckpt_every": 50}
+            "value_grad_ms": vg_ms, "value_grad_points_per_s": w.n / (vg_ms * 1e-3), "ckpt_every": 50,
+            "cpu_oracle": oracle_sample(w, 64) if cpu else None}
 
 
-def bench_configs(torch, dev, subset):
+def bench_configs(torch, dev, subset, cpu=False):
     """Batched (persistent, default tiles, hipGraph) against plain (one point
     per lane) on the other workloads: the eikonal set in full (FP64), the
     quadrotor and pursuit-evasion sets on their first `subset` points (FP32,
@@ -166,6 +190,8 @@ def bench_configs(torch, dev, subset):
             rec[label] = {"ms": ms, "converged": conv, "solves_per_s": conv / (ms * 1e-3)}
             s.close()
         rec["speedup"] = rec["batched"]["solves_per_s"] / max(rec["plain"]["solves_per_s"], 1e-30)
+        if cpu:
+            rec["cpu_oracle"] = oracle_sample(w, {"eikonal2d": 256, "quadrotor12": 512, "pursuit12": 1024}[name])
         out[name] = rec
         if name == "quadrotor12":
             # robustness recipes (section 6): cap 5,000, then up to three more
@@ -362,26 +388,12 @@ def main():
     # ---- matrix-core path (linear-tanh, d = 100): forward and reverse mode ------------------
     c5_rec = None
     if not args.no_c5:
-        c5_rec = bench_lintanh(torch, dev, args.steps)
+        c5_rec = bench_lintanh(torch, dev, args.steps, cpu=not args.no_cpu)
 
-    cfg_rec = bench_configs(torch, dev, args.configs) if args.configs > 0 else None
+    cfg_rec = bench_configs(torch, dev, args.configs, cpu=not args.no_cpu) if args.configs > 0 else None
 
     # ---- CPU oracle baseline on a bounded sample ------------------------------------------
-    cpu_rec = None
-    if not args.no_cpu:
-        from oracle import oracle as O
-        O.build()
-        m = min(args.cpu_sample, n)
-        sub = w.subset(np.arange(m))
-        pb = O.Problem(sub.H, sub.g, sub.d, sub.d_y, sub.hp.astype(np.float32).astype(np.float64),
-                       sub.gp.astype(np.float32).astype(np.float64))
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        t0 = time.perf_counter()
-        r = O.solve(pb, sub.x, sub.t, sub.N, sigma=sub.sigma, tau=sub.tau, theta=sub.theta, tol=sub.tol,
-                    max_iter=sub.max_iter, seed=sub.init_seed, N_max=sub.N_max, ids=sub.ids, threads=threads)
-        dt = time.perf_counter() - t0
-        cpu_rec = {"value": float((r.status == 0).sum() / dt), "unit": "solves/s", "cores": threads, "kind": "oracle",
-                   "sample": "first %d of the %d points, FP64 C oracle, OpenMP over points, %.1f s wall" % (m, n, dt)}
+    cpu_rec = oracle_sample(w, args.cpu_sample) if not args.no_cpu else None
 
     rec = {
         "metric": "converged (x,t) solves/sec at PDHG residual 1e-6, batched vs plain kernel",
