@@ -829,7 +829,9 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_mix(
 // step.  For the shifted quadratic g the node-0 prox is affine,
 // m (x_0 + dx) + f, and is applied to the step as m dx + ((m - 1) x_0 + f).
 // The p residual is tau^2 times the unscaled one and is tested against
-// tau^2 tol; the value and p outputs are scaled back by 1/tau.
+// tau^2 tol; the value and p outputs are scaled back by 1/tau.  The p residual
+// matters only once the x residual is below tol; in FP32 tiles with at most
+// two nodes per lane it is formed only then.
 // Hopf formulation (Algorithm 2, kHopf): node 0 does not exist; its slot
 // keeps x_0 = z_0 = 0 (the Hopf difference operator) and takes no step, node
 // 1's dual step is the joint prox with g*, and the value has -g*(p_1) in
@@ -854,6 +856,10 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
   T m0, f0[D];
   const bool aff0 = F::prox0_affine(P, first, m0, f0);
   const T mm0 = m0 - T(1);
+  // Lazy p residual (below) keeps the previous dual live through the primal
+  // step: K*D more registers, taken only where the register budget is modest
+  // (FP32, at most two nodes per lane).
+  constexpr bool kLazyRp = sizeof(T) == 4 && K <= 2;
 
   T x[K][D], ps[K][D], z[K][D];
   T xe[D], ce;      // the query point x and c(x) in the group's last lane, 0 elsewhere
@@ -912,6 +918,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
     const T cnext = group_next0<L>(cj[0], l) + ce;
     // ---- dual step: tau p_{j+1} in slot kk -------------------------------------
     T pn[K];  // tau |p_{j+1}|
+    T pold[K][D];
     T rp = T(0), rx = T(0);
 #pragma unroll
     for (int kk = 0; kk < K; kk++) {
@@ -927,8 +934,12 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
       }
 #pragma unroll
       for (int i = 0; i < D; i++) {
-        const T dp = v[i] - ps[kk][i];
-        rp += dp * dp;
+        if constexpr (kLazyRp) {
+          pold[kk][i] = ps[kk][i];
+        } else {
+          const T dp = v[i] - ps[kk][i];
+          rp += dp * dp;
+        }
         ps[kk][i] = v[i];
       }
     }
@@ -973,7 +984,25 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
     }
     // ---- stopping rule (section 6 set-up) ------------------------------------
     k++;
-    const T rxs = group_sum<L>(rx), rps = group_sum<L>(rp);
+    // Lazy form: the p residual decides only where the x residual is already
+    // below tol, so it is formed (from the stored iterates) only when some
+    // group of the wave gets there, and is 0 otherwise.
+    const T rxs = group_sum<L>(rx);
+    T rps = T(0);
+    if constexpr (kLazyRp) {
+      if (__any(active && rxs < a.tol)) {
+#pragma unroll
+        for (int kk = 0; kk < K; kk++)
+#pragma unroll
+          for (int i = 0; i < D; i++) {
+            const T dp = ps[kk][i] - pold[kk][i];
+            rp += dp * dp;
+          }
+        rps = group_sum<L>(rp);
+      }
+    } else {
+      rps = group_sum<L>(rp);
+    }
     const bool fin = M<T>::finite(rxs + rps);
     const bool small = (rxs < a.tol) && (rps < tolp);
     const bool done = active && (!fin || (!a.fixed && small) || k >= a.max_iter);
