@@ -207,6 +207,11 @@ struct hjpd_ctx {
   size_t work_bytes = 0;
   // graph replay (captured on an internal stream, launched on the caller's)
   hipStream_t cap_stream = nullptr;
+  // capacity classes after the first run on side streams, forked from and
+  // joined back to the solve's stream (parallel branches of a captured graph)
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> ev_join;
+  hipEvent_t ev_fork = nullptr;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   std::vector<uintptr_t> gkey;
@@ -486,12 +491,24 @@ int enqueue_solve(hjpd_ctx* c, int64_t n, const void* x, const void* t, const in
     HIP_OK(hipLaunchKernel(c->plain_kern, dim3(nb), dim3(256), args, 0, s), "plain kernel launch");
     launches = 1;
   } else {
-    for (int ci = 0; ci < ncls; ci++) {
+    // One persistent launch per capacity class.  Each launch ends with its own
+    // slowest points; the classes run on parallel branches (class 0 on the
+    // solve's stream, the others on side streams forked from it and joined
+    // back), so one class's tail overlaps the others' bulk.  The classes read
+    // disjoint queue segments and write disjoint points.
+    const bool fork = ncls > 1 && int(c->side.size()) >= ncls - 1;
+    if (fork) HIP_OK(hipEventRecord(c->ev_fork, s), "hipEventRecord");
+    for (int ci = ncls - 1; ci >= 0; ci--) {
+      hipStream_t st = (fork && ci > 0) ? c->side[ci - 1] : s;
+      if (st != s) HIP_OK(hipStreamWaitEvent(st, c->ev_fork, 0), "hipStreamWaitEvent");
       a.cls = ci;
-      HIP_OK(hipLaunchKernel(c->plan[ci].kern, dim3(launch_grid(c, c->plan[ci], n)), dim3(256), args, 0, s),
+      HIP_OK(hipLaunchKernel(c->plan[ci].kern, dim3(launch_grid(c, c->plan[ci], n)), dim3(256), args, 0, st),
              "persistent kernel launch");
+      if (st != s) HIP_OK(hipEventRecord(c->ev_join[ci - 1], st), "hipEventRecord");
       launches++;
     }
+    if (fork)
+      for (int ci = 1; ci < ncls; ci++) HIP_OK(hipStreamWaitEvent(s, c->ev_join[ci - 1], 0), "hipStreamWaitEvent");
   }
   if (timed) HIP_OK(hipEventRecord(c->ev1, s), "hipEventRecord");
   c->timing_launches = launches;
@@ -561,6 +578,23 @@ int hjpd_create(const hjpd_desc* desc, hjpd_ctx** out) {
   } else {
     rc = build_plan(c, nullptr, nullptr);
     if (!rc) rc = upload_plan(c);
+    if (!rc && c->plan.size() > 1) {
+      if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess) rc = fail(HJPD_EDEVICE, "hipEventCreate failed");
+      for (size_t ci = 1; ci < c->plan.size() && !rc; ci++) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+          rc = fail(HJPD_EDEVICE, "hipStreamCreate failed");
+          break;
+        }
+        c->side.push_back(st);
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+          rc = fail(HJPD_EDEVICE, "hipEventCreate failed");
+          break;
+        }
+        c->ev_join.push_back(ev);
+      }
+    }
     if (!rc && (hipMalloc(&c->d_counts, sizeof(int32_t) * (desc->N_max + 1) * kHintBuckets) != hipSuccess ||
                 hipMalloc(&c->d_cursor, sizeof(int32_t) * (desc->N_max + 1) * kHintBuckets) != hipSuccess))
       rc = fail(HJPD_ENOMEM, "counter allocation");
@@ -592,6 +626,9 @@ int hjpd_destroy(hjpd_ctx* c) {
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  for (hipStream_t st : c->side) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : c->ev_join) (void)hipEventDestroy(ev);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->lt) hjpd::lt_destroy(c->lt);
   delete c;
   return HJPD_OK;
