@@ -587,225 +587,6 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_rec(
 }
 
 // ---------------------------------------------------------------------------
-// Persistent lane-group kernel for the weighted Euler discretisations of the
-// Lax saddle (section 4.1: eq. disclaxFE, and the trapezoidal average of the
-// forward and backward Euler rules), eikonal family H = c(x)|p|.  With p_j
-// the costate of the interval (j-1, j) the saddle is
-//   g(x_0) + sum_j <p_j, x_j - x_{j-1}> - delta sum_j (wl c(x_{j-1}) + wr c(x_j)) |p_j|
-// ((wl, wr) = (1, 0) forward Euler, (1/2, 1/2) trapezoid).  Per iteration:
-//   p_j <- shrink_2(p_j + sigma (z_j - z_{j-1}), sigma delta (wl c(x_{j-1}) + wr c(x_j)))
-//   x_0 <- prox_{tau g}(x_0 + tau p_1 + tau delta wl |p_1| grad c(x_0))
-//   x_j <- x_j - tau (p_j - p_{j+1}) + tau delta (wr |p_j| + wl |p_{j+1}|) grad c(x_j)
-// (x_0 in the increment form of k_group_control's node-0 step.)  Same lane layout, queue and stopping rule as k_group_control; the speed of
-// the node left of a lane's first node and the norm of the costate right of
-// its last node cross the lane boundary as one DPP value each.
-// ---------------------------------------------------------------------------
-template <typename T, class F, int L, int K>
-__global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_mix(KArgs<T> a) {
-  constexpr int D = F::D;
-  const int lane = threadIdx.x & 63;
-  const int l = lane & (L - 1);
-  const int leader = lane - l;
-
-  typename F::template Par<T> P;
-  F::load(P, a.hp, a.gp, a.gkind, a.tau);
-  const WavePrio prio(a.max_iter);
-  const int beg = a.cls_range[2 * a.cls], end = a.cls_range[2 * a.cls + 1];
-  int32_t* head = a.heads + a.cls;
-  const T sigma = a.sigma, tau = a.tau, theta = a.theta, wl = a.wl, wr = a.wr;
-
-  T x[K][D], p[K][D], z[K][D], x0[D], z0[D];
-  T tj[K], tdj[K];  // per node: tau and tau*delta where the node takes a primal step, else 0
-  T delta = T(0), sd = T(0), td = T(0);
-  int Np = 0, k = 0;
-  int64_t pt = -1;
-  bool active = false;
-
-  auto pop_and_init = [&]() {
-    int idx = 0;
-    if (l == 0) idx = atomicAdd(head, 1);
-    idx = __shfl(idx, leader, 64);
-    const int qi = beg + idx;
-    active = qi < end;
-    if (!active) return;
-    pt = a.queue[qi];
-    Np = a.N[pt];
-    delta = a.t[pt] / T(Np);
-    sd = sigma * delta;
-    td = tau * delta;
-    k = 0;
-    T xt[D];
-#pragma unroll
-    for (int i = 0; i < D; i++) xt[i] = a.x[pt * a.d + i];
-#pragma unroll
-    for (int kk = 0; kk < K; kk++) {
-      const int j = 1 + l * K + kk;
-#pragma unroll
-      for (int i = 0; i < D; i++) {
-        x[kk][i] = (j < Np) ? init_x(xt[i], a.seed, pt, kArrX, j, i) : xt[i];
-        p[kk][i] = (j <= Np) ? T(start_noise(a.seed, uint64_t(pt), kArrP, j, i)) : T(0);
-        z[kk][i] = x[kk][i];
-      }
-      tj[kk] = (j < Np) ? tau : T(0);
-      tdj[kk] = (j < Np) ? td : T(0);
-    }
-#pragma unroll
-    for (int i = 0; i < D; i++) {
-      x0[i] = (l == 0) ? init_x(xt[i], a.seed, pt, kArrX, 0, i) : T(0);
-      z0[i] = x0[i];
-    }
-  };
-
-  pop_and_init();
-
-  while (__any(active)) {
-    // ---- speeds at the current iterate ------------------------------------
-    T cj[K], gc0[K], gc1[K], c0, g00, g01;
-#pragma unroll
-    for (int kk = 0; kk < K; kk++) F::speed(P, x[kk], cj[kk], gc0[kk], gc1[kk]);
-    F::speed(P, x0, c0, g00, g01);  // only c0 is kept: the node-0 step re-evaluates grad c(x_0)
-    // speed of the node left of the lane's first node: node 0 in the group's
-    // first lane, else the previous lane's last node.  The shift is taken by
-    // every lane and the first lane's term added: a select around the DPP
-    // read lets the compiler run it with the first lane masked off, and a
-    // masked-off source lane reads as 0.
-    const T cprev = group_prev0<L>(cj[K - 1], l) + ((l == 0) ? c0 : T(0));
-    // ---- dual step -----------------------------------------------------------
-    T zprev[D];
-#pragma unroll
-    for (int i = 0; i < D; i++) zprev[i] = group_prev0<L>(z[K - 1][i], l) + z0[i];
-    T pn[K];
-    T rp = T(0), rx = T(0);
-#pragma unroll
-    for (int kk = 0; kk < K; kk++) {
-      T v[D];
-#pragma unroll
-      for (int i = 0; i < D; i++) v[i] = p[kk][i] + sigma * (z[kk][i] - (kk == 0 ? zprev[i] : z[kk - 1][i]));
-      const T cl = (kk == 0) ? cprev : cj[kk - 1];
-      pn[kk] = F::shrink(v, sd * (wl * cl + wr * cj[kk]));
-#pragma unroll
-      for (int i = 0; i < D; i++) {
-        const T dp = v[i] - p[kk][i];
-        rp += dp * dp;
-        p[kk][i] = v[i];
-      }
-    }
-    // ---- node 0: proximal-gradient step ------------------------------------
-    T pnext[D];
-#pragma unroll
-    for (int i = 0; i < D; i++) pnext[i] = group_next0<L>(p[0][i], l);
-    const T pnnext = group_next0<L>(pn[0], l);
-    if (l == 0) {
-      // prox_{tau g}(x_0 + tau q) - x_0 with q = p_1 + delta wl |p_1| grad c(x_0)
-      // (the increment form of the node-0 step)
-      T q[D], dx0[D];
-#pragma unroll
-      for (int i = 0; i < D; i++) q[i] = p[0][i];
-      F::speed(P, x0, c0, g00, g01);
-      const T s0 = delta * wl * pn[0];
-      q[0] += s0 * g00;
-      q[1] += s0 * g01;
-      F::step0(P, x0, q, tau, dx0);
-#pragma unroll
-      for (int i = 0; i < D; i++) {
-        rx += dx0[i] * dx0[i];
-        z0[i] = x0[i] + (T(1) + theta) * dx0[i];
-        x0[i] += dx0[i];
-      }
-    }
-    // ---- primal step, nodes 1..N-1 (tau and tau*delta are 0 from node N on) ---
-#pragma unroll
-    for (int kk = 0; kk < K; kk++) {
-      const T pr = (kk == K - 1) ? pnnext : pn[kk + 1];
-      const T coef = tdj[kk] * (wr * pn[kk] + wl * pr);
-#pragma unroll
-      for (int i = 0; i < D; i++) {
-        const T pp = (kk == K - 1) ? pnext[i] : p[kk + 1][i];
-        T dx = -tj[kk] * (p[kk][i] - pp);
-        if (i == 0) dx += coef * gc0[kk];
-        if (i == 1) dx += coef * gc1[kk];
-        rx += dx * dx;
-        z[kk][i] = x[kk][i] + (T(1) + theta) * dx;
-        x[kk][i] += dx;
-      }
-    }
-    // ---- stopping rule (section 6 set-up) ------------------------------------
-    k++;
-    const T rxs = group_sum<L>(rx), rps = group_sum<L>(rp);
-    const bool fin = M<T>::finite(rxs + rps);
-    const bool small = (rxs < a.tol) && (rps < a.tol);
-    const bool done = active && (!fin || (!a.fixed && small) || k >= a.max_iter);
-    if (done) {
-      // value: the weighted Lagrangian at the last iterate
-#pragma unroll
-      for (int kk = 0; kk < K; kk++) F::speed(P, x[kk], cj[kk], gc0[kk], gc1[kk]);
-      F::speed(P, x0, c0, g00, g01);
-      const T cl0 = group_prev0<L>(cj[K - 1], l) + ((l == 0) ? c0 : T(0));
-      T xprev[D];
-#pragma unroll
-      for (int i = 0; i < D; i++) xprev[i] = group_prev0<L>(x[K - 1][i], l) + x0[i];
-      T acc = T(0);
-      int bad = 0;
-#pragma unroll
-      for (int kk = 0; kk < K; kk++) {
-        const int j = 1 + l * K + kk;
-        if (j <= Np) {
-          T s = T(0), ss = T(0);
-#pragma unroll
-          for (int i = 0; i < D; i++) {
-            s += p[kk][i] * (x[kk][i] - (kk == 0 ? xprev[i] : x[kk - 1][i]));
-            ss += p[kk][i] * p[kk][i];
-          }
-          const T cl = (kk == 0) ? cl0 : cj[kk - 1];
-          acc += s - delta * (wl * cl + wr * cj[kk]) * M<T>::sqrt(ss);
-          bad |= !(all_finite<T, D>(x[kk]) && all_finite<T, D>(p[kk]));
-        }
-      }
-      if (l == 0) {
-        acc += F::g(P, x0);
-        bad |= !all_finite<T, D>(x0);
-      }
-      acc = group_sum<L>(acc);
-      bad = group_or<L>(bad);
-      int st = !fin ? kNonFinite : (small ? kConverged : kMaxIter);
-      if (bad || !M<T>::finite(acc)) st = kNonFinite;
-      if (l == 0) {
-        a.phi[pt] = acc;
-        a.iters[pt] = k;
-        a.status[pt] = st;
-      }
-      const int64_t base = pt * int64_t(a.N_max + 1) * a.d;
-      if (a.xtraj) {
-#pragma unroll
-        for (int kk = 0; kk < K; kk++) {
-          const int j = 1 + l * K + kk;
-          if (j <= Np)
-#pragma unroll
-            for (int i = 0; i < D; i++) a.xtraj[base + j * D + i] = x[kk][i];
-        }
-        if (l == 0)
-#pragma unroll
-          for (int i = 0; i < D; i++) a.xtraj[base + i] = x0[i];
-      }
-      if (a.ptraj) {
-#pragma unroll
-        for (int kk = 0; kk < K; kk++) {
-          const int j = 1 + l * K + kk;
-          if (j <= Np)
-#pragma unroll
-            for (int i = 0; i < D; i++) a.ptraj[base + j * D + i] = p[kk][i];
-        }
-        if (l == 0)
-#pragma unroll
-          for (int i = 0; i < D; i++) a.ptraj[base + i] = T(0);
-      }
-      pop_and_init();
-    }
-    if (__any(done || (active && prio.step(k)))) set_wave_priority(active, k, prio);
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Persistent lane-group kernel for the eikonal family, Lax formulation, with
 // the node layout shifted by one: slot kk of lane l holds the primal node
 // j = lK + kk (x_j, z_j) and the dual node j + 1 (p_{j+1}).  Node 0 is the
@@ -837,8 +618,21 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_mix(
 // 1's dual step is the joint prox with g*, and the value has -g*(p_1) in
 // place of g(x_0).
 // ---------------------------------------------------------------------------
+// The family F marked for the weighted Euler rules (forward Euler, trapezoid)
+// in k_group_control_shift: the saddle g(x_0) + sum_j <p_j, x_j - x_{j-1}> -
+// delta sum_j (wl c(x_{j-1}) + wr c(x_j)) |p_j| (KArgs::wl, wr).  Slot kk's
+// dual p_{j+1} shrinks by sigma delta (wl c(x_j) + wr c(x_{j+1})); x_j's
+// gradient weight is tau delta (wr |p_j| + wl |p_{j+1}|), so node 0 takes the
+// proximal-gradient step prox_{tau g}(x_0 + tau p_1 + tau delta wl |p_1|
+// grad c(x_0)).
+template <class F> struct Weighted : F {};
+template <class F> struct IsWeighted { static constexpr bool value = false; };
+template <class F> struct IsWeighted<Weighted<F>> { static constexpr bool value = true; };
+
 template <typename T, class F, int L, int K, bool kHopf>
 __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shift(KArgs<T> a) {
+  constexpr bool kMix = IsWeighted<F>::value;  // the weighted Euler rules (Weighted<F> below)
+  static_assert(!(kHopf && kMix), "weighted Euler rules are built for the Lax formulation only");
   constexpr int D = F::D;
   const int lane = threadIdx.x & 63;
   const int l = lane & (L - 1);
@@ -852,6 +646,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
   int32_t* head = a.heads + a.cls;
   const T sigma = a.sigma, tau = a.tau, theta = a.theta;
   const T ts = tau * sigma, itau = T(1) / tau, tolp = a.tol * tau * tau;
+  const T wl = a.wl, wr = a.wr;  // weighted rule (kMix): H weights at an interval's left / right node
   // node-0 prox as m v + f (first lane; identity elsewhere) when it is affine
   T m0, f0[D];
   const bool aff0 = F::prox0_affine(P, first, m0, f0);
@@ -925,7 +720,10 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
       T v[D];
 #pragma unroll
       for (int i = 0; i < D; i++) v[i] = ps[kk][i] + ts * ((kk == K - 1 ? znext[i] : z[kk + 1][i]) - z[kk][i]);
-      const T cr = (kk == K - 1) ? cnext : cj[kk + 1];
+      // interval (j, j+1): speed of its right node; the weighted rule mixes
+      // in its left node's (this slot's own primal node)
+      const T cr = kMix ? wl * cj[kk] + wr * ((kk == K - 1) ? cnext : cj[kk + 1])
+                        : ((kk == K - 1) ? cnext : cj[kk + 1]);
       if constexpr (kHopf) {
         if (kk == 0) pn[kk] = F::shrink_hopf1(P, v, tsd * cr, sigma, first, tau);  // node 1: with g*
         else pn[kk] = F::shrink(v, tsd * cr);
@@ -951,7 +749,10 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
     const T pnprev = group_prev0<L>(pn[K - 1], l);
 #pragma unroll
     for (int kk = 0; kk < K; kk++) {
-      const T coef = delta * ((kk == 0) ? pnprev : pn[kk - 1]);  // tau delta |p_j|
+      // tau delta |p_j| (interval (j-1, j)); the weighted rule takes
+      // tau delta (wr |p_j| + wl |p_{j+1}|), x_j bounding both intervals
+      const T pj = (kk == 0) ? pnprev : pn[kk - 1];
+      const T coef = kMix ? delta * (wr * pj + wl * pn[kk]) : delta * pj;
       T dx[D];
 #pragma unroll
       for (int i = 0; i < D; i++) dx[i] = ps[kk][i] - ((kk == 0) ? pprev[i] : ps[kk - 1][i]);
@@ -1027,7 +828,8 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
             s += ps[kk][i] * ((kk == K - 1 ? xnext[i] : x[kk + 1][i]) - x[kk][i]);
             ss += ps[kk][i] * ps[kk][i];
           }
-          const T cr = (kk == K - 1) ? cn2 : cj[kk + 1];
+          const T cr = kMix ? wl * cj[kk] + wr * ((kk == K - 1) ? cn2 : cj[kk + 1])
+                            : ((kk == K - 1) ? cn2 : cj[kk + 1]);
           acc += s - delta * cr * M<T>::sqrt(ss);
           bad |= !(all_finite<T, D>(x[kk]) && all_finite<T, D>(ps[kk]));
         }
@@ -1082,6 +884,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shif
     if (__any(done || (active && prio.step(k)))) set_wave_priority(active, k, prio);
   }
 }
+
 
 // ---------------------------------------------------------------------------
 // Persistent lane-group kernel, game path (Algorithm 3) for games whose

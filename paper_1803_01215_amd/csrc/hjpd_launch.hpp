@@ -30,7 +30,7 @@ const void* group_ptr(int variant) {
     if (variant == kVarRecipe) return reinterpret_cast<const void*>(&k_group_control_rec<T, F, L, K, true>);
     if constexpr (F::kMix) {
       // eikonal family: the shifted layout (Algorithms 1 and 2) or the weighted rules
-      if (variant == kVarMix) return reinterpret_cast<const void*>(&k_group_control_mix<T, F, L, K>);
+      if (variant == kVarMix) return reinterpret_cast<const void*>(&k_group_control_shift<T, Weighted<F>, L, K, false>);
       if (variant == kVarShiftHopf) return reinterpret_cast<const void*>(&k_group_control_shift<T, F, L, K, true>);
       return reinterpret_cast<const void*>(&k_group_control_shift<T, F, L, K, false>);
     } else {
