@@ -37,6 +37,13 @@ namespace hjpd {
 template <typename T, int K>
 inline constexpr int kGroupWaves = sizeof(T) == 8 ? 1 : (K == 1 ? 4 : (K == 2 ? 3 : 2));
 
+// The shifted-layout kernel in FP64 with at most two nodes per lane is held
+// to two waves per SIMD (256 VGPRs, a few spilled to scratch): unconstrained
+// it takes 284 registers and one wave per SIMD, and the second wave hides more
+// than the spills cost (cnorm10, 16x2: 17.1 -> 13.5 ms).
+template <typename T, int K>
+inline constexpr int kShiftWaves = (sizeof(T) == 8 && K <= 2) ? 2 : kGroupWaves<T, K>;
+
 // Issue priority of a wave (s_setprio) from the iteration count of the
 // oldest point it holds.  A point still iterating after a tenth, a fifth and
 // two fifths of the iteration cap is in the slow tail of the batch: the few
@@ -630,7 +637,7 @@ template <class F> struct IsWeighted { static constexpr bool value = false; };
 template <class F> struct IsWeighted<Weighted<F>> { static constexpr bool value = true; };
 
 template <typename T, class F, int L, int K, bool kHopf>
-__global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_shift(KArgs<T> a) {
+__global__ void __launch_bounds__(256, (kShiftWaves<T, K>)) k_group_control_shift(KArgs<T> a) {
   constexpr bool kMix = IsWeighted<F>::value;  // the weighted Euler rules (Weighted<F> below)
   static_assert(!(kHopf && kMix), "weighted Euler rules are built for the Lax formulation only");
   constexpr int D = F::D;
