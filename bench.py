@@ -382,8 +382,25 @@ def main():
         o64 = b64.alloc(n)
         ms64 = timed_steps(b64, inp64, o64, max(1, args.steps // 2), 1)
         c64 = int((o64.status.cpu().numpy() == 0).sum())
-        fp64_rec = {"value": c64 / (ms64 * 1e-3), "ms_per_step": ms64, "converged": c64}
+        it64 = o64.iters.cpu().numpy().astype(np.int64)
         b64.close()
+        # the FP64 kernel's own time (library HIP events, one launch per solve)
+        p64 = make(torch.float64, timing=True, lanes_per_point=16, nodes_per_lane=2)
+        q64 = p64.alloc(n)
+        p64.solve(*inp64, out=q64)
+        k64 = []
+        for _ in range(max(1, args.steps // 2)):
+            p64.solve(*inp64, out=q64)
+            k64.append(p64.timing()[0])
+        p64.close()
+        kms64 = float(np.mean(k64))
+        fl64 = float(sum(it64 * flops_per_iter_cnorm(w.N_max, w.d)))
+        fp64_rec = {"value": c64 / (ms64 * 1e-3), "ms_per_step": ms64, "converged": c64,
+                    "roofline": {"bound": "alu", "achieved": fl64 / (kms64 * 1e-3) / 1e12,
+                                 "peak": PEAK["fp64_vector"] / 1e12, "unit": "TFLOP/s",
+                                 "frac": fl64 / (kms64 * 1e-3) / PEAK["fp64_vector"],
+                                 "kernel": "k_group_control_shift<double, CNorm<10>, 16, 2, false>",
+                                 "kernel_ms": kms64, "flops_per_launch": fl64}}
 
     # ---- matrix-core path (linear-tanh, d = 100): forward and reverse mode ------------------
     c5_rec = None
