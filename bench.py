@@ -152,6 +152,43 @@ def bench_lintanh(torch, dev, steps, cpu=False):
             "cpu_oracle": oracle_sample(w, 64) if cpu else None}
 
 
+def bench_full_sets(torch, dev):
+    """The batched path (persistent, default tiles, hipGraph) on the full
+    quadrotor set with both trajectories written and on the full
+    pursuit-evasion set: one warm-up, then the median of two solves."""
+    import workloads as W
+    from paper_1803_01215_amd.solver import Solver
+
+    out = {}
+    for name, traj in (("quadrotor12", True), ("pursuit12", False)):
+        w = W.get(name)
+        td = torch.float32
+        inp = (torch.tensor(w.x, dtype=td, device=dev), torch.tensor(w.t, dtype=td, device=dev),
+               torch.tensor(w.N, dtype=torch.int32, device=dev), torch.tensor(w.hp, dtype=td, device=dev),
+               torch.tensor(w.gp, dtype=td, device=dev))
+        s = Solver(d=w.d, d_y=w.d_y, H=w.H, g=w.g, N_max=w.N_max, sigma=w.sigma, tau=w.tau, theta=w.theta,
+                   tol=w.tol, max_iter=w.max_iter, seed=w.init_seed, dtype=td, graph=True)
+        o = s.alloc(w.n, traj=traj)
+        s.solve(*inp, out=o, traj=traj)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s.solve(*inp, out=o, traj=traj)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        conv = int((o.status == 0).sum())
+        out[name] = {"points": w.n, "dtype": "f32", "max_iter": w.max_iter, "trajectories": traj, "ms": ms,
+                     "converged": conv, "solves_per_s": conv / (ms * 1e-3),
+                     "iterations": int(o.iters.to(torch.int64).sum())}
+        s.close()
+        del o, inp
+    return out
+
+
 def bench_configs(torch, dev, subset, cpu=False):
     """Batched (persistent, default tiles, hipGraph) against plain (one point
     per lane) on the other workloads: the eikonal set in full (FP64), the
@@ -236,6 +273,9 @@ def main():
     ap.add_argument("--configs", type=int, default=0, metavar="M",
                     help="also time batched vs plain on the eikonal, quadrotor and pursuit-evasion workloads "
                          "(the last two on their first M points)")
+    ap.add_argument("--full-sets", action="store_true",
+                    help="also time the batched path on the full quadrotor set (131,072 points, trajectories "
+                         "written) and the full pursuit-evasion set (262,144 points)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -408,6 +448,7 @@ def main():
         c5_rec = bench_lintanh(torch, dev, args.steps, cpu=not args.no_cpu)
 
     cfg_rec = bench_configs(torch, dev, args.configs, cpu=not args.no_cpu) if args.configs > 0 else None
+    full_rec = bench_full_sets(torch, dev) if args.full_sets else None
 
     # ---- CPU oracle baseline on a bounded sample ------------------------------------------
     cpu_rec = oracle_sample(w, args.cpu_sample) if not args.no_cpu else None
@@ -434,6 +475,7 @@ def main():
         "isaacs2_game_hopf": isaacs_rec,
         "lintanh100": c5_rec,
         "configs": cfg_rec,
+        "full_sets": full_rec,
     }
     print(json.dumps(rec))
 
