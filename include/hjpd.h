@@ -36,8 +36,12 @@
  *    costate is -q (section 4.2).
  *  - Calls are asynchronous: work is enqueued on `stream` (a hipStream_t; NULL
  *    means the default stream) and outputs are valid once the stream has
- *    completed.  Calls on one context must not overlap in time (the context's
- *    work queue and scratch are shared by its calls).
+ *    completed.  A solve with several capacity classes runs all but the first
+ *    on the context's own streams, forked from `stream` by an event after the
+ *    work already on it and joined back to it before the call's work ends, so
+ *    ordering with respect to `stream` is as if everything ran on it.  Calls
+ *    on one context must not overlap in time (the context's work queue, side
+ *    streams and scratch are shared by its calls).
  *  - Return codes are HJPD_* below; on a non-OK return hjpd_last_error()
  *    gives a message (thread-local, valid until the next call on the thread).
  *    Non-convergence is not an error: it is reported per point in `status`.

@@ -638,7 +638,7 @@ template <class F> struct IsWeighted<Weighted<F>> { static constexpr bool value 
 
 template <typename T, class F, int L, int K, bool kHopf>
 __global__ void __launch_bounds__(256, (kShiftWaves<T, K>)) k_group_control_shift(KArgs<T> a) {
-  constexpr bool kMix = IsWeighted<F>::value;  // the weighted Euler rules (Weighted<F> below)
+  constexpr bool kMix = IsWeighted<F>::value;  // the weighted Euler rules (F = Weighted<...>, above)
   static_assert(!(kHopf && kMix), "weighted Euler rules are built for the Lax formulation only");
   constexpr int D = F::D;
   const int lane = threadIdx.x & 63;
