@@ -154,20 +154,23 @@ def bench_lintanh(torch, dev, steps, cpu=False):
 
 def bench_full_sets(torch, dev):
     """The batched path (persistent, default tiles, hipGraph) on the full
-    quadrotor set with both trajectories written and on the full
+    quadrotor set with both trajectories written (Lax, and the Hopf
+    formulation the paper uses for its quadcopter) and on the full
     pursuit-evasion set: one warm-up, then the median of two solves."""
     import workloads as W
     from paper_1803_01215_amd.solver import Solver
 
     out = {}
-    for name, traj in (("quadrotor12", True), ("pursuit12", False)):
+    for key, name, traj, hopf in (("quadrotor12", "quadrotor12", True, False),
+                                  ("quadrotor12_hopf", "quadrotor12", True, True),
+                                  ("pursuit12", "pursuit12", False, False)):
         w = W.get(name)
         td = torch.float32
         inp = (torch.tensor(w.x, dtype=td, device=dev), torch.tensor(w.t, dtype=td, device=dev),
                torch.tensor(w.N, dtype=torch.int32, device=dev), torch.tensor(w.hp, dtype=td, device=dev),
                torch.tensor(w.gp, dtype=td, device=dev))
         s = Solver(d=w.d, d_y=w.d_y, H=w.H, g=w.g, N_max=w.N_max, sigma=w.sigma, tau=w.tau, theta=w.theta,
-                   tol=w.tol, max_iter=w.max_iter, seed=w.init_seed, dtype=td, graph=True)
+                   tol=w.tol, max_iter=w.max_iter, seed=w.init_seed, dtype=td, graph=True, hopf=hopf)
         o = s.alloc(w.n, traj=traj)
         s.solve(*inp, out=o, traj=traj)
         torch.cuda.synchronize()
@@ -181,7 +184,8 @@ def bench_full_sets(torch, dev):
             times.append(e0.elapsed_time(e1))
         ms = float(np.median(times))
         conv = int((o.status == 0).sum())
-        out[name] = {"points": w.n, "dtype": "f32", "max_iter": w.max_iter, "trajectories": traj, "ms": ms,
+        out[key] = {"points": w.n, "dtype": "f32", "max_iter": w.max_iter, "trajectories": traj,
+                    "formulation": "Hopf (Algorithm 2)" if hopf else "Lax (Algorithm 1)", "ms": ms,
                      "converged": conv, "solves_per_s": conv / (ms * 1e-3),
                      "iterations": int(o.iters.to(torch.int64).sum())}
         s.close()
@@ -275,7 +279,7 @@ def main():
                          "(the last two on their first M points)")
     ap.add_argument("--full-sets", action="store_true",
                     help="also time the batched path on the full quadrotor set (131,072 points, trajectories "
-                         "written) and the full pursuit-evasion set (262,144 points)")
+                         "written; Lax and Hopf) and the full pursuit-evasion set (262,144 points)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()

@@ -149,7 +149,10 @@ enum {
                                     Lax (Algorithm 1): nodes 1..N, no x_0; the dual step at j = 1 is the
                                     joint prox of g* + delta H(x_1,.) (Appendix A.1.2); the value is
                                     -g*(p_1) + <p_N,x> + sum_{j<N} <p_j - p_{j+1}, x_j> - delta sum H.
-                                    Built for H = CNORM with g = NORM or QUAD_SHIFT (control path);
+                                    Built for H = CNORM with g = NORM or QUAD_SHIFT (control path) and
+                                    for H = QUADROTOR with g = QUAD_SHIFT (persistent kernel; node 1's
+                                    step is the family's p-prox with step sigma delta/(1 + sigma) at
+                                    (v - sigma a)/(1 + sigma));
                                     for H = ISAACS it selects the game Hopf formulation (section 4.2
                                     eq. discgenlaxhopfdghopf, Algorithm 4): value -e*(p_1) - h_*(-q_1)
                                     + <p_N,x> - <q_N,y> + sum_{j<N} (<p_j - p_{j+1}, x_j>

@@ -718,25 +718,27 @@ double or_gstar(const or_problem *pb, const double *p)
 
 /* Hopf dual step at j = 1 (Algorithm 2; Appendix A.1.2):
  *   argmin_p  g*(p) + delta H(x_1, p, s_1) + |p - v|^2 / (2 sigma)
- * for the eikonal family H = c(x)|p| (c(x_1) is a constant here):
- *  - QUAD_SHIFT: sigma g*(p) + |p - v|^2/2 = (1+sigma)/2 |p - w|^2 + const with
- *    w = (v - sigma a)/(1 + sigma), so p = shrink_2(w, sigma delta c/(1+sigma));
- *  - NORM: every term is a function of |p| along the direction of v, so
- *    p = v/|v| * clip(|v| - sigma delta c, 0, 1) (shrink, then the ball).
+ *  - QUAD_SHIFT (any control family with a p-prox): sigma g*(p) + |p - v|^2/2
+ *    = (1+sigma)/2 |p - w|^2 + const with w = (v - sigma a)/(1 + sigma), so p
+ *    is the family's p-prox of w with step sigma delta/(1+sigma); for the
+ *    eikonal family H = c(x)|p| that is shrink_2(w, sigma delta c/(1+sigma));
+ *  - NORM, eikonal family: every term is a function of |p| along the
+ *    direction of v, so p = v/|v| * clip(|v| - sigma delta c, 0, 1) (shrink,
+ *    then the ball).
  * Returns -1 when the pair (H, g) has no Hopf step here. */
 int or_hopf_prox1(const or_problem *pb, const double *x1, const double *v, double sigma, double delta,
                   double *out)
 {
     int d = pb->d;
-    if (pb->H != OR_H_CNORM) return -1;
-    double c = cnorm_c(pb->hp, x1);
-    if (pb->g == OR_G_QUAD_SHIFT) {
+    if (pb->g == OR_G_QUAD_SHIFT && (pb->H == OR_H_CNORM || pb->H == OR_H_QUADROTOR)) {
         double *w = malloc(sizeof(double) * d);
         for (int i = 0; i < d; i++) w[i] = (v[i] - sigma * pb->gp[1 + i]) / (1.0 + sigma);
-        or_shrink2(w, sigma * delta * c / (1.0 + sigma), d, out);
+        or_prox_p(pb, x1, w, sigma * delta / (1.0 + sigma), delta, out);
         free(w);
         return 0;
     }
+    if (pb->H != OR_H_CNORM) return -1;
+    double c = cnorm_c(pb->hp, x1);
     if (pb->g == OR_G_NORM) {
         double nv = norm2(v, d);
         double r = nv - sigma * delta * c;
@@ -1343,7 +1345,8 @@ static int solve_batch(const or_problem *pb, long n, const double *x, const doub
     if (game && !isaacs && !(pb->H == OR_H_PURSUIT_EVASION && pb->g == OR_G_PAIR_DIST)) return -1;
     if (!game && (pb->H == OR_H_ISAACS || pb->g == OR_G_SADDLE_QUAD)) return -1;
     if (!game && (pb->H == OR_H_PURSUIT_EVASION || pb->g == OR_G_PAIR_DIST)) return -1;
-    if (hopf && !isaacs && (game || pb->H != OR_H_CNORM || !(pb->g == OR_G_NORM || pb->g == OR_G_QUAD_SHIFT)))
+    if (hopf && !isaacs && (game || !((pb->H == OR_H_CNORM && (pb->g == OR_G_NORM || pb->g == OR_G_QUAD_SHIFT)) ||
+                                      (pb->H == OR_H_QUADROTOR && pb->g == OR_G_QUAD_SHIFT))))
         return -1;
     if (mix && (game || hopf || recipe || pb->H != OR_H_CNORM || !(pb->g == OR_G_NORM || pb->g == OR_G_QUAD_SHIFT)))
         return -1;

@@ -385,8 +385,10 @@ int validate_desc(const hjpd_desc* d) {
   if (has_recipe(*d) && (game || d->H == HJPD_H_LINEAR_TANH || (d->flags & (HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_HOPF))))
     return fail(HJPD_EUNSUPPORTED, "recipes are built for the persistent Lax control path in tolerance mode");
   if ((d->flags & HJPD_HOPF) && !(d->H == HJPD_H_CNORM && !game && (d->g == HJPD_G_NORM || d->g == HJPD_G_QUAD_SHIFT)) &&
+      !(d->H == HJPD_H_QUADROTOR && !game && d->g == HJPD_G_QUAD_SHIFT && !(d->flags & HJPD_PLAIN)) &&
       d->H != HJPD_H_ISAACS)
-    return fail(HJPD_EUNSUPPORTED, "the Hopf formulation is built for CNORM with NORM or QUAD_SHIFT, and for ISAACS");
+    return fail(HJPD_EUNSUPPORTED, "the Hopf formulation is built for CNORM with NORM or QUAD_SHIFT, for QUADROTOR "
+                                   "with QUAD_SHIFT (persistent kernel), and for ISAACS");
   if (has_mix(*d) && (game || d->H != HJPD_H_CNORM || !(d->g == HJPD_G_NORM || d->g == HJPD_G_QUAD_SHIFT) ||
                       (d->flags & (HJPD_PLAIN | HJPD_HOPF)) || has_recipe(*d)))
     return fail(HJPD_EUNSUPPORTED,

@@ -311,7 +311,8 @@ struct Quad {
   static constexpr int D = 12;
   static constexpr bool kGame = false;
   static constexpr bool kZeroSafe = false;
-  static constexpr bool kHopf = false;
+  static constexpr bool kHopf = false;      // no Hopf step in the plain kernel
+  static constexpr bool kHopfGroup = true;  // Hopf formulation in k_group_control
   static constexpr bool kMix = false;
 
   template <typename T> struct Par {
@@ -465,6 +466,30 @@ struct Quad {
     for (int i = 0; i < 12; i++) dx[i] = P.s1pt * (p1[i] - x0[i]) + P.sa[i];
   }
 
+
+  // Hopf formulation, dual step at j = 1 (Algorithm 2): the joint prox of
+  // g* + delta H(x_1,.) for the shifted quadratic g, g*(p) = |p|^2/2 + <a,p> +
+  // c0.  Completing the square, sigma g*(p) + |p - v|^2/2 = (1 + sigma)/2
+  // |p - w|^2 + const with w = (v - sigma a)/(1 + sigma), so it is the p-prox
+  // of w with lam/(1 + sigma).  Applied to (v, lam) before dual() in the
+  // group's first lane; identity elsewhere (first = false).
+  template <typename T>
+  __device__ static void hopf1_in(const Par<T>& P, T (&v)[12], T& lam, T sigma, bool first) {
+    const T r1 = first ? T(1) / (T(1) + sigma) : T(1);
+    const T sg = first ? sigma : T(0);
+#pragma unroll
+    for (int i = 0; i < 12; i++) v[i] = (v[i] - sg * P.a[i]) * r1;
+    lam *= r1;
+  }
+
+  // g*(p) = |p|^2/2 + <a,p> + c0 (the value's -g*(p_1) term, Hopf formulation)
+  template <typename T>
+  __device__ static T gstar(const Par<T>& P, const T (&p)[12]) {
+    T s = P.c0;
+#pragma unroll
+    for (int i = 0; i < 12; i++) s += p[i] * (T(0.5) * p[i] + P.a[i]);
+    return s;
+  }
 
   template <typename T>
   __device__ static T g(const Par<T>& P, const T (&x)[12]) {

@@ -126,6 +126,10 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
   const int beg = a.cls_range[2 * a.cls], end = a.cls_range[2 * a.cls + 1];
   int32_t* head = a.heads + a.cls;
   const T sigma = a.sigma, tau = a.tau, theta = a.theta;
+  // Hopf formulation (Algorithm 2): no node 0 (x_0 = z_0 = 0, the Hopf
+  // difference operator), node 1's dual step is the joint prox with g*, and
+  // the value has -g*(p_1) in place of g(x_0).  A uniform switch.
+  const bool hopf = F::kHopfGroup && a.hopf;
 
   T x[K][D], p[K][D], z[K][D], x0[D], z0[D];
   T tj[K], tdj[K];  // per node: tau and tau*delta where the node takes a primal step, else 0
@@ -163,7 +167,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
     // node 0 lives in the group's first lane; the other lanes keep x0 = z0 = 0
 #pragma unroll
     for (int i = 0; i < D; i++) {
-      x0[i] = (l == 0) ? init_x(xt[i], a.seed, pt, kArrX, 0, i) : T(0);
+      x0[i] = (l == 0 && !hopf) ? init_x(xt[i], a.seed, pt, kArrX, 0, i) : T(0);
       z0[i] = x0[i];
     }
 #pragma unroll
@@ -191,7 +195,11 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
       T v[D];
 #pragma unroll
       for (int i = 0; i < D; i++) v[i] = p[kk][i] + sigma * (z[kk][i] - (kk == 0 ? zprev[i] : z[kk - 1][i]));
-      F::dual(P, x[kk], v, sd, C[kk]);
+      T lam = sd;
+      if constexpr (F::kHopfGroup) {
+        if (kk == 0 && hopf) F::hopf1_in(P, v, lam, sigma, l == 0);  // node 1: with g*
+      }
+      F::dual(P, x[kk], v, lam, C[kk]);
       if constexpr (!F::kZeroSafe) {
         // nodes past N keep p = 0
         const int j = 1 + l * K + kk;
@@ -209,7 +217,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
     T pnext[D];
 #pragma unroll
     for (int i = 0; i < D; i++) pnext[i] = group_next0<L>(p[0][i], l);
-    if (l == 0) {
+    if (l == 0 && !hopf) {
       T dx0[D];
       F::step0(P, x0, p[0], tau, dx0);
 #pragma unroll
@@ -260,7 +268,11 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
         }
       }
       if (l == 0) {
-        acc += F::g(P, x0);
+        if constexpr (F::kHopfGroup) {
+          acc += hopf ? -F::gstar(P, p[0]) : F::g(P, x0);
+        } else {
+          acc += F::g(P, x0);
+        }
         bad |= !all_finite<T, D>(x0);
       }
       acc = group_sum<L>(acc);

@@ -72,7 +72,8 @@ def test_create_rejects_invalid_descriptors(lib, bad):
     dict(H=2, d=12, d_y=0, g=2),                         # pursuit needs d_y = 6
     dict(H=3, d=100, g=3, dtype=1),                      # linear-tanh float32 only
     dict(N_max=300),                                     # beyond the largest tile
-    dict(H=1, d=12, flags=32),                           # Hopf: built for CNORM only
+    dict(H=1, d=12, flags=32 | 1),                       # quadrotor Hopf: persistent kernel only
+    dict(H=1, d=12, g=0, flags=32),                      # quadrotor Hopf: QUAD_SHIFT g only
     dict(H=2, d=12, d_y=6, g=2, flags=32),               # no Hopf for the game path
     dict(H=1, d=12, flags=64),                           # forward Euler: built for CNORM only
     dict(H=2, d=12, d_y=6, g=2, flags=128),              # no trapezoid for the game path

@@ -50,3 +50,30 @@ def test_hopf_and_lax_reach_the_same_value():
     ok = (a["status"] == 0) & (b["status"] == 0)
     assert ok.mean() > 0.95
     assert np.max(np.abs(a["phi"] - b["phi"])[ok]) < 1e-6
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_hopf_quadrotor12_matches_oracle(oracle_mod, dtype):
+    """The Hopf formulation on the quadrotor (general control kernel; node 1's
+    step is the family's p-prox with step sigma delta/(1 + sigma) at (v -
+    sigma a)/(1 + sigma)), with the settings of the Lax quadrotor test: FP64 at
+    a 2500-iteration cap, FP32 at converged points with trajectories at the
+    stop rule's resolution sqrt(tol)."""
+    w = W.quadrotor12().subset(np.arange(97))
+    if dtype == "f64":
+        _check(oracle_mod, w, dtype, max_iter=2500, check_kstop=False, max_ill=0.35, hopf=True)
+    else:
+        _check(oracle_mod, w, dtype, max_iter=20000, check_kstop=False, max_ill=0.35, converged_only=True,
+               traj_tol=float(np.sqrt(w.tol)), hopf=True)
+
+
+def test_hopf_quadrotor12_largest_tiles_f64(oracle_mod):
+    """N = 256 and 255 (64 x 4 tile) and 129 (64 x 3): FP64, 300 fixed
+    iterations, trajectories compared (node 0 reported as zero)."""
+    w = W.quadrotor12().subset(np.arange(9))
+    w.N = np.array([256, 255, 129] * 3, dtype=np.int32)
+    w.N_max = 256
+    w.t = np.full(w.n, 3.0)
+    w.fixed_iters = True
+    g = _check(oracle_mod, w, "f64", max_iter=300, check_kstop=False, max_ill=0.35, hopf=True)
+    assert np.all(g["iters"] == 300)

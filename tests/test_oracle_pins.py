@@ -1165,3 +1165,46 @@ def test_isaacs_fixed_point_is_stationary_for_independent_lagrangian(oracle_mod)
                 smooth = d(ps, j)  # central difference across the kink cancels the |p| term
                 ps[j] = p0
                 assert abs(smooth) <= 2 * delta + 1e-7
+
+
+def test_quadrotor_hopf_prox1_is_the_joint_argmin(oracle_mod):
+    """Hopf formulation, quadrotor, shifted quadratic g (section 4.1 eq.
+    dischopf; Algorithm 2): the node-1 step minimises g*(p) + delta H(x_1, p)
+    + |p - v|^2/(2 sigma) with g*(p) = |p|^2/2 + <a,p> + c0.  Checked against a
+    direct numerical minimisation of that objective (BFGS): the oracle's point
+    is at least as low and within the minimiser's precision of BFGS's."""
+    from scipy.optimize import minimize
+    O = oracle_mod
+    w = W.quadrotor12(8)
+    rng = np.random.default_rng(5)
+    gp = np.concatenate([[0.3], rng.uniform(-0.5, 0.5, 12)])
+    pb = O.Problem(w.H, w.g, 12, 0, w.hp, gp)
+    a = gp[1:]
+    for sigma in (0.5, 2.0, 8.0):
+        x1, v, delta = rng.uniform(-1, 1, 12), rng.normal(size=12), 0.05
+        p = pb.hopf_prox1(x1, v, sigma, delta)
+        f = lambda q: 0.5 * q @ q + a @ q + gp[0] + delta * pb.H_val(x1, q, delta) + np.sum((q - v) ** 2) / (2 * sigma)
+        r = minimize(f, v, method="BFGS", options={"gtol": 1e-11, "maxiter": 10000})
+        assert f(p) <= r.fun + 1e-11
+        assert np.max(np.abs(p - r.x)) < 1e-6
+
+
+def test_quadrotor_hopf_and_lax_reach_the_same_value(oracle_mod):
+    """Both formulations are saddle points of one Lagrangian: minimising the
+    Lax Lagrangian over x_0 turns g(x_0) - <p_1, x_0> into -g*(p_1), the Hopf
+    objective.  Iterated to the same point, the two values agree (quadrotor,
+    shifted quadratic g with a nonzero shift; 24 points, t = 0.3, N = 6,
+    30,000 iterations)."""
+    O = oracle_mod
+    w = W.quadrotor12(64)
+    rng = np.random.default_rng(7)
+    gp = np.concatenate([[0.3], rng.uniform(-0.5, 0.5, 12)])
+    pb = O.Problem(w.H, w.g, 12, 0, w.hp, gp)
+    m = 24
+    x, t, N = w.x[:m], np.full(m, 0.3), np.full(m, 6, np.int32)
+    kw = dict(sigma=w.sigma, tau=w.tau, tol=1e-20, max_iter=30000, seed=3, N_max=6, threads=4)
+    lax = O.solve(pb, x, t, N, **kw)
+    hopf = O.solve(pb, x, t, N, hopf=True, **kw)
+    d = np.abs(lax.phi - hopf.phi) / np.maximum(np.abs(lax.phi), 1.0)
+    assert np.all(np.isfinite(hopf.phi))
+    assert np.median(d) < 1e-7 and d.max() < 1e-5
