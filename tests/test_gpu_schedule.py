@@ -49,3 +49,15 @@ def test_quadrotor_prefix_matches_whole_batch():
     print("[quadrotor12 f32] full n=%d, prefix m=%d, converged %d / %d" % (
         w.n, m, int((full["status"] == 0).sum()), int((part["status"] == 0).sum())), flush=True)
     _same(full, part, m)
+
+
+def test_pursuit_prefix_matches_whole_batch():
+    # the game kernel with four capacity classes on parallel branches:
+    # 16,384 points (two blocks per CU) against 1,024 (fill limit)
+    w = W.pursuit12().subset(np.arange(16384))
+    full = gpu_solve(w, dtype="f32", traj=False, max_iter=3000)
+    m = 1024
+    part = gpu_solve(w.subset(np.arange(m)), dtype="f32", traj=False, max_iter=3000)
+    print("[pursuit12 f32] n=%d, prefix m=%d, converged %d / %d" % (
+        w.n, m, int((full["status"] == 0).sum()), int((part["status"] == 0).sum())), flush=True)
+    _same(full, part, m)
