@@ -77,3 +77,15 @@ def test_hopf_quadrotor12_largest_tiles_f64(oracle_mod):
     w.fixed_iters = True
     g = _check(oracle_mod, w, "f64", max_iter=300, check_kstop=False, max_ill=0.35, hopf=True)
     assert np.all(g["iters"] == 300)
+
+
+@pytest.mark.parametrize("hopf", [False, True])
+def test_quadrotor12_small_and_ragged_N_f64(oracle_mod, hopf):
+    """N = 1 (the only dual is p_1, the Hopf joint prox; no interior node
+    moves), 2, 3 and N at and below the tile edges, Lax and Hopf, FP64 at a
+    1500-iteration cap.  t = 0.05 N keeps the workload's step delta = 0.05
+    (the step sizes sigma, tau are set for it)."""
+    w = W.quadrotor12().subset(np.arange(40))
+    w.N = np.array([1, 2, 3, 15, 16, 17, 31, 32] * 5, dtype=np.int32)
+    w.t = 0.05 * w.N
+    _check(oracle_mod, w, "f64", max_iter=1500, check_kstop=False, max_ill=0.35, hopf=hopf)
