@@ -129,6 +129,17 @@ def test_fullsize_quadrotor12_with_trajectories(oracle_mod):
                    traj_tol=float(np.sqrt(w.tol)), max_iter=20000)
 
 
+def test_fullsize_quadrotor12_hopf_with_trajectories(oracle_mod):
+    """The same full set in the Hopf formulation (the paper's method for its
+    quadcopter): graph-captured and replayed, sampled points against the
+    oracle's Hopf path as in the Lax test above."""
+    w = W.quadrotor12()
+    g = _graph_solve(w, "f32", traj=True, max_iter=20000, hopf=True)
+    idx = _sample(g, w.n, 64, 16, seed=17)
+    _check_sampled(oracle_mod, w, g, idx, "f32", traj=True, hopf=True, max_ill=0.35, converged_only=True,
+                   traj_tol=float(np.sqrt(w.tol)), max_iter=20000)
+
+
 def test_fullsize_pursuit12_uneven_N(oracle_mod):
     """262,144 points, N in 16..96 across several tile classes in one graph,
     cap 20,000.  About 6 % of the points are still moving at the cap; some of
