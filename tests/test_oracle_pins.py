@@ -539,6 +539,51 @@ def test_pursuit_fixed_point_is_stationary_for_independent_lagrangian(oracle_mod
         assert abs(Lf(Z) - r.phi[0]) < 1e-10
 
 
+def _pe_shoot_minmax(X, N, t, r, hp, UP=None, UE=None):
+    """Direct shooting of the discretised game: from X_N = X, X_{j-1} = X_j +
+    delta f_phys(X_j, uP_j, uE_j); payoff g(X_0) + delta sum_j (|uP_j|^2/(2 wP)
+    - |uE_j|^2/(2 wE)).  The two players' states evolve independently, so the
+    open-loop value is min over uP of max over uE (the inner problem is
+    strictly concave where the pair is apart, the outer one convex).  With UP
+    and UE given, returns the payoff of those controls instead."""
+    kappa, wP, wE = hp
+    delta = t / N
+
+    def G(up, ue):
+        up, ue = up.reshape(N, 3), ue.reshape(N, 3)
+        s, run = X.copy(), 0.0
+        for j in range(N, 0, -1):
+            s = s + delta * pe_f_phys(s, up[j - 1], ue[j - 1], kappa)
+            run += delta * (0.5 / wP * up[j - 1] @ up[j - 1] - 0.5 / wE * ue[j - 1] @ ue[j - 1])
+        return np.linalg.norm(s[0:3] - s[6:9]) - r + run
+    if UP is not None:
+        return G(UP, UE)
+
+    def inner(up):
+        return -minimize(lambda ue: -G(up, ue), np.zeros(3 * N), method="BFGS", options={"gtol": 1e-12}).fun
+    return minimize(inner, np.zeros(3 * N), method="BFGS", options={"gtol": 1e-11}).fun
+
+
+@pytest.mark.parametrize("N,t", [(2, 0.4), (2, 0.8), (3, 0.6)])
+def test_pursuit_matches_minmax_shooting(oracle_mod, N, t):
+    """The game value is the open-loop min-max of the discretised game over
+    both players' controls (section 4.2, eq. discgenlaxhopfdg with the
+    Lagrangian's p and q maximised and minimised out), found by nested BFGS
+    on dynamics written independently in this file."""
+    rng = _rng(40 + N + int(10 * t))
+    r0 = 0.5
+    pb = oracle_mod.Problem(W.H_PURSUIT_EVASION, W.G_PAIR_DIST, 12, 6, W.PE_PARAMS, [r0])
+    X = np.concatenate([rng.uniform(-1, 1, 3), rng.uniform(-.3, .3, 3), rng.uniform(-1, 1, 3) + 2,
+                        rng.uniform(-.3, .3, 3)])
+    res = oracle_mod.solve(pb, X[None], t, N, sigma=8.0, tau=0.25 / 8, tol=1e-28, max_iter=200000, seed=6)
+    assert res.status[0] == 0
+    brute = _pe_shoot_minmax(X, N, t, r0, W.PE_PARAMS)
+    assert abs(res.phi[0] - brute) < 1e-9 * max(1, abs(brute)), (res.phi[0], brute)
+    # the controls move the value well beyond the tolerance: the pin sees the running payoff
+    idle = _pe_shoot_minmax(X, N, t, r0, W.PE_PARAMS, np.zeros(3 * N), np.zeros(3 * N))
+    assert abs(brute - idle) > 1e-4
+
+
 def _quad_lagrangian(Z, N, hp, x_t, delta):
     xs = np.vstack([Z[:N * 12].reshape(N, 12), x_t])
     ps = Z[N * 12:].reshape(N, 12)
