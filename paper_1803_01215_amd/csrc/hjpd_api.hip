@@ -5,7 +5,7 @@
 //   2. k_queue_count    validate each point (bad inputs get HJPD_PT_BADINPUT
 //                       and are not queued), count points per bucket: N
 //                       major, a quantised work hint minor;
-//   3. k_queue_scan     one thread: bucket offsets in descending N and, within
+//   3. k_queue_scan     one block: bucket offsets in descending N and, within
 //                       one N, descending hint; begin/end of each tile
 //                       class's segment; zero the pop counters;
 //   4. k_queue_scatter  write point ids into their bucket;
@@ -104,80 +104,121 @@ __device__ bool point_ok(int64_t i, int d, int N_max, const T* x, const T* t, co
   return !bad;
 }
 
-// Wave-aggregated atomic add on counter[key]: one atomic per distinct key in
-// the wavefront (all points usually share a few N values).  Returns, for each
-// participating lane, old value + its rank among the lanes with that key.
-__device__ int aggregated_add(bool part, int key, int32_t* counter) {
-  const int lane = threadIdx.x & 63;
-  uint64_t rem = __ballot(part);
-  int pos = 0;
-  while (rem) {
-    const int leader = __ffsll((unsigned long long)rem) - 1;
-    const int kl = __shfl(key, leader, 64);
-    const uint64_t m = __ballot(part && key == kl);
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&counter[kl], __popcll(m));
-    base = __shfl(base, leader, 64);
-    if ((m >> lane) & 1ull) pos = base + __popcll(m & ((1ull << lane) - 1ull));
-    rem &= ~m;
-  }
-  return pos;
-}
+// Bucket keys of every context that uses the queue: N <= kMaxCapacity, so a
+// block's histogram over all keys fits in 16.4 KB of LDS.
+constexpr int kMaxKeys = (hjpd::kMaxCapacity + 1) * kHintBuckets;
+constexpr int kQueueBlock = 256;
+constexpr int kQueuePerThread = 4;  // points per thread: 1,024 per block
+constexpr int kScanBlock = 1024;
 
+// Counting and scattering share one shape: each block takes 1,024 consecutive
+// points, builds its histogram over keys with LDS atomics, and then issues
+// one global atomic per key it holds.  All blocks hit the same few dozen
+// counters (points share a few N values), so aggregating per block rather
+// than per wave keeps those global atomics from serialising.  The position of
+// a point inside its block's share of a bucket is the value its LDS atomic
+// returned, so the order within a bucket varies from run to run; every point
+// is solved on its own and its results do not depend on that order.
 template <typename T>
-__global__ void k_queue_count(int64_t n, int d, int d_y, int N_max, const T* x, const T* t, const int32_t* N,
-                              int hint, const T* gp, int32_t* counts, T* phi, int32_t* iters, int32_t* status) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  bool ok = false;
-  int key = 0;
-  if (i < n) {
-    ok = point_ok(i, d, N_max, x, t, N);
-    if (ok) key = N[i] * kHintBuckets + hint_bucket(hint, i, d, d_y, x, gp);
-    if (!ok) {
+__global__ __launch_bounds__(kQueueBlock) void k_queue_count(int64_t n, int d, int d_y, int N_max, const T* x,
+                                                             const T* t, const int32_t* N, int hint, const T* gp,
+                                                             int nkeys, int32_t* counts, T* phi, int32_t* iters,
+                                                             int32_t* status) {
+  __shared__ int32_t hist[kMaxKeys];
+  for (int k = threadIdx.x; k < nkeys; k += kQueueBlock) hist[k] = 0;
+  __syncthreads();
+  const int64_t base = int64_t(blockIdx.x) * (kQueueBlock * kQueuePerThread) + threadIdx.x;
+  for (int r = 0; r < kQueuePerThread; r++) {
+    const int64_t i = base + int64_t(r) * kQueueBlock;
+    if (i >= n) break;
+    if (point_ok(i, d, N_max, x, t, N)) {
+      atomicAdd(&hist[N[i] * kHintBuckets + hint_bucket(hint, i, d, d_y, x, gp)], 1);
+    } else {
       phi[i] = T(NAN);
       iters[i] = 0;
       status[i] = hjpd::kBadInput;
     }
   }
-  (void)aggregated_add(ok, key, counts);
-}
-
-// cls_bounds: [2*ncls] (lo, hi) N-range of each class, classes disjoint.
-// cls_range:  [2*(ncls+1)] begin/end of each class; the extra last entry is
-//             the whole queue (used by the plain kernel).
-__global__ void k_queue_scan(int N_max, int ncls, const int32_t* cls_bounds, const int32_t* counts,
-                             int32_t* cursor, int32_t* cls_range, int32_t* heads) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int off = 0;
-  for (int v = N_max; v >= 1; v--)
-    for (int b = 0; b < kHintBuckets; b++) {
-      cursor[v * kHintBuckets + b] = off;
-      off += counts[v * kHintBuckets + b];
-    }
-  for (int c = 0; c < ncls; c++) {
-    const int lo = cls_bounds[2 * c], hi = cls_bounds[2 * c + 1];
-    const int last = lo * kHintBuckets + kHintBuckets - 1;
-    cls_range[2 * c] = cursor[hi * kHintBuckets];
-    cls_range[2 * c + 1] = cursor[last] + counts[last];
-    heads[c] = 0;
-  }
-  cls_range[2 * ncls] = 0;
-  cls_range[2 * ncls + 1] = off;
-  heads[ncls] = 0;
+  __syncthreads();
+  for (int k = threadIdx.x; k < nkeys; k += kQueueBlock)
+    if (hist[k]) atomicAdd(&counts[k], hist[k]);
 }
 
 template <typename T>
-__global__ void k_queue_scatter(int64_t n, int d, int d_y, int N_max, const T* x, const T* t, const int32_t* N,
-                                int hint, const T* gp, int32_t* cursor, int32_t* queue) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  bool ok = false;
-  int key = 0;
-  if (i < n) {
-    ok = point_ok(i, d, N_max, x, t, N);
-    if (ok) key = N[i] * kHintBuckets + hint_bucket(hint, i, d, d_y, x, gp);
+__global__ __launch_bounds__(kQueueBlock) void k_queue_scatter(int64_t n, int d, int d_y, int N_max, const T* x,
+                                                               const T* t, const int32_t* N, int hint, const T* gp,
+                                                               int nkeys, int32_t* cursor, int32_t* queue) {
+  __shared__ int32_t hist[kMaxKeys];
+  for (int k = threadIdx.x; k < nkeys; k += kQueueBlock) hist[k] = 0;
+  __syncthreads();
+  const int64_t base = int64_t(blockIdx.x) * (kQueueBlock * kQueuePerThread) + threadIdx.x;
+  int key[kQueuePerThread], rank[kQueuePerThread];
+  for (int r = 0; r < kQueuePerThread; r++) {
+    const int64_t i = base + int64_t(r) * kQueueBlock;
+    key[r] = -1;
+    if (i < n && point_ok(i, d, N_max, x, t, N)) {
+      key[r] = N[i] * kHintBuckets + hint_bucket(hint, i, d, d_y, x, gp);
+      rank[r] = atomicAdd(&hist[key[r]], 1);
+    }
   }
-  const int pos = aggregated_add(ok, key, cursor);
-  if (ok) queue[pos] = int32_t(i);
+  __syncthreads();
+  // reserve this block's share of each bucket; the histogram now holds its start
+  for (int k = threadIdx.x; k < nkeys; k += kQueueBlock)
+    if (hist[k]) hist[k] = atomicAdd(&cursor[k], hist[k]);
+  __syncthreads();
+  for (int r = 0; r < kQueuePerThread; r++)
+    if (key[r] >= 0) queue[hist[key[r]] + rank[r]] = int32_t(base + int64_t(r) * kQueueBlock);
+}
+
+// Bucket offsets: buckets are laid out in descending N and, within one N,
+// ascending hint bucket (bucket 0 holds the largest hint).  Position o of
+// that order holds key (N_max - o / kHintBuckets) * kHintBuckets +
+// o % kHintBuckets.  One block: each thread sums a run of consecutive
+// positions, a block-wide scan in LDS gives the run's start, and the thread
+// writes its offsets.  A class [lo, hi] spans the positions from (hi, 0) up
+// to but not including the one after (lo, kHintBuckets - 1).
+// cls_bounds: [2*ncls] (lo, hi) N-range of each class, classes disjoint.
+// cls_range:  [2*(ncls+1)] begin/end of each class; the extra last entry is
+//             the whole queue (used by the plain kernel).
+__global__ __launch_bounds__(kScanBlock) void k_queue_scan(int N_max, int ncls, const int32_t* cls_bounds,
+                                                           const int32_t* counts, int32_t* cursor, int32_t* cls_range,
+                                                           int32_t* heads) {
+  __shared__ int32_t part[kScanBlock];
+  const int tid = threadIdx.x;
+  const int nord = N_max * kHintBuckets;
+  const int run = (nord + kScanBlock - 1) / kScanBlock;
+  const int o0 = tid * run, o1 = min(o0 + run, nord);
+  auto key_of = [&](int o) { return (N_max - o / kHintBuckets) * kHintBuckets + o % kHintBuckets; };
+  int mine = 0;
+  for (int o = o0; o < o1; o++) mine += counts[key_of(o)];
+  part[tid] = mine;
+  __syncthreads();
+  for (int off = 1; off < kScanBlock; off <<= 1) {  // inclusive scan of the run sums
+    const int v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int off = part[tid] - mine;
+  for (int o = o0; o < o1; o++) {
+    for (int c = 0; c < ncls; c++) {
+      if (o == (N_max - cls_bounds[2 * c + 1]) * kHintBuckets) cls_range[2 * c] = off;
+      if (o == (N_max - cls_bounds[2 * c] + 1) * kHintBuckets) cls_range[2 * c + 1] = off;
+    }
+    const int k = key_of(o);
+    cursor[k] = off;
+    off += counts[k];
+  }
+  if (tid == 0) {
+    const int total = part[kScanBlock - 1];
+    for (int c = 0; c < ncls; c++) {
+      if (cls_bounds[2 * c] == 1) cls_range[2 * c + 1] = total;  // the class that ends the order
+      heads[c] = 0;
+    }
+    cls_range[2 * ncls] = 0;
+    cls_range[2 * ncls + 1] = total;
+    heads[ncls] = 0;
+  }
 }
 
 struct Cls {
@@ -443,13 +484,15 @@ int enqueue_solve(hjpd_ctx* c, int64_t n, const void* x, const void* t, const in
   if (!(D.flags & HJPD_NO_ORDER_HINT))
     hint = D.g == HJPD_G_QUAD_SHIFT ? kHintShift
                                     : ((D.g == HJPD_G_NORM || D.g == HJPD_G_SADDLE_QUAD) ? kHintNorm : kHintPair);
+  if (nkeys > kMaxKeys) return fail(HJPD_EUNSUPPORTED, "N_max above the queue's bucket range");
+  const int nqb = int((n + kQueueBlock * kQueuePerThread - 1) / (kQueueBlock * kQueuePerThread));
   hipLaunchKernelGGL(k_queue_zero, dim3((nkeys + 255) / 256), dim3(256), 0, s, c->d_counts, nkeys);
-  hipLaunchKernelGGL(k_queue_count<T>, dim3(nb), dim3(256), 0, s, n, D.d, D.d_y, D.N_max, (const T*)x, (const T*)t,
-                     N, hint, (const T*)gp, c->d_counts, (T*)phi, iters, status);
-  hipLaunchKernelGGL(k_queue_scan, dim3(1), dim3(64), 0, s, D.N_max, ncls, c->d_cls_bounds, c->d_counts, c->d_cursor,
-                     c->d_cls_range, c->d_heads);
-  hipLaunchKernelGGL(k_queue_scatter<T>, dim3(nb), dim3(256), 0, s, n, D.d, D.d_y, D.N_max, (const T*)x,
-                     (const T*)t, N, hint, (const T*)gp, c->d_cursor, c->d_queue);
+  hipLaunchKernelGGL(k_queue_count<T>, dim3(nqb), dim3(kQueueBlock), 0, s, n, D.d, D.d_y, D.N_max, (const T*)x,
+                     (const T*)t, N, hint, (const T*)gp, nkeys, c->d_counts, (T*)phi, iters, status);
+  hipLaunchKernelGGL(k_queue_scan, dim3(1), dim3(kScanBlock), 0, s, D.N_max, ncls, c->d_cls_bounds, c->d_counts,
+                     c->d_cursor, c->d_cls_range, c->d_heads);
+  hipLaunchKernelGGL(k_queue_scatter<T>, dim3(nqb), dim3(kQueueBlock), 0, s, n, D.d, D.d_y, D.N_max, (const T*)x,
+                     (const T*)t, N, hint, (const T*)gp, nkeys, c->d_cursor, c->d_queue);
   HIP_OK(hipGetLastError(), "queue kernels");
 
   hjpd::KArgs<T> a;
