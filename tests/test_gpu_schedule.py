@@ -61,3 +61,36 @@ def test_pursuit_prefix_matches_whole_batch():
     print("[pursuit12 f32] n=%d, prefix m=%d, converged %d / %d" % (
         w.n, m, int((full["status"] == 0).sum()), int((part["status"] == 0).sum())), flush=True)
     _same(full, part, m)
+
+
+@pytest.mark.parametrize("n", [1, 255, 1025, 3079])
+def test_queue_ragged_batches_with_bad_points(n):
+    """The queue takes 1,024 points per block: batches of one point, below one
+    block, one past a block and a ragged multiple, with N spread over several
+    capacity classes and two invalid points.  Bad points are flagged and not
+    queued; every good point is solved exactly once from its own inputs, so a
+    queue in a wholly different order (the work hint off) gives the same
+    outputs bit for bit."""
+    import torch
+
+    from paper_1803_01215_amd.solver import Solver
+    w = W.quadrotor12().subset(np.arange(n))
+    t, N = w.t.copy(), w.N.copy()
+    bad = [k for k in (n // 2, n - 1) if n >= 3]
+    if bad:
+        t[bad[0]] = -1.0
+        N[bad[1]] = 0
+    g = gpu_solve(w, dtype="f32", t=t, N=N, max_iter=200, traj=False)
+    s = Solver(d=w.d, d_y=w.d_y, H=w.H, g=w.g, N_max=w.N_max, sigma=w.sigma, tau=w.tau, theta=w.theta, tol=w.tol,
+               max_iter=200, seed=w.init_seed, dtype=torch.float32, order_hint=False)
+    dev = "cuda"
+    f = lambda a: torch.tensor(a, dtype=torch.float32, device=dev)
+    out = s.solve(f(w.x), f(t), torch.tensor(N, dtype=torch.int32, device=dev), f(w.hp), f(w.gp), traj=False)
+    torch.cuda.synchronize()
+    good = np.setdiff1d(np.arange(n), bad)
+    assert np.all(g["status"][bad] == 3) and np.all(g["iters"][bad] == 0) and np.all(np.isnan(g["phi"][bad]))
+    assert np.all(np.isin(g["status"][good], (0, 1))) and np.all((g["iters"][good] >= 1) & (g["iters"][good] <= 200))
+    for k in ("phi", "iters", "status"):
+        v = getattr(out, k).cpu().numpy()
+        assert np.array_equal(g[k].astype(v.dtype), v, equal_nan=(k == "phi")), k
+    s.close()
