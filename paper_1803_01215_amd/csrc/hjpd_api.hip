@@ -108,11 +108,11 @@ __device__ bool point_ok(int64_t i, int d, int N_max, const T* x, const T* t, co
 // block's histogram over all keys fits in 16.4 KB of LDS.
 constexpr int kMaxKeys = (hjpd::kMaxCapacity + 1) * kHintBuckets;
 constexpr int kQueueBlock = 256;
-constexpr int kQueuePerThread = 4;  // points per thread: 1,024 per block
+constexpr int kQueuePerThread = 1;  // points per thread: 256 per block, enough blocks to cover the chip
 constexpr int kScanBlock = 1024;
 
-// Counting and scattering share one shape: each block takes 1,024 consecutive
-// points, builds its histogram over keys with LDS atomics, and then issues
+// Counting and scattering share one shape: each block takes kQueueBlock *
+// kQueuePerThread consecutive points, builds its histogram over keys with LDS atomics, and then issues
 // one global atomic per key it holds.  All blocks hit the same few dozen
 // counters (points share a few N values), so aggregating per block rather
 // than per wave keeps those global atomics from serialising.  The position of

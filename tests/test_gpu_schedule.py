@@ -65,8 +65,8 @@ def test_pursuit_prefix_matches_whole_batch():
 
 @pytest.mark.parametrize("n", [1, 255, 1025, 3079])
 def test_queue_ragged_batches_with_bad_points(n):
-    """The queue takes 1,024 points per block: batches of one point, below one
-    block, one past a block and a ragged multiple, with N spread over several
+    """The queue takes 256 points per block: batches of one point, below one
+    block, one past a multiple of blocks and a ragged multiple, with N spread over several
     capacity classes and two invalid points.  Bad points are flagged and not
     queued; every good point is solved exactly once from its own inputs, so a
     queue in a wholly different order (the work hint off) gives the same
