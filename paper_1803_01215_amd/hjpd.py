@@ -51,6 +51,15 @@ def load():
         if not os.path.exists(LIB_PATH):
             raise ImportError("libhjpd.so not built: run __graft_entry__.build() or "
                               "python paper_1803_01215_amd/build.py")
+        # The library and torch must run on one HIP runtime.  Both depend on
+        # libamdhip64.so.7 and a process keeps the first copy it loads; torch
+        # ships its own, so it is loaded first.  Were the system copy loaded
+        # first (by this library), torch would find no GPU, and tensors it
+        # allocated could not be handed to the library's kernels.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(LIB_PATH)
         vp, i64, i32p = ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p
         lib.hjpd_create.argtypes = [ctypes.POINTER(hjpd_desc), ctypes.POINTER(ctypes.c_void_p)]

@@ -120,3 +120,17 @@ def test_flag_values_match_header():
         m = re.search(name + r"\s*=\s*1u\s*<<\s*(\d+)", src)
         assert m, name
         assert getattr(hjpd, name) == 1 << int(m.group(1)), name
+
+
+def test_library_shares_torchs_hip_runtime():
+    """Loading the library through the binding, before anything imported
+    torch, leaves one HIP runtime in the process: torch's copy."""
+    import subprocess
+    import sys
+    code = ("import re\n"
+            "from paper_1803_01215_amd import hjpd\n"
+            "hjpd.load()\n"
+            "print(sorted(set(re.findall(r'\\S*libamdhip64\\S*', open('/proc/self/maps').read()))))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, check=True).stdout
+    libs = eval(out.strip())
+    assert len(libs) == 1 and "/torch/lib/" in libs[0], libs
