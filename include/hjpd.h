@@ -236,6 +236,31 @@ int hjpd_solve_batch(hjpd_ctx *ctx, int64_t n, const void *x, const void *t, con
                      int32_t *iters, int32_t *status, void *stream);
 
 /*
+ * hjpd_solve_batch without any allocation, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, kernels and results as
+ * hjpd_solve_batch (bitwise: each point is solved on its own), for contexts
+ * of the persistent kernels (not HJPD_PLAIN, not HJPD_H_LINEAR_TANH:
+ * HJPD_EUNSUPPORTED).  Differences:
+ *  - the work queue and its counters live in a static device array of the
+ *    library, one copy per GPU (4.03 MiB, held until the process ends),
+ *    instead of the context's workspace, so n is limited to 1,048,576 points
+ *    (HJPD_EINVAL above);
+ *  - the call never allocates or frees memory (device or host) and never
+ *    builds a graph: with HJPD_GRAPH set it still enqueues the kernels
+ *    directly on `stream`, so the caller may capture them into a graph of
+ *    its own;
+ *  - every call on a GPU shares that GPU's array: calls on one GPU whose
+ *    work overlaps in time (from any context or thread, on different
+ *    streams) race and give wrong results; serialise them (one stream, or
+ *    events).  Each call clears what it needs before use.
+ * The context's current device must be the current device (HJPD_EINVAL).
+ */
+int hjpd_solve_batch_noalloc(hjpd_ctx *ctx, int64_t n, const void *x, const void *t, const int32_t *N,
+                             const void *h_params, const void *g_params, void *phi, void *x_traj, void *p_traj,
+                             int32_t *iters, int32_t *status, void *stream);
+
+/*
  * Value and reverse-mode gradients for HJPD_H_LINEAR_TANH with
  * HJPD_G_QUAD_FORM (float32): phi after exactly K_iters iterations
  * (fixed-iteration Algorithm 1), and, for upstream weights grad_phi [n],

@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -226,6 +227,29 @@ struct Cls {
   const void* kern;
   int grid;  // persistent grid (blocks of 256)
 };
+
+// Device scratch of one solve: the bucket counters and cursors, the class
+// segments, the per-class pop counters and the work queue.  hjpd_solve_batch
+// takes it from the context (grown on demand); the allocation-free entry
+// point takes it from the library's static per-GPU array.
+struct Workspace {
+  int32_t* counts;     // [(N_max+1) * kHintBuckets]
+  int32_t* cursor;     // [(N_max+1) * kHintBuckets]
+  int32_t* cls_range;  // [2*(ncls+1)]
+  int32_t* heads;      // [ncls+1]
+  int32_t* queue;      // [n]
+};
+
+// Allocation-free entry point: its scratch is a file-scope device array of
+// fixed size (one copy per GPU, resident until the process ends), addressed
+// from the host only through the per-device address hipGetSymbolAddress
+// returns.  Layout in int32 words: queue [kStaticMaxPoints], counts
+// [kMaxKeys], cursor [kMaxKeys], class segments [2*(kStaticMaxCls+1)], pop
+// counters [kStaticMaxCls+1].
+constexpr int64_t kStaticMaxPoints = int64_t(1) << 20;
+constexpr int kStaticMaxCls = 16;
+constexpr int64_t kStaticWords = kStaticMaxPoints + 2 * int64_t(kMaxKeys) + 2 * (kStaticMaxCls + 1) + (kStaticMaxCls + 1);
+static __device__ __align__(256) int32_t scratch[kStaticWords];
 
 }  // namespace
 
@@ -473,9 +497,9 @@ void drop_graph(hjpd_ctx* c) {
 }
 
 template <typename T>
-int enqueue_solve(hjpd_ctx* c, int64_t n, const void* x, const void* t, const int32_t* N, const void* hp,
-                  const void* gp, void* phi, void* xtraj, void* ptraj, int32_t* iters, int32_t* status,
-                  hipStream_t s, bool timed) {
+int enqueue_solve(hjpd_ctx* c, const Workspace& ws, int64_t n, const void* x, const void* t, const int32_t* N,
+                  const void* hp, const void* gp, void* phi, void* xtraj, void* ptraj, int32_t* iters,
+                  int32_t* status, hipStream_t s, bool timed) {
   const hjpd_desc& D = c->desc;
   const int ncls = int(c->plan.size());
   const int nb = int((n + 255) / 256);
@@ -486,13 +510,13 @@ int enqueue_solve(hjpd_ctx* c, int64_t n, const void* x, const void* t, const in
                                     : ((D.g == HJPD_G_NORM || D.g == HJPD_G_SADDLE_QUAD) ? kHintNorm : kHintPair);
   if (nkeys > kMaxKeys) return fail(HJPD_EUNSUPPORTED, "N_max above the queue's bucket range");
   const int nqb = int((n + kQueueBlock * kQueuePerThread - 1) / (kQueueBlock * kQueuePerThread));
-  hipLaunchKernelGGL(k_queue_zero, dim3((nkeys + 255) / 256), dim3(256), 0, s, c->d_counts, nkeys);
+  hipLaunchKernelGGL(k_queue_zero, dim3((nkeys + 255) / 256), dim3(256), 0, s, ws.counts, nkeys);
   hipLaunchKernelGGL(k_queue_count<T>, dim3(nqb), dim3(kQueueBlock), 0, s, n, D.d, D.d_y, D.N_max, (const T*)x,
-                     (const T*)t, N, hint, (const T*)gp, nkeys, c->d_counts, (T*)phi, iters, status);
-  hipLaunchKernelGGL(k_queue_scan, dim3(1), dim3(kScanBlock), 0, s, D.N_max, ncls, c->d_cls_bounds, c->d_counts,
-                     c->d_cursor, c->d_cls_range, c->d_heads);
+                     (const T*)t, N, hint, (const T*)gp, nkeys, ws.counts, (T*)phi, iters, status);
+  hipLaunchKernelGGL(k_queue_scan, dim3(1), dim3(kScanBlock), 0, s, D.N_max, ncls, c->d_cls_bounds, ws.counts,
+                     ws.cursor, ws.cls_range, ws.heads);
   hipLaunchKernelGGL(k_queue_scatter<T>, dim3(nqb), dim3(kQueueBlock), 0, s, n, D.d, D.d_y, D.N_max, (const T*)x,
-                     (const T*)t, N, hint, (const T*)gp, nkeys, c->d_cursor, c->d_queue);
+                     (const T*)t, N, hint, (const T*)gp, nkeys, ws.cursor, ws.queue);
   HIP_OK(hipGetLastError(), "queue kernels");
 
   hjpd::KArgs<T> a;
@@ -506,9 +530,9 @@ int enqueue_solve(hjpd_ctx* c, int64_t n, const void* x, const void* t, const in
   a.ptraj = (T*)ptraj;
   a.iters = iters;
   a.status = status;
-  a.queue = c->d_queue;
-  a.cls_range = c->d_cls_range;
-  a.heads = c->d_heads;
+  a.queue = ws.queue;
+  a.cls_range = ws.cls_range;
+  a.heads = ws.heads;
   a.work = (T*)c->d_work;
   a.work_stride = int64_t(nb) * 256;
   a.sigma = T(D.sigma);
@@ -558,6 +582,38 @@ int enqueue_solve(hjpd_ctx* c, int64_t n, const void* x, const void* t, const in
   if (timed) HIP_OK(hipEventRecord(c->ev1, s), "hipEventRecord");
   c->timing_launches = launches;
   return HJPD_OK;
+}
+
+Workspace ctx_workspace(const hjpd_ctx* c) {
+  return Workspace{c->d_counts, c->d_cursor, c->d_cls_range, c->d_heads, c->d_queue};
+}
+
+// Device address of `scratch` on each GPU, resolved once per device (with that
+// device current) by hjpd_create.  The array's name in host code is only a
+// host-side handle; kernels and copies get these addresses.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch_ptr[kMaxDevices] = {};
+
+int resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(HJPD_EDEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return HJPD_OK;
+  void* p = nullptr;
+  HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+  g_scratch_ptr[device] = static_cast<int32_t*>(p);
+  return HJPD_OK;
+}
+
+Workspace static_workspace(int device) {
+  int32_t* b = g_scratch_ptr[device];
+  Workspace w;
+  w.queue = b;
+  w.counts = b + kStaticMaxPoints;
+  w.cursor = w.counts + kMaxKeys;
+  w.cls_range = w.cursor + kMaxKeys;
+  w.heads = w.cls_range + 2 * (kStaticMaxCls + 1);
+  return w;
 }
 
 int ensure_capacity(hjpd_ctx* c, int64_t n) {
@@ -621,7 +677,8 @@ int hjpd_create(const hjpd_desc* desc, hjpd_ctx** out) {
       return rc;
     }
   } else {
-    rc = build_plan(c, nullptr, nullptr);
+    rc = resolve_scratch(c->device);
+    if (!rc) rc = build_plan(c, nullptr, nullptr);
     if (!rc) rc = upload_plan(c);
     if (!rc && c->plan.size() > 1) {
       if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess) rc = fail(HJPD_EDEVICE, "hipEventCreate failed");
@@ -701,8 +758,10 @@ int hjpd_solve_batch(hjpd_ctx* c, int64_t n, const void* x, const void* t, const
   auto enqueue_on = [&](hipStream_t st) -> int {
     const bool inner_timed = timed && st == s;
     if (c->desc.dtype == HJPD_F64)
-      return enqueue_solve<double>(c, n, x, t, N, hp, gp, phi, xtraj, ptraj, iters, status, st, inner_timed);
-    return enqueue_solve<float>(c, n, x, t, N, hp, gp, phi, xtraj, ptraj, iters, status, st, inner_timed);
+      return enqueue_solve<double>(c, ctx_workspace(c), n, x, t, N, hp, gp, phi, xtraj, ptraj, iters, status, st,
+                                    inner_timed);
+    return enqueue_solve<float>(c, ctx_workspace(c), n, x, t, N, hp, gp, phi, xtraj, ptraj, iters, status, st,
+                                 inner_timed);
   };
   if (c->desc.flags & HJPD_GRAPH) {
     std::vector<uintptr_t> key = {uintptr_t(n),     uintptr_t(x),     uintptr_t(t),     uintptr_t(N),
@@ -733,6 +792,37 @@ int hjpd_solve_batch(hjpd_ctx* c, int64_t n, const void* x, const void* t, const
     return HJPD_OK;
   }
   rc = enqueue_on(s);
+  if (rc) return rc;
+  c->timing_valid = timed;
+  return HJPD_OK;
+}
+
+int hjpd_solve_batch_noalloc(hjpd_ctx* c, int64_t n, const void* x, const void* t, const int32_t* N,
+                             const void* hp, const void* gp, void* phi, void* xtraj, void* ptraj, int32_t* iters,
+                             int32_t* status, void* stream) {
+  g_err.clear();
+  if (!c) return fail(HJPD_EINVAL, "ctx is NULL");
+  if (c->lt || (c->desc.flags & HJPD_PLAIN))
+    return fail(HJPD_EUNSUPPORTED, "the allocation-free solve is built for the persistent kernels");
+  if (n < 0) return fail(HJPD_EINVAL, "n < 0");
+  if (n > kStaticMaxPoints)
+    return fail(HJPD_EINVAL, "n exceeds the allocation-free solve's limit of 1048576 points");
+  if (n == 0) return HJPD_OK;
+  if (!x || !t || !N || !hp || !gp || !phi || !iters || !status) return fail(HJPD_EINVAL, "required pointer is NULL");
+  if (int(c->plan.size()) > kStaticMaxCls) return fail(HJPD_EUNSUPPORTED, "more capacity classes than the scratch holds");
+  int dev = -1;
+  HIP_OK(hipGetDevice(&dev), "hipGetDevice");
+  if (dev != c->device) return fail(HJPD_EINVAL, "the context's device is not the current device");
+  if (dev < 0 || dev >= kMaxDevices || !g_scratch_ptr[dev]) return fail(HJPD_EDEVICE, "scratch address not resolved");
+  const Workspace ws = static_workspace(dev);
+  hipStream_t s = (hipStream_t)stream;
+  const bool timed = (c->desc.flags & HJPD_TIMING) != 0;
+  c->timing_valid = false;
+  int rc;
+  if (c->desc.dtype == HJPD_F64)
+    rc = enqueue_solve<double>(c, ws, n, x, t, N, hp, gp, phi, xtraj, ptraj, iters, status, s, timed);
+  else
+    rc = enqueue_solve<float>(c, ws, n, x, t, N, hp, gp, phi, xtraj, ptraj, iters, status, s, timed);
   if (rc) return rc;
   c->timing_valid = timed;
   return HJPD_OK;
@@ -790,9 +880,11 @@ int hjpd_autotune(hjpd_ctx* c, int64_t n, const void* x, const void* t, const in
       double ms_total = 0;
       for (int rep = 0; rep < 2 && !rc; rep++) {
         if (c->desc.dtype == HJPD_F64)
-          rc = enqueue_solve<double>(c, n, x, t, N, hp, gp, phi, nullptr, nullptr, iters, status, s, true);
+          rc = enqueue_solve<double>(c, ctx_workspace(c), n, x, t, N, hp, gp, phi, nullptr, nullptr, iters, status, s,
+                                    true);
         else
-          rc = enqueue_solve<float>(c, n, x, t, N, hp, gp, phi, nullptr, nullptr, iters, status, s, true);
+          rc = enqueue_solve<float>(c, ctx_workspace(c), n, x, t, N, hp, gp, phi, nullptr, nullptr, iters, status, s,
+                                   true);
         if (rc) break;
         if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(HJPD_EDEVICE, "autotune sync"); break; }
         float f = 0;

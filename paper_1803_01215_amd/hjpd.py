@@ -22,8 +22,8 @@ HJPD_PERSISTENT, HJPD_PLAIN, HJPD_FIXED_ITERS, HJPD_GRAPH, HJPD_TIMING, HJPD_NO_
     0, 1, 2, 4, 8, 16, 32)
 HJPD_FORWARD_EULER, HJPD_TRAPEZOID = 64, 128
 
-EXPORTED = ["hjpd_create", "hjpd_solve_batch", "hjpd_value_grad", "hjpd_autotune", "hjpd_get_timing",
-            "hjpd_destroy", "hjpd_last_error"]
+EXPORTED = ["hjpd_create", "hjpd_solve_batch", "hjpd_solve_batch_noalloc", "hjpd_value_grad", "hjpd_autotune",
+            "hjpd_get_timing", "hjpd_destroy", "hjpd_last_error"]
 
 
 class HjpdError(RuntimeError):
@@ -66,6 +66,8 @@ def load():
         lib.hjpd_create.restype = ctypes.c_int
         lib.hjpd_solve_batch.argtypes = [vp, i64, vp, vp, i32p, vp, vp, vp, vp, vp, i32p, i32p, vp]
         lib.hjpd_solve_batch.restype = ctypes.c_int
+        lib.hjpd_solve_batch_noalloc.argtypes = lib.hjpd_solve_batch.argtypes
+        lib.hjpd_solve_batch_noalloc.restype = ctypes.c_int
         lib.hjpd_value_grad.argtypes = [vp, i64, vp, vp, i32p, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp,
                                         vp, vp]
         lib.hjpd_value_grad.restype = ctypes.c_int
@@ -121,6 +123,13 @@ def hjpd_solve_batch(ctx, n, x, t, N, h_params, g_params, phi, x_traj, p_traj, i
     _check(load().hjpd_solve_batch(ctx, int(n), _ptr(x), _ptr(t), _ptr(N), _ptr(h_params), _ptr(g_params),
                                    _ptr(phi), _ptr(x_traj), _ptr(p_traj), _ptr(iters), _ptr(status),
                                    _stream(stream)))
+
+
+def hjpd_solve_batch_noalloc(ctx, n, x, t, N, h_params, g_params, phi, x_traj, p_traj, iters, status,
+                             stream=None):
+    _check(load().hjpd_solve_batch_noalloc(ctx, int(n), _ptr(x), _ptr(t), _ptr(N), _ptr(h_params),
+                                           _ptr(g_params), _ptr(phi), _ptr(x_traj), _ptr(p_traj), _ptr(iters),
+                                           _ptr(status), _stream(stream)))
 
 
 def hjpd_value_grad(ctx, n, x, t, N, h_params, g_params, grad_phi, K_iters, ckpt_every, phi, dphi_dx,
