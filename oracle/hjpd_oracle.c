@@ -114,6 +114,26 @@
 #include <omp.h>
 #endif
 
+/*
+ * Rounding variants.  The default build evaluates everything in binary64 with
+ * no fused multiply-add.  The same source is also compiled
+ *  - with FMA contraction (-mfma -ffp-contract=fast): the same arithmetic with
+ *    another rounding sequence;
+ *  - with OR_BINARY32 (and -fsingle-precision-constant): every floating-point
+ *    variable, argument and constant below becomes binary32, so every
+ *    operation rounds to binary32 (libm transcendentals are evaluated in
+ *    binary64 and rounded on assignment), with and without FMA contraction.
+ * These variants compute nothing new.  They measure how far a second rounding
+ * sequence of the same iteration, or any binary32 evaluation of it, lands
+ * from this binary64 one after the same number of iterations: the rounding
+ * floor below which no implementation's agreement with the oracle can be
+ * expected at a given point.  (The macro is defined after the standard
+ * headers, so their declarations keep binary64.)
+ */
+#ifdef OR_BINARY32
+#define double float
+#endif
+
 /* Family ids: identical numbering to the public header, restated here. */
 enum { OR_H_CNORM = 0, OR_H_QUADROTOR = 1, OR_H_PURSUIT_EVASION = 2, OR_H_LINEAR_TANH = 3, OR_H_ISAACS = 4 };
 enum { OR_G_NORM = 0, OR_G_QUAD_SHIFT = 1, OR_G_PAIR_DIST = 2, OR_G_QUAD_FORM = 3, OR_G_SADDLE_QUAD = 4 };
@@ -710,7 +730,10 @@ double or_gstar(const or_problem *pb, const double *p)
 {
     int d = pb->d;
     switch (pb->g) {
-    case OR_G_NORM: return norm2(p, d) <= 1.0 + 1e-12 ? pb->gp[0] : INFINITY;
+    case OR_G_NORM:
+        /* the indicator of the unit ball; the slack covers the rounding of the clip that puts p on
+         * the sphere, in the working precision (binary64, or the binary32 rounding variant) */
+        return norm2(p, d) <= 1.0 + (sizeof(double) == 8 ? 1e-12 : 1e-5) ? pb->gp[0] : INFINITY;
     case OR_G_QUAD_SHIFT: return 0.5 * dot(p, p, d) + dot(pb->gp + 1, p, d) + pb->gp[0];
     }
     return NAN;

@@ -26,13 +26,37 @@ PT_CONVERGED, PT_MAXITER, PT_NONFINITE, PT_BADINPUT = 0, 1, 2, 3
 ARR_X, ARR_P, ARR_Y, ARR_Q = 0, 1, 2, 3
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, OpenMP across points only)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+# Rounding variants of the same source (see the C file's header): the oracle
+# itself ("f64"), binary64 with FMA contraction, and binary32 without / with
+# FMA contraction.  The variants only measure rounding floors for the parity
+# tests; every reference value comes from "f64".
+_VARIANT_FLAGS = {
+    "f64": [],
+    "f64fma": ["-mfma", "-ffp-contract=fast"],
+    "f32": ["-DOR_BINARY32", "-fsingle-precision-constant"],
+    "f32fma": ["-DOR_BINARY32", "-fsingle-precision-constant", "-mfma", "-ffp-contract=fast"],
+}
+
+
+def _lib_path(variant: str) -> str:
+    return _LIB if variant == "f64" else os.path.join(_HERE, "liboracle_%s.so" % variant)
+
+
+def build(force: bool = False, variant: str = "f64") -> str:
+    """Compile the oracle with gcc (plain -O2, OpenMP across points only);
+    `variant` selects one of the rounding variants."""
+    path = _lib_path(variant)
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        tmp = path + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", *_VARIANT_FLAGS[variant],
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, path)
+    return path
+
+
+def build_all(force: bool = False) -> None:
+    for v in _VARIANT_FLAGS:
+        build(force, v)
 
 
 class _Problem(ctypes.Structure):
@@ -105,6 +129,39 @@ def lib():
         _lib.or_game_prox_x0.argtypes = [P, D, D, ctypes.c_double, D]
         _lib.or_game_stretch_y0.argtypes = [P, D, D, ctypes.c_double, D]
     return _lib
+
+
+_vlibs = {}
+
+
+def _variant_lib(variant: str):
+    """ctypes handle of a rounding variant's batch solvers (binary32 variants
+    take float arrays and float scalars where the oracle takes double)."""
+    if variant == "f64":
+        return lib()
+    if variant not in _vlibs:
+        L = ctypes.CDLL(build(variant=variant))
+        R = ctypes.c_float if variant.startswith("f32") else ctypes.c_double
+        Rp = ctypes.POINTER(R)
+        I = ctypes.POINTER(ctypes.c_int)
+
+        class _P(ctypes.Structure):
+            _fields_ = [("H", ctypes.c_int), ("g", ctypes.c_int), ("d", ctypes.c_int), ("d_y", ctypes.c_int),
+                        ("hp", Rp), ("gp", Rp)]
+        L.Problem = _P
+        L.real = np.float32 if variant.startswith("f32") else np.float64
+        L.or_solve.argtypes = [ctypes.POINTER(_P), ctypes.c_long, Rp, Rp, I, R, R, R, R, ctypes.c_int, ctypes.c_int,
+                               ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), Rp, I, I, Rp, Rp,
+                               ctypes.c_int]
+        L.or_solve.restype = ctypes.c_int
+        L.or_solve_hopf.argtypes = L.or_solve.argtypes
+        L.or_solve_hopf.restype = ctypes.c_int
+        L.or_solve_mix.argtypes = [ctypes.POINTER(_P), ctypes.c_long, Rp, Rp, I, R, R, R, R, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), R, R,
+                                   Rp, I, I, Rp, Rp, ctypes.c_int]
+        L.or_solve_mix.restype = ctypes.c_int
+        _vlibs[variant] = L
+    return _vlibs[variant]
 
 
 def _dp(a: np.ndarray):
@@ -208,6 +265,53 @@ class Result:
 
 # Hamiltonian weights (wl, wr) of the interval (j-1, j): H at its left and right node.
 DISC_WEIGHTS = {"be": (0.0, 1.0), "fe": (1.0, 0.0), "trap": (0.5, 0.5)}
+
+
+def solve_variant(variant: str, pb: Problem, x, t, N, *, sigma, tau, theta=1.0, tol=1e-8, max_iter=5000,
+                  fixed_iters=False, seed=0, N_max=None, ids=None, traj=False, threads=0, hopf=False,
+                  disc="be") -> Result:
+    """solve() (Algorithms 1 to 3, the Hopf formulation, the weighted
+    discretisations; no recipes) in one of the rounding variants: "f64fma",
+    "f32" or "f32fma".  Binary32 variants take their inputs rounded to
+    binary32; results are returned as float64 arrays."""
+    if variant == "f64":
+        return solve(pb, x, t, N, sigma=sigma, tau=tau, theta=theta, tol=tol, max_iter=max_iter,
+                     fixed_iters=fixed_iters, seed=seed, N_max=N_max, ids=ids, traj=traj, threads=threads, hopf=hopf,
+                     disc=disc)
+    L = _variant_lib(variant)
+    R = L.real
+    Rp = ctypes.POINTER(ctypes.c_float if R == np.float32 else ctypes.c_double)
+    rp = lambda a: a.ctypes.data_as(Rp)  # noqa: E731
+    hp = np.ascontiguousarray(pb.hp, R)
+    gp = np.ascontiguousarray(pb.gp, R)
+    P = L.Problem(pb.H, pb.g, pb.d, pb.d_y, rp(hp), rp(gp))
+    x = np.ascontiguousarray(np.asarray(x, np.float64).reshape(-1, pb.d), R)
+    n = x.shape[0]
+    t = np.ascontiguousarray(np.broadcast_to(np.asarray(t, np.float64), (n,)), R)
+    N = np.ascontiguousarray(np.broadcast_to(np.asarray(N, np.int32), (n,))).astype(np.int32)
+    if N_max is None:
+        N_max = int(N.max()) if n else 1
+    phi = np.zeros(n, R); iters = np.zeros(n, np.int32); status = np.zeros(n, np.int32)
+    xt = np.zeros((n, N_max + 1, pb.d), R) if traj else None
+    pt = np.zeros((n, N_max + 1, pb.d), R) if traj else None
+    idp = None
+    if ids is not None:
+        ids = np.ascontiguousarray(ids, np.int64)
+        idp = ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    I = ctypes.POINTER(ctypes.c_int)
+    common = (ctypes.byref(P), n, rp(x), rp(t), N.ctypes.data_as(I), sigma, tau, theta, tol, int(max_iter),
+              int(bool(fixed_iters)), int(seed) & (2**64 - 1), int(N_max), idp)
+    outs = (rp(phi), iters.ctypes.data_as(I), status.ctypes.data_as(I), rp(xt) if traj else None,
+            rp(pt) if traj else None, int(threads))
+    if disc != "be":
+        wl, wr = (float(v) for v in (DISC_WEIGHTS.get(disc, disc) if isinstance(disc, str) else disc))
+        rc = L.or_solve_mix(*common, wl, wr, *outs)
+    else:
+        rc = (L.or_solve_hopf if hopf else L.or_solve)(*common, *outs)
+    if rc != 0:
+        raise ValueError("oracle: unsupported problem")
+    f = lambda a: None if a is None else a.astype(np.float64)  # noqa: E731
+    return Result(f(phi), iters, status, f(xt), f(pt))
 
 
 def solve(pb: Problem, x, t, N, *, sigma, tau, theta=1.0, tol=1e-8, max_iter=5000, fixed_iters=False,

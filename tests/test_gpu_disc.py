@@ -83,8 +83,8 @@ def test_norm_g_f32_matches_oracle(oracle_mod, variant):
     affine), in FP32 (the eikonal set, 16 x 1 tile, where the p residual is
     formed only once the x residual is below tol); tol 1e-6.  The value
     function has a kink at |x| = t, so a few points near it move by more than
-    a tenth of the tolerance under an FP32 rounding of the input and are
-    screened (at most 2 %)."""
+    the bar under an FP32 rounding sequence and are compared at their rounding
+    floor (at most 2 %)."""
     w = W.eikonal2d()
     w.tol = 1e-6
-    _check(oracle_mod, w, "f32", check_kstop=False, max_ill=0.02, **variant)
+    _check(oracle_mod, w, "f32", check_kstop=False, max_above=0.02, **variant)

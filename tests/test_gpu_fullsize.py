@@ -4,15 +4,15 @@ benchmark's tile and iteration cap.  The oracle cannot rerun every point, so
 it reruns a seeded sample: random points plus the slowest ones (the last to
 leave the persistent queue), each for exactly the GPU's stop iteration, and
 the sample is compared element by element at the usual bar (FP64 1e-9, FP32
-1e-4 relative, with the rounding-sensitivity screen of the small-size tests).
-Every point of the full batch is also checked for a valid status and count.
+1e-4 relative; where a point amplifies rounding, at ten times its rounding
+floor, as in the small-size tests; nothing is screened out).  Every point of
+the full batch is also checked for a valid status and count.
 """
 import numpy as np
 import pytest
 
 import workloads as W
-from helpers import oracle_fixed, rel_err, traj_err, well_conditioned
-from test_gpu_parity import TOL
+from helpers import check_against_oracle, oracle_fixed, rel_err, traj_err
 
 pytestmark = pytest.mark.gpu
 
@@ -55,8 +55,8 @@ def _sample(g, n, n_rand, n_slow, seed):
     return np.unique(np.concatenate([slow, rand]))
 
 
-def _check_sampled(O, w, g, idx, dtype, *, traj=False, hopf=False, disc="be", max_ill=0.0, converged_only=False,
-                   traj_tol=None, max_iter=None, ill_only_at_cap=False):
+def _check_sampled(O, w, g, idx, dtype, *, traj=False, hopf=False, disc="be", max_iter=None, max_above=0.0,
+                   max_undetermined=0.0):
     # whole batch: every point written, counts within the cap
     cap = w.max_iter if max_iter is None else max_iter
     assert np.all(np.isin(g["status"], [0, 1, 2])), np.bincount(g["status"][g["status"] >= 0])
@@ -66,31 +66,12 @@ def _check_sampled(O, w, g, idx, dtype, *, traj=False, hopf=False, disc="be", ma
         ws.max_iter = max_iter
     gs = {k: v[idx] for k, v in g.items()}
     o = oracle_fixed(O, ws, gs["iters"], traj=traj, inputs_dtype=dtype, hopf=hopf, disc=disc)
-    tol = TOL[dtype]
-    ok = well_conditioned(O, ws, gs["iters"], o, dtype, tol, hopf=hopf, disc=disc)
-    print("[%s %s n=%d sample=%d] status=%s screened=%d" % (w.name, dtype, w.n, len(idx),
-          np.bincount(g["status"], minlength=3), (~ok).sum()), flush=True)
-    if (~ok).any():
-        print("  screened: iters %s status %s" % (gs["iters"][~ok], gs["status"][~ok]), flush=True)
-    assert np.mean(~ok) <= max_ill
-    if ill_only_at_cap:
-        # rounding-sensitive points are allowed only among points still moving at the cap
-        assert np.all(gs["status"][~ok] == 1)
-    if converged_only:
-        ok &= gs["status"] == 0
-        assert ok.sum() >= 0.3 * len(idx)
-    e = rel_err(gs["phi"], o["phi"])[ok]
-    worst = np.nonzero(ok)[0][np.argmax(e)]
-    print("  phi rel err max %.3g over %d points (worst: status %d, iters %d)" % (
-        e.max(), ok.sum(), gs["status"][worst], gs["iters"][worst]), flush=True)
-    assert e.max() <= tol
-    if traj:
-        ex = traj_err(gs["x_traj"][ok], o["x_traj"][ok], ws.N[ok])
-        ep = traj_err(gs["p_traj"][ok], o["p_traj"][ok], ws.N[ok])
-        print("  traj rel err x %.3g p %.3g" % (ex.max(), ep.max()), flush=True)
-        ttol = tol if traj_tol is None else max(tol, traj_tol)
-        assert ex.max() <= ttol and ep.max() <= ttol
-    assert np.all((gs["status"][ok] == 2) == (o["status"][ok] == 2))
+    print("[%s %s n=%d sample=%d] status=%s, sample status=%s" % (
+        w.name, dtype, w.n, len(idx), np.bincount(g["status"], minlength=3), np.bincount(gs["status"], minlength=3)),
+        flush=True)
+    r = check_against_oracle(O, ws, gs, o, dtype, traj=traj, hopf=hopf, disc=disc, max_undetermined=max_undetermined)
+    assert np.mean(r["above"]) <= max_above, np.mean(r["above"])
+    return r
 
 
 HEADLINE_CAP = 5000  # the benchmark's iteration cap for cnorm10
@@ -120,13 +101,12 @@ def test_fullsize_cnorm10_variants_f32(oracle_mod, variant):
 def test_fullsize_quadrotor12_with_trajectories(oracle_mod):
     """131,072 points, N = ceil(t/0.05) in 10..60, trajectories written, FP32,
     cap 20,000, default tiles per N class.  The sample is compared as the
-    small-size quadrotor test does: rounding-sensitive points screened, FP32
-    trajectories at converged points at sqrt(tol)."""
+    small-size quadrotor test does: every sampled point, converged or at the
+    cap, at the plain bar or at its rounding floor."""
     w = W.quadrotor12()
     g = _graph_solve(w, "f32", traj=True, max_iter=20000)
     idx = _sample(g, w.n, 64, 16, seed=13)
-    _check_sampled(oracle_mod, w, g, idx, "f32", traj=True, max_ill=0.35, converged_only=True,
-                   traj_tol=float(np.sqrt(w.tol)), max_iter=20000)
+    _check_sampled(oracle_mod, w, g, idx, "f32", traj=True, max_iter=20000, max_above=0.25, max_undetermined=0.08)
 
 
 def test_fullsize_quadrotor12_hopf_with_trajectories(oracle_mod):
@@ -136,25 +116,25 @@ def test_fullsize_quadrotor12_hopf_with_trajectories(oracle_mod):
     w = W.quadrotor12()
     g = _graph_solve(w, "f32", traj=True, max_iter=20000, hopf=True)
     idx = _sample(g, w.n, 64, 16, seed=17)
-    _check_sampled(oracle_mod, w, g, idx, "f32", traj=True, hopf=True, max_ill=0.35, converged_only=True,
-                   traj_tol=float(np.sqrt(w.tol)), max_iter=20000)
+    _check_sampled(oracle_mod, w, g, idx, "f32", traj=True, hopf=True, max_iter=20000, max_above=0.25,
+                   max_undetermined=0.08)
 
 
 def test_fullsize_pursuit12_uneven_N(oracle_mod):
     """262,144 points, N in 16..96 across several tile classes in one graph,
-    cap 20,000.  About 6 % of the points are still moving at the cap; some of
-    those are oscillating, rounding-sensitive iterates (as for the quadrotor),
-    so the screen may remove points that ended at the cap, and none else.
-    After 20,000 FP32 iterations an iterate that is still moving has drifted
-    from the FP64 one by more than the FP32 bar, so values are compared at the
-    sampled points that converged (the small-size test compares every point
-    at a 2,500 cap)."""
+    cap 20,000.  About 6 % of the points are still moving at the cap; after
+    20,000 FP32 iterations such an iterate has drifted from the FP64 one by
+    more than the FP32 bar, as far as the oracle's own binary32 builds drift:
+    those are compared at their rounding floor, every other sampled point at
+    the plain bar, converged or not."""
     w = W.pursuit12()
     g = _graph_solve(w, "f32", max_iter=20000)
     assert len(np.unique(w.N)) > 40
     idx = _sample(g, w.n, 64, 16, seed=14)
-    _check_sampled(oracle_mod, w, g, idx, "f32", max_iter=20000, max_ill=0.1, ill_only_at_cap=True,
-                   converged_only=True)
+    r = _check_sampled(oracle_mod, w, g, idx, "f32", max_iter=20000, max_above=0.25, max_undetermined=0.25)
+    # the bar is out of the oracle's own reach, or no digit is determined, only where the iterate was
+    # still moving at the cap
+    assert np.all(g["status"][idx][r["above"] | ~r["det"]] == 1)
 
 
 def test_fullsize_lintanh100_forward_and_reverse(oracle_mod):

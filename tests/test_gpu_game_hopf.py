@@ -18,10 +18,9 @@ def test_isaacs_game_hopf_matches_oracle(oracle_mod, dtype):
     """A seeded 600-point sample of the section's grid at its four times
     (N = 5, 10, 15, 20: three capacity classes in one solve)."""
     w = W.isaacs2(600)
-    # FP32: the few points still moving at the 20,000 cap are oscillating,
-    # rounding-sensitive iterates; the screen may remove those and no others
-    g = _check(oracle_mod, w, dtype, hopf=True, check_kstop=(dtype == "f64"), max_ill=0.02 if dtype == "f32" else 0.0,
-               ill_only_at_cap=True)
+    # FP32: the few points still moving at the 20,000 cap are oscillating
+    # iterates that amplify rounding; they are compared at their rounding floor
+    g = _check(oracle_mod, w, dtype, hopf=True, check_kstop=(dtype == "f64"), max_above=0.02 if dtype == "f32" else 0.0)
     assert np.mean(g["status"] == 0) > 0.97
     assert np.all(g["x_traj"][:, 0, :] == 0) and np.all(g["p_traj"][:, 0, :] == 0)
     assert np.array_equal(g["x_traj"][np.arange(w.n), w.N], w.x.astype(np.float32).astype(np.float64)

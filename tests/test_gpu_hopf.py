@@ -56,15 +56,13 @@ def test_hopf_and_lax_reach_the_same_value():
 def test_hopf_quadrotor12_matches_oracle(oracle_mod, dtype):
     """The Hopf formulation on the quadrotor (general control kernel; node 1's
     step is the family's p-prox with step sigma delta/(1 + sigma) at (v -
-    sigma a)/(1 + sigma)), with the settings of the Lax quadrotor test: FP64 at
-    a 2500-iteration cap, FP32 at converged points with trajectories at the
-    stop rule's resolution sqrt(tol)."""
+    sigma a)/(1 + sigma)), with the settings of the Lax quadrotor test: every
+    point at the 20,000 cap, values and trajectories, at the plain bar or at
+    the point's rounding floor where the flat attitude directions amplify
+    rounding."""
     w = W.quadrotor12().subset(np.arange(97))
-    if dtype == "f64":
-        _check(oracle_mod, w, dtype, max_iter=2500, check_kstop=False, max_ill=0.35, hopf=True)
-    else:
-        _check(oracle_mod, w, dtype, max_iter=20000, check_kstop=False, max_ill=0.35, converged_only=True,
-               traj_tol=float(np.sqrt(w.tol)), hopf=True)
+    _check(oracle_mod, w, dtype, max_iter=20000, check_kstop=False, max_undetermined=0.08, max_above=0.25,
+           hopf=True)
 
 
 def test_hopf_quadrotor12_largest_tiles_f64(oracle_mod):
@@ -75,7 +73,7 @@ def test_hopf_quadrotor12_largest_tiles_f64(oracle_mod):
     w.N_max = 256
     w.t = np.full(w.n, 3.0)
     w.fixed_iters = True
-    g = _check(oracle_mod, w, "f64", max_iter=300, check_kstop=False, max_ill=0.35, hopf=True)
+    g = _check(oracle_mod, w, "f64", max_iter=300, check_kstop=False, hopf=True)
     assert np.all(g["iters"] == 300)
 
 
@@ -88,4 +86,4 @@ def test_quadrotor12_small_and_ragged_N_f64(oracle_mod, hopf):
     w = W.quadrotor12().subset(np.arange(40))
     w.N = np.array([1, 2, 3, 15, 16, 17, 31, 32] * 5, dtype=np.int32)
     w.t = 0.05 * w.N
-    _check(oracle_mod, w, "f64", max_iter=1500, check_kstop=False, max_ill=0.35, hopf=hopf)
+    _check(oracle_mod, w, "f64", max_iter=1500, check_kstop=False, hopf=hopf)

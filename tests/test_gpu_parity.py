@@ -3,30 +3,31 @@
 Protocol (the stopping rule can flip on one ulp): the GPU runs with the
 tolerance rule and reports its stop iteration k_i per point; the oracle is
 then run for exactly k_i iterations at point i and compared element by
-element:
+element, at every point:
   FP64: value and trajectories within 1e-9 relative (|a-b| <= 1e-9 max(|b|,1),
         trajectories in the inf-norm per point), and the stop iteration of an
         independent tolerance-mode oracle run within 1 of the GPU's for
         >= 99.9% of points;
   FP32: within 1e-4 relative, inputs rounded to FP32 on both sides.
-Points where the oracle's own result moves by more than a tenth of the
-tolerance under a rounding-sized input change (1e-15 relative for FP64, 1e-6
-for FP32) are screened out and counted: the quadrotor workload has such
-points, the screen must remove none elsewhere.
+Where the iteration amplifies rounding, a point's bound is raised to ten
+times its rounding floor: how far other rounding sequences of the same
+iteration (the oracle's binary32 builds for FP32 runs; its FMA build and
+one-ulp input changes for FP64 runs) land from the oracle at the same
+iteration count.  Nothing is screened out; points whose result no rounding
+sequence determines (one of them leaves the finite range, another does not)
+are counted, and allowed only where stated.
 """
 import numpy as np
 import pytest
 
 import workloads as W
-from helpers import gpu_solve, oracle_fixed, oracle_tol, rel_err, traj_err, well_conditioned
+from helpers import TOL, check_against_oracle, gpu_solve, oracle_fixed, oracle_tol, rel_err
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-9, "f32": 1e-4}
-
 
 def _check(O, w, dtype, *, plain=False, max_iter=None, lanes_per_point=0, nodes_per_lane=0, check_kstop=True,
-           traj=True, max_ill=0.0, converged_only=False, traj_tol=None, hopf=False, disc="be", ill_only_at_cap=False):
+           traj=True, hopf=False, disc="be", max_undetermined=0.0, max_above=0.0):
     if max_iter is not None:
         w.max_iter = max_iter
     g = gpu_solve(w, dtype=dtype, plain=plain, lanes_per_point=lanes_per_point, nodes_per_lane=nodes_per_lane,
@@ -36,29 +37,9 @@ def _check(O, w, dtype, *, plain=False, max_iter=None, lanes_per_point=0, nodes_
         np.bincount(g["status"], minlength=4)), flush=True)
     assert np.all(g["status"] >= 0) and np.all(g["iters"] >= 1)
     o = oracle_fixed(O, w, g["iters"], traj=traj, inputs_dtype=dtype, hopf=hopf, disc=disc)
-    tol = TOL[dtype]
-    ok = well_conditioned(O, w, g["iters"], o, dtype, tol, hopf=hopf, disc=disc)
-    print("  ill-conditioned points screened: %d of %d" % ((~ok).sum(), w.n), flush=True)
-    assert np.mean(~ok) <= max_ill
-    if ill_only_at_cap:
-        # rounding-sensitive points are allowed only among points still moving at the cap
-        assert np.all(g["status"][~ok] == 1), (g["status"][~ok], g["iters"][~ok])
-    if converged_only:
-        ok &= g["status"] == 0
-        print("  compared at converged points: %d" % ok.sum(), flush=True)
-        assert ok.sum() >= 0.3 * w.n
-    e = rel_err(g["phi"], o["phi"])[ok]
-    print("  phi rel err max %.3g" % e.max(), flush=True)
-    assert e.max() <= tol
-    if traj:
-        ex = traj_err(g["x_traj"][ok], o["x_traj"][ok], w.N[ok])
-        ep = traj_err(g["p_traj"][ok], o["p_traj"][ok], w.N[ok])
-        print("  traj rel err x %.3g p %.3g" % (ex.max(), ep.max()), flush=True)
-        ttol = tol if traj_tol is None else max(tol, traj_tol)
-        assert ex.max() <= ttol and ep.max() <= ttol
-    # NONFINITE status agrees (the fixed-K oracle cannot tell converged-at-k
-    # from max-iter-at-k beyond the final residual)
-    assert np.all((g["status"][ok] == 2) == (o["status"][ok] == 2))
+    r = check_against_oracle(O, w, g, o, dtype, traj=traj, hopf=hopf, disc=disc, max_undetermined=max_undetermined)
+    # points where FP arithmetic itself cannot meet the bar: only where the workload is known to amplify rounding
+    assert np.mean(r["above"]) <= max_above, np.mean(r["above"])
     if check_kstop:
         ot = oracle_tol(O, w, inputs_dtype=dtype, hopf=hopf, disc=disc)
         dk = np.abs(ot["iters"].astype(np.int64) - g["iters"])
@@ -95,18 +76,17 @@ def test_cnorm10_tiles_match_oracle(oracle_mod, tile):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("plain", [False, True])
 def test_quadrotor12_matches_oracle(oracle_mod, dtype, plain):
-    """FP64 at a 2500-iteration cap (mostly unconverged iterates); FP32 at
-    converged points.  FP32 values at 1e-4.  FP32 trajectories at the stop
-    rule's own resolution: the rule (squared 2-norm of the change below tol)
-    stops quadrotor iterates that still move by 1e-4..1e-3 per iteration along
-    a slowly decaying oscillation, so the FP32 and FP64 iterates at the same k
-    agree only to about one step's motion, sqrt(tol) = 1e-3."""
+    """Every point at the 20,000 cap, converged or not, values and both
+    trajectories.  The quadrotor's saddle is nearly flat along the attitude
+    path (the body-rate control costs J_i^2 |d omega/dt|^2 / 2 with J_i ~ 5e-3),
+    so rounding moves the yaw and body-rate iterates by up to ~1e-2 in FP32:
+    about one point in six is compared at its rounding floor (the oracle's own
+    binary32 builds move as far), the rest at the plain bar.  A few points
+    diverge in one rounding sequence and not in another (transient pitch
+    excursions): counted as undetermined."""
     w = W.quadrotor12().subset(np.arange(97))
-    if dtype == "f64":
-        _check(oracle_mod, w, dtype, plain=plain, max_iter=2500, check_kstop=False, max_ill=0.35)
-    else:
-        _check(oracle_mod, w, dtype, plain=plain, max_iter=20000, check_kstop=False, max_ill=0.35,
-               converged_only=True, traj_tol=float(np.sqrt(w.tol)))
+    _check(oracle_mod, w, dtype, plain=plain, max_iter=20000, check_kstop=False, max_undetermined=0.08,
+           max_above=0.25)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -147,7 +127,7 @@ def test_largest_tile_N_256_other_families(oracle_mod, name):
     w.N_max = 256
     w.t = np.full(w.n, 3.0)
     w.fixed_iters = True
-    g = _check(oracle_mod, w, "f64", max_iter=300, check_kstop=False, max_ill=0.35 if name == "quadrotor12" else 0.0)
+    g = _check(oracle_mod, w, "f64", max_iter=300, check_kstop=False)
     assert np.all(g["iters"] == 300)
 
 

@@ -354,6 +354,36 @@ def test_eikonal_matches_hopf_lax_closed_form(oracle_mod):
     assert np.max(np.abs(r2.phi - exact)) < 1e-6
 
 
+@pytest.mark.parametrize("variant,bound", [("f64fma", 1e-12), ("f32", 2e-5), ("f32fma", 2e-5)])
+def test_rounding_variants_compute_the_same_method(oracle_mod, variant, bound):
+    """The oracle's rounding variants (binary64 with FMA contraction, binary32
+    without and with it), which the parity tests use to measure rounding
+    floors, run the same iteration: on the eikonal workload, whose value is
+    the classical Lax closed form, each reaches max(||x|| - t, 0) - 1 to its
+    precision, and at a fixed iteration count each stays within its
+    precision of the binary64 oracle."""
+    w = W.eikonal2d(64)
+    pb = oracle_mod.Problem(w.H, w.g, w.d, w.d_y, w.hp, w.gp)
+    exact = np.maximum(np.linalg.norm(w.x, axis=1) - w.t, 0) - 1
+    tol = 1e-26 if variant == "f64fma" else 1e-10
+    r = oracle_mod.solve_variant(variant, pb, w.x, w.t, w.N, sigma=w.sigma, tau=w.tau, tol=tol, max_iter=30000,
+                                 seed=w.init_seed, traj=True)
+    assert np.max(np.abs(r.phi - exact)) < (1e-9 if variant == "f64fma" else 5e-5)
+    # fixed count, against the oracle itself
+    K = 400
+    a = oracle_mod.solve(pb, w.x, w.t, w.N, sigma=w.sigma, tau=w.tau, max_iter=K, fixed_iters=True,
+                         seed=w.init_seed, traj=True)
+    b = oracle_mod.solve_variant(variant, pb, w.x, w.t, w.N, sigma=w.sigma, tau=w.tau, max_iter=K,
+                                 fixed_iters=True, seed=w.init_seed, traj=True)
+    assert np.all(b.iters == K)
+    assert np.max(np.abs(a.phi - b.phi)) < bound
+    assert np.max(np.abs(a.x_traj - b.x_traj)) < 10 * bound
+    # a planted difference in the arithmetic is not hidden by the comparison
+    c = oracle_mod.solve_variant(variant, pb, w.x, w.t, w.N, sigma=1.01 * w.sigma, tau=w.tau, max_iter=K,
+                                 fixed_iters=True, seed=w.init_seed, traj=True)
+    assert np.max(np.abs(a.phi - c.phi)) > 10 * bound
+
+
 def test_cnorm_constant_speed_matches_closed_form(oracle_mod):
     """c = 1 (alpha = 0), g = ||x-a||^2/2 - 1: phi = max(||x - a|| - t, 0)^2/2 - 1 exactly."""
     w = W.cnorm10(48, alpha=0.0)
