@@ -36,10 +36,11 @@
  *    costate is -q (section 4.2).
  *  - Calls are asynchronous: work is enqueued on `stream` (a hipStream_t; NULL
  *    means the default stream) and outputs are valid once the stream has
- *    completed.  A solve with several capacity classes runs all but the first
- *    on the context's own streams, forked from `stream` by an event after the
- *    work already on it and joined back to it before the call's work ends, so
- *    ordering with respect to `stream` is as if everything ran on it.  Calls
+ *    completed.  A solve with several capacity classes runs up to three of
+ *    them (those of largest N) on the context's own streams, forked from
+ *    `stream` by an event after the work already on it and joined back to it
+ *    before the call's work ends, and the others on `stream`, so ordering with
+ *    respect to `stream` is as if everything ran on it.  Calls
  *    on one context must not overlap in time (the context's work queue, side
  *    streams and scratch are shared by its calls).
  *  - Return codes are HJPD_* below; on a non-OK return hjpd_last_error()
@@ -171,7 +172,11 @@ enum {
                                     delta where both Euler rules are first-order.  HJPD_FORWARD_EULER and
                                     HJPD_TRAPEZOID are built for H = CNORM with g = NORM or QUAD_SHIFT on the
                                     persistent control path (not with HJPD_PLAIN, HJPD_HOPF or the recipes:
-                                    HJPD_EUNSUPPORTED); setting both is HJPD_EINVAL. */
+                                    HJPD_EUNSUPPORTED); setting both is HJPD_EINVAL. */,
+    HJPD_NO_REFILL = 1u << 8      /* persistent kernels without retire and refill: every lane group solves
+                                    exactly one point and the launch has a group for every point, so a wave
+                                    stays resident until its slowest point stops (the same kernels, layout and
+                                    queue order; for measuring what refill buys).  Not with HJPD_PLAIN. */
 };
 
 typedef struct {
@@ -187,7 +192,7 @@ typedef struct {
     int max_iter;    /* iteration cap (>= 1); with HJPD_FIXED_ITERS the exact count */
     uint64_t seed;   /* random start: counter-based SplitMix64 stream */
     unsigned flags;  /* HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_GRAPH | HJPD_TIMING | HJPD_NO_ORDER_HINT | HJPD_HOPF
-                        | HJPD_FORWARD_EULER | HJPD_TRAPEZOID */
+                        | HJPD_FORWARD_EULER | HJPD_TRAPEZOID | HJPD_NO_REFILL */
     int lanes_per_point; /* persistent tile override: lanes per point (8,16,32,64), 0 = tuned/default */
     int nodes_per_lane;  /* persistent tile override: time nodes per lane (1..4), 0 = tuned/default */
     /* Robustness recipes (section 6, remarks on slow points); all zero = plain
@@ -279,25 +284,82 @@ int hjpd_value_grad(hjpd_ctx *ctx, int64_t n, const void *x, const void *t, cons
                     void *stream);
 
 /*
- * Choose the persistent kernel's tile (lanes per point, nodes per lane) for
- * each range of N by timing the candidates on this batch for `probe_iters`
- * fixed iterations (default 200 if <= 0), and store the choice in the
- * context (and in the on-disk cache named by $HJPD_TUNE_CACHE, if set).
- * Synchronises `stream`.  Arguments as for hjpd_solve_batch; outputs are
- * scratch here.
+ * Tune the persistent path on this batch: the capacity classes (which ranges
+ * of N share one launch) and each class's tile, i.e. lanes per point L
+ * (64/L points per wavefront) and nodes per lane K (the unroll of each lane's
+ * loop over its time nodes), with L*K covering the class's largest N.  It
+ * starts from a class boundary at every compiled capacity (8, 16, 24, 32, 48,
+ * 64, 96, 128, 192, 256), picks each class's fastest tile among those of
+ * capacity up to twice its top, then merges neighbouring classes while a
+ * merge is at least 1 % faster.  Each candidate is timed as a whole solve of
+ * exactly `probe_iters` iterations per point (default 200 if <= 0).  The
+ * chosen plan is installed in the context and, when $HJPD_TUNE_CACHE names a
+ * file, appended to it; hjpd_create reads that file and starts from the last
+ * plan recorded for the same problem (family, g, d, d_y, dtype, N_max, kernel
+ * variant, gfx950).  Synchronises `stream`.  Arguments as for
+ * hjpd_solve_batch; phi, iters and status are scratch here.  EINVAL if the
+ * descriptor fixes the tile; EUNSUPPORTED for HJPD_PLAIN or linear-tanh.
  */
 int hjpd_autotune(hjpd_ctx *ctx, int64_t n, const void *x, const void *t, const int32_t *N,
                   const void *h_params, const void *g_params, void *phi, int32_t *iters, int32_t *status,
                   int probe_iters, void *stream);
 
 /*
+ * Queue-integrity hook: with a non-NULL `counts` (caller-owned device int32
+ * array of at least n entries for the solves that follow, zeroed by the
+ * caller), every pop of point i from the work queue adds 1 to counts[i]; a
+ * correct queue pops every valid point exactly once and no bad-input point.
+ * NULL turns counting off.  Persistent kernels only (EUNSUPPORTED otherwise).
+ * Drops a captured graph.
+ */
+int hjpd_set_pop_counter(hjpd_ctx *ctx, int32_t *counts);
+
+/*
+ * Set the persistent path's capacity classes explicitly: class c serves the
+ * points with hi[c-1] < N <= hi[c] (hi[-1] = 0) with the tile (L[c], K[c]).
+ * hi ascending, the last one >= N_max (it is clamped to N_max), L[c]*K[c] >=
+ * min(hi[c], N_max), 1..16 classes, tiles among the compiled ones (L in {8,
+ * 16, 32, 64}, K in 1..4; capacities 8, 16, 24, 32, 48, 64, 96, 128, 192,
+ * 256).  EINVAL / EUNSUPPORTED otherwise, with the previous plan kept.
+ * A point's result depends on the tile that serves it (its lanes and nodes
+ * per lane fix the summation order of its residuals, so a stop decision can
+ * differ in the last bit) but not on the class boundaries, the other points
+ * or the queue order.
+ */
+int hjpd_set_plan(hjpd_ctx *ctx, int n_classes, const int32_t *hi, const int32_t *L, const int32_t *K);
+
+/*
+ * The current plan: *n_classes classes, the first max_classes of them written
+ * to hi, L, K (any may be NULL); *from_cache (may be NULL) is 1 when the plan
+ * came from the tuning cache at hjpd_create.
+ */
+int hjpd_get_plan(hjpd_ctx *ctx, int max_classes, int32_t *hi, int32_t *L, int32_t *K, int *n_classes,
+                  int *from_cache);
+
+/*
  * With HJPD_TIMING: device milliseconds of the main solve kernel(s) of the
- * last completed hjpd_solve_batch (sum over its launches), measured with HIP
- * events on the call's stream; *launches receives the number of main-kernel
- * launches.  Synchronises on those events.  EINVAL if timing is off or no
+ * last completed hjpd_solve_batch (from the first launch's start to the
+ * last one's end), measured with HIP events on the call's stream, or of the
+ * reverse-sweep kernel of the last hjpd_value_grad; *launches receives the
+ * number of those kernel launches.  Synchronises on those events.  EINVAL if timing is off or no
  * solve has run.
  */
 int hjpd_get_timing(hjpd_ctx *ctx, double *ms, int *launches);
+
+/*
+ * With HJPD_TIMING, after an eager solve on the persistent kernels (not
+ * HJPD_PLAIN, not HJPD_GRAPH, not HJPD_H_LINEAR_TANH): device milliseconds of
+ * launch i (0 <= i < the launch count hjpd_get_timing reports) of the last
+ * completed solve, measured with HIP events on the stream that launch ran on
+ * (each capacity class is one persistent launch, section 7's per-point
+ * independence lets the classes run side by side), and the launch's class:
+ * the N range [*N_lo, *N_hi] it served and its tile (lanes per point, nodes
+ * per lane).  Output pointers other than ms may be NULL.  Synchronises on
+ * the launch's end event.  EINVAL if timing is off, no such solve has run,
+ * or i is out of range.
+ */
+int hjpd_get_launch_timing(hjpd_ctx *ctx, int i, double *ms, int *N_lo, int *N_hi, int *lanes_per_point,
+                           int *nodes_per_lane);
 
 /* Release the context and its device workspace.  NULL is allowed. */
 int hjpd_destroy(hjpd_ctx *ctx);

@@ -17,10 +17,11 @@ from .solver import Solver
 class LinearTanhValue:
     """Context for H = -<p, A x + eps tanh x> + |p|^2/2, g = x^T Q x / 2 (float32)."""
 
-    def __init__(self, d, N_max, sigma, tau, K, ckpt_every=50, theta=1.0, seed=0):
+    def __init__(self, d, N_max, sigma, tau, K, ckpt_every=50, theta=1.0, seed=0, timing=False):
         self.K, self.ckpt_every = int(K), int(ckpt_every)
         self.solver = Solver(d=d, H=C.HJPD_H_LINEAR_TANH, g=C.HJPD_G_QUAD_FORM, N_max=N_max, sigma=sigma, tau=tau,
-                             theta=theta, tol=1e-30, max_iter=K, seed=seed, dtype=torch.float32, fixed_iters=True)
+                             theta=theta, tol=1e-30, max_iter=K, seed=seed, dtype=torch.float32, fixed_iters=True,
+                             timing=timing)
         self.d = d
 
     def value(self, x, t, N, hp, Q):

@@ -284,8 +284,13 @@ struct hjpd_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timing_valid = false;
   int timing_launches = 0;
+  // per persistent launch (one per capacity class), recorded on the launch's own stream
+  std::vector<hipEvent_t> ev_cls0, ev_cls1;
+  std::vector<int> timed_cls;  // class index of each timed launch, in launch order
   // linear-tanh (differentiation) state
   hjpd::LtState* lt = nullptr;
+  bool plan_from_cache = false;  // the plan came from the on-disk tuning cache
+  int32_t* d_pops = nullptr;     // caller's pop counter (hjpd_set_pop_counter), not owned
 };
 
 namespace {
@@ -310,21 +315,32 @@ Lookup lookup_for(const hjpd_desc& d) {
   return nullptr;
 }
 
-// Default tile for a capacity class.
-hjpd::Tile default_tile(int cap) {
-  switch (cap) {
-    case 8: return {8, 1};
-    case 16: return {16, 1};
-    case 32: return {16, 2};
-    case 64: return {32, 2};
-    case 96: return {32, 3};
-    case 128: return {32, 4};
-    case 192: return {64, 3};
-    default: return {64, 4};
-  }
-}
+// A capacity class of the persistent path: the points with N in (previous
+// class's hi, hi] run one launch of the tile (L lanes per point, K nodes per
+// lane, L*K >= hi).
+struct ClassSpec {
+  int hi, L, K;
+};
 
-const int kCaps[] = {8, 16, 32, 64, 96, 128, 192, 256};
+// Capacities a class boundary may sit at (the capacities L*K of the compiled tiles).
+const int kCaps[] = {8, 16, 24, 32, 48, 64, 96, 128, 192, 256};
+constexpr int kNumCaps = sizeof(kCaps) / sizeof(kCaps[0]);
+constexpr int kMaxClasses = 16;
+// Parallel branches of a solve: HIP's default number of hardware queues per process.
+constexpr int kMaxBranches = 4;
+
+// Default partition: classes at the power-of-two capacities and 96, 192,
+// with the tile measured best for each capacity.
+std::vector<ClassSpec> default_spec(int N_max) {
+  static const ClassSpec kDefault[] = {{8, 8, 1},   {16, 16, 1}, {32, 16, 2}, {64, 32, 2},
+                                       {96, 32, 3}, {128, 32, 4}, {192, 64, 3}, {256, 64, 4}};
+  std::vector<ClassSpec> v;
+  for (const ClassSpec& cs : kDefault) {
+    v.push_back(cs);
+    if (cs.hi >= N_max) break;
+  }
+  return v;
+}
 
 // Persistent grid at full occupancy: resident blocks per CU times CUs.
 int persistent_grid(hjpd_ctx* c, const void* kern) {
@@ -347,6 +363,9 @@ constexpr int64_t kBulkFactor = 8;
 
 int launch_grid(const hjpd_ctx* c, const Cls& cl, int64_t n) {
   const int per_block = 256 / cl.L;                          // points one block holds at once
+  // without refill every group takes one point: enough groups for the whole
+  // batch (an upper bound on the class), each block leaving when its groups finish
+  if (c->desc.flags & HJPD_NO_REFILL) return int(std::max<int64_t>(1, (n + per_block - 1) / per_block));
   const int64_t resident = int64_t(cl.grid) * per_block;     // points held at once, full occupancy
   int64_t grid = cl.grid;
   if (n <= kBulkFactor * resident) {
@@ -358,57 +377,151 @@ int launch_grid(const hjpd_ctx* c, const Cls& cl, int64_t n) {
   return int(grid);
 }
 
-int build_plan(hjpd_ctx* c, const int* tile_override_L, const int* tile_override_K) {
-  Lookup lk = lookup_for(c->desc);
-  c->plan.clear();
+void drop_graph(hjpd_ctx* c);
+int ensure_class_events(hjpd_ctx* c);
+
+// Install a class partition: validate it, look up the kernels, upload the
+// class bounds, and make sure there are side streams for the parallel
+// branches and (with HJPD_TIMING) per-launch events.  The last class's hi is
+// clamped to N_max; classes past N_max are dropped.
+int apply_spec(hjpd_ctx* c, const std::vector<ClassSpec>& spec) {
+  const hjpd_desc& D = c->desc;
+  Lookup lk = lookup_for(D);
+  if (!lk) return fail(HJPD_EUNSUPPORTED, "no persistent kernels for this family");
+  std::vector<Cls> plan;
   int prev = 0;
-  for (int ci = 0; ci < 8 && prev < c->desc.N_max; ci++) {
-    const int cap = kCaps[ci];
+  for (const ClassSpec& cs : spec) {
+    if (cs.hi <= prev) return fail(HJPD_EINVAL, "plan: class bounds must ascend");
+    if (cs.L * cs.K < std::min(cs.hi, D.N_max)) return fail(HJPD_EINVAL, "plan: a tile's capacity L*K is below its class's N");
     Cls cl;
     cl.lo = prev + 1;
-    cl.hi = std::min(cap, c->desc.N_max);
-    hjpd::Tile t = default_tile(cap);
-    if (tile_override_L && tile_override_L[ci] > 0) t = {tile_override_L[ci], tile_override_K[ci]};
-    if (c->desc.lanes_per_point > 0) {
-      t.L = c->desc.lanes_per_point;
-      t.K = c->desc.nodes_per_lane > 0 ? c->desc.nodes_per_lane : 1;
-      if (t.L * t.K < c->desc.N_max) return fail(HJPD_EINVAL, "tile override capacity below N_max");
-    }
-    cl.L = t.L;
-    cl.K = t.K;
-    cl.kern = lk(0, t.L, t.K, kernel_variant(c->desc));
-    if (!cl.kern) return fail(HJPD_EUNSUPPORTED, "tile not built");
+    cl.hi = std::min(cs.hi, D.N_max);
+    cl.L = cs.L;
+    cl.K = cs.K;
+    cl.kern = lk(0, cs.L, cs.K, kernel_variant(D));
+    if (!cl.kern) return fail(HJPD_EUNSUPPORTED, "plan: tile not built");
     cl.grid = persistent_grid(c, cl.kern);
-    c->plan.push_back(cl);
+    plan.push_back(cl);
     prev = cl.hi;
-    if (c->desc.lanes_per_point > 0) {  // one class covers everything
-      c->plan.back().lo = 1;
-      c->plan.back().hi = c->desc.N_max;
-      break;
-    }
+    if (prev >= D.N_max) break;
   }
-  c->plain_kern = lk(1, 0, 0, 0);
-  return HJPD_OK;
-}
-
-int upload_plan(hjpd_ctx* c) {
-  const int ncls = int(c->plan.size());
+  if (plan.empty() || prev < D.N_max) return fail(HJPD_EINVAL, "plan: the classes must cover N = 1..N_max");
+  if (int(plan.size()) > kMaxClasses) return fail(HJPD_EINVAL, "plan: at most 16 classes");
+  const int ncls = int(plan.size());
   if (ncls > c->ncls_alloc) {
     if (c->d_cls_bounds) (void)hipFree(c->d_cls_bounds);
     if (c->d_cls_range) (void)hipFree(c->d_cls_range);
     if (c->d_heads) (void)hipFree(c->d_heads);
+    c->d_cls_bounds = c->d_cls_range = c->d_heads = nullptr;
+    c->ncls_alloc = 0;
     HIP_OK(hipMalloc(&c->d_cls_bounds, sizeof(int32_t) * 2 * ncls), "hipMalloc");
     HIP_OK(hipMalloc(&c->d_cls_range, sizeof(int32_t) * 2 * (ncls + 1)), "hipMalloc");
     HIP_OK(hipMalloc(&c->d_heads, sizeof(int32_t) * (ncls + 1)), "hipMalloc");
     c->ncls_alloc = ncls;
   }
-  std::vector<int32_t> b(2 * ncls);
+  std::vector<int32_t> bnd(2 * ncls);
   for (int i = 0; i < ncls; i++) {
-    b[2 * i] = c->plan[i].lo;
-    b[2 * i + 1] = c->plan[i].hi;
+    bnd[2 * i] = plan[i].lo;
+    bnd[2 * i + 1] = plan[i].hi;
   }
-  HIP_OK(hipMemcpy(c->d_cls_bounds, b.data(), sizeof(int32_t) * 2 * ncls, hipMemcpyHostToDevice), "hipMemcpy");
+  HIP_OK(hipMemcpy(c->d_cls_bounds, bnd.data(), sizeof(int32_t) * 2 * ncls, hipMemcpyHostToDevice), "hipMemcpy");
+  if (ncls > 1 && !c->ev_fork)
+    HIP_OK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "hipEventCreate");
+  while (int(c->side.size()) < std::min(ncls - 1, kMaxBranches - 1)) {
+    hipStream_t st = nullptr;
+    HIP_OK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+    c->side.push_back(st);
+    hipEvent_t ev = nullptr;
+    HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
+    c->ev_join.push_back(ev);
+  }
+  drop_graph(c);
+  c->plan = plan;
+  if (D.flags & HJPD_TIMING) return ensure_class_events(c);
   return HJPD_OK;
+}
+
+std::vector<ClassSpec> current_spec(const hjpd_ctx* c) {
+  std::vector<ClassSpec> v;
+  for (const Cls& cl : c->plan) v.push_back({cl.hi, cl.L, cl.K});
+  return v;
+}
+
+// On-disk tuning cache ($HJPD_TUNE_CACHE): one line per tuned plan,
+//   <key> plan=<hi>:<L>x<K>,<hi>:<L>x<K>,...
+// where the key names everything the choice depends on.  hjpd_autotune
+// appends; hjpd_create takes the last line whose key matches.
+std::string tune_key(const hjpd_desc& d) {
+  char buf[192];
+  std::snprintf(buf, sizeof(buf), "hjpd-tune v2 arch=gfx950 H=%d g=%d d=%d d_y=%d dtype=%d N_max=%d variant=%d",
+                d.H, d.g, d.d, d.d_y, d.dtype, d.N_max, kernel_variant(d));
+  return buf;
+}
+
+bool read_cached_spec(const hjpd_desc& d, std::vector<ClassSpec>* out) {
+  const char* path = std::getenv("HJPD_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  const std::string key = tune_key(d) + " plan=";
+  char line[1024];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    if (std::strncmp(line, key.c_str(), key.size()) != 0) continue;
+    std::vector<ClassSpec> v;
+    const char* q = line + key.size();
+    int hi, L, K, used = 0;
+    bool ok = true;
+    while (std::sscanf(q, "%d:%dx%d%n", &hi, &L, &K, &used) == 3) {
+      v.push_back({hi, L, K});
+      q += used;
+      if (*q == ',') q++;
+      else break;
+      if (v.size() > size_t(kMaxClasses)) { ok = false; break; }
+    }
+    if (ok && !v.empty()) {
+      *out = v;
+      found = true;  // later lines win
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void append_cached_spec(const hjpd_desc& d, const std::vector<ClassSpec>& v) {
+  const char* path = std::getenv("HJPD_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s plan=", tune_key(d).c_str());
+  for (size_t i = 0; i < v.size(); i++) std::fprintf(f, "%s%d:%dx%d", i ? "," : "", v[i].hi, v[i].L, v[i].K);
+  std::fprintf(f, "\n");
+  std::fclose(f);
+}
+
+// The plan a new context starts with: the descriptor's tile override (one
+// class), else the tuning cache's entry for this problem, else the default.
+int build_plan(hjpd_ctx* c, bool* from_cache) {
+  if (from_cache) *from_cache = false;
+  if (c->desc.lanes_per_point > 0) {
+    const int L = c->desc.lanes_per_point, K = c->desc.nodes_per_lane > 0 ? c->desc.nodes_per_lane : 1;
+    if (L * K < c->desc.N_max) return fail(HJPD_EINVAL, "tile override capacity below N_max");
+    int rc = apply_spec(c, {{c->desc.N_max, L, K}});
+    c->plain_kern = lookup_for(c->desc)(1, 0, 0, 0);
+    return rc;
+  }
+  std::vector<ClassSpec> v;
+  if (read_cached_spec(c->desc, &v)) {
+    if (apply_spec(c, v) == HJPD_OK) {
+      if (from_cache) *from_cache = true;
+      c->plain_kern = lookup_for(c->desc)(1, 0, 0, 0);
+      return HJPD_OK;
+    }
+    g_err.clear();  // an unusable cache entry falls back to the default
+  }
+  int rc = apply_spec(c, default_spec(c->desc.N_max));
+  c->plain_kern = lookup_for(c->desc)(1, 0, 0, 0);
+  return rc;
 }
 
 size_t elem_size(const hjpd_desc& d) { return d.dtype == HJPD_F64 ? 8 : 4; }
@@ -430,8 +543,10 @@ int validate_desc(const hjpd_desc* d) {
   if (d->g < 0 || d->g > 4) return fail(HJPD_EINVAL, "unknown initial-cost family");
   if (d->dtype != HJPD_F32 && d->dtype != HJPD_F64) return fail(HJPD_EINVAL, "unknown dtype");
   if (d->flags & ~unsigned(HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_GRAPH | HJPD_TIMING | HJPD_NO_ORDER_HINT | HJPD_HOPF |
-                          HJPD_FORWARD_EULER | HJPD_TRAPEZOID))
+                          HJPD_FORWARD_EULER | HJPD_TRAPEZOID | HJPD_NO_REFILL))
     return fail(HJPD_EINVAL, "unknown flag bits");
+  if ((d->flags & HJPD_NO_REFILL) && (d->flags & HJPD_PLAIN))
+    return fail(HJPD_EINVAL, "HJPD_NO_REFILL applies to the persistent kernels");
   if ((d->flags & HJPD_FORWARD_EULER) && (d->flags & HJPD_TRAPEZOID))
     return fail(HJPD_EINVAL, "HJPD_FORWARD_EULER and HJPD_TRAPEZOID exclude each other");
   if (d->lanes_per_point != 0) {
@@ -552,6 +667,8 @@ int enqueue_solve(hjpd_ctx* c, const Workspace& ws, int64_t n, const void* x, co
   a.sigma_inc = T(D.sigma_inc);
   a.value_tol = T(D.value_tol);
   a.seed = D.seed;
+  a.refill = (D.flags & HJPD_NO_REFILL) ? 0 : 1;
+  a.pops = c->d_pops;
   void* args[] = {&a};
   if (timed) HIP_OK(hipEventRecord(c->ev0, s), "hipEventRecord");
   int launches = 0;
@@ -565,22 +682,49 @@ int enqueue_solve(hjpd_ctx* c, const Workspace& ws, int64_t n, const void* x, co
     // solve's stream, the others on side streams forked from it and joined
     // back), so one class's tail overlaps the others' bulk.  The classes read
     // disjoint queue segments and write disjoint points.
-    const bool fork = ncls > 1 && int(c->side.size()) >= ncls - 1;
+    // The classes of largest N (the most work) each get a branch of their own;
+    // the rest run one after another on the solve's stream.  A process has
+    // kMaxBranches hardware queues, so more streams would only share them.
+    const int nside = std::min(ncls - 1, kMaxBranches - 1);
+    const bool fork = nside > 0 && int(c->side.size()) >= nside;
+    const bool per_launch = timed && int(c->ev_cls0.size()) >= ncls;
+    if (per_launch) c->timed_cls.clear();
     if (fork) HIP_OK(hipEventRecord(c->ev_fork, s), "hipEventRecord");
     for (int ci = ncls - 1; ci >= 0; ci--) {
-      hipStream_t st = (fork && ci > 0) ? c->side[ci - 1] : s;
+      const int rank = ncls - 1 - ci;  // 0: the class of largest N
+      hipStream_t st = (fork && rank < nside) ? c->side[rank] : s;
       if (st != s) HIP_OK(hipStreamWaitEvent(st, c->ev_fork, 0), "hipStreamWaitEvent");
       a.cls = ci;
+      if (per_launch) HIP_OK(hipEventRecord(c->ev_cls0[ci], st), "hipEventRecord");
       HIP_OK(hipLaunchKernel(c->plan[ci].kern, dim3(launch_grid(c, c->plan[ci], n)), dim3(256), args, 0, st),
              "persistent kernel launch");
-      if (st != s) HIP_OK(hipEventRecord(c->ev_join[ci - 1], st), "hipEventRecord");
+      if (per_launch) {
+        HIP_OK(hipEventRecord(c->ev_cls1[ci], st), "hipEventRecord");
+        c->timed_cls.push_back(ci);
+      }
+      if (st != s) HIP_OK(hipEventRecord(c->ev_join[rank], st), "hipEventRecord");
       launches++;
     }
     if (fork)
-      for (int ci = 1; ci < ncls; ci++) HIP_OK(hipStreamWaitEvent(s, c->ev_join[ci - 1], 0), "hipStreamWaitEvent");
+      for (int r = 0; r < nside; r++) HIP_OK(hipStreamWaitEvent(s, c->ev_join[r], 0), "hipStreamWaitEvent");
   }
   if (timed) HIP_OK(hipEventRecord(c->ev1, s), "hipEventRecord");
   c->timing_launches = launches;
+  return HJPD_OK;
+}
+
+// Start/end events of each class launch, for HJPD_TIMING (created outside any solve).
+int ensure_class_events(hjpd_ctx* c) {
+  while (c->ev_cls0.size() < c->plan.size()) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_OK(hipEventCreate(&e0), "hipEventCreate");
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return fail(HJPD_EDEVICE, "hipEventCreate failed");
+    }
+    c->ev_cls0.push_back(e0);
+    c->ev_cls1.push_back(e1);
+  }
   return HJPD_OK;
 }
 
@@ -678,25 +822,7 @@ int hjpd_create(const hjpd_desc* desc, hjpd_ctx** out) {
     }
   } else {
     rc = resolve_scratch(c->device);
-    if (!rc) rc = build_plan(c, nullptr, nullptr);
-    if (!rc) rc = upload_plan(c);
-    if (!rc && c->plan.size() > 1) {
-      if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess) rc = fail(HJPD_EDEVICE, "hipEventCreate failed");
-      for (size_t ci = 1; ci < c->plan.size() && !rc; ci++) {
-        hipStream_t st = nullptr;
-        hipEvent_t ev = nullptr;
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-          rc = fail(HJPD_EDEVICE, "hipStreamCreate failed");
-          break;
-        }
-        c->side.push_back(st);
-        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-          rc = fail(HJPD_EDEVICE, "hipEventCreate failed");
-          break;
-        }
-        c->ev_join.push_back(ev);
-      }
-    }
+    if (!rc) rc = build_plan(c, &c->plan_from_cache);
     if (!rc && (hipMalloc(&c->d_counts, sizeof(int32_t) * (desc->N_max + 1) * kHintBuckets) != hipSuccess ||
                 hipMalloc(&c->d_cursor, sizeof(int32_t) * (desc->N_max + 1) * kHintBuckets) != hipSuccess))
       rc = fail(HJPD_ENOMEM, "counter allocation");
@@ -709,6 +835,11 @@ int hjpd_create(const hjpd_desc* desc, hjpd_ctx** out) {
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
       hjpd_destroy(c);
       return fail(HJPD_EDEVICE, "hipEventCreate failed");
+    }
+    rc = ensure_class_events(c);
+    if (rc) {
+      hjpd_destroy(c);
+      return rc;
     }
   }
   *out = c;
@@ -727,6 +858,8 @@ int hjpd_destroy(hjpd_ctx* c) {
   if (c->d_work) (void)hipFree(c->d_work);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (hipEvent_t ev : c->ev_cls0) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : c->ev_cls1) (void)hipEventDestroy(ev);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipStream_t st : c->side) (void)hipStreamDestroy(st);
   for (hipEvent_t ev : c->ev_join) (void)hipEventDestroy(ev);
@@ -840,11 +973,75 @@ int hjpd_get_timing(hjpd_ctx* c, double* ms, int* launches) {
   return HJPD_OK;
 }
 
+int hjpd_get_launch_timing(hjpd_ctx* c, int i, double* ms, int* N_lo, int* N_hi, int* lanes_per_point,
+                           int* nodes_per_lane) {
+  g_err.clear();
+  if (!c || !ms) return fail(HJPD_EINVAL, "NULL argument");
+  if (!(c->desc.flags & HJPD_TIMING) || !c->timing_valid) return fail(HJPD_EINVAL, "no timed solve recorded");
+  if (c->lt || (c->desc.flags & (HJPD_PLAIN | HJPD_GRAPH)))
+    return fail(HJPD_EINVAL, "per-launch timing is recorded for eager persistent solves only");
+  if (i < 0 || i >= int(c->timed_cls.size())) return fail(HJPD_EINVAL, "launch index out of range");
+  const int ci = c->timed_cls[i];
+  HIP_OK(hipEventSynchronize(c->ev_cls1[ci]), "hipEventSynchronize");
+  float f = 0;
+  HIP_OK(hipEventElapsedTime(&f, c->ev_cls0[ci], c->ev_cls1[ci]), "hipEventElapsedTime");
+  *ms = f;
+  if (N_lo) *N_lo = c->plan[ci].lo;
+  if (N_hi) *N_hi = c->plan[ci].hi;
+  if (lanes_per_point) *lanes_per_point = c->plan[ci].L;
+  if (nodes_per_lane) *nodes_per_lane = c->plan[ci].K;
+  return HJPD_OK;
+}
+
+int hjpd_set_pop_counter(hjpd_ctx* c, int32_t* counts) {
+  g_err.clear();
+  if (!c) return fail(HJPD_EINVAL, "ctx is NULL");
+  if (c->lt || (c->desc.flags & HJPD_PLAIN)) return fail(HJPD_EUNSUPPORTED, "pop counting is for the persistent kernels");
+  drop_graph(c);  // a captured graph holds the old kernel arguments
+  c->d_pops = counts;
+  return HJPD_OK;
+}
+
+int hjpd_set_plan(hjpd_ctx* c, int n_classes, const int32_t* hi, const int32_t* L, const int32_t* K) {
+  g_err.clear();
+  if (!c) return fail(HJPD_EINVAL, "ctx is NULL");
+  if (c->lt || (c->desc.flags & HJPD_PLAIN)) return fail(HJPD_EUNSUPPORTED, "no persistent plan for this context");
+  if (n_classes < 1 || n_classes > kMaxClasses || !hi || !L || !K) return fail(HJPD_EINVAL, "1..16 classes, non-NULL arrays");
+  std::vector<ClassSpec> v;
+  for (int i = 0; i < n_classes; i++) v.push_back({hi[i], L[i], K[i]});
+  const std::vector<ClassSpec> old = current_spec(c);
+  int rc = apply_spec(c, v);
+  if (rc) {
+    const std::string msg = g_err;
+    (void)apply_spec(c, old);
+    return fail(rc, msg);
+  }
+  c->plan_from_cache = false;
+  return HJPD_OK;
+}
+
+int hjpd_get_plan(hjpd_ctx* c, int max_classes, int32_t* hi, int32_t* L, int32_t* K, int* n_classes,
+                  int* from_cache) {
+  g_err.clear();
+  if (!c || !n_classes) return fail(HJPD_EINVAL, "NULL argument");
+  if (c->lt || (c->desc.flags & HJPD_PLAIN)) return fail(HJPD_EUNSUPPORTED, "no persistent plan for this context");
+  const int nc = int(c->plan.size());
+  *n_classes = nc;
+  if (from_cache) *from_cache = c->plan_from_cache ? 1 : 0;
+  for (int i = 0; i < nc && i < max_classes; i++) {
+    if (hi) hi[i] = c->plan[i].hi;
+    if (L) L[i] = c->plan[i].L;
+    if (K) K[i] = c->plan[i].K;
+  }
+  return HJPD_OK;
+}
+
 int hjpd_autotune(hjpd_ctx* c, int64_t n, const void* x, const void* t, const int32_t* N, const void* hp,
                   const void* gp, void* phi, int32_t* iters, int32_t* status, int probe_iters, void* stream) {
   g_err.clear();
   if (!c) return fail(HJPD_EINVAL, "ctx is NULL");
   if (c->lt) return fail(HJPD_EUNSUPPORTED, "LINEAR_TANH has a single tile");
+  if (c->desc.flags & HJPD_PLAIN) return fail(HJPD_EUNSUPPORTED, "the plain kernel has no tile");
   if (n <= 0) return fail(HJPD_EINVAL, "n must be > 0");
   if (!x || !t || !N || !hp || !gp || !phi || !iters || !status) return fail(HJPD_EINVAL, "required pointer is NULL");
   if (c->desc.lanes_per_point > 0) return fail(HJPD_EINVAL, "tile fixed by the descriptor");
@@ -853,6 +1050,9 @@ int hjpd_autotune(hjpd_ctx* c, int64_t n, const void* x, const void* t, const in
   int rc = ensure_capacity(c, n);
   if (rc) return rc;
   const hjpd_desc saved = c->desc;
+  const std::vector<ClassSpec> start_spec = current_spec(c);
+  // probes: exactly probe_iters iterations at every point, timed from the
+  // first class launch to the last one's end on the caller's stream
   c->desc.flags = (saved.flags | HJPD_FIXED_ITERS | HJPD_TIMING) & ~unsigned(HJPD_GRAPH | HJPD_PLAIN);
   c->desc.max_iter = probe_iters;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -861,42 +1061,89 @@ int hjpd_autotune(hjpd_ctx* c, int64_t n, const void* x, const void* t, const in
   hipEvent_t sv0 = c->ev0, sv1 = c->ev1;
   c->ev0 = e0;
   c->ev1 = e1;
-  drop_graph(c);
   Lookup lk = lookup_for(c->desc);
-  const int nclass = int(c->plan.size());
-  int bestL[8] = {0}, bestK[8] = {0};
-  for (int ci = 0; ci < nclass && !rc; ci++) {
-    const int cap_hi = (ci < 8) ? kCaps[ci] : 256;
+  const int Nmax = c->desc.N_max;
+
+  auto measure = [&](const std::vector<ClassSpec>& spec, double* ms) -> int {
+    int r = apply_spec(c, spec);
+    if (r) return r;
     double best = 1e300;
+    for (int rep = 0; rep < 2; rep++) {
+      r = c->desc.dtype == HJPD_F64
+              ? enqueue_solve<double>(c, ctx_workspace(c), n, x, t, N, hp, gp, phi, nullptr, nullptr, iters, status, s, true)
+              : enqueue_solve<float>(c, ctx_workspace(c), n, x, t, N, hp, gp, phi, nullptr, nullptr, iters, status, s, true);
+      if (r) return r;
+      if (hipEventSynchronize(e1) != hipSuccess) return fail(HJPD_EDEVICE, "autotune sync");
+      float f = 0;
+      (void)hipEventElapsedTime(&f, e0, e1);
+      best = std::min(best, double(f));
+    }
+    *ms = best;
+    return HJPD_OK;
+  };
+  // tiles that can hold a class whose top is hi: capacity from hi up to twice hi
+  auto candidates = [&](int hi) {
+    std::vector<hjpd::Tile> v;
     for (int ti = 0; ti < hjpd::kNumTiles; ti++) {
       const hjpd::Tile tl = hjpd::kTiles[ti];
-      if (tl.L * tl.K != cap_hi) continue;
-      // time the whole solve with this class's tile replaced
-      std::vector<Cls> saved_plan = c->plan;
-      c->plan[ci].L = tl.L;
-      c->plan[ci].K = tl.K;
-      c->plan[ci].kern = lk(0, tl.L, tl.K, kernel_variant(c->desc));
-      c->plan[ci].grid = persistent_grid(c, c->plan[ci].kern);
-      double ms_total = 0;
-      for (int rep = 0; rep < 2 && !rc; rep++) {
-        if (c->desc.dtype == HJPD_F64)
-          rc = enqueue_solve<double>(c, ctx_workspace(c), n, x, t, N, hp, gp, phi, nullptr, nullptr, iters, status, s,
-                                    true);
-        else
-          rc = enqueue_solve<float>(c, ctx_workspace(c), n, x, t, N, hp, gp, phi, nullptr, nullptr, iters, status, s,
-                                   true);
+      const int cap = tl.L * tl.K;
+      if (cap >= hi && cap <= std::max(2 * hi, 8) && lk(0, tl.L, tl.K, kernel_variant(c->desc))) v.push_back(tl);
+    }
+    return v;
+  };
+
+  // 1. finest partition: a class boundary at every tile capacity below N_max
+  std::vector<ClassSpec> spec;
+  for (int ci = 0; ci < kNumCaps && (spec.empty() || spec.back().hi < Nmax); ci++) {
+    const int hi = std::min(kCaps[ci], Nmax);
+    const std::vector<hjpd::Tile> cand = candidates(hi);
+    if (cand.empty()) continue;
+    spec.push_back({hi, cand[0].L, cand[0].K});
+  }
+  double best_ms = 0;
+  rc = measure(spec, &best_ms);
+  // 2. each class's tile (lanes per point L: 64/L points per wavefront; nodes
+  //    per lane K: the unroll of each lane's node loop), whole solve timed
+  for (size_t ci = 0; ci < spec.size() && !rc; ci++) {
+    for (const hjpd::Tile& tl : candidates(spec[ci].hi)) {
+      if (tl.L == spec[ci].L && tl.K == spec[ci].K) continue;
+      std::vector<ClassSpec> trial = spec;
+      trial[ci].L = tl.L;
+      trial[ci].K = tl.K;
+      double ms = 0;
+      rc = measure(trial, &ms);
+      if (rc) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        spec = trial;
+      }
+    }
+  }
+  // 3. class boundaries: merge neighbouring classes while that is faster
+  //    (one launch and one tail fewer against more masked nodes)
+  for (bool improved = true; improved && !rc && spec.size() > 1;) {
+    improved = false;
+    std::vector<ClassSpec> best_trial;
+    double best_trial_ms = best_ms * 0.99;
+    for (size_t ci = 0; ci + 1 < spec.size() && !rc; ci++) {
+      for (const hjpd::Tile& tl : candidates(spec[ci + 1].hi)) {
+        std::vector<ClassSpec> trial = spec;
+        trial[ci + 1].L = tl.L;
+        trial[ci + 1].K = tl.K;
+        trial.erase(trial.begin() + ci);
+        double ms = 0;
+        rc = measure(trial, &ms);
         if (rc) break;
-        if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(HJPD_EDEVICE, "autotune sync"); break; }
-        float f = 0;
-        (void)hipEventElapsedTime(&f, e0, e1);
-        if (rep == 1) ms_total = f;
+        if (ms < best_trial_ms) {
+          best_trial_ms = ms;
+          best_trial = trial;
+        }
       }
-      if (!rc && ms_total < best) {
-        best = ms_total;
-        bestL[ci] = tl.L;
-        bestK[ci] = tl.K;
-      }
-      c->plan = saved_plan;
+    }
+    if (!rc && !best_trial.empty()) {
+      spec = best_trial;
+      best_ms = best_trial_ms;
+      improved = true;
     }
   }
   c->ev0 = sv0;
@@ -904,20 +1151,15 @@ int hjpd_autotune(hjpd_ctx* c, int64_t n, const void* x, const void* t, const in
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->desc = saved;
-  if (rc) return rc;
-  rc = build_plan(c, bestL, bestK);
-  if (!rc) rc = upload_plan(c);
+  if (rc) {
+    const std::string msg = g_err;
+    (void)apply_spec(c, start_spec);
+    return fail(rc, msg);
+  }
+  rc = apply_spec(c, spec);
   if (!rc) {
-    const char* path = std::getenv("HJPD_TUNE_CACHE");
-    if (path && *path) {
-      FILE* f = std::fopen(path, "a");
-      if (f) {
-        for (size_t ci = 0; ci < c->plan.size(); ci++)
-          std::fprintf(f, "H=%d d=%d dtype=%d class=%d..%d L=%d K=%d\n", c->desc.H, c->desc.d, c->desc.dtype,
-                       c->plan[ci].lo, c->plan[ci].hi, c->plan[ci].L, c->plan[ci].K);
-        std::fclose(f);
-      }
-    }
+    append_cached_spec(saved, spec);
+    c->plan_from_cache = false;
   }
   return rc;
 }
@@ -932,8 +1174,10 @@ int hjpd_value_grad(hjpd_ctx* c, int64_t n, const void* x, const void* t, const 
   if (n == 0) return HJPD_OK;
   if (!x || !t || !N || !hp || !gp || !grad_phi || !phi || !dphi_dx || !dh || !dg)
     return fail(HJPD_EINVAL, "required pointer is NULL");
+  const bool timed = (c->desc.flags & HJPD_TIMING) != 0;
   return hjpd::lt_value_grad(c->lt, c->desc, n, x, t, N, hp, gp, grad_phi, K_iters, ckpt_every, phi, dphi_dx, dh, dg,
-                             (hipStream_t)stream);
+                             (hipStream_t)stream, timed ? c->ev0 : nullptr, timed ? c->ev1 : nullptr,
+                             &c->timing_launches, &c->timing_valid);
 }
 
 }  // extern "C"

@@ -61,6 +61,12 @@ template <> struct M<float> {
   static __device__ __forceinline__ float fmax(float a, float b) { return ::fmaxf(a, b); }
   static __device__ __forceinline__ float fabs_(float a) { return ::fabsf(a); }
   static __device__ __forceinline__ bool finite(float a) { return __builtin_isfinite(a); }
+  // Quotient and square root inside the iteration: the hardware reciprocal
+  // and square root (about 1 ulp) instead of the correctly rounded sequences
+  // (about ten instructions each, with a branch for the quotient).  FP32
+  // results move by rounding only.
+  static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+  static __device__ __forceinline__ float sqrt_fast(float a) { return __builtin_amdgcn_sqrtf(a); }
 };
 
 template <> struct M<double> {
@@ -73,20 +79,24 @@ template <> struct M<double> {
   static __device__ __forceinline__ double fmax(double a, double b) { return ::fmax(a, b); }
   static __device__ __forceinline__ double fabs_(double a) { return ::fabs(a); }
   static __device__ __forceinline__ bool finite(double a) { return __builtin_isfinite(a); }
+  static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+  static __device__ __forceinline__ double sqrt_fast(double a) { return ::sqrt(a); }
 };
 
 // ---------------------------------------------------------------------------
 // Cross-lane movement.  DPP wavefront shifts (GFX9-family controls kept by
 // CDNA): wave_shr:1 gives lane i the value of lane i-1, wave_shl:1 gives lane i
-// the value of lane i+1.  Edge lanes receive garbage-free 0 / old value and
-// are overwritten by the caller (group boundaries use their own data).
+// the value of lane i+1.  Edge lanes receive 0 and are overwritten by the
+// caller (group boundaries use their own data).
 // ---------------------------------------------------------------------------
 
+// bound_ctrl set: the lane without a source (lane 0 for wave_shr, lane 63 for
+// wave_shl) reads 0, so no register has to be cleared first.
 __device__ __forceinline__ int dpp_from_prev(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);  // wave_shr:1
+  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true);  // wave_shr:1
 }
 __device__ __forceinline__ int dpp_from_next(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);  // wave_shl:1
+  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true);  // wave_shl:1
 }
 
 __device__ __forceinline__ float from_prev(float v) {
@@ -141,6 +151,21 @@ __device__ __forceinline__ T group_prev0(T v, int l) {
     const T s = dpp_f<kDppRowShr1>(v);  // row start reads 0
     if constexpr (L == 16) return s;
     else return (l == 0) ? T(0) : s;
+  }
+}
+
+// Value of v held by the previous lane of the group, and `fill` in the
+// group's first lane (fill must be 0 in every other lane).  One select (or
+// one add for 16-lane groups, whose row shift already reads 0 there).
+template <int L, typename T>
+__device__ __forceinline__ T group_prev_fill(T v, int l, T fill) {
+  if constexpr (L >= 32) {
+    const T s = from_prev(v);
+    return (l == 0) ? fill : s;
+  } else {
+    const T s = dpp_f<kDppRowShr1>(v);  // row start reads 0
+    if constexpr (L == 16) return s + fill;
+    else return (l == 0) ? fill : s;
   }
 }
 

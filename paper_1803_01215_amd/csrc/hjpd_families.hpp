@@ -31,6 +31,7 @@ enum : int { kGNorm = 0, kGQuadShift = 1, kGPairDist = 2, kGQuadForm = 3 };
 template <int D_>
 struct CNorm {
   static constexpr int D = D_;
+  static constexpr int kWavesK[5] = {0, 4, 3, 2, 2};  // FP32 waves per SIMD by nodes per lane
   static constexpr bool kGame = false;
   // dual step maps v = 0 to p = 0 exactly (nodes past N stay at p = 0 without a mask)
   static constexpr bool kZeroSafe = true;
@@ -167,7 +168,7 @@ struct CNorm {
   template <typename T>
   __device__ static T shrink_hopf1(const Par<T>& P, T (&v)[D], T mu, T sigma, bool first, T unit) {
     if (P.gkind != kGNorm) {
-      const T r1 = first ? T(1) / (T(1) + sigma) : T(1);
+      const T r1 = first ? M<T>::div(T(1), T(1) + sigma) : T(1);
       const T sg = first ? sigma * unit : T(0);
 #pragma unroll
       for (int i = 0; i < D; i++) v[i] = (v[i] - sg * P.a[i]) * r1;
@@ -199,7 +200,7 @@ struct CNorm {
     const T c = T(1) + P.alpha * s1 * c2;
     T mu = lam * c;
     if (P.gkind != kGNorm) {
-      const T r1 = T(1) / (T(1) + sigma);
+      const T r1 = M<T>::div(T(1), T(1) + sigma);
 #pragma unroll
       for (int i = 0; i < D; i++) v[i] = (v[i] - sigma * P.a[i]) * r1;
       mu *= r1;
@@ -309,6 +310,9 @@ struct CNorm {
 // ===========================================================================
 struct Quad {
   static constexpr int D = 12;
+  // FP32 waves per SIMD by nodes per lane: x, p, z and the 29-value geometry
+  // cache of a node take about 65 registers
+  static constexpr int kWavesK[5] = {0, 3, 2, 2, 2};
   static constexpr bool kGame = false;
   static constexpr bool kZeroSafe = false;
   static constexpr bool kHopf = false;      // no Hopf step in the plain kernel
@@ -407,13 +411,13 @@ struct Quad {
     v[5] -= lam * P.gz;
     const T bw = C.b[0] * v[3] + C.b[1] * v[4] + C.b[2] * v[5];
     const T bb = C.b[0] * C.b[0] + C.b[1] * C.b[1] + C.b[2] * C.b[2];
-    const T coef = lam * bw / (T(1) + lam * bb);
+    const T coef = M<T>::div(lam * bw, T(1) + lam * bb);
     v[3] -= coef * C.b[0];
     v[4] -= coef * C.b[1];
     v[5] -= coef * C.b[2];
     // body-rate costate
 #pragma unroll
-    for (int i = 0; i < 3; i++) v[9 + i] = v[9 + i] / (T(1) + lam * P.iJ2[i]);
+    for (int i = 0; i < 3; i++) v[9 + i] = M<T>::div(v[9 + i], T(1) + lam * P.iJ2[i]);
     C.bp = C.b[0] * v[3] + C.b[1] * v[4] + C.b[2] * v[5];
   }
 
@@ -475,7 +479,7 @@ struct Quad {
   // group's first lane; identity elsewhere (first = false).
   template <typename T>
   __device__ static void hopf1_in(const Par<T>& P, T (&v)[12], T& lam, T sigma, bool first) {
-    const T r1 = first ? T(1) / (T(1) + sigma) : T(1);
+    const T r1 = first ? M<T>::div(T(1), T(1) + sigma) : T(1);
     const T sg = first ? sigma : T(0);
 #pragma unroll
     for (int i = 0; i < 12; i++) v[i] = (v[i] - sg * P.a[i]) * r1;
@@ -518,6 +522,7 @@ struct Quad {
 // ===========================================================================
 struct Pursuit {
   static constexpr int D = 12;
+  static constexpr int kWavesK[5] = {0, 4, 2, 2, 2};  // FP32 waves per SIMD by nodes per lane
   static constexpr int DX = 6, DY = 6;
   static constexpr bool kGame = true;
   static constexpr bool kZeroSafe = false;
@@ -529,10 +534,10 @@ struct Pursuit {
     T kappa, wP, wE, r;
   };
   template <typename T> struct CacheX {
-    T nv;  // |v_P| at x_j^k
+    T nv, inv;  // |v_P| at x_j^k and 1/|v_P| (0 at v_P = 0)
   };
   template <typename T> struct CacheY {
-    T nv;  // |v_E| at y_j^k
+    T nv, inv;  // |v_E| at y_j^k and 1/|v_E| (0 at v_E = 0)
   };
 
   template <typename T>
@@ -545,39 +550,57 @@ struct Pursuit {
 
   template <typename T>
   __device__ static T speed(const T (&s)[6]) {
-    return M<T>::sqrt(s[3] * s[3] + s[4] * s[4] + s[5] * s[5]);
+    return M<T>::sqrt_fast(s[3] * s[3] + s[4] * s[4] + s[5] * s[5]);
   }
 
-  // p-step for node j: v -> p^{k+1}
+  // |v| and 1/|v| of a state from one reciprocal square root (both 0 at v = 0).
   template <typename T>
-  __device__ static void dual_p(const Par<T>& P, const T (&x)[6], T (&v)[6], T lam, CacheX<T>& C) {
-    C.nv = speed(x);
-    const T kn = P.kappa * C.nv;
-    const T inv = T(1) / (T(1) + lam * P.wP);
+  __device__ static void speed_inv(const T (&s)[6], T& nv, T& inv) {
+    const T ss = s[3] * s[3] + s[4] * s[4] + s[5] * s[5];
+    const T rs = M<T>::rsqrt(ss);
+    const bool nz = ss > T(0);
+    nv = nz ? ss * rs : T(0);
+    inv = nz ? rs : T(0);
+  }
+
+  // Velocity-costate factors of the p- and q-steps for the step lam = sigma
+  // delta: 1/(1 + lam wP) and 1/(1 + lam wE) (constants of a point).
+  template <typename T>
+  __device__ static void dual_scales(const Par<T>& P, T lam, T& ip, T& iq) {
+    ip = M<T>::div(T(1), T(1) + lam * P.wP);
+    iq = M<T>::div(T(1), T(1) + lam * P.wE);
+  }
+
+  // p-step for node j: v -> p^{k+1}, with ip = 1/(1 + lam wP).  lam = 0 (and
+  // ip = 1) leaves v unchanged: a node past N keeps p = 0.
+  template <typename T>
+  __device__ static void dual_p(const Par<T>& P, const T (&x)[6], T (&v)[6], T lam, T ip, CacheX<T>& C) {
+    speed_inv(x, C.nv, C.inv);
+    const T lkn = lam * P.kappa * C.nv;
 #pragma unroll
     for (int i = 0; i < 3; i++) {
       v[i] += lam * x[3 + i];
-      v[3 + i] = (v[3 + i] - lam * kn * x[3 + i]) * inv;
+      v[3 + i] = (v[3 + i] - lkn * x[3 + i]) * ip;
     }
   }
 
+  // q-step for node j, with iq = 1/(1 + lam wE).
   template <typename T>
-  __device__ static void dual_q(const Par<T>& P, const T (&y)[6], T (&v)[6], T lam, CacheY<T>& C) {
-    C.nv = speed(y);
-    const T kn = P.kappa * C.nv;
-    const T inv = T(1) / (T(1) + lam * P.wE);
+  __device__ static void dual_q(const Par<T>& P, const T (&y)[6], T (&v)[6], T lam, T iq, CacheY<T>& C) {
+    speed_inv(y, C.nv, C.inv);
+    const T lkn = lam * P.kappa * C.nv;
 #pragma unroll
     for (int i = 0; i < 3; i++) {
       v[i] += lam * y[3 + i];
-      v[3 + i] = (v[3 + i] - lam * kn * y[3 + i]) * inv;
+      v[3 + i] = (v[3 + i] - lkn * y[3 + i]) * iq;
     }
   }
 
-  // J_F(s)^T pi with |v| precomputed
+  // J_F(s)^T pi with |v| and 1/|v| precomputed (the term (v.pi) v/|v| is 0 at v = 0)
   template <typename T>
-  __device__ static void jft(const Par<T>& P, const T (&s)[6], T nv, const T (&pi)[6], T (&o)[6]) {
+  __device__ static void jft(const Par<T>& P, const T (&s)[6], T nv, T inv, const T (&pi)[6], T (&o)[6]) {
     const T vp = s[3] * pi[3] + s[4] * pi[4] + s[5] * pi[5];
-    const T w = (nv > T(0)) ? vp / nv : T(0);
+    const T w = vp * inv;
 #pragma unroll
     for (int i = 0; i < 3; i++) {
       o[i] = T(0);
@@ -587,14 +610,14 @@ struct Pursuit {
 
   template <typename T>
   __device__ static void grad_x(const Par<T>& P, const T (&x)[6], const T (&p)[6], const CacheX<T>& C, T (&g)[6]) {
-    jft(P, x, C.nv, p, g);
+    jft(P, x, C.nv, C.inv, p, g);
 #pragma unroll
     for (int i = 0; i < 6; i++) g[i] = -g[i];
   }
 
   template <typename T>
   __device__ static void grad_y(const Par<T>& P, const T (&y)[6], const T (&q)[6], const CacheY<T>& C, T (&g)[6]) {
-    jft(P, y, C.nv, q, g);
+    jft(P, y, C.nv, C.inv, q, g);
   }
 
   template <typename T>
@@ -658,6 +681,7 @@ struct Pursuit {
 // ===========================================================================
 struct Isaacs {
   static constexpr int D = 2;
+  static constexpr int kWavesK[5] = {0, 4, 3, 2, 2};  // FP32 waves per SIMD by nodes per lane
   static constexpr int DX = 1, DY = 1;
   static constexpr bool kGame = true;
   static constexpr bool kZeroSafe = false;
@@ -696,7 +720,7 @@ struct Isaacs {
     const T g = ss > T(0) ? p * M<T>::rsqrt(ss) : T(0);
     T vv = v + sd * g, lam = T(2) * sd;
     if (first) {
-      const T r = T(1) / (T(1) + sigma * P.ia2);
+      const T r = M<T>::div(T(1), T(1) + sigma * P.ia2);
       vv *= r;
       lam *= r;
     }
@@ -711,7 +735,7 @@ struct Isaacs {
     const T ss = p * p + q * q;
     const T g = ss > T(0) ? q * M<T>::rsqrt(ss) : T(0);
     const T uu = u + sd * c - sd * g;
-    return first ? uu / (T(1) + sigma * P.ib2) : uu;
+    return first ? M<T>::div(uu, T(1) + sigma * P.ib2) : uu;
   }
 
   // H at the costate pair (p, -q).

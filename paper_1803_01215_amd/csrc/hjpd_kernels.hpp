@@ -37,6 +37,12 @@ namespace hjpd {
 template <typename T, int K>
 inline constexpr int kGroupWaves = sizeof(T) == 8 ? 1 : (K == 1 ? 4 : (K == 2 ? 3 : 2));
 
+// The same per family: a family lists its FP32 waves per SIMD by K (its state
+// and per-node cache decide how many registers a node takes), so that no
+// tile spills registers to memory inside the iteration.
+template <typename T, class F, int K>
+inline constexpr int kFamWaves = sizeof(T) == 8 ? 1 : F::kWavesK[K];
+
 // The shifted-layout kernel in FP64 with at most two nodes per lane is held
 // to two waves per SIMD (256 VGPRs, a few spilled to scratch): unconstrained
 // it takes 284 registers and one wave per SIMD, and the second wave hides more
@@ -90,6 +96,8 @@ struct KArgs {
   int hopf;                  // 1: Hopf formulation (Algorithm 2), no node 0
   T wl, wr;                  // Hamiltonian weights at an interval's left / right node (weighted kernel only)
   uint64_t seed;
+  int refill;                // 1: a group that finishes a point pops the next (retire and refill)
+  int32_t* pops;             // optional [n] pop count per point id (queue integrity checks)
   // robustness recipes (kernels compiled with them only)
   int starts, restarts;
   T sigma_inc, value_tol;
@@ -114,7 +122,7 @@ __device__ __forceinline__ T init_x(T xt, uint64_t seed, int64_t pt, int arr, in
 // The eikonal family runs k_group_control_shift below.
 // ---------------------------------------------------------------------------
 template <typename T, class F, int L, int K>
-__global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArgs<T> a) {
+__global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_control(KArgs<T> a) {
   constexpr int D = F::D;
   const int lane = threadIdx.x & 63;
   const int l = lane & (L - 1);
@@ -140,12 +148,14 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
 
   auto pop_and_init = [&]() {
     int idx = 0;
-    if (l == 0) idx = atomicAdd(head, 1);
+    // without refill a group serves the one point it popped first
+    if (l == 0) idx = (a.refill || pt < 0) ? atomicAdd(head, 1) : (end - beg);
     idx = __shfl(idx, leader, 64);
     const int qi = beg + idx;
     active = qi < end;
     if (!active) return;
     pt = a.queue[qi];
+    if (a.pops && l == 0) atomicAdd(a.pops + pt, 1);
     Np = a.N[pt];
     delta = a.t[pt] / T(Np);
     sd = sigma * delta;
@@ -187,7 +197,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
     // Hopf difference operator has z_0 = 0).
     T zprev[D];
 #pragma unroll
-    for (int i = 0; i < D; i++) zprev[i] = group_prev0<L>(z[K - 1][i], l) + z0[i];
+    for (int i = 0; i < D; i++) zprev[i] = group_prev_fill<L>(z[K - 1][i], l, z0[i]);
     typename F::template Cache<T> C[K];
     T rp = T(0), rx = T(0);
 #pragma unroll
@@ -253,7 +263,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
       // value: Lagrangian at the last iterate (Algorithm 1)
       T xprev[D];
 #pragma unroll
-      for (int i = 0; i < D; i++) xprev[i] = group_prev0<L>(x[K - 1][i], l) + x0[i];
+      for (int i = 0; i < D; i++) xprev[i] = group_prev_fill<L>(x[K - 1][i], l, x0[i]);
       T acc = T(0);
       int bad = 0;
 #pragma unroll
@@ -324,7 +334,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control(KArg
 // iteration (the same arithmetic as k_group_control).
 // ---------------------------------------------------------------------------
 template <typename T, class F, int L, int K, bool kRec = true>
-__global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_rec(KArgs<T> a) {
+__global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_control_rec(KArgs<T> a) {
   constexpr int D = F::D;
   const int lane = threadIdx.x & 63;
   const int l = lane & (L - 1);
@@ -398,12 +408,14 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_rec(
 
   auto pop_and_init = [&]() __attribute__((always_inline)) {
     int idx = 0;
-    if (l == 0) idx = atomicAdd(head, 1);
+    // without refill a group serves the one point it popped first
+    if (l == 0) idx = (a.refill || pt < 0) ? atomicAdd(head, 1) : (end - beg);
     idx = __shfl(idx, leader, 64);
     const int qi = beg + idx;
     active = qi < end;
     if (!active) return;
     pt = a.queue[qi];
+    if (a.pops && l == 0) atomicAdd(a.pops + pt, 1);
     Np = a.N[pt];
     delta = a.t[pt] / T(Np);
     if constexpr (kRec) best_rank = 3;
@@ -415,7 +427,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_rec(
   auto lagrangian = [&](int& bad) __attribute__((always_inline)) {
     T xprev[D];
 #pragma unroll
-    for (int i = 0; i < D; i++) xprev[i] = group_prev0<L>(x[K - 1][i], l) + x0[i];
+    for (int i = 0; i < D; i++) xprev[i] = group_prev_fill<L>(x[K - 1][i], l, x0[i]);
     T acc = T(0);
     bad = 0;
 #pragma unroll
@@ -446,7 +458,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_control_rec(
     // Hopf difference operator has z_0 = 0).
     T zprev[D];
 #pragma unroll
-    for (int i = 0; i < D; i++) zprev[i] = group_prev0<L>(z[K - 1][i], l) + z0[i];
+    for (int i = 0; i < D; i++) zprev[i] = group_prev_fill<L>(z[K - 1][i], l, z0[i]);
     typename F::template Cache<T> C[K];
     T rp = T(0), rx = T(0);
 #pragma unroll
@@ -685,12 +697,14 @@ __global__ void __launch_bounds__(256, (kShiftWaves<T, K>)) k_group_control_shif
 
   auto pop_and_init = [&]() {
     int idx = 0;
-    if (l == 0) idx = atomicAdd(head, 1);
+    // without refill a group serves the one point it popped first
+    if (l == 0) idx = (a.refill || pt < 0) ? atomicAdd(head, 1) : (end - beg);
     idx = __shfl(idx, leader, 64);
     const int qi = beg + idx;
     active = qi < end;
     if (!active) return;
     pt = a.queue[qi];
+    if (a.pops && l == 0) atomicAdd(a.pops + pt, 1);
     Np = a.N[pt];
     delta = a.t[pt] / T(Np);
     tsd = ts * delta;
@@ -910,7 +924,7 @@ __global__ void __launch_bounds__(256, (kShiftWaves<T, K>)) k_group_control_shif
 // Hamiltonian separates as H = Hx(x, p) + Hy(y, q): block order p, q, x, y.
 // ---------------------------------------------------------------------------
 template <typename T, class F, int L, int K>
-__global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_game(KArgs<T> a) {
+__global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game(KArgs<T> a) {
   constexpr int DX = F::DX, DY = F::DY, D = F::D;
   const int lane = threadIdx.x & 63;
   const int l = lane & (L - 1);
@@ -926,6 +940,10 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_game(KArgs<T
   T x[K][DX], p[K][DX], z[K][DX], y[K][DY], q[K][DY], w[K][DY];
   T x0[DX], z0[DX], y0[DY], w0[DY];
   T tj[K], tdj[K];  // per node: tau and tau*delta where the node takes a primal step, else 0
+  // per node: sigma*delta and the velocity-costate factors of the p- and q-steps
+  // where the node has a dual (j <= N), else 0 and 1 (the step then maps the
+  // zero costate of a node past N to itself, with no branch)
+  T sdj[K], ipj[K], iqj[K];
   T delta = T(0), sd = T(0), td = T(0);
   int Np = 0, k = 0;
   int64_t pt = -1;
@@ -933,12 +951,14 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_game(KArgs<T
 
   auto pop_and_init = [&]() {
     int idx = 0;
-    if (l == 0) idx = atomicAdd(head, 1);
+    // without refill a group serves the one point it popped first
+    if (l == 0) idx = (a.refill || pt < 0) ? atomicAdd(head, 1) : (end - beg);
     idx = __shfl(idx, leader, 64);
     const int qi = beg + idx;
     active = qi < end;
     if (!active) return;
     pt = a.queue[qi];
+    if (a.pops && l == 0) atomicAdd(a.pops + pt, 1);
     Np = a.N[pt];
     delta = a.t[pt] / T(Np);
     sd = sigma * delta;
@@ -974,11 +994,16 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_game(KArgs<T
       y0[i] = (l == 0) ? init_x(xt[DX + i], a.seed, pt, kArrY, 0, i) : T(0);
       w0[i] = y0[i];
     }
+    T ip, iq;
+    F::dual_scales(P, sd, ip, iq);
 #pragma unroll
     for (int kk = 0; kk < K; kk++) {
       const int j = 1 + l * K + kk;
       tj[kk] = (j < Np) ? tau : T(0);
       tdj[kk] = (j < Np) ? td : T(0);
+      sdj[kk] = (j <= Np) ? sd : T(0);
+      ipj[kk] = (j <= Np) ? ip : T(1);
+      iqj[kk] = (j <= Np) ? iq : T(1);
     }
   };
 
@@ -987,37 +1012,35 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_game(KArgs<T
   while (__any(active)) {
     T zprev[DX], wprev[DY];
 #pragma unroll
-    for (int i = 0; i < DX; i++) zprev[i] = group_prev0<L>(z[K - 1][i], l) + z0[i];
+    for (int i = 0; i < DX; i++) zprev[i] = group_prev_fill<L>(z[K - 1][i], l, z0[i]);
 #pragma unroll
-    for (int i = 0; i < DY; i++) wprev[i] = group_prev0<L>(w[K - 1][i], l) + w0[i];
+    for (int i = 0; i < DY; i++) wprev[i] = group_prev_fill<L>(w[K - 1][i], l, w0[i]);
     typename F::template CacheX<T> CX[K];
     typename F::template CacheY<T> CY[K];
     T rp = T(0), rq = T(0), rx = T(0), ry = T(0);
     // ---- p block, then q block ----------------------------------------------
 #pragma unroll
     for (int kk = 0; kk < K; kk++) {
-      const int j = 1 + l * K + kk;
       T v[DX];
 #pragma unroll
       for (int i = 0; i < DX; i++) v[i] = p[kk][i] + sigma * (z[kk][i] - (kk == 0 ? zprev[i] : z[kk - 1][i]));
-      F::dual_p(P, x[kk], v, sd, CX[kk]);
+      F::dual_p(P, x[kk], v, sdj[kk], ipj[kk], CX[kk]);
       T u[DY];
 #pragma unroll
       for (int i = 0; i < DY; i++) u[i] = q[kk][i] + sigma * (w[kk][i] - (kk == 0 ? wprev[i] : w[kk - 1][i]));
-      F::dual_q(P, y[kk], u, sd, CY[kk]);
-      if (j <= Np) {
+      F::dual_q(P, y[kk], u, sdj[kk], iqj[kk], CY[kk]);
+      // nodes past N: v = u = 0 and the step leaves them at 0 (p = q = 0 stays, no residual)
 #pragma unroll
-        for (int i = 0; i < DX; i++) {
-          const T dp = v[i] - p[kk][i];
-          rp += dp * dp;
-          p[kk][i] = v[i];
-        }
+      for (int i = 0; i < DX; i++) {
+        const T dp = v[i] - p[kk][i];
+        rp += dp * dp;
+        p[kk][i] = v[i];
+      }
 #pragma unroll
-        for (int i = 0; i < DY; i++) {
-          const T dq = u[i] - q[kk][i];
-          rq += dq * dq;
-          q[kk][i] = u[i];
-        }
+      for (int i = 0; i < DY; i++) {
+        const T dq = u[i] - q[kk][i];
+        rq += dq * dq;
+        q[kk][i] = u[i];
       }
     }
     T pnext[DX], qnext[DY];
@@ -1088,9 +1111,9 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_game(KArgs<T
     if (done) {
       T xprev[DX], yprev[DY];
 #pragma unroll
-      for (int i = 0; i < DX; i++) xprev[i] = group_prev0<L>(x[K - 1][i], l) + x0[i];
+      for (int i = 0; i < DX; i++) xprev[i] = group_prev_fill<L>(x[K - 1][i], l, x0[i]);
 #pragma unroll
-      for (int i = 0; i < DY; i++) yprev[i] = group_prev0<L>(y[K - 1][i], l) + y0[i];
+      for (int i = 0; i < DY; i++) yprev[i] = group_prev_fill<L>(y[K - 1][i], l, y0[i]);
       T acc = T(0);
       int bad = 0;
 #pragma unroll
@@ -1172,7 +1195,7 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_game(KArgs<T
 // which is eq. discgenlaxhopfdghopf's objective after summation by parts.
 // ---------------------------------------------------------------------------
 template <typename T, class F, int L, int K>
-__global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_game_hopf(KArgs<T> a) {
+__global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game_hopf(KArgs<T> a) {
   static_assert(F::DX == 1 && F::DY == 1, "scalar players");
   constexpr int D = F::D;
   const int lane = threadIdx.x & 63;
@@ -1195,12 +1218,14 @@ __global__ void __launch_bounds__(256, (kGroupWaves<T, K>)) k_group_game_hopf(KA
 
   auto pop_and_init = [&]() {
     int idx = 0;
-    if (l == 0) idx = atomicAdd(head, 1);
+    // without refill a group serves the one point it popped first
+    if (l == 0) idx = (a.refill || pt < 0) ? atomicAdd(head, 1) : (end - beg);
     idx = __shfl(idx, leader, 64);
     const int qi = beg + idx;
     active = qi < end;
     if (!active) return;
     pt = a.queue[qi];
+    if (a.pops && l == 0) atomicAdd(a.pops + pt, 1);
     Np = a.N[pt];
     delta = a.t[pt] / T(Np);
     sd = sigma * delta;
@@ -1525,6 +1550,8 @@ __global__ void __launch_bounds__(256) k_plain_game(KArgs<T> a) {
   const T sigma = a.sigma, tau = a.tau, theta = a.theta;
   const int Np = a.N[pt];
   const T delta = a.t[pt] / T(Np), sd = sigma * delta, td = tau * delta;
+  T ip, iq;
+  F::dual_scales(P, sd, ip, iq);
   const int64_t ax = int64_t(a.N_max + 1) * DX * S, ay = int64_t(a.N_max + 1) * DY * S;
   T* WX = a.work;
   T* WP = WX + ax;
@@ -1581,8 +1608,8 @@ __global__ void __launch_bounds__(256) k_plain_game(KArgs<T> a) {
         qv[i] = qold[i] + sigma * (ww - wm[i]);
         wm[i] = ww;
       }
-      F::dual_p(P, xv, pv, sd, cx);
-      F::dual_q(P, yv, qv, sd, cy);
+      F::dual_p(P, xv, pv, sd, ip, cx);
+      F::dual_q(P, yv, qv, sd, iq, cy);
 #pragma unroll
       for (int i = 0; i < DX; i++) {
         const T d = pv[i] - pold[i];

@@ -8,8 +8,8 @@ namespace hjpd {
 // Persistent tiles (lanes per point L, nodes per lane K) that are compiled.
 // Capacity L*K bounds the N a tile can hold.
 struct Tile { int L, K; };
-inline constexpr Tile kTiles[] = {{8, 1},  {16, 1}, {8, 2},  {32, 1}, {16, 2}, {8, 4},  {64, 1},
-                                  {32, 2}, {16, 4}, {32, 3}, {64, 2}, {32, 4}, {64, 3}, {64, 4}};
+inline constexpr Tile kTiles[] = {{8, 1},  {16, 1}, {8, 2},  {8, 3},  {32, 1}, {16, 2}, {8, 4},  {16, 3},
+                                  {64, 1}, {32, 2}, {16, 4}, {32, 3}, {64, 2}, {32, 4}, {64, 3}, {64, 4}};
 inline constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 inline constexpr int kMaxCapacity = 256;
 
@@ -56,8 +56,9 @@ const void* pick_kernel(int plain, int L, int K, int variant) {
   }
 #define HJPD_TILE_CASE(LL, KK) \
   if (L == LL && K == KK) return group_ptr<T, F, LL, KK>(variant);
-  HJPD_TILE_CASE(8, 1) HJPD_TILE_CASE(16, 1) HJPD_TILE_CASE(8, 2) HJPD_TILE_CASE(32, 1) HJPD_TILE_CASE(16, 2) HJPD_TILE_CASE(8, 4) HJPD_TILE_CASE(64, 1)
-  HJPD_TILE_CASE(32, 2) HJPD_TILE_CASE(16, 4) HJPD_TILE_CASE(32, 3) HJPD_TILE_CASE(64, 2) HJPD_TILE_CASE(32, 4) HJPD_TILE_CASE(64, 3) HJPD_TILE_CASE(64, 4)
+  HJPD_TILE_CASE(8, 1) HJPD_TILE_CASE(16, 1) HJPD_TILE_CASE(8, 2) HJPD_TILE_CASE(8, 3) HJPD_TILE_CASE(32, 1) HJPD_TILE_CASE(16, 2)
+  HJPD_TILE_CASE(8, 4) HJPD_TILE_CASE(16, 3) HJPD_TILE_CASE(64, 1) HJPD_TILE_CASE(32, 2) HJPD_TILE_CASE(16, 4) HJPD_TILE_CASE(32, 3)
+  HJPD_TILE_CASE(64, 2) HJPD_TILE_CASE(32, 4) HJPD_TILE_CASE(64, 3) HJPD_TILE_CASE(64, 4)
 #undef HJPD_TILE_CASE
   return nullptr;
 }

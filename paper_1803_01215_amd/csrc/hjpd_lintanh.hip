@@ -1047,7 +1047,9 @@ static int grow(void** p, size_t* cap, size_t need) {
 
 int lt_value_grad(LtState* st, const hjpd_desc& d, int64_t n, const void* x, const void* t, const int32_t* N,
                   const void* hp, const void* gp, const void* grad_phi, int K, int E, void* phi, void* dphi_dx,
-                  void* dh, void* dg, hipStream_t s) {
+                  void* dh, void* dg, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, int* launches,
+                  bool* timing_valid) {
+  if (timing_valid) *timing_valid = false;
   if (E > K) E = K;
   const int n_ckpt = (K + E - 1) / E;
   const size_t CK = size_t(d.N_max + 1) * d.d;
@@ -1085,7 +1087,9 @@ int lt_value_grad(LtState* st, const hjpd_desc& d, int64_t n, const void* x, con
   b.part = st->part;
   b.K = K;
   void* bargs[] = {&b};
+  if (ev0) LT_HIP(hipEventRecord(ev0, s), "hipEventRecord");
   LT_HIP(hipLaunchKernel(kb, dim3(grid_b), dim3(kLtThreads), bargs, lds_b, s), "linear-tanh backward");
+  if (ev1) LT_HIP(hipEventRecord(ev1, s), "hipEventRecord");
   const int W = int(3 * dd + 1);
   hipLaunchKernelGGL(k_lt_reduce_parts, dim3((W + 255) / 256), dim3(256), 0, s, st->part, grid_b, d.d, st->sums);
   // S = -tau M (dM M)
@@ -1094,6 +1098,10 @@ int lt_value_grad(LtState* st, const hjpd_desc& d, int64_t n, const void* x, con
   hipLaunchKernelGGL(k_lt_matmul, dim3(nb), dim3(256), 0, s, st->M, st->tmp, d.d, st->tmp + dd, -float(d.tau));
   hipLaunchKernelGGL(k_lt_grad_out, dim3(nb), dim3(256), 0, s, st->sums, st->tmp + dd, d.d, (float*)dh, (float*)dg);
   LT_HIP(hipGetLastError(), "linear-tanh gradient kernels");
+  if (ev0 && ev1) {
+    if (launches) *launches = 1;
+    if (timing_valid) *timing_valid = true;
+  }
   return HJPD_OK;
 }
 

@@ -22,7 +22,8 @@ int lt_solve(LtState* st, const hjpd_desc& d, int64_t n, const void* x, const vo
              hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, int* launches, bool* timing_valid);
 int lt_value_grad(LtState* st, const hjpd_desc& d, int64_t n, const void* x, const void* t, const int32_t* N,
                   const void* hp, const void* gp, const void* grad_phi, int K_iters, int ckpt_every, void* phi,
-                  void* dphi_dx, void* dh, void* dg, hipStream_t s);
+                  void* dphi_dx, void* dh, void* dg, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, int* launches,
+                  bool* timing_valid);
 
 }  // namespace hjpd
 

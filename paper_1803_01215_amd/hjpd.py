@@ -20,10 +20,11 @@ HJPD_G_NORM, HJPD_G_QUAD_SHIFT, HJPD_G_PAIR_DIST, HJPD_G_QUAD_FORM, HJPD_G_SADDL
 HJPD_F32, HJPD_F64 = 0, 1
 HJPD_PERSISTENT, HJPD_PLAIN, HJPD_FIXED_ITERS, HJPD_GRAPH, HJPD_TIMING, HJPD_NO_ORDER_HINT, HJPD_HOPF = (
     0, 1, 2, 4, 8, 16, 32)
-HJPD_FORWARD_EULER, HJPD_TRAPEZOID = 64, 128
+HJPD_FORWARD_EULER, HJPD_TRAPEZOID, HJPD_NO_REFILL = 64, 128, 256
 
 EXPORTED = ["hjpd_create", "hjpd_solve_batch", "hjpd_solve_batch_noalloc", "hjpd_value_grad", "hjpd_autotune",
-            "hjpd_get_timing", "hjpd_destroy", "hjpd_last_error"]
+            "hjpd_get_timing", "hjpd_get_launch_timing", "hjpd_set_plan", "hjpd_get_plan", "hjpd_set_pop_counter", "hjpd_destroy",
+            "hjpd_last_error"]
 
 
 class HjpdError(RuntimeError):
@@ -75,6 +76,15 @@ def load():
         lib.hjpd_autotune.restype = ctypes.c_int
         lib.hjpd_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         lib.hjpd_get_timing.restype = ctypes.c_int
+        ip = ctypes.POINTER(ctypes.c_int)
+        lib.hjpd_get_launch_timing.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ip, ip, ip, ip]
+        lib.hjpd_get_launch_timing.restype = ctypes.c_int
+        lib.hjpd_set_pop_counter.argtypes = [vp, vp]
+        lib.hjpd_set_pop_counter.restype = ctypes.c_int
+        lib.hjpd_set_plan.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+        lib.hjpd_set_plan.restype = ctypes.c_int
+        lib.hjpd_get_plan.argtypes = [vp, ctypes.c_int, vp, vp, vp, ip, ip]
+        lib.hjpd_get_plan.restype = ctypes.c_int
         lib.hjpd_destroy.argtypes = [vp]
         lib.hjpd_destroy.restype = ctypes.c_int
         lib.hjpd_last_error.argtypes = []
@@ -149,3 +159,32 @@ def hjpd_get_timing(ctx):
     nl = ctypes.c_int()
     _check(load().hjpd_get_timing(ctx, ctypes.byref(ms), ctypes.byref(nl)))
     return ms.value, nl.value
+
+
+def hjpd_get_launch_timing(ctx, i):
+    """(ms, N_lo, N_hi, lanes_per_point, nodes_per_lane) of launch i of the last timed solve."""
+    ms = ctypes.c_double()
+    v = [ctypes.c_int() for _ in range(4)]
+    _check(load().hjpd_get_launch_timing(ctx, int(i), ctypes.byref(ms), *[ctypes.byref(x) for x in v]))
+    return (ms.value, *[x.value for x in v])
+
+
+def hjpd_set_plan(ctx, classes):
+    """classes: [(hi, L, K), ...] (host values)."""
+    n = len(classes)
+    arr = [(ctypes.c_int32 * n)(*[int(c[k]) for c in classes]) for k in range(3)]
+    _check(load().hjpd_set_plan(ctx, n, *[ctypes.cast(a, ctypes.c_void_p) for a in arr]))
+
+
+def hjpd_get_plan(ctx):
+    """([(hi, L, K), ...], from_cache) of the context's persistent plan."""
+    m = 16
+    arr = [(ctypes.c_int32 * m)() for _ in range(3)]
+    n, fc = ctypes.c_int(), ctypes.c_int()
+    _check(load().hjpd_get_plan(ctx, m, *[ctypes.cast(a, ctypes.c_void_p) for a in arr], ctypes.byref(n),
+                                ctypes.byref(fc)))
+    return [(arr[0][i], arr[1][i], arr[2][i]) for i in range(n.value)], bool(fc.value)
+
+
+def hjpd_set_pop_counter(ctx, counts):
+    _check(load().hjpd_set_pop_counter(ctx, _ptr(counts)))

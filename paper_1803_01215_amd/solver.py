@@ -42,7 +42,7 @@ class Solver:
     def __init__(self, *, d, H, g, N_max, sigma, tau, theta=1.0, tol=1e-6, max_iter=20000, seed=0, d_y=0,
                  dtype=torch.float32, plain=False, fixed_iters=False, graph=False, timing=False,
                  lanes_per_point=0, nodes_per_lane=0, order_hint=True, hopf=False, starts=1, restarts=0,
-                 sigma_inc=0.0, value_tol=0.0, disc="be"):
+                 sigma_inc=0.0, value_tol=0.0, disc="be", refill=True):
         # disc: time discretisation of the Lax saddle, "be" backward Euler (Algorithm 1),
         # "fe" forward Euler, "trap" trapezoid (eikonal family)
         if disc not in _DISC_FLAGS:
@@ -52,7 +52,7 @@ class Solver:
         flags = ((C.HJPD_PLAIN if plain else 0) | (C.HJPD_FIXED_ITERS if fixed_iters else 0)
                  | (C.HJPD_GRAPH if graph else 0) | (C.HJPD_TIMING if timing else 0)
                  | (0 if order_hint else C.HJPD_NO_ORDER_HINT) | (C.HJPD_HOPF if hopf else 0)
-                 | _DISC_FLAGS[disc])
+                 | _DISC_FLAGS[disc] | (0 if refill else C.HJPD_NO_REFILL))
         self.desc = C.hjpd_desc(d=d, d_y=d_y, H=H, g=g, dtype=C.HJPD_F64 if dtype == torch.float64 else C.HJPD_F32,
                                 N_max=N_max, sigma=sigma, tau=tau, theta=theta, tol=tol, max_iter=max_iter,
                                 seed=seed & (2**64 - 1), flags=flags, lanes_per_point=lanes_per_point,
@@ -109,3 +109,26 @@ class Solver:
 
     def timing(self):
         return C.hjpd_get_timing(self.ctx)
+
+    def plan(self):
+        """([(hi, L, K), ...], from_cache): the persistent path's capacity classes and tiles."""
+        return C.hjpd_get_plan(self.ctx)
+
+    def set_plan(self, classes):
+        C.hjpd_set_plan(self.ctx, classes)
+
+    def set_pop_counter(self, counts):
+        """counts: zeroed int32 GPU tensor with one entry per point (None turns counting off)."""
+        if counts is not None:
+            _need(counts, "counts", torch.int32)
+        C.hjpd_set_pop_counter(self.ctx, counts)
+
+    def launch_timings(self):
+        """Per persistent launch of the last timed eager solve: dicts with ms,
+        the N range of its capacity class and its tile."""
+        _, nl = C.hjpd_get_timing(self.ctx)
+        out = []
+        for i in range(nl):
+            ms, lo, hi, L, K = C.hjpd_get_launch_timing(self.ctx, i)
+            out.append({"ms": ms, "N_lo": lo, "N_hi": hi, "L": L, "K": K})
+        return out

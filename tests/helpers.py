@@ -27,7 +27,7 @@ def traj_err(a, b, N):
 
 def gpu_solve(w: W.Workload, *, dtype="f32", plain=False, fixed_iters=None, max_iter=None, tol=None, traj=True,
               graph=False, lanes_per_point=0, nodes_per_lane=0, x=None, t=None, N=None, timing=False, hopf=False,
-              disc="be"):
+              disc="be", **kw):
     import torch
 
     from paper_1803_01215_amd.solver import Solver
@@ -37,7 +37,8 @@ def gpu_solve(w: W.Workload, *, dtype="f32", plain=False, fixed_iters=None, max_
                tol=w.tol if tol is None else tol, max_iter=w.max_iter if max_iter is None else max_iter,
                seed=w.init_seed, dtype=td, plain=plain,
                fixed_iters=w.fixed_iters if fixed_iters is None else fixed_iters, graph=graph,
-               lanes_per_point=lanes_per_point, nodes_per_lane=nodes_per_lane, timing=timing, hopf=hopf, disc=disc)
+               lanes_per_point=lanes_per_point, nodes_per_lane=nodes_per_lane, timing=timing, hopf=hopf, disc=disc,
+               **kw)
     dev = "cuda"
     xs = torch.tensor(w.x if x is None else x, dtype=td, device=dev).contiguous()
     ts = torch.tensor(w.t if t is None else t, dtype=td, device=dev).contiguous()

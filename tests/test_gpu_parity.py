@@ -27,11 +27,11 @@ pytestmark = pytest.mark.gpu
 
 
 def _check(O, w, dtype, *, plain=False, max_iter=None, lanes_per_point=0, nodes_per_lane=0, check_kstop=True,
-           traj=True, hopf=False, disc="be", max_undetermined=0.0, max_above=0.0):
+           traj=True, hopf=False, disc="be", max_undetermined=0.0, max_above=0.0, **kw):
     if max_iter is not None:
         w.max_iter = max_iter
     g = gpu_solve(w, dtype=dtype, plain=plain, lanes_per_point=lanes_per_point, nodes_per_lane=nodes_per_lane,
-                  traj=traj, hopf=hopf, disc=disc)
+                  traj=traj, hopf=hopf, disc=disc, **kw)
     print("[%s %s plain=%s tile=%s,%s] n=%d iters p50=%d max=%d status=%s" % (
         w.name, dtype, plain, lanes_per_point, nodes_per_lane, w.n, np.median(g["iters"]), g["iters"].max(),
         np.bincount(g["status"], minlength=4)), flush=True)
