@@ -1,21 +1,28 @@
 """Throughput benchmark: converged (x,t) solves per second at PDHG residual 1e-6.
 
-One step = one full solve of the workload (every point runs the primal-dual
-iteration of section 5.1, Algorithm 1, until both squared residuals are below
-1e-6 or the cap is hit) with all inputs resident in HBM.
+One step = one full solve of the headline workload (every point runs the
+primal-dual iteration of section 5.1 until both squared residuals are below
+1e-6, or the iteration cap) with all inputs resident in HBM.
 
-Default workload (cnorm10): d = 10, H = c(x)||p||, c = 1 + 0.5 sin(x1) cos(x2),
-g = ||x - a||^2/2 - 1, 65,536 points x ~ N(0, I), t ~ U[0.2, 1], N = 32, FP32.
-The batched path is the persistent lane-group kernel replayed from a hipGraph;
-the plain path (one point per lane, state in HBM) is timed beside it.
+Headline workload (pursuit12): the pursuit-evasion game of two 3-D point
+masses with drag, d = 12 (6 + 6), solved by Algorithm 3 (section 4.2),
+262,144 points with t ~ U[0.5, 4] and N = clamp(ceil(24 t), 16, 96), so the
+uneven N spans four capacity classes in one hipGraph-captured solve, FP32,
+cap 20,000.  The batched path (persistent lane-group kernels with a device
+queue, retire/refill, classes on parallel branches) is timed over the whole
+set; the plain path (one point per lane, state in HBM, no refill) and the FP64
+CPU oracle on seeded samples beside it.  The other workloads (the 2-D eikonal,
+cnorm10, the quadrotor with trajectories, linear-tanh forward and reverse)
+follow as extra keys, each with its own roofline and CPU baseline.
 
-Prints one JSON line (rank 0, one GPU).
+Prints one JSON line (one GPU).
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -27,9 +34,16 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp32_vector": 157.3e12, "fp64_vector": 78.6e12, "fp32_matrix": 157.3e12}
 
 
+# ---------------------------------------------------------------------------
+# Algorithmic flops per point-iteration (FMA = 2 flops, a product or a sum 1;
+# square roots, reciprocals, rsqrt and sin/cos are not counted; constants of a
+# point, such as sigma delta or 1/(1 + sigma delta w), are counted once per
+# point, not per iteration).  Counted from the kernels' source, node by node.
+# ---------------------------------------------------------------------------
+
 def flops_per_iter_cnorm(N: int, d: int) -> int:
-    """Algorithmic flops of one iteration of one point for H = c(x)||p|| with
-    g = ||x-a||^2/2 - c0 (FMA = 2 flops; transcendentals not counted):
+    """H = c(x)||p||, g = ||x-a||^2/2 - c0 (also used for the norm g, whose
+    node-0 shrink costs about the same):
       dual step,   nodes 1..N:   9d + 12  (stencil 3d, c(x) 3, ||v||^2 2d,
                                            shrink 5, scale d, residual 3d,
                                            grad c 4)
@@ -40,11 +54,64 @@ def flops_per_iter_cnorm(N: int, d: int) -> int:
     return N * (9 * d + 12) + (N - 1) * (8 * d + 6) + 9 * d
 
 
-# Sources of the persistent kernel: HBM traffic measured by rocprofv3 counters
-# is reported only while these files are unchanged since the measurement.
+def flops_per_iter_quad(N: int) -> int:
+    """Quadrotor, d = 12 (k_group_control with the Quad family):
+      dual step, nodes 1..N: 182
+        stencil 36 (3 per coordinate);
+        geometry at x_j 59: b = R e3/m 12, its Jacobian db 30, W and tan/sec
+          products 5, dW/droll 4, sec^2 and sec tan 4, dW/dpitch 4;
+        prox 51: position costate 6, angle costate W omega 6 + 5 + 5, gravity
+          1, b.w 5, |b|^2 5, coefficient 4, rank-one correction 6, body-rate
+          scaling 3, b.p 5;
+        residual 36 (3 per coordinate);
+      primal step, nodes 1..N-1: 153
+        grad_x H 51: roll and pitch terms of -W^T p 14 + 9, thrust terms
+          7 + 7 + 4, body-rate rows of -W^T p 5 + 5;
+        update 102: positions (no gradient) 3 x (2 + 5), others 9 x (4 + 5),
+          where 5 = residual 2, extrapolation 2, step 1;
+      node 0: 96 (affine prox increment 3, residual 2, extrapolation 2, step 1,
+        per coordinate).
+    Plus 3 sin/cos pairs and a reciprocal per dual node (not counted)."""
+    return N * 182 + (N - 1) * 153 + 96
+
+
+def flops_per_iter_pursuit(N: int) -> int:
+    """Pursuit-evasion game, 6 + 6 (k_group_game with the Pursuit family):
+      dual steps (p and q blocks), nodes 1..N: 2 x 58
+        stencil 18, speed |v| 5, kappa |v| 1, position costate 6, velocity
+        costate 10, residual 18;
+      primal steps (x descent, y ascent), nodes 1..N-1: 2 x 69
+        J_F^T pi 21 (v.pi 5, ratio 1, three rows of 5), update 48 (positions
+        3 x 7 with no gradient, velocities 3 x 9);
+      node 0 (prox of g(., y_0) for x_0, stretch of -g for y_0): 2 x 59.
+    Plus one square root per block and node and two rsqrt at node 0."""
+    return N * 116 + (N - 1) * 138 + 118
+
+
+def mfma_flops_per_iter_lintanh(N: int, d: int) -> int:
+    """Matrix-core flops of one forward iteration of one point for the
+    linear-tanh family: A x_j for the dual step at j = 1..N and A^T p_j for the
+    primal step at j = 1..N-1, each a d x d by d product (FMA = 2 flops)."""
+    return 2 * d * d * (2 * N - 1)
+
+
+def mfma_flops_per_iter_lintanh_backward(N: int, d: int) -> int:
+    """Flops of one reverse-sweep iteration of one point (k_lt_backward): the
+    segment recompute of the forward products 2d^2(2N-1); the vector-Jacobian
+    products A xbar_j (j < N) and A^T vbar_j (j <= N), 2d^2(2N-1); the
+    outer products of dA over the same nodes, 2d^2(2N-1); and at node 0 the
+    product M xbar_0 and the rank-one dM update, 4d^2."""
+    return 3 * 2 * d * d * (2 * N - 1) + 4 * d * d
+
+
+# ---------------------------------------------------------------------------
+# Counter traffic (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a copy
+# calibration), reported only while the kernel sources match the measurement.
+# ---------------------------------------------------------------------------
+
 KERNEL_SOURCES = ["paper_1803_01215_amd/csrc/hjpd_kernels.hpp", "paper_1803_01215_amd/csrc/hjpd_families.hpp",
                   "paper_1803_01215_amd/csrc/hjpd_device.hpp", "paper_1803_01215_amd/csrc/hjpd_api.hip"]
-TRAFFIC_FILE = "profiles/traffic_cnorm10_f32_group16x2.json"
+TRAFFIC_FILES = ["profiles/traffic_pursuit12_f32.json", "profiles/traffic_cnorm10_f32_group16x2.json"]
 
 
 def kernel_sources_sha256() -> str:
@@ -57,209 +124,258 @@ def kernel_sources_sha256() -> str:
 
 
 def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when the summary is absent, names another kernel, or the kernel
-    sources changed after the counters were taken."""
-    path = os.path.join(ROOT, TRAFFIC_FILE)
-    if not os.path.exists(path):
-        return None
-    with open(path) as fh:
-        rec = json.load(fh)
-    if rec.get("kernel") != kernel or rec.get("sources_sha256") != kernel_sources_sha256():
-        return None
-    return float(rec["bytes_per_launch"])
+    """HBM bytes per launch of `kernel` from a committed counter summary, or
+    None when no summary names it or the kernel sources changed after the
+    counters were taken."""
+    for name in TRAFFIC_FILES:
+        path = os.path.join(ROOT, name)
+        if not os.path.exists(path):
+            continue
+        with open(path) as fh:
+            rec = json.load(fh)
+        if rec.get("kernel") == kernel and rec.get("sources_sha256") == kernel_sources_sha256():
+            return float(rec["bytes_per_launch"])
+    return None
 
 
-def mfma_flops_per_iter_lintanh(N: int, d: int) -> int:
-    """Matrix-core flops of one iteration of one point for the linear-tanh
-    family: A x_j for the dual step at j = 1..N and A^T p_j for the primal
-    step at j = 1..N-1, each a d x d by d product (FMA = 2 flops)."""
-    return 2 * d * d * (2 * N - 1)
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
-def oracle_sample(w, m):
+def iteration_histogram(iters) -> dict:
+    """Counts of points per iteration range (edges 1, 10, 30, 100, ..., 30000)."""
+    edges = [1, 10, 30, 100, 300, 1000, 3000, 10000, 20000, 30000]
+    h, _ = np.histogram(np.asarray(iters), bins=edges)
+    return {"edges": edges, "counts": [int(c) for c in h]}
+
+
+def oracle_sample(w, m, threads=None):
     """The FP64 oracle on the first m points of a workload (FP32-rounded
-    parameters, the GPU's stopping rule), OpenMP over points on the host's
-    cores: converged solves/s of the sample (fixed-iteration workloads count
-    every finished point), with the sample and thread count stated."""
+    parameters, the GPU's stopping rule and cap), OpenMP over points on the
+    host's cores: converged solves/s of the sample (fixed-iteration workloads
+    count every finished point), with the sample, thread count and CPU model
+    stated."""
     from oracle import oracle as O
     O.build()
     m = min(m, w.n)
     sub = w.subset(np.arange(m))
     pb = O.Problem(sub.H, sub.g, sub.d, sub.d_y, sub.hp.astype(np.float32).astype(np.float64),
                    sub.gp.astype(np.float32).astype(np.float64))
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = threads or int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
     r = O.solve(pb, sub.x, sub.t, sub.N, sigma=sub.sigma, tau=sub.tau, theta=sub.theta, tol=sub.tol,
                 max_iter=sub.max_iter, seed=sub.init_seed, N_max=sub.N_max, ids=sub.ids, threads=threads,
                 fixed_iters=sub.fixed_iters)
     dt = time.perf_counter() - t0
     done = m if sub.fixed_iters else int((r.status == 0).sum())
-    return {"value": done / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": "first %d of the %d points, FP64 C oracle, OpenMP over points, %.1f s wall, %d %s" % (
-                m, w.n, dt, done, "finished" if sub.fixed_iters else "converged")}
+    return {"value": done / dt, "unit": "solves/s", "cores": threads, "kind": "oracle", "cpu": cpu_model(),
+            "sample": "first %d of the %d points, FP64 C oracle, cap %d, OpenMP over points, %.1f s wall, %d %s" % (
+                m, w.n, sub.max_iter, dt, done, "finished" if sub.fixed_iters else "converged")}
 
 
-def bench_lintanh(torch, dev, steps, cpu=False):
-    """Forward solves/s and MFMA throughput at K = 500 fixed iterations, and
-    the reverse-mode call (forward with checkpoints every 50 + backward +
-    reductions) on the same 16,384 points."""
+class Bench:
+    def __init__(self, torch, dev):
+        self.torch, self.dev = torch, dev
+
+    def tensors(self, w, td):
+        t = self.torch
+        return (t.tensor(w.x, dtype=td, device=self.dev), t.tensor(w.t, dtype=td, device=self.dev),
+                t.tensor(w.N, dtype=t.int32, device=self.dev), t.tensor(w.hp, dtype=td, device=self.dev),
+                t.tensor(w.gp, dtype=td, device=self.dev))
+
+    def solver(self, w, td, **kw):
+        from paper_1803_01215_amd.solver import Solver
+        return Solver(d=w.d, d_y=w.d_y, H=w.H, g=w.g, N_max=w.N_max, sigma=w.sigma, tau=w.tau, theta=w.theta,
+                      tol=w.tol, max_iter=w.max_iter, seed=w.init_seed, dtype=td, **kw)
+
+    def timed(self, s, inp, out, steps, warmup, traj=False):
+        """Mean ms per solve over `steps` solves after `warmup` solves, HIP
+        events on the solve's stream (torch's current stream)."""
+        torch = self.torch
+        for _ in range(warmup):
+            s.solve(*inp, out=out, traj=traj)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            s.solve(*inp, out=out, traj=traj)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / max(steps, 1)
+
+    def batched(self, w, td, steps, warmup, traj=False, plan=None, **kw):
+        """The batched path, graph-replayed: ms per solve, statuses, iterations."""
+        s = self.solver(w, td, graph=True, **kw)
+        if plan is not None:
+            s.set_plan(plan)
+        inp = self.tensors(w, td)
+        out = s.alloc(w.n, traj=traj)
+        ms = self.timed(s, inp, out, steps, warmup, traj=traj)
+        st = out.status.cpu().numpy()
+        it = out.iters.cpu().numpy().astype(np.int64)
+        s.close()
+        del out, inp
+        conv = int((st == 0).sum())
+        return {"ms": ms, "converged": conv, "solves_per_s": conv / (ms * 1e-3), "status": st, "iters": it}
+
+    def launches(self, w, td, flops_fn, peak, traj=False, reps=3, plan=None, **kw):
+        """Per capacity class of the plan: one eager solve of just the class's
+        points (same plan and tile), timed by the library with HIP events on
+        the class launch's own stream (mean over reps), so no other class
+        shares the GPU or a hardware queue with it.  Returns per class the
+        launch's ms, N range, tile, its points' algorithmic flops (their
+        iterations times the count at their N) and the resulting rate."""
+        s = self.solver(w, td, timing=True, **kw)
+        if plan is not None:
+            s.set_plan(plan)
+        classes = s.plan()[0]
+        s.close()
+        N = np.asarray(w.N)
+        out = []
+        lo = 1
+        for hi, L, K in classes:
+            sel = np.nonzero((N >= lo) & (N <= hi))[0]
+            rec = {"N_lo": lo, "N_hi": hi, "L": L, "K": K, "points": int(len(sel)), "ms": 0.0, "flops": 0.0,
+                   "tflops": 0.0, "frac": 0.0}
+            lo = hi + 1
+            if len(sel) == 0:
+                out.append(rec)
+                continue
+            sub = w.subset(sel)
+            s = self.solver(sub, td, timing=True, **kw)
+            s.set_plan(classes)
+            inp = self.tensors(sub, td)
+            o = s.alloc(sub.n, traj=traj)
+            s.solve(*inp, out=o, traj=traj)
+            self.torch.cuda.synchronize()
+            ms = []
+            for _ in range(reps):
+                s.solve(*inp, out=o, traj=traj)
+                lt = [a for a in s.launch_timings() if a["N_lo"] == rec["N_lo"]]
+                ms.append(lt[0]["ms"])
+            it = o.iters.cpu().numpy().astype(np.int64)
+            st = o.status.cpu().numpy()
+            s.close()
+            del o, inp
+            fl = np.array([flops_fn(int(n)) for n in sub.N], dtype=np.float64)
+            ok = st != 3
+            rec["ms"] = float(np.mean(ms))
+            rec["flops"] = float(np.sum(it[ok] * fl[ok]))
+            rec["tflops"] = rec["flops"] / (rec["ms"] * 1e-3) / 1e12
+            rec["frac"] = rec["flops"] / (rec["ms"] * 1e-3) / peak
+            out.append(rec)
+        return out
+
+    def tune(self, w, td, probe_iters=100, **kw):
+        """The library's autotuner on the whole workload: the chosen plan
+        [(hi, L, K), ...] and the seconds tuning took (0 when the plan came
+        from the tuning cache named by $HJPD_TUNE_CACHE)."""
+        s = self.solver(w, td, **kw)
+        plan, cached = s.plan()
+        if cached:
+            s.close()
+            return plan, 0.0
+        inp = self.tensors(w, td)
+        t0 = time.perf_counter()
+        s.autotune(*inp, probe_iters=probe_iters)
+        self.torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        plan = s.plan()[0]
+        s.close()
+        return plan, dt
+
+    def plain(self, w, td, steps=1):
+        s = self.solver(w, td, plain=True)
+        inp = self.tensors(w, td)
+        out = s.alloc(w.n)
+        ms = self.timed(s, inp, out, steps, 1)
+        conv = int((out.status.cpu().numpy() == 0).sum())
+        s.close()
+        return {"ms": ms, "converged": conv, "solves_per_s": conv / (ms * 1e-3)}
+
+
+def copy_calibration(torch, dev):
+    """One device copy of 256 MiB (read 256 MiB, write 256 MiB): the scale of
+    rocprofv3's FETCH_SIZE and WRITE_SIZE counters for known traffic."""
+    src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def roofline_of(launches, kernel_fmt, dtype_name, peak, bound="alu"):
+    """The dominant launch (the class with the longest kernel time) and every class's figures."""
+    dom = max(launches, key=lambda a: a["ms"])
+    kernel = kernel_fmt % (dtype_name, dom["L"], dom["K"])
+    return {"bound": bound, "achieved": dom["tflops"], "peak": peak / 1e12, "unit": "TFLOP/s", "frac": dom["frac"],
+            "traffic": measured_traffic(kernel), "kernel": kernel, "kernel_ms": dom["ms"],
+            "flops_per_launch": dom["flops"], "class_N": [dom["N_lo"], dom["N_hi"]],
+            "launches": [{k: a[k] for k in ("N_lo", "N_hi", "L", "K", "ms", "points", "tflops", "frac")}
+                         for a in launches]}
+
+
+def bench_c5(B, steps, cpu):
+    """Linear-tanh, d = 100: forward solves/s and matrix-core throughput at
+    K = 500 fixed iterations, and hjpd_value_grad (forward with checkpoints
+    every 50 + reverse sweep + reductions), with the reverse-sweep kernel
+    timed on its own."""
     import workloads as W
     from paper_1803_01215_amd.autograd import LinearTanhValue
-    from paper_1803_01215_amd.solver import Solver
-
+    torch = B.torch
     w = W.lintanh100()
     K = w.max_iter
     f32 = torch.float32
-    x = torch.tensor(w.x, dtype=f32, device=dev)
-    t = torch.tensor(w.t, dtype=f32, device=dev)
-    N = torch.tensor(w.N, dtype=torch.int32, device=dev)
-    hp = torch.tensor(w.hp, dtype=f32, device=dev)
-    Q = torch.tensor(w.gp, dtype=f32, device=dev)
-    s = Solver(d=w.d, H=w.H, g=w.g, N_max=w.N_max, sigma=w.sigma, tau=w.tau, tol=w.tol, max_iter=K,
-               seed=w.init_seed, dtype=f32, fixed_iters=True, timing=True)
+    x, t, N, hp, Q = B.tensors(w, f32)
+    s = B.solver(w, f32, fixed_iters=True, timing=True)
     out = s.alloc(w.n)
     s.solve(x, t, N, hp, Q, out=out)
     torch.cuda.synchronize()
     kms = []
     for _ in range(max(1, steps // 2)):
         s.solve(x, t, N, hp, Q, out=out)
-        ms, nl = s.timing()
-        kms.append(ms)
+        kms.append(s.timing()[0])
     fwd_ms = float(np.mean(kms))
     s.close()
     flops = float(w.n) * K * mfma_flops_per_iter_lintanh(w.N_max, w.d)
-    lt = LinearTanhValue(w.d, w.N_max, w.sigma, w.tau, K, ckpt_every=50, seed=w.init_seed)
-    gphi = torch.ones(w.n, dtype=f32, device=dev)
+    lt = LinearTanhValue(w.d, w.N_max, w.sigma, w.tau, K, ckpt_every=50, seed=w.init_seed, timing=True)
+    gphi = torch.ones(w.n, dtype=f32, device=B.dev)
     lt.value_grad(x, t, N, hp, Q, gphi)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = max(1, steps // 5)
+    bms = []
     e0.record()
     for _ in range(reps):
         lt.value_grad(x, t, N, hp, Q, gphi)
+        bms.append(lt.solver.timing()[0])
     e1.record()
     torch.cuda.synchronize()
     vg_ms = e0.elapsed_time(e1) / reps
+    bwd_ms = float(np.mean(bms))
     lt.close()
+    bflops = float(w.n) * K * mfma_flops_per_iter_lintanh_backward(w.N_max, w.d)
     return {"workload": "lintanh100: d=100, H=-<p,Ax+0.1 tanh x>+|p|^2/2, g=x^T Q x/2, 16,384 points, N=50, "
                         "K=500 fixed iterations, FP32",
             "forward_kernel_ms": fwd_ms, "forward_solves_per_s": w.n / (fwd_ms * 1e-3),
-            "mfma": {"bound": "mfma", "achieved": flops / (fwd_ms * 1e-3) / 1e12, "peak": PEAK["fp32_matrix"] / 1e12,
-                     "unit": "TFLOP/s", "frac": flops / (fwd_ms * 1e-3) / PEAK["fp32_matrix"],
-                     "kernel": "k_lt_forward<100>", "flops_per_launch": flops},
+            "roofline": {"bound": "mfma", "achieved": flops / (fwd_ms * 1e-3) / 1e12, "peak": PEAK["fp32_matrix"] / 1e12,
+                         "unit": "TFLOP/s", "frac": flops / (fwd_ms * 1e-3) / PEAK["fp32_matrix"],
+                         "kernel": "k_lt_forward<100>", "flops_per_launch": flops, "traffic": None},
             "value_grad_ms": vg_ms, "value_grad_points_per_s": w.n / (vg_ms * 1e-3), "ckpt_every": 50,
-            "cpu_oracle": oracle_sample(w, 64) if cpu else None}
-
-
-def bench_full_sets(torch, dev):
-    """The batched path (persistent, default tiles, hipGraph) on the full
-    quadrotor set with both trajectories written (Lax, and the Hopf
-    formulation the paper uses for its quadcopter) and on the full
-    pursuit-evasion set: one warm-up, then the median of two solves."""
-    import workloads as W
-    from paper_1803_01215_amd.solver import Solver
-
-    out = {}
-    for key, name, traj, hopf in (("quadrotor12", "quadrotor12", True, False),
-                                  ("quadrotor12_hopf", "quadrotor12", True, True),
-                                  ("pursuit12", "pursuit12", False, False)):
-        w = W.get(name)
-        td = torch.float32
-        inp = (torch.tensor(w.x, dtype=td, device=dev), torch.tensor(w.t, dtype=td, device=dev),
-               torch.tensor(w.N, dtype=torch.int32, device=dev), torch.tensor(w.hp, dtype=td, device=dev),
-               torch.tensor(w.gp, dtype=td, device=dev))
-        s = Solver(d=w.d, d_y=w.d_y, H=w.H, g=w.g, N_max=w.N_max, sigma=w.sigma, tau=w.tau, theta=w.theta,
-                   tol=w.tol, max_iter=w.max_iter, seed=w.init_seed, dtype=td, graph=True, hopf=hopf)
-        o = s.alloc(w.n, traj=traj)
-        s.solve(*inp, out=o, traj=traj)
-        torch.cuda.synchronize()
-        times = []
-        for _ in range(2):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            s.solve(*inp, out=o, traj=traj)
-            e1.record()
-            torch.cuda.synchronize()
-            times.append(e0.elapsed_time(e1))
-        ms = float(np.median(times))
-        conv = int((o.status == 0).sum())
-        out[key] = {"points": w.n, "dtype": "f32", "max_iter": w.max_iter, "trajectories": traj,
-                    "formulation": "Hopf (Algorithm 2)" if hopf else "Lax (Algorithm 1)", "ms": ms,
-                     "converged": conv, "solves_per_s": conv / (ms * 1e-3),
-                     "iterations": int(o.iters.to(torch.int64).sum())}
-        s.close()
-        del o, inp
-    return out
-
-
-def bench_configs(torch, dev, subset, cpu=False):
-    """Batched (persistent, default tiles, hipGraph) against plain (one point
-    per lane) on the other workloads: the eikonal set in full (FP64), the
-    quadrotor and pursuit-evasion sets on their first `subset` points (FP32,
-    20,000-iteration cap; the plain kernel streams each point's state through
-    HBM every iteration, so a full-size plain run would take minutes)."""
-    import workloads as W
-    from paper_1803_01215_amd.solver import Solver
-
-    out = {}
-    for name, td, m in (("eikonal2d", torch.float64, None), ("quadrotor12", torch.float32, subset),
-                        ("pursuit12", torch.float32, subset)):
-        w = W.get(name)
-        if m is not None and m < w.n:
-            w = w.subset(np.arange(m))
-        inp = (torch.tensor(w.x, dtype=td, device=dev), torch.tensor(w.t, dtype=td, device=dev),
-               torch.tensor(w.N, dtype=torch.int32, device=dev), torch.tensor(w.hp, dtype=td, device=dev),
-               torch.tensor(w.gp, dtype=td, device=dev))
-        rec = {"points": w.n, "dtype": "f64" if td == torch.float64 else "f32", "max_iter": w.max_iter}
-        for label, kw in (("batched", dict(graph=True)), ("plain", dict(plain=True))):
-            s = Solver(d=w.d, d_y=w.d_y, H=w.H, g=w.g, N_max=w.N_max, sigma=w.sigma, tau=w.tau, theta=w.theta,
-                       tol=w.tol, max_iter=w.max_iter, seed=w.init_seed, dtype=td, **kw)
-            o = s.alloc(w.n)
-            s.solve(*inp, out=o)
-            torch.cuda.synchronize()
-            times = []
-            for _ in range(3 if label == "batched" else 1):  # median of 3: one launch can be an outlier
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                s.solve(*inp, out=o)
-                e1.record()
-                torch.cuda.synchronize()
-                times.append(e0.elapsed_time(e1))
-            ms = float(np.median(times))
-            conv = int((o.status == 0).sum())
-            rec[label] = {"ms": ms, "converged": conv, "solves_per_s": conv / (ms * 1e-3)}
-            s.close()
-        rec["speedup"] = rec["batched"]["solves_per_s"] / max(rec["plain"]["solves_per_s"], 1e-30)
-        if cpu:
-            rec["cpu_oracle"] = oracle_sample(w, {"eikonal2d": 256, "quadrotor12": 512, "pursuit12": 1024}[name])
-        out[name] = rec
-        if name == "quadrotor12":
-            # robustness recipes (section 6): cap 5,000, then up to three more
-            # phases, stopping also on a stalled value (rel. change <= 1e-7)
-            rw = w.subset(np.arange(w.n))
-            rw.max_iter = 5000
-            s = Solver(d=rw.d, d_y=rw.d_y, H=rw.H, g=rw.g, N_max=rw.N_max, sigma=rw.sigma, tau=rw.tau,
-                       theta=rw.theta, tol=rw.tol, max_iter=rw.max_iter, seed=rw.init_seed, dtype=td, graph=True,
-                       restarts=3, sigma_inc=0.0, value_tol=1e-7)
-            o = s.alloc(rw.n)
-            s.solve(*inp, out=o)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            s.solve(*inp, out=o)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1)
-            st = np.bincount(o.status.cpu().numpy(), minlength=5)
-            out["quadrotor12_recipes"] = {
-                "points": rw.n, "recipe": "max_iter 5000, restarts 3, sigma_inc 0, value_tol 1e-7", "ms": ms,
-                "converged": int(st[0]), "value_stalled": int(st[4]), "max_iter": int(st[1]),
-                "solves_per_s": float(st[0] + st[4]) / (ms * 1e-3)}
-            s.close()
-        print("[configs] %s: batched %.1f ms, plain %.1f ms" % (name, rec["batched"]["ms"], rec["plain"]["ms"]),
-              file=sys.stderr, flush=True)
-    return out
+            "backward_kernel_ms": bwd_ms,
+            "backward_roofline": {"bound": "mfma", "achieved": bflops / (bwd_ms * 1e-3) / 1e12,
+                                  "peak": PEAK["fp32_matrix"] / 1e12, "unit": "TFLOP/s",
+                                  "frac": bflops / (bwd_ms * 1e-3) / PEAK["fp32_matrix"],
+                                  "kernel": "k_lt_backward<100>", "flops_per_launch": bflops, "traffic": None},
+            "cpu_baseline": oracle_sample(w, 64) if cpu else None}
 
 
 def main():
@@ -267,22 +383,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--plain-steps", type=int, default=2)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run")
-    ap.add_argument("--cpu-sample", type=int, default=65536)
-    ap.add_argument("--max-iter", type=int, default=5000,
-                    help="iteration cap of the headline run (points above it count as not converged)")
-    ap.add_argument("--no-c5", action="store_true", help="skip the linear-tanh (d=100) forward/reverse timing")
-    ap.add_argument("--configs", type=int, default=0, metavar="M",
-                    help="also time batched vs plain on the eikonal, quadrotor and pursuit-evasion workloads "
-                         "(the last two on their first M points)")
-    ap.add_argument("--full-sets", action="store_true",
-                    help="also time the batched path on the full quadrotor set (131,072 points, trajectories "
-                         "written; Lax and Hopf) and the full pursuit-evasion set (262,144 points)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
+    ap.add_argument("--no-extra", action="store_true", help="headline workload only")
+    ap.add_argument("--plain-sample", type=int, default=4096,
+                    help="points of the seeded sample the plain kernel (and the batched path beside it) solves")
+    ap.add_argument("--cpu-sample", type=int, default=2048, help="headline points the CPU oracle solves")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
+    ap.add_argument("--tune-cache", metavar="FILE",
+                    help="tuning cache: the headline's plan is read from FILE if recorded there, else tuned and "
+                         "recorded (so a profiled run can repeat the measured plan without tuning)")
+    ap.add_argument("--profile", action="store_true",
+                    help="headline solves only (warmup + steps, plan from --tune-cache or tuned), for rocprofv3")
     args = ap.parse_args()
+    if args.tune_cache:
+        os.environ["HJPD_TUNE_CACHE"] = os.path.abspath(args.tune_cache)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU (the query points are independent; several GPUs would each take a "
               "share of them): run it with --gpus 1", file=sys.stderr)
@@ -291,196 +406,159 @@ def main():
     import torch
 
     import workloads as W
-    from paper_1803_01215_amd.solver import Solver
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
-    w = W.cnorm10()
-    n = w.n
-    cap_default = w.max_iter
-    w.max_iter = args.max_iter
+    B = Bench(torch, torch.device("cuda:0"))
+    f32, f64 = torch.float32, torch.float64
+    cpu = not args.no_cpu
 
-    def tensors(td):
-        return (torch.tensor(w.x, dtype=td, device=dev), torch.tensor(w.t, dtype=td, device=dev),
-                torch.tensor(w.N, dtype=torch.int32, device=dev), torch.tensor(w.hp, dtype=td, device=dev),
-                torch.tensor(w.gp, dtype=td, device=dev))
+    def log(msg):
+        print("[bench] " + msg, file=sys.stderr, flush=True)
 
-    def make(td, **kw):
-        return Solver(d=w.d, H=w.H, g=w.g, N_max=w.N_max, sigma=w.sigma, tau=w.tau, theta=w.theta, tol=w.tol,
-                      max_iter=w.max_iter, seed=w.init_seed, dtype=td, **kw)
-
-    def timed_steps(solver, inp, out, steps, warmup):
-        for _ in range(warmup):
-            solver.solve(*inp, out=out)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
-            solver.solve(*inp, out=out)
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / steps
-
-    # ---- batched FP32 (the headline) ------------------------------------------------
-    td = torch.float32
-    inp = tensors(td)
-    batched = make(td, graph=True, lanes_per_point=16, nodes_per_lane=2)
-    out = batched.alloc(n)
-    ms_step = timed_steps(batched, inp, out, args.steps, args.warmup)
-    status = out.status.cpu().numpy()
-    iters = out.iters.cpu().numpy().astype(np.int64)
-    conv = int((status == 0).sum())
-    value = conv / (ms_step * 1e-3)
-
-    # dominant kernel: per-launch device time from the library's HIP events on
-    # the same stream, over the same number of steps (no graph, one launch)
-    probe = make(td, timing=True, lanes_per_point=16, nodes_per_lane=2)
-    out2 = probe.alloc(n)
-    probe.solve(*inp, out=out2)
-    torch.cuda.synchronize()
-    kms = []
-    for _ in range(args.steps):
-        probe.solve(*inp, out=out2)
-        ms, nl = probe.timing()
-        assert nl == 1
-        kms.append(ms)
-    kern_ms = float(np.mean(kms))
-    flops = float(sum(iters * flops_per_iter_cnorm(w.N_max, w.d)))
-    achieved = flops / (kern_ms * 1e-3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK["fp32_vector"] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK["fp32_vector"],
-                "traffic": measured_traffic("k_group_control_shift<float, CNorm<10>, 16, 2, false>"),
-                "kernel": "k_group_control_shift<float, CNorm<10>, 16, 2, false>", "kernel_ms": kern_ms,
-                "flops_per_launch": flops}
-
-    # ---- the same with the long iteration cap (20000) -----------------------------
-    w.max_iter = cap_default
-    long = make(td, graph=True, lanes_per_point=16, nodes_per_lane=2)
-    outl = long.alloc(n)
-    ms_long = timed_steps(long, inp, outl, max(1, args.steps // 2), 1)
-    conv_long = int((outl.status.cpu().numpy() == 0).sum())
-    long_rec = {"max_iter": cap_default, "value": conv_long / (ms_long * 1e-3), "ms_per_step": ms_long,
-                "converged": conv_long}
-    long.close()
-    w.max_iter = args.max_iter
-
-    if args.copy_calib:
-        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    # ---- Hopf formulation (Algorithm 2) on the same workload, same tile and cap ---------
-    hopf = make(td, graph=True, lanes_per_point=16, nodes_per_lane=2, hopf=True)
-    outh = hopf.alloc(n)
-    ms_hopf = timed_steps(hopf, inp, outh, max(1, args.steps // 2), 1)
-    conv_hopf = int((outh.status.cpu().numpy() == 0).sum())
-    hopf_rec = {"value": conv_hopf / (ms_hopf * 1e-3), "ms_per_step": ms_hopf, "converged": conv_hopf,
-                "iters_p50": float(np.median(outh.iters.cpu().numpy()))}
-    hopf.close()
-
-    # ---- forward-Euler and trapezoidal discretisations, same workload, tile and cap --------
-    disc_rec = {}
-    for disc in ("fe", "trap"):
-        sd = make(td, graph=True, lanes_per_point=16, nodes_per_lane=2, disc=disc)
-        outd = sd.alloc(n)
-        ms_d = timed_steps(sd, inp, outd, max(1, args.steps // 2), 1)
-        conv_d = int((outd.status.cpu().numpy() == 0).sum())
-        disc_rec[disc] = {"value": conv_d / (ms_d * 1e-3), "ms_per_step": ms_d, "converged": conv_d,
-                          "iters_p50": float(np.median(outd.iters.cpu().numpy()))}
-        sd.close()
-
-    # ---- game Hopf formulation (Algorithm 4): Isaacs' game on the section's full grid -------
-    wi = W.isaacs2()
-    si = Solver(d=wi.d, d_y=wi.d_y, H=wi.H, g=wi.g, N_max=wi.N_max, sigma=wi.sigma, tau=wi.tau, theta=wi.theta,
-                tol=wi.tol, max_iter=wi.max_iter, seed=wi.init_seed, dtype=td, graph=True, hopf=True)
-    inp_i = (torch.tensor(wi.x, dtype=td, device=dev), torch.tensor(wi.t, dtype=td, device=dev),
-             torch.tensor(wi.N, dtype=torch.int32, device=dev), torch.tensor(wi.hp, dtype=td, device=dev),
-             torch.tensor(wi.gp, dtype=td, device=dev))
-    outi = si.alloc(wi.n)
-    ms_i = timed_steps(si, inp_i, outi, max(1, args.steps // 2), 1)
-    st_i = outi.status.cpu().numpy()
-    conv_i = int((st_i == 0).sum())
-    isaacs_rec = {"workload": "isaacs2: Isaacs' game, H=-c(x,y)q+2|p|-sqrt(p^2+q^2)-1, g=(2.5x)^2/2-1/2-y^2/2, "
-                              "73x73 grid on [-3,3]^2 x t in {0.025,0.05,0.075,0.1}, delta=0.005, game Hopf",
-                  "points": wi.n, "tol": wi.tol, "max_iter": wi.max_iter, "value": conv_i / (ms_i * 1e-3),
-                  "unit": "converged solves/s", "ms_per_step": ms_i, "converged": conv_i,
-                  "iters_p50": float(np.median(outi.iters.cpu().numpy()))}
-    si.close()
-
-    # ---- plain FP32 -------------------------------------------------------------------
-    plain = make(td, plain=True)
-    outp = plain.alloc(n)
-    ms_plain = timed_steps(plain, inp, outp, max(1, args.plain_steps), 1)
-    conv_plain = int((outp.status.cpu().numpy() == 0).sum())
-    plain_rec = {"value": conv_plain / (ms_plain * 1e-3), "ms_per_step": ms_plain, "converged": conv_plain}
-    batched.close(); probe.close(); plain.close()
-
-    # ---- batched FP64 --------------------------------------------------------------------
-    fp64_rec = None
-    if not args.no_fp64:
-        inp64 = tensors(torch.float64)
-        b64 = make(torch.float64, graph=True, lanes_per_point=16, nodes_per_lane=2)
-        o64 = b64.alloc(n)
-        ms64 = timed_steps(b64, inp64, o64, max(1, args.steps // 2), 1)
-        c64 = int((o64.status.cpu().numpy() == 0).sum())
-        it64 = o64.iters.cpu().numpy().astype(np.int64)
-        b64.close()
-        # the FP64 kernel's own time (library HIP events, one launch per solve)
-        p64 = make(torch.float64, timing=True, lanes_per_point=16, nodes_per_lane=2)
-        q64 = p64.alloc(n)
-        p64.solve(*inp64, out=q64)
-        k64 = []
-        for _ in range(max(1, args.steps // 2)):
-            p64.solve(*inp64, out=q64)
-            k64.append(p64.timing()[0])
-        p64.close()
-        kms64 = float(np.mean(k64))
-        fl64 = float(sum(it64 * flops_per_iter_cnorm(w.N_max, w.d)))
-        fp64_rec = {"value": c64 / (ms64 * 1e-3), "ms_per_step": ms64, "converged": c64,
-                    "roofline": {"bound": "alu", "achieved": fl64 / (kms64 * 1e-3) / 1e12,
-                                 "peak": PEAK["fp64_vector"] / 1e12, "unit": "TFLOP/s",
-                                 "frac": fl64 / (kms64 * 1e-3) / PEAK["fp64_vector"],
-                                 "kernel": "k_group_control_shift<double, CNorm<10>, 16, 2, false>",
-                                 "kernel_ms": kms64, "flops_per_launch": fl64}}
-
-    # ---- matrix-core path (linear-tanh, d = 100): forward and reverse mode ------------------
-    c5_rec = None
-    if not args.no_c5:
-        c5_rec = bench_lintanh(torch, dev, args.steps, cpu=not args.no_cpu)
-
-    cfg_rec = bench_configs(torch, dev, args.configs, cpu=not args.no_cpu) if args.configs > 0 else None
-    full_rec = bench_full_sets(torch, dev) if args.full_sets else None
-
-    # ---- CPU oracle baseline on a bounded sample ------------------------------------------
-    cpu_rec = oracle_sample(w, args.cpu_sample) if not args.no_cpu else None
+    # ---- headline: pursuit-evasion, full set, one graph ------------------------------------
+    w = W.pursuit12()
+    plan, tune_s = B.tune(w, f32)
+    log("pursuit12 tuned plan %s (%.1f s)" % (plan, tune_s))
+    head = B.batched(w, f32, args.steps, args.warmup, plan=plan)
+    log("pursuit12 batched %.1f ms, %d converged" % (head["ms"], head["converged"]))
+    if args.profile:
+        if args.copy_calib:
+            copy_calibration(torch, B.dev)
+        print(json.dumps({"profile": "pursuit12 headline solves", "plan": plan, "steps": args.steps,
+                          "warmup": args.warmup, "ms_per_step": head["ms"], "converged": head["converged"]}))
+        return
+    dflt = B.batched(w, f32, 3, 1)
+    norefill = B.batched(w, f32, 2, 1, plan=plan, refill=False)
+    log("pursuit12 default plan %.1f ms, no refill %.1f ms" % (dflt["ms"], norefill["ms"]))
+    lts = B.launches(w, f32, flops_per_iter_pursuit, PEAK["fp32_vector"], plan=plan)
+    roofline = roofline_of(lts, "k_group_game<%s, Pursuit, %d, %d>", "float", PEAK["fp32_vector"])
+    sub = w.subset(np.arange(min(args.plain_sample, w.n)))
+    plain = B.plain(sub, f32)
+    bsub = B.batched(sub, f32, 3, 1)
+    bsub.pop("status"); bsub.pop("iters")
+    log("pursuit12 sample: plain %.1f ms, batched %.1f ms" % (plain["ms"], bsub["ms"]))
+    cpu_rec = oracle_sample(w, args.cpu_sample) if cpu else None
+    it = head["iters"]
+    st = head["status"]
+    value = head["solves_per_s"]
 
     rec = {
         "metric": "converged (x,t) solves/sec at PDHG residual 1e-6, batched vs plain kernel",
         "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "ms_per_step": head["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "cnorm10: d=10 state-dependent eikonal H=c(x)||p||, c=1+0.5 sin(x1)cos(x2), "
-                               "g=||x-a||^2/2-1, 65,536 points x~N(0,I), t~U[0.2,1], N=32, tol 1e-6",
-                   "points": n, "N": w.N_max, "d": w.d, "sigma": w.sigma, "tau": w.tau, "tile": "16 lanes x 2 nodes", "max_iter": args.max_iter,
-                   "converged": conv, "iters_p50": float(np.median(iters)), "iters_p95": float(np.percentile(iters, 95)),
-                   "iters_max": int(iters.max())},
+        "config": {"workload": "pursuit12: pursuit-evasion game, two 3-D point masses with drag 0.1, d=12 (6+6), "
+                               "H=<p,f0>-|B_p^T p|^2/2+|B_e^T p|^2/8 (paper convention: its negative), "
+                               "g=|r_P-r_E|-0.5, 262,144 points, r~U[-2,2]^3, v~U[-0.5,0.5]^3, t~U[0.5,4], "
+                               "N=clamp(ceil(24t),16,96), Algorithm 3, tol 1e-6, cap 20,000, one hipGraph",
+                   "points": w.n, "N_range": [int(w.N.min()), int(w.N.max())], "d": w.d, "sigma": w.sigma,
+                   "tau": w.tau, "max_iter": w.max_iter,
+                   "plan": {"classes": [{"N_hi": hi, "lanes_per_point": L, "nodes_per_lane": K,
+                                         "points_per_wavefront": 64 // L} for hi, L, K in plan],
+                            "source": "hjpd_autotune on this workload (100 fixed probe iterations), %.1f s" % tune_s},
+                   "converged": head["converged"], "status_counts": np.bincount(st, minlength=4).tolist(),
+                   "iters_p50": float(np.median(it)), "iters_p95": float(np.percentile(it, 95)),
+                   "iters_max": int(it.max()), "iters_hist": iteration_histogram(it)},
         "roofline": roofline,
         "cpu_baseline": cpu_rec,
-        "plain": plain_rec,
-        "speedup_vs_plain": value / plain_rec["value"] if plain_rec["value"] > 0 else None,
-        "fp64": fp64_rec,
-        "long_cap": long_rec,
-        "hopf": hopf_rec,
-        "forward_euler": disc_rec["fe"],
-        "trapezoid": disc_rec["trap"],
-        "isaacs2_game_hopf": isaacs_rec,
-        "lintanh100": c5_rec,
-        "configs": cfg_rec,
-        "full_sets": full_rec,
+        "plain": dict(plain, sample="first %d points" % sub.n),
+        "batched_same_sample": dict(bsub, sample="first %d points" % sub.n),
+        "speedup_vs_plain": bsub["solves_per_s"] / plain["solves_per_s"] if plain["solves_per_s"] > 0 else None,
+        "default_plan": {"ms_per_step": dflt["ms"], "converged": dflt["converged"], "value": dflt["solves_per_s"]},
+        "no_refill": {"ms_per_step": norefill["ms"], "converged": norefill["converged"],
+                      "value": norefill["solves_per_s"],
+                      "what": "same kernels, plan and queue order; one point per lane group, a group for every "
+                              "point (a wave stays until its slowest point stops)"},
     }
+    del head, dflt, norefill
+
+    if not args.no_extra:
+        # ---- C3: quadrotor, full set, both trajectories written --------------------------------
+        wq = W.quadrotor12()
+        qplan, qtune_s = B.tune(wq, f32)
+        q = B.batched(wq, f32, max(1, args.steps // 3), 1, traj=True, plan=qplan)
+        log("quadrotor12 tuned plan %s; batched %.1f ms, %d converged" % (qplan, q["ms"], q["converged"]))
+        qd = B.batched(wq, f32, 2, 1, traj=True)
+        qn = B.batched(wq, f32, 2, 1, traj=True, plan=qplan, refill=False)
+        qlts = B.launches(wq, f32, flops_per_iter_quad, PEAK["fp32_vector"], traj=True, reps=2, plan=qplan)
+        qs = wq.subset(np.arange(min(args.plain_sample, wq.n)))
+        qp = B.plain(qs, f32)
+        qb = B.batched(qs, f32, 3, 1)
+        qb.pop("status"); qb.pop("iters")
+        rec["quadrotor12"] = {
+            "workload": "quadrotor12: 12-state quadrotor-like control, cost |u|^2/2, g=|x|^2/2, 131,072 points "
+                        "x~U[-1,1]^12, t~U[0.5,3], N=ceil(t/0.05), Algorithm 1, tol 1e-6, cap 20,000, both "
+                        "trajectories written, FP32, one hipGraph",
+            "value": q["solves_per_s"], "unit": "converged solves/s", "ms_per_step": q["ms"],
+            "converged": q["converged"], "status_counts": np.bincount(q["status"], minlength=4).tolist(),
+            "iters_p50": float(np.median(q["iters"])), "iters_hist": iteration_histogram(q["iters"]),
+            "roofline": roofline_of(qlts, "k_group_control<%s, Quad, %d, %d>", "float", PEAK["fp32_vector"]),
+            "plan": [[hi, L, K] for hi, L, K in qplan],
+            "default_plan": {"ms_per_step": qd["ms"], "converged": qd["converged"], "value": qd["solves_per_s"]},
+            "no_refill": {"ms_per_step": qn["ms"], "converged": qn["converged"], "value": qn["solves_per_s"]},
+            "plain": dict(qp, sample="first %d points" % qs.n),
+            "batched_same_sample": dict(qb, sample="first %d points" % qs.n),
+            "speedup_vs_plain": qb["solves_per_s"] / qp["solves_per_s"] if qp["solves_per_s"] > 0 else None,
+            "cpu_baseline": oracle_sample(wq, 512) if cpu else None}
+        del q
+
+        # ---- C2: cnorm10 (state-dependent eikonal, d = 10), FP32 and FP64 ------------------------
+        wc = W.cnorm10()
+        wc.max_iter = 5000
+        c = B.batched(wc, f32, args.steps, 1)
+        clts = B.launches(wc, f32, lambda n: flops_per_iter_cnorm(n, wc.d), PEAK["fp32_vector"])
+        cp = B.plain(wc, f32)
+        c64 = B.batched(wc, f64, max(1, args.steps // 2), 1)
+        c64lts = B.launches(wc, f64, lambda n: flops_per_iter_cnorm(n, wc.d), PEAK["fp64_vector"])
+        extra = {}
+        for key, kw in (("hopf", dict(hopf=True)), ("forward_euler", dict(disc="fe")), ("trapezoid", dict(disc="trap"))):
+            r = B.batched(wc, f32, max(1, args.steps // 2), 1, **kw)
+            extra[key] = {"ms_per_step": r["ms"], "converged": r["converged"], "value": r["solves_per_s"]}
+        rec["cnorm10"] = {
+            "workload": "cnorm10: d=10 state-dependent eikonal H=c(x)||p||, c=1+0.5 sin(x1)cos(x2), g=||x-a||^2/2-1, "
+                        "65,536 points x~N(0,I), t~U[0.2,1], N=32, tol 1e-6, cap 5,000, FP32, one hipGraph",
+            "value": c["solves_per_s"], "unit": "converged solves/s", "ms_per_step": c["ms"],
+            "converged": c["converged"], "iters_p50": float(np.median(c["iters"])),
+            "iters_hist": iteration_histogram(c["iters"]),
+            "roofline": roofline_of(clts, "k_group_control_shift<%s, CNorm<10>, %d, %d, false>", "float",
+                                    PEAK["fp32_vector"]),
+            "plain": cp, "speedup_vs_plain": c["solves_per_s"] / cp["solves_per_s"] if cp["solves_per_s"] else None,
+            "fp64": {"value": c64["solves_per_s"], "ms_per_step": c64["ms"], "converged": c64["converged"],
+                     "roofline": roofline_of(c64lts, "k_group_control_shift<%s, CNorm<10>, %d, %d, false>", "double",
+                                             PEAK["fp64_vector"])},
+            "cpu_baseline": oracle_sample(wc, 16384) if cpu else None, **extra}
+        log("cnorm10 batched %.2f ms" % c["ms"])
+
+        # ---- C1: 2-D eikonal, FP64 ---------------------------------------------------------------
+        we = W.eikonal2d()
+        e = B.batched(we, f64, args.steps, 2)
+        elts = B.launches(we, f64, lambda n: flops_per_iter_cnorm(n, we.d), PEAK["fp64_vector"])
+        ep = B.plain(we, f64, steps=3)
+        rec["eikonal2d"] = {
+            "workload": "eikonal2d: H=||p||, g=||x||-1, 256 points x~U[-2,2]^2, t=1, N=16, tol 1e-8, cap 5,000, FP64",
+            "value": e["solves_per_s"], "unit": "converged solves/s", "ms_per_step": e["ms"],
+            "converged": e["converged"], "iters_hist": iteration_histogram(e["iters"]),
+            "roofline": roofline_of(elts, "k_group_control_shift<%s, CNorm<2>, %d, %d, false>", "double",
+                                    PEAK["fp64_vector"]),
+            "plain": ep, "speedup_vs_plain": e["solves_per_s"] / ep["solves_per_s"] if ep["solves_per_s"] else None,
+            "cpu_baseline": oracle_sample(we, 256) if cpu else None}
+
+        # ---- C5: linear-tanh, d = 100, forward and reverse ----------------------------------------
+        rec["lintanh100"] = bench_c5(B, args.steps, cpu)
+        log("lintanh100 done")
+
+        # ---- game Hopf formulation (Algorithm 4): Isaacs' game on the section's full grid ----------
+        wi = W.isaacs2()
+        i = B.batched(wi, f32, max(1, args.steps // 2), 1, hopf=True)
+        rec["isaacs2_game_hopf"] = {
+            "workload": "isaacs2: Isaacs' game, H=-c(x,y)q+2|p|-sqrt(p^2+q^2)-1, g=(2.5x)^2/2-1/2-y^2/2, 73x73 grid "
+                        "on [-3,3]^2 x t in {0.025,0.05,0.075,0.1}, delta=0.005, game Hopf, tol 1e-8, FP32",
+            "points": wi.n, "value": i["solves_per_s"], "unit": "converged solves/s", "ms_per_step": i["ms"],
+            "converged": i["converged"], "iters_p50": float(np.median(i["iters"]))}
+
+    if args.copy_calib:
+        copy_calibration(torch, B.dev)
+
     print(json.dumps(rec))
 
 
