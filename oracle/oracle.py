@@ -38,7 +38,17 @@ _VARIANT_FLAGS = {
 }
 
 
+# HJPD_ORACLE_SANITIZE=1: every build is instrumented with AddressSanitizer and
+# UndefinedBehaviorSanitizer (any finding aborts) and kept apart from the plain
+# builds; the process must preload the sanitizer runtimes (tests/test_sanitizers.py).
+_SANITIZE = os.environ.get("HJPD_ORACLE_SANITIZE") == "1"
+_SANITIZE_FLAGS = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+                   "-fno-sanitize-recover=undefined"]
+
+
 def _lib_path(variant: str) -> str:
+    if _SANITIZE:
+        return os.path.join(_HERE, "liboracle_%s_sanitized.so" % variant)
     return _LIB if variant == "f64" else os.path.join(_HERE, "liboracle_%s.so" % variant)
 
 
@@ -49,7 +59,7 @@ def build(force: bool = False, variant: str = "f64") -> str:
     if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
         tmp = path + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", *_VARIANT_FLAGS[variant],
-                               "-o", tmp, _SRC, "-lm"])
+                               *(_SANITIZE_FLAGS if _SANITIZE else []), "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, path)
     return path
 
