@@ -555,6 +555,12 @@ def main():
                         "on [-3,3]^2 x t in {0.025,0.05,0.075,0.1}, delta=0.005, game Hopf, tol 1e-8, FP32",
             "points": wi.n, "value": i["solves_per_s"], "unit": "converged solves/s", "ms_per_step": i["ms"],
             "converged": i["converged"], "iters_p50": float(np.median(i["iters"]))}
+        # ---- Algorithm 3 on the same grid: node 0 by the proxes of e and -h --------------------------
+        il = B.batched(wi, f32, max(1, args.steps // 2), 1)
+        rec["isaacs2_game_lax"] = {
+            "workload": "isaacs2 as above, Algorithm 3 (initial cost g(x_0, y_0) itself), tol 1e-8, FP32",
+            "points": wi.n, "value": il["solves_per_s"], "unit": "converged solves/s", "ms_per_step": il["ms"],
+            "converged": il["converged"], "iters_p50": float(np.median(il["iters"]))}
 
     if args.copy_calib:
         copy_calibration(torch, B.dev)

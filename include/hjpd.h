@@ -110,9 +110,11 @@ enum {
  *                        H(x,y,p,q) = -c(x,y) q + 2|p| - sqrt(p^2 + q^2) - 1
  *                        (costate (p,-q) in the game formulation), bump speed
  *                        c = b0 (1 + b1 exp(-b2 |(x,y) - (cx,cy)|^2)).
- *                        h_params = [b0, b1, b2, cx, cy].  Game Hopf
- *                        formulation only (HJPD_HOPF, Algorithm 4), with
- *                        g = HJPD_G_SADDLE_QUAD; persistent kernel.
+ *                        h_params = [b0, b1, b2, cx, cy].  With
+ *                        g = HJPD_G_SADDLE_QUAD, persistent kernel: the game
+ *                        Hopf formulation (HJPD_HOPF, Algorithm 4), or
+ *                        Algorithm 3 without it (node 0 by the proxes of e
+ *                        and of -h, value g(x_0, y_0) + ...).
  */
 enum { HJPD_H_CNORM = 0, HJPD_H_QUADROTOR = 1, HJPD_H_PURSUIT_EVASION = 2, HJPD_H_LINEAR_TANH = 3,
        HJPD_H_ISAACS = 4 };
@@ -157,7 +159,8 @@ enum {
                                     for H = ISAACS it selects the game Hopf formulation (section 4.2
                                     eq. discgenlaxhopfdghopf, Algorithm 4): value -e*(p_1) - h_*(-q_1)
                                     + <p_N,x> - <q_N,y> + sum_{j<N} (<p_j - p_{j+1}, x_j>
-                                    - <q_j - q_{j+1}, y_j>) - delta sum H(x_j, y_j, p_j, -q_j).
+                                    - <q_j - q_{j+1}, y_j>) - delta sum H(x_j, y_j, p_j, -q_j)
+                                    (without the flag, Algorithm 3 for the same game).
                                     Other pairs return HJPD_EUNSUPPORTED.  Trajectory node 0 is zero. */
     HJPD_FORWARD_EULER = 1u << 6, /* forward-Euler discretisation of the Lax saddle (section 4.1, eq.
                                     disclaxFE) instead of backward Euler.  With p_j the costate of the

@@ -45,6 +45,7 @@ int kernel_variant(const hjpd_desc& d) {
   if (has_mix(d)) return hjpd::kVarMix;
   // Algorithms 1 and 2 for the eikonal family run in the shifted layout (node 0 is an ordinary slot)
   if (d.H == HJPD_H_CNORM && d.d_y == 0) return (d.flags & HJPD_HOPF) ? hjpd::kVarShiftHopf : hjpd::kVarShift;
+  if (d.H == HJPD_H_ISAACS && !(d.flags & HJPD_HOPF)) return hjpd::kVarGameLax;
   return hjpd::kVarPlain;
 }
 
@@ -579,8 +580,7 @@ int validate_desc(const hjpd_desc* d) {
   } else if (d->H == HJPD_H_ISAACS) {
     if (!(game && d->g == HJPD_G_SADDLE_QUAD && d->d == 2 && d->d_y == 1))
       return fail(HJPD_EUNSUPPORTED, "ISAACS needs d = 2, d_y = 1, g = SADDLE_QUAD");
-    if (!(d->flags & HJPD_HOPF) || (d->flags & HJPD_PLAIN))
-      return fail(HJPD_EUNSUPPORTED, "ISAACS is built for the game Hopf formulation on the persistent kernel");
+    if (d->flags & HJPD_PLAIN) return fail(HJPD_EUNSUPPORTED, "ISAACS is built for the persistent kernel");
   } else if (game || d->g == HJPD_G_SADDLE_QUAD) {
     return fail(HJPD_EUNSUPPORTED, "the game path is built for the pursuit-evasion and Isaacs families only");
   } else if (d->H == HJPD_H_CNORM) {

@@ -692,14 +692,30 @@ struct Isaacs {
   template <typename T> struct Par {
     T b0, b1, b2, cx, cy;
     T c0, ia2, ib2;  // c0, 1/a^2, 1/b^2
+    T ea2, hb2;      // a^2, b^2 of the initial cost
   };
 
   template <typename T>
   __device__ static void load(Par<T>& P, const T* hp, const T* gp, int, T) {
     P.b0 = hp[0]; P.b1 = hp[1]; P.b2 = hp[2]; P.cx = hp[3]; P.cy = hp[4];
     P.c0 = gp[0];
-    P.ia2 = T(1) / (gp[1] * gp[1]);
-    P.ib2 = T(1) / (gp[2] * gp[2]);
+    P.ea2 = gp[1] * gp[1];
+    P.hb2 = gp[2] * gp[2];
+    P.ia2 = T(1) / P.ea2;
+    P.ib2 = T(1) / P.hb2;
+  }
+
+  // Algorithm 3's node 0: prox of tau e(x) = tau ((a x)^2/2 - c0) at v, and the
+  // concave counterpart for y, prox of -tau h(y) = tau (b y)^2/2 at v.
+  template <typename T>
+  __device__ static T prox_e(const Par<T>& P, T v, T tau) { return M<T>::div(v, T(1) + tau * P.ea2); }
+  template <typename T>
+  __device__ static T prox_mh(const Par<T>& P, T v, T tau) { return M<T>::div(v, T(1) + tau * P.hb2); }
+
+  // g(x_0, y_0) = e(x_0) + h(y_0) (Algorithm 3's value)
+  template <typename T>
+  __device__ static T g(const Par<T>& P, T x0, T y0) {
+    return T(0.5) * P.ea2 * x0 * x0 - P.c0 - T(0.5) * P.hb2 * y0 * y0;
   }
 
   // c(x,y) and its partial derivatives.

@@ -1194,7 +1194,7 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game(KArgs<
 //   - delta sum_j H(x_j, y_j, p_j, -q_j),  x_0 = y_0 = 0,
 // which is eq. discgenlaxhopfdghopf's objective after summation by parts.
 // ---------------------------------------------------------------------------
-template <typename T, class F, int L, int K>
+template <typename T, class F, int L, int K, bool kLax = false>
 __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game_hopf(KArgs<T> a) {
   static_assert(F::DX == 1 && F::DY == 1, "scalar players");
   constexpr int D = F::D;
@@ -1210,6 +1210,8 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game_hopf(K
   const T sigma = a.sigma, tau = a.tau, theta = a.theta;
 
   T x[K], y[K], p[K], q[K], z[K], w[K];
+  // node 0 (kLax: Algorithm 3) in the group's first lane; zero elsewhere and in the Hopf formulation
+  T x0 = T(0), y0 = T(0), z0 = T(0), w0 = T(0);
   T tj[K], tdj[K];  // per node: tau and tau*delta where the node takes a primal step, else 0
   T delta = T(0), sd = T(0), td = T(0), xN = T(0), yN = T(0);
   int Np = 0, k = 0;
@@ -1245,21 +1247,27 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game_hopf(K
       tj[kk] = (j < Np) ? tau : T(0);
       tdj[kk] = (j < Np) ? td : T(0);
     }
+    if constexpr (kLax) {
+      x0 = (l == 0) ? init_x(xN, a.seed, pt, kArrX, 0, 0) : T(0);
+      y0 = (l == 0) ? init_x(yN, a.seed, pt, kArrY, 0, 0) : T(0);
+      z0 = x0;
+      w0 = y0;
+    }
   };
 
   pop_and_init();
 
   while (__any(active)) {
-    // z_{j-1}, w_{j-1} of the lane's first node; zero in the group's first
-    // lane (no node 0 in the Hopf formulation)
-    const T zprev = group_prev0<L>(z[K - 1], l), wprev = group_prev0<L>(w[K - 1], l);
+    // z_{j-1}, w_{j-1} of the lane's first node; in the group's first lane
+    // node 0's (zero in the Hopf formulation, which has no node 0)
+    const T zprev = group_prev_fill<L>(z[K - 1], l, z0), wprev = group_prev_fill<L>(w[K - 1], l, w0);
     T gx[K];  // d c/dx at (x^k, y^k)
     T rp = T(0), rq = T(0), rx = T(0), ry = T(0);
     // ---- p, then q, node by node ------------------------------------------------
 #pragma unroll
     for (int kk = 0; kk < K; kk++) {
       const int j = 1 + l * K + kk;
-      const bool first = (l == 0) && (kk == 0);
+      const bool first = !kLax && (l == 0) && (kk == 0);  // Hopf node 1: with e* and h_*
       T dcy;
       const T c = F::speed(P, x[kk], y[kk], gx[kk], dcy);
       const T v = p[kk] + sigma * (z[kk] - (kk == 0 ? zprev : z[kk - 1]));
@@ -1274,7 +1282,15 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game_hopf(K
       }
     }
     const T pnext = group_next0<L>(p[0], l), qnext = group_next0<L>(q[0], l);
-    // ---- x: descent, grad_x H(x, y, p, -q) = q dc/dx ------------------------------
+    // ---- x: node 0 by the prox of e (Algorithm 3), then descent, grad_x H(x, y, p, -q) = q dc/dx
+    if constexpr (kLax) {
+      if (l == 0) {
+        const T dx0 = F::prox_e(P, x0 + tau * p[0], tau) - x0;
+        rx += dx0 * dx0;
+        z0 = x0 + (T(1) + theta) * dx0;
+        x0 += dx0;
+      }
+    }
 #pragma unroll
     for (int kk = 0; kk < K; kk++) {
       const T pp = (kk == K - 1) ? pnext : p[kk + 1];
@@ -1283,7 +1299,15 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game_hopf(K
       z[kk] = x[kk] + (T(1) + theta) * dx;
       x[kk] += dx;
     }
-    // ---- y: ascent at the new x ---------------------------------------------------
+    // ---- y: node 0 by the prox of -h (Algorithm 3), then ascent at the new x ---------
+    if constexpr (kLax) {
+      if (l == 0) {
+        const T dy0 = F::prox_mh(P, y0 + tau * q[0], tau) - y0;
+        ry += dy0 * dy0;
+        w0 = y0 + (T(1) + theta) * dy0;
+        y0 += dy0;
+      }
+    }
 #pragma unroll
     for (int kk = 0; kk < K; kk++) {
       T dcx, dcy;
@@ -1301,7 +1325,7 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game_hopf(K
     const bool small = (rxs < a.tol) && (rps < a.tol) && (rys < a.tol) && (rqs < a.tol);
     const bool done = active && (!fin || (!a.fixed && small) || k >= a.max_iter);
     if (done) {
-      const T xprev = group_prev0<L>(x[K - 1], l), yprev = group_prev0<L>(y[K - 1], l);
+      const T xprev = group_prev_fill<L>(x[K - 1], l, x0), yprev = group_prev_fill<L>(y[K - 1], l, y0);
       T acc = T(0);
       int bad = 0;
 #pragma unroll
@@ -1315,7 +1339,12 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game_hopf(K
           bad |= !(M<T>::finite(x[kk]) && M<T>::finite(y[kk]) && M<T>::finite(p[kk]) && M<T>::finite(q[kk]));
         }
       }
-      if (l == 0) acc += F::conj_terms(P, p[0], q[0]);
+      if (l == 0) {
+        // Algorithm 3: g(x_0, y_0); Algorithm 4: -e*(p_1) - h_*(-q_1)
+        if constexpr (kLax) acc += F::g(P, x0, y0);
+        else acc += F::conj_terms(P, p[0], q[0]);
+        bad |= !(M<T>::finite(x0) && M<T>::finite(y0));
+      }
       acc = group_sum<L>(acc);
       bad = group_or<L>(bad);
       int st = !fin ? kNonFinite : (small ? kConverged : kMaxIter);
@@ -1336,8 +1365,8 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game_hopf(K
           }
         }
         if (l == 0) {
-          a.xtraj[base] = T(0);
-          a.xtraj[base + 1] = T(0);
+          a.xtraj[base] = x0;
+          a.xtraj[base + 1] = y0;
         }
       }
       if (a.ptraj) {

@@ -18,14 +18,20 @@ inline constexpr int kMaxCapacity = 256;
 // recipes, the eikonal family's weighted discretisations (forward Euler,
 // trapezoid), and the eikonal family's shifted-layout kernel for Algorithms 1
 // and 2 (which kVarPlain also selects for that family).
-enum Variant { kVarPlain = 0, kVarRecipe = 1, kVarMix = 2, kVarShift = 3, kVarShiftHopf = 4 };
+enum Variant { kVarPlain = 0, kVarRecipe = 1, kVarMix = 2, kVarShift = 3, kVarShiftHopf = 4, kVarGameLax = 5 };
 
 template <typename T, class F, int L, int K>
 const void* group_ptr(int variant) {
   if constexpr (F::kGame) {
-    if (variant != kVarPlain) return nullptr;
-    if constexpr (F::kGameHopf) return reinterpret_cast<const void*>(&k_group_game_hopf<T, F, L, K>);
-    else return reinterpret_cast<const void*>(&k_group_game<T, F, L, K>);
+    if constexpr (F::kGameHopf) {
+      // scalar-player game: Algorithm 4 (kVarPlain) or Algorithm 3 (kVarGameLax) in one kernel
+      if (variant == kVarGameLax) return reinterpret_cast<const void*>(&k_group_game_hopf<T, F, L, K, true>);
+      if (variant != kVarPlain) return nullptr;
+      return reinterpret_cast<const void*>(&k_group_game_hopf<T, F, L, K>);
+    } else {
+      if (variant != kVarPlain) return nullptr;
+      return reinterpret_cast<const void*>(&k_group_game<T, F, L, K>);
+    }
   } else {
     if (variant == kVarRecipe) return reinterpret_cast<const void*>(&k_group_control_rec<T, F, L, K, true>);
     if constexpr (F::kMix) {
@@ -43,7 +49,7 @@ const void* group_ptr(int variant) {
 // variant: kVarPlain (Algorithm 1 / 2 / 3), kVarRecipe (control kernel with
 // the robustness recipes), kVarMix (weighted Euler discretisations),
 // kVarShift / kVarShiftHopf (Algorithm 1 / 2 in the shifted layout, eikonal
-// family).
+// family), kVarGameLax (Algorithm 3 for the scalar-player game).
 template <typename T, class F>
 const void* pick_kernel(int plain, int L, int K, int variant) {
   if (plain) {

@@ -80,8 +80,8 @@ def test_create_rejects_invalid_descriptors(lib, bad):
     dict(flags=64 | 1),                                  # no weighted discretisation on the plain kernel
     dict(flags=128 | 32),                                # nor with the Hopf formulation
     dict(flags=64, starts=3),                            # nor with the recipes
-    dict(H=4, g=4, d=2, d_y=1),                          # Isaacs: game Hopf formulation only
-    dict(H=4, g=4, d=2, d_y=1, flags=32 | 1),            # no plain kernel for it
+    dict(H=4, g=4, d=2, d_y=1, flags=32 | 1),            # Isaacs: no plain kernel, Algorithm 4
+    dict(H=4, g=4, d=2, d_y=1, flags=1),                 # nor Algorithm 3
     dict(H=4, g=4, d=3, d_y=1, flags=32),                # scalar players only
     dict(H=4, g=1, d=2, d_y=1, flags=32),                # Isaacs pairs with SADDLE_QUAD
     dict(g=4, d=10, flags=32),                           # SADDLE_QUAD is a game cost
@@ -102,13 +102,16 @@ def test_null_arguments(lib):
     assert lib.hjpd_get_timing(None, ctypes.byref(ms), None) == hjpd.HJPD_EINVAL
 
 
-def test_valid_descriptor_without_gpu_reports_device_error(lib):
+@pytest.mark.parametrize("ok", [dict(), dict(H=4, g=4, d=2, d_y=1), dict(H=4, g=4, d=2, d_y=1, flags=32)])
+def test_valid_descriptor_without_gpu_reports_device_error(lib, ok):
+    """Descriptors that validate (eikonal; Isaacs' game by Algorithm 3 and by
+    Algorithm 4) get as far as the device query."""
     import torch
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     from paper_1803_01215_amd import hjpd
     ctx = ctypes.c_void_p()
-    assert lib.hjpd_create(ctypes.byref(_desc()), ctypes.byref(ctx)) == hjpd.HJPD_EDEVICE
+    assert lib.hjpd_create(ctypes.byref(_desc(**ok)), ctypes.byref(ctx)) == hjpd.HJPD_EDEVICE
 
 
 def test_flag_values_match_header():

@@ -198,11 +198,13 @@ def test_fullsize_lintanh100_forward_and_reverse(oracle_mod):
         assert np.max(np.abs(a[k] + b[k] - c[k])) <= 1e-4 * scale, k
 
 
-def test_fullsize_isaacs2_game_hopf(oracle_mod):
+@pytest.mark.parametrize("hopf", [True, False])
+def test_fullsize_isaacs2_game(oracle_mod, hopf):
     """Isaacs' game, the section's whole 73 x 73 grid at its four times
-    (21,316 points, N = 5..20), game Hopf formulation, FP32, cap 20,000."""
+    (21,316 points, N = 5..20), FP32, cap 20,000: the game Hopf formulation
+    (Algorithm 4) and Algorithm 3."""
     w = W.isaacs2()
-    g = _graph_solve(w, "f32", max_iter=20000, hopf=True)
+    g = _graph_solve(w, "f32", max_iter=20000, hopf=hopf)
     assert np.mean(g["status"] == 0) > 0.97
     idx = _sample(g, w.n, 96, 32, seed=16)
-    _check_sampled(oracle_mod, w, g, idx, "f32", max_iter=20000, hopf=True)
+    _check_sampled(oracle_mod, w, g, idx, "f32", max_iter=20000, hopf=hopf)
