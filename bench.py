@@ -312,6 +312,25 @@ def copy_calibration(torch, dev):
     del src, dst
 
 
+def fma_calibration(rounds=5000):
+    """What the vector ALUs sustain for single (not packed) FMAs, the form
+    every solver kernel is compiled to: the library's calibration kernel over
+    independent chains per lane x resident waves per SIMD, FP32 and FP64.
+    TFLOP/s from exact flop counts and HIP-event launch times."""
+    from paper_1803_01215_amd import hjpd as C
+    out = {}
+    for name, dt, grid in (("fp32", C.HJPD_F32, [(c, w) for c in (1, 2, 4, 8, 16) for w in (1, 2, 4, 8)]),
+                           ("fp64", C.HJPD_F64, [(c, w) for c in (1, 4, 8) for w in (1, 2, 8)])):
+        rows = []
+        for c, w in grid:
+            r = C.hjpd_calibrate_fma(dt, c, w, rounds)
+            rows.append({"chains": c, "waves_per_simd": w, "ms": r["ms"],
+                         "tflops": r["flops"] / (r["ms"] * 1e-3) / 1e12})
+        out[name] = rows
+        out[name + "_best_tflops"] = max(r["tflops"] for r in rows)
+    return out
+
+
 def roofline_of(launches, kernel_fmt, dtype_name, peak, bound="alu"):
     """The dominant launch (the class with the longest kernel time) and every class's figures."""
     dom = max(launches, key=lambda a: a["ms"])
@@ -393,6 +412,8 @@ def main():
     ap.add_argument("--tune-cache", metavar="FILE",
                     help="tuning cache: the headline's plan is read from FILE if recorded there, else tuned and "
                          "recorded (so a profiled run can repeat the measured plan without tuning)")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="only the FMA calibration sweep (for hardware-counter runs), one JSON line")
     ap.add_argument("--profile", action="store_true",
                     help="headline solves only (warmup + steps, plan from --tune-cache or tuned), for rocprofv3")
     args = ap.parse_args()
@@ -415,6 +436,10 @@ def main():
     def log(msg):
         print("[bench] " + msg, file=sys.stderr, flush=True)
 
+    if args.calibrate:
+        print(json.dumps({"fma_calibration": fma_calibration()}))
+        return
+
     # ---- headline: pursuit-evasion, full set, one graph ------------------------------------
     w = W.pursuit12()
     plan, tune_s = B.tune(w, f32)
@@ -424,8 +449,16 @@ def main():
     if args.profile:
         if args.copy_calib:
             copy_calibration(torch, B.dev)
+        # per class: points and summed iterations of one solve (to put counters per wave-iteration)
+        cls, lo = [], 1
+        for hi, L, K in plan:
+            m = (w.N >= lo) & (w.N <= hi)
+            cls.append({"N_lo": lo, "N_hi": hi, "L": L, "K": K, "points": int(m.sum()),
+                        "iters_sum": int(head["iters"][m].sum())})
+            lo = hi + 1
         print(json.dumps({"profile": "pursuit12 headline solves", "plan": plan, "steps": args.steps,
-                          "warmup": args.warmup, "ms_per_step": head["ms"], "converged": head["converged"]}))
+                          "warmup": args.warmup, "ms_per_step": head["ms"], "converged": head["converged"],
+                          "classes": cls}))
         return
     dflt = B.batched(w, f32, 3, 1)
     norefill = B.batched(w, f32, 2, 1, plan=plan, refill=False)
@@ -561,6 +594,11 @@ def main():
             "workload": "isaacs2 as above, Algorithm 3 (initial cost g(x_0, y_0) itself), tol 1e-8, FP32",
             "points": wi.n, "value": il["solves_per_s"], "unit": "converged solves/s", "ms_per_step": il["ms"],
             "converged": il["converged"], "iters_p50": float(np.median(il["iters"]))}
+
+    # what single FMAs sustain on this GPU (context for the FP32 roofline fractions)
+    rec["fma_calibration"] = fma_calibration()
+    log("fma calibration: fp32 best %.1f TFLOP/s, fp64 best %.1f TFLOP/s" % (
+        rec["fma_calibration"]["fp32_best_tflops"], rec["fma_calibration"]["fp64_best_tflops"]))
 
     if args.copy_calib:
         copy_calibration(torch, B.dev)

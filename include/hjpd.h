@@ -364,6 +364,23 @@ int hjpd_get_timing(hjpd_ctx *ctx, double *ms, int *launches);
 int hjpd_get_launch_timing(hjpd_ctx *ctx, int i, double *ms, int *N_lo, int *N_hi, int *lanes_per_point,
                            int *nodes_per_lane);
 
+/*
+ * Calibration of the FLOP accounting (no context; runs on the current
+ * device): a kernel whose every lane runs `chains` independent chains of
+ * fused multiply-adds a <- a b + c (chains in {1, 2, 4, 8, 16}), 32 per chain
+ * and round, for `rounds` rounds (1 .. 2^30), in FP32 (single, not packed,
+ * FMAs, as in every kernel of this library) or FP64 (dtype HJPD_F32 or
+ * HJPD_F64), with `waves_per_simd` (1..8) blocks of four waves per compute
+ * unit.  One warm-up launch, then one launch timed with HIP events on a
+ * stream of its own: *ms receives its device milliseconds, *flops (if not
+ * NULL) its exact flop count (2 per lane and FMA) and *wave_instructions (if
+ * not NULL) its count of wave64 FMA instructions.  Allocates and frees a
+ * small output buffer; synchronous.  EINVAL on a bad argument, EDEVICE on a
+ * HIP error.
+ */
+int hjpd_calibrate_fma(int dtype, int chains, int waves_per_simd, int64_t rounds, double *ms, double *flops,
+                       double *wave_instructions);
+
 /* Release the context and its device workspace.  NULL is allowed. */
 int hjpd_destroy(hjpd_ctx *ctx);
 

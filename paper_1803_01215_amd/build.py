@@ -53,7 +53,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         cmds.append([HIPCC, *FLAGS, "-DHJPD_FAM=%s" % fam, "-DHJPD_REAL=%s" % real, "-DHJPD_NAME=%s" % name,
                      "-c", os.path.join(CSRC, "hjpd_inst.hip"), "-o", o])
         objs.append(o)
-    for unit in ("hjpd_api", "hjpd_lintanh"):
+    for unit in ("hjpd_api", "hjpd_lintanh", "hjpd_calib"):
         o = os.path.join(BUILD, unit + ".o")
         cmds.append([HIPCC, *FLAGS, "-c", os.path.join(CSRC, unit + ".hip"), "-o", o])
         objs.append(o)

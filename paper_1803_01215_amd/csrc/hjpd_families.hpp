@@ -534,10 +534,10 @@ struct Pursuit {
     T kappa, wP, wE, r;
   };
   template <typename T> struct CacheX {
-    T nv, inv;  // |v_P| at x_j^k and 1/|v_P| (0 at v_P = 0)
+    T knv, kinv;  // kappa |v_P| at x_j^k and kappa / |v_P| (0 at v_P = 0)
   };
   template <typename T> struct CacheY {
-    T nv, inv;  // |v_E| at y_j^k and 1/|v_E| (0 at v_E = 0)
+    T knv, kinv;  // kappa |v_E| at y_j^k and kappa / |v_E| (0 at v_E = 0)
   };
 
   template <typename T>
@@ -553,14 +553,17 @@ struct Pursuit {
     return M<T>::sqrt_fast(s[3] * s[3] + s[4] * s[4] + s[5] * s[5]);
   }
 
-  // |v| and 1/|v| of a state from one reciprocal square root (both 0 at v = 0).
+  // kappa |v| and kappa / |v| of a state from one reciprocal square root, of
+  // max(|v|^2, e) with e = 1e-30 (FP32) or 1e-300 (FP64): at v = 0 the two
+  // terms they scale (kappa |v| and kappa (v.pi) v/|v|) come out exactly 0
+  // (|v|^2 and v.pi are 0, the reciprocal finite), and for |v|^2 < e each
+  // differs from its exact value by less than kappa |pi| sqrt(e).
   template <typename T>
-  __device__ static void speed_inv(const T (&s)[6], T& nv, T& inv) {
+  __device__ static void speed_inv(const Par<T>& P, const T (&s)[6], T& knv, T& kinv) {
     const T ss = s[3] * s[3] + s[4] * s[4] + s[5] * s[5];
-    const T rs = M<T>::rsqrt(ss);
-    const bool nz = ss > T(0);
-    nv = nz ? ss * rs : T(0);
-    inv = nz ? rs : T(0);
+    const T e = sizeof(T) == 4 ? T(1e-30) : T(1e-300);
+    kinv = P.kappa * M<T>::rsqrt(M<T>::fmax(ss, e));
+    knv = ss * kinv;
   }
 
   // Velocity-costate factors of the p- and q-steps for the step lam = sigma
@@ -575,8 +578,8 @@ struct Pursuit {
   // ip = 1) leaves v unchanged: a node past N keeps p = 0.
   template <typename T>
   __device__ static void dual_p(const Par<T>& P, const T (&x)[6], T (&v)[6], T lam, T ip, CacheX<T>& C) {
-    speed_inv(x, C.nv, C.inv);
-    const T lkn = lam * P.kappa * C.nv;
+    speed_inv(P, x, C.knv, C.kinv);
+    const T lkn = lam * C.knv;
 #pragma unroll
     for (int i = 0; i < 3; i++) {
       v[i] += lam * x[3 + i];
@@ -587,8 +590,8 @@ struct Pursuit {
   // q-step for node j, with iq = 1/(1 + lam wE).
   template <typename T>
   __device__ static void dual_q(const Par<T>& P, const T (&y)[6], T (&v)[6], T lam, T iq, CacheY<T>& C) {
-    speed_inv(y, C.nv, C.inv);
-    const T lkn = lam * P.kappa * C.nv;
+    speed_inv(P, y, C.knv, C.kinv);
+    const T lkn = lam * C.knv;
 #pragma unroll
     for (int i = 0; i < 3; i++) {
       v[i] += lam * y[3 + i];
@@ -596,28 +599,30 @@ struct Pursuit {
     }
   }
 
-  // J_F(s)^T pi with |v| and 1/|v| precomputed (the term (v.pi) v/|v| is 0 at v = 0)
+  // J_F(s)^T pi with kappa |v| and kappa / |v| precomputed (the term
+  // (v.pi) v/|v| is 0 at v = 0): velocity rows pi_i - kappa |v| pi_{3+i} -
+  // kappa (v.pi)/|v| v_i, position rows 0.
   template <typename T>
-  __device__ static void jft(const Par<T>& P, const T (&s)[6], T nv, T inv, const T (&pi)[6], T (&o)[6]) {
+  __device__ static void jft(const T (&s)[6], T knv, T kinv, const T (&pi)[6], T (&o)[6]) {
     const T vp = s[3] * pi[3] + s[4] * pi[4] + s[5] * pi[5];
-    const T w = vp * inv;
+    const T kw = vp * kinv;
 #pragma unroll
     for (int i = 0; i < 3; i++) {
       o[i] = T(0);
-      o[3 + i] = pi[i] - P.kappa * (nv * pi[3 + i] + w * s[3 + i]);
+      o[3 + i] = pi[i] - knv * pi[3 + i] - kw * s[3 + i];
     }
   }
 
   template <typename T>
-  __device__ static void grad_x(const Par<T>& P, const T (&x)[6], const T (&p)[6], const CacheX<T>& C, T (&g)[6]) {
-    jft(P, x, C.nv, C.inv, p, g);
+  __device__ static void grad_x(const Par<T>&, const T (&x)[6], const T (&p)[6], const CacheX<T>& C, T (&g)[6]) {
+    jft(x, C.knv, C.kinv, p, g);
 #pragma unroll
     for (int i = 0; i < 6; i++) g[i] = -g[i];
   }
 
   template <typename T>
-  __device__ static void grad_y(const Par<T>& P, const T (&y)[6], const T (&q)[6], const CacheY<T>& C, T (&g)[6]) {
-    jft(P, y, C.nv, C.inv, q, g);
+  __device__ static void grad_y(const Par<T>&, const T (&y)[6], const T (&q)[6], const CacheY<T>& C, T (&g)[6]) {
+    jft(y, C.knv, C.kinv, q, g);
   }
 
   template <typename T>
@@ -644,18 +649,18 @@ struct Pursuit {
     o[3] = v[3]; o[4] = v[4]; o[5] = v[5];
   }
 
+  // Prox of -tau g(x0, .) at v: the position moves away from x0's by tau along
+  // v - x0; where v's position equals x0's the direction is taken as the first
+  // axis.  Branch-free.
   template <typename T>
   __device__ static void stretch_y0(const Par<T>&, const T (&v)[6], const T (&x0)[6], T tau, T (&o)[6]) {
     const T w0 = v[0] - x0[0], w1 = v[1] - x0[1], w2 = v[2] - x0[2];
     const T ss = w0 * w0 + w1 * w1 + w2 * w2;
-    if (ss > T(0)) {
-      const T scale = T(1) + tau * M<T>::rsqrt(ss);
-      o[0] = x0[0] + scale * w0;
-      o[1] = x0[1] + scale * w1;
-      o[2] = x0[2] + scale * w2;
-    } else {
-      o[0] = x0[0] + tau; o[1] = x0[1]; o[2] = x0[2];
-    }
+    const bool nz = ss > T(0);
+    const T scale = T(1) + (nz ? tau * M<T>::rsqrt(ss) : T(0));
+    o[0] = x0[0] + scale * w0 + (nz ? T(0) : tau);
+    o[1] = x0[1] + scale * w1;
+    o[2] = x0[2] + scale * w2;
     o[3] = v[3]; o[4] = v[4]; o[5] = v[5];
   }
 

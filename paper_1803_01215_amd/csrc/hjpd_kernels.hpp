@@ -1048,12 +1048,18 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game(KArgs<
     for (int i = 0; i < DX; i++) pnext[i] = group_next0<L>(p[0][i], l);
 #pragma unroll
     for (int i = 0; i < DY; i++) qnext[i] = group_next0<L>(q[0][i], l);
-    // ---- x block: node 0 (prox of g(., y_0^k)), then descent steps ----------
+    // ---- node 0 (the group's first lane): x_0 by the prox of g(., y_0^k), then
+    //      y_0 by the prox of -g(x_0^{k+1}, .), in one branch (neither depends
+    //      on the other nodes' primal steps).  A branch, not masked arithmetic
+    //      in every lane: measured, the branch costs the wave less.
     if (l == 0) {
-      T v0[DX], xn0[DX];
+      T v0[DX], xn0[DX], u0[DY], yn0[DY];
 #pragma unroll
       for (int i = 0; i < DX; i++) v0[i] = x0[i] + tau * p[0][i];
       F::prox_x0(P, v0, y0, tau, xn0);
+#pragma unroll
+      for (int i = 0; i < DY; i++) u0[i] = y0[i] + tau * q[0][i];
+      F::stretch_y0(P, u0, xn0, tau, yn0);
 #pragma unroll
       for (int i = 0; i < DX; i++) {
         const T dx = xn0[i] - x0[i];
@@ -1061,7 +1067,15 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game(KArgs<
         z0[i] = xn0[i] + theta * dx;
         x0[i] = xn0[i];
       }
+#pragma unroll
+      for (int i = 0; i < DY; i++) {
+        const T dy = yn0[i] - y0[i];
+        ry += dy * dy;
+        w0[i] = yn0[i] + theta * dy;
+        y0[i] = yn0[i];
+      }
     }
+    // ---- x block: descent steps ---------------------------------------------------
 #pragma unroll
     for (int kk = 0; kk < K; kk++) {
       T g[DX];
@@ -1075,20 +1089,7 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game(KArgs<
         x[kk][i] += dx;
       }
     }
-    // ---- y block: node 0 (prox of -g(x_0^{k+1}, .)), then ascent steps ------
-    if (l == 0) {
-      T u0[DY], yn0[DY];
-#pragma unroll
-      for (int i = 0; i < DY; i++) u0[i] = y0[i] + tau * q[0][i];
-      F::stretch_y0(P, u0, x0, tau, yn0);
-#pragma unroll
-      for (int i = 0; i < DY; i++) {
-        const T dy = yn0[i] - y0[i];
-        ry += dy * dy;
-        w0[i] = yn0[i] + theta * dy;
-        y0[i] = yn0[i];
-      }
-    }
+    // ---- y block: ascent steps -----------------------------------------------------
 #pragma unroll
     for (int kk = 0; kk < K; kk++) {
       T g[DY];

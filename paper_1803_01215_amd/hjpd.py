@@ -23,8 +23,8 @@ HJPD_PERSISTENT, HJPD_PLAIN, HJPD_FIXED_ITERS, HJPD_GRAPH, HJPD_TIMING, HJPD_NO_
 HJPD_FORWARD_EULER, HJPD_TRAPEZOID, HJPD_NO_REFILL = 64, 128, 256
 
 EXPORTED = ["hjpd_create", "hjpd_solve_batch", "hjpd_solve_batch_noalloc", "hjpd_value_grad", "hjpd_autotune",
-            "hjpd_get_timing", "hjpd_get_launch_timing", "hjpd_set_plan", "hjpd_get_plan", "hjpd_set_pop_counter", "hjpd_destroy",
-            "hjpd_last_error"]
+            "hjpd_get_timing", "hjpd_get_launch_timing", "hjpd_set_plan", "hjpd_get_plan", "hjpd_set_pop_counter",
+            "hjpd_calibrate_fma", "hjpd_destroy", "hjpd_last_error"]
 
 
 class HjpdError(RuntimeError):
@@ -85,6 +85,9 @@ def load():
         lib.hjpd_set_plan.restype = ctypes.c_int
         lib.hjpd_get_plan.argtypes = [vp, ctypes.c_int, vp, vp, vp, ip, ip]
         lib.hjpd_get_plan.restype = ctypes.c_int
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.hjpd_calibrate_fma.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, i64, dp, dp, dp]
+        lib.hjpd_calibrate_fma.restype = ctypes.c_int
         lib.hjpd_destroy.argtypes = [vp]
         lib.hjpd_destroy.restype = ctypes.c_int
         lib.hjpd_last_error.argtypes = []
@@ -123,6 +126,15 @@ def hjpd_create(desc: hjpd_desc) -> int:
     ctx = ctypes.c_void_p()
     _check(load().hjpd_create(ctypes.byref(desc), ctypes.byref(ctx)))
     return ctx.value
+
+
+def hjpd_calibrate_fma(dtype: int, chains: int, waves_per_simd: int, rounds: int) -> dict:
+    """One timed launch of the FMA calibration kernel: device ms, exact flops
+    and wave64 FMA instructions."""
+    ms, fl, wi = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(load().hjpd_calibrate_fma(int(dtype), int(chains), int(waves_per_simd), int(rounds), ctypes.byref(ms),
+                                     ctypes.byref(fl), ctypes.byref(wi)))
+    return {"ms": ms.value, "flops": fl.value, "wave_instructions": wi.value}
 
 
 def hjpd_destroy(ctx: int) -> None:

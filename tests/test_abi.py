@@ -137,3 +137,12 @@ def test_library_shares_torchs_hip_runtime():
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, check=True).stdout
     libs = eval(out.strip())
     assert len(libs) == 1 and "/torch/lib/" in libs[0], libs
+
+
+@pytest.mark.parametrize("args", [(2, 8, 1, 10), (0, 3, 1, 10), (0, 8, 0, 10), (0, 8, 9, 10), (1, 8, 1, 0)])
+def test_calibrate_fma_rejects_bad_arguments(lib, args):
+    """Bad dtype, chain count, waves per SIMD or rounds: EINVAL before any device call."""
+    from paper_1803_01215_amd import hjpd
+    ms = ctypes.c_double()
+    assert lib.hjpd_calibrate_fma(*args[:3], ctypes.c_int64(args[3]), ctypes.byref(ms), None, None) == hjpd.HJPD_EINVAL
+    assert lib.hjpd_calibrate_fma(0, 8, 1, ctypes.c_int64(10), None, None, None) == hjpd.HJPD_EINVAL
