@@ -414,8 +414,9 @@ def main():
                          "recorded (so a profiled run can repeat the measured plan without tuning)")
     ap.add_argument("--calibrate", action="store_true",
                     help="only the FMA calibration sweep (for hardware-counter runs), one JSON line")
-    ap.add_argument("--profile", action="store_true",
-                    help="headline solves only (warmup + steps, plan from --tune-cache or tuned), for rocprofv3")
+    ap.add_argument("--profile", nargs="?", const="pursuit12", choices=["pursuit12", "cnorm10"],
+                    help="one workload's solves only, for rocprofv3: pursuit12 (the headline; plan from "
+                         "--tune-cache or tuned) or cnorm10 (FP32, cap 5,000)")
     args = ap.parse_args()
     if args.tune_cache:
         os.environ["HJPD_TUNE_CACHE"] = os.path.abspath(args.tune_cache)
@@ -438,6 +439,17 @@ def main():
 
     if args.calibrate:
         print(json.dumps({"fma_calibration": fma_calibration()}))
+        return
+
+    if args.profile == "cnorm10":
+        wc = W.cnorm10()
+        wc.max_iter = 5000
+        c = B.batched(wc, f32, args.steps, args.warmup)
+        if args.copy_calib:
+            copy_calibration(torch, B.dev)
+        print(json.dumps({"profile": "cnorm10 FP32 solves", "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": c["ms"], "converged": c["converged"], "points": wc.n,
+                          "iters_sum": int(c["iters"].sum())}))
         return
 
     # ---- headline: pursuit-evasion, full set, one graph ------------------------------------
