@@ -97,7 +97,7 @@
  *  - Hamiltonians of the quadrotor, pursuit-evasion and linear-tanh families
  *    are given by the caller in the physical, terminal-value convention
  *    H_c = min_u {<f,p> + L} (section 2.1).  The algorithms use the
- *    initial-value ("backwards in time") convention H = max_u {<f,p> - L} of
+ *    initial-value (time-reversed) convention H = max_u {<f,p> - L} of
  *    the same section; reversing time turns f into -f, so H = -H_c.  The
  *    eikonal family is already in the paper's convention.
  *  - Initialisation (section 6 set-up): every free coordinate of x_j (j<N)
