@@ -73,15 +73,19 @@
  * linear and quadratic parts are kept exact); x and y take one descent /
  * ascent step each, y after x.
  *
- * Robustness recipes (section 6, remarks on slow points), control path:
+ * Robustness recipes (section 6, remarks on slow points), control path and
+ * the pursuit-evasion game (Algorithm 3; section 6.2 applies the first two
+ * to a game):
  *  - on reaching the iteration cap, continue from the current iterate with
  *    sigma raised by sigma_inc and tau = sigma0 tau0 / sigma, at most
  *    `restarts` times (sigma_inc = 0 is the plain rerun);
  *  - after the first cap, also stop when the value changes by at most
  *    value_tol max(|value|, 1) between consecutive iterations;
- *  - `starts` random starts (seed, seed+1, ...); the reported point is the
- *    lowest value among the starts that stopped by a tolerance rule, else
- *    the lowest finite value, ties to the earlier start.  The two-player game path follows section 4.2, eq.
+ *  - control path only: `starts` random starts (seed, seed+1, ...); the
+ *    reported point is the lowest value among the starts that stopped by a
+ *    tolerance rule, else the lowest finite value, ties to the earlier start.
+ *
+ * The two-player game path follows section 4.2, eq.
  * discgenlaxhopfdg, and Algorithm 3 / Appendix A.2.1: blocks p, q, x, y in
  * that order, with the evader's costate entering H as -q.
  *
@@ -1123,8 +1127,27 @@ static void solve_mix_point(const or_problem *pb, const or_opts *o, long pt, con
 }
 
 /* ------------------------------------------------------------------ */
-/* One query point: game path (Algorithm 3, Appendix A.2.1).          */
+/* One query point: game path (Algorithm 3, Appendix A.2.1), with the  */
+/* recipes of section 6 that the paper applies to a game (sigma raised */
+/* at the cap, value-change stop after the first cap; one start).      */
 /* ------------------------------------------------------------------ */
+
+/* The game value: g(x_0, y_0) + sum_j (<p_j, x_j - x_{j-1}> - <q_j, y_j - y_{j-1}>) - delta sum_j H. */
+static double game_value(const or_problem *pb, const double *x, const double *y, const double *p, const double *q,
+                         int N, double delta)
+{
+    int d = pb->d, dy = pb->d_y, dx = d - dy;
+    double x0y0[64];
+    for (int i = 0; i < dx; i++) x0y0[i] = x[i];
+    for (int i = 0; i < dy; i++) x0y0[dx + i] = y[i];
+    double val = or_g(pb, x0y0);
+    for (int j = 1; j <= N; j++) {
+        for (int i = 0; i < dx; i++) val += p[j * dx + i] * (x[j * dx + i] - x[(j - 1) * dx + i]);
+        for (int i = 0; i < dy; i++) val -= q[j * dy + i] * (y[j * dy + i] - y[(j - 1) * dy + i]);
+        val -= delta * or_game_H(pb, &x[j * dx], &y[j * dy], &p[j * dx], &q[j * dy]);
+    }
+    return val;
+}
 
 static void solve_game_point(const or_problem *pb, const or_opts *o, long pt, const double *xt,
                              double t, int N, double *phi, int *iters, int *status,
@@ -1136,6 +1159,8 @@ static void solve_game_point(const or_problem *pb, const or_opts *o, long pt, co
     double *x = calloc(sx, 8), *p = calloc(sx, 8), *z = calloc(sx, 8), *xn = calloc(sx, 8), *pn = calloc(sx, 8);
     double *y = calloc(sy, 8), *q = calloc(sy, 8), *w = calloc(sy, 8), *yn = calloc(sy, 8), *qn = calloc(sy, 8);
     double v[64], gr[64];
+    double sigma = o->sigma, tau = o->tau;
+    const double st_product = o->sigma * o->tau;
 
     for (int j = 0; j < N; j++) {
         for (int i = 0; i < dx; i++) x[j * dx + i] = xt[i] + or_init_noise(o->seed, pt, OR_ARR_X, j, i);
@@ -1150,39 +1175,40 @@ static void solve_game_point(const or_problem *pb, const or_opts *o, long pt, co
     memcpy(z, x, sx * 8);
     memcpy(w, y, sy * 8);
 
-    int k = 0, st = OR_PT_MAXITER;
+    int k = 0, kp = 0, phase = 0, st = OR_PT_MAXITER;
+    double prev_val = NAN;
     for (;;) {
         /* p block (maximiser's costate): uses x^k, y^k, q^k */
         for (int i = 0; i < dx; i++) pn[i] = 0.0;
         for (int j = 1; j <= N; j++) {
-            for (int i = 0; i < dx; i++) v[i] = p[j * dx + i] + o->sigma * (z[j * dx + i] - z[(j - 1) * dx + i]);
-            or_game_prox_p(pb, &x[j * dx], &y[j * dy], &q[j * dy], v, o->sigma * delta, &pn[j * dx]);
+            for (int i = 0; i < dx; i++) v[i] = p[j * dx + i] + sigma * (z[j * dx + i] - z[(j - 1) * dx + i]);
+            or_game_prox_p(pb, &x[j * dx], &y[j * dy], &q[j * dy], v, sigma * delta, &pn[j * dx]);
         }
         /* q block: uses p^{k+1} */
         for (int i = 0; i < dy; i++) qn[i] = 0.0;
         for (int j = 1; j <= N; j++) {
-            for (int i = 0; i < dy; i++) v[i] = q[j * dy + i] + o->sigma * (w[j * dy + i] - w[(j - 1) * dy + i]);
-            or_game_prox_q(pb, &x[j * dx], &y[j * dy], &pn[j * dx], v, o->sigma * delta, &qn[j * dy]);
+            for (int i = 0; i < dy; i++) v[i] = q[j * dy + i] + sigma * (w[j * dy + i] - w[(j - 1) * dy + i]);
+            or_game_prox_q(pb, &x[j * dx], &y[j * dy], &pn[j * dx], v, sigma * delta, &qn[j * dy]);
         }
         /* x block: x_0 by the prox of g(., y_0^k); x_j by a descent step */
-        for (int i = 0; i < dx; i++) v[i] = x[i] + o->tau * pn[dx + i];
-        or_game_prox_x0(pb, v, y, o->tau, xn);
+        for (int i = 0; i < dx; i++) v[i] = x[i] + tau * pn[dx + i];
+        or_game_prox_x0(pb, v, y, tau, xn);
         for (int j = 1; j < N; j++) {
             or_game_grad_x(pb, &x[j * dx], &y[j * dy], &pn[j * dx], &qn[j * dy], gr);
             for (int i = 0; i < dx; i++)
-                xn[j * dx + i] = x[j * dx + i] - o->tau * (pn[j * dx + i] - pn[(j + 1) * dx + i])
-                                 + o->tau * delta * gr[i];
+                xn[j * dx + i] = x[j * dx + i] - tau * (pn[j * dx + i] - pn[(j + 1) * dx + i])
+                                 + tau * delta * gr[i];
         }
         for (int i = 0; i < dx; i++) xn[N * dx + i] = x[N * dx + i];
         /* y block (maximiser): y_0 by the prox of -g(x_0^{k+1}, .); y_j by an
          * ascent step on the Lagrangian */
-        for (int i = 0; i < dy; i++) v[i] = y[i] + o->tau * qn[dy + i];
-        or_game_stretch_y0(pb, v, xn, o->tau, yn);
+        for (int i = 0; i < dy; i++) v[i] = y[i] + tau * qn[dy + i];
+        or_game_stretch_y0(pb, v, xn, tau, yn);
         for (int j = 1; j < N; j++) {
             or_game_grad_y(pb, &xn[j * dx], &y[j * dy], &pn[j * dx], &qn[j * dy], gr);
             for (int i = 0; i < dy; i++)
-                yn[j * dy + i] = y[j * dy + i] - o->tau * (qn[j * dy + i] - qn[(j + 1) * dy + i])
-                                 - o->tau * delta * gr[i];
+                yn[j * dy + i] = y[j * dy + i] - tau * (qn[j * dy + i] - qn[(j + 1) * dy + i])
+                                 - tau * delta * gr[i];
         }
         for (int i = 0; i < dy; i++) yn[N * dy + i] = y[N * dy + i];
 
@@ -1200,22 +1226,39 @@ static void solve_game_point(const or_problem *pb, const or_opts *o, long pt, co
         memcpy(x, xn, sx * 8); memcpy(p, pn, sx * 8);
         memcpy(y, yn, sy * 8); memcpy(q, qn, sy * 8);
         k++;
+        kp++;
         if (!isfinite(rx + rp + ry + rq)) { st = OR_PT_NONFINITE; break; }
         int small = rx < o->tol && rp < o->tol && ry < o->tol && rq < o->tol;
         if (!o->fixed_iters && small) { st = OR_PT_CONVERGED; break; }
-        if (k >= o->max_iter) { st = small ? OR_PT_CONVERGED : OR_PT_MAXITER; break; }
+        if (o->fixed_iters) {
+            if (k >= o->max_iter) { st = small ? OR_PT_CONVERGED : OR_PT_MAXITER; break; }
+            continue;
+        }
+        /* value-change rule, after the first cap */
+        if (phase >= 1 && o->value_tol > 0.0) {
+            double val = game_value(pb, x, y, p, q, N, delta);
+            if (isfinite(prev_val) && fabs(val - prev_val) <= o->value_tol * fmax(fabs(val), 1.0)) {
+                st = OR_PT_VALUE_STALLED;
+                break;
+            }
+            prev_val = val;
+        }
+        if (kp >= o->max_iter) {
+            if (phase < o->restarts) {
+                /* cap reached: raise sigma, keep sigma tau, continue from this iterate */
+                phase++;
+                kp = 0;
+                sigma += o->sigma_inc;
+                tau = st_product / sigma;
+                prev_val = NAN;
+                continue;
+            }
+            st = OR_PT_MAXITER;
+            break;
+        }
     }
 
-    /* value: g(x_0,y_0) + sum <(p_j,-q_j),(dx_j,dy_j)> - delta sum H */
-    double x0y0[64];
-    for (int i = 0; i < dx; i++) x0y0[i] = x[i];
-    for (int i = 0; i < dy; i++) x0y0[dx + i] = y[i];
-    double val = or_g(pb, x0y0);
-    for (int j = 1; j <= N; j++) {
-        for (int i = 0; i < dx; i++) val += p[j * dx + i] * (x[j * dx + i] - x[(j - 1) * dx + i]);
-        for (int i = 0; i < dy; i++) val -= q[j * dy + i] * (y[j * dy + i] - y[(j - 1) * dy + i]);
-        val -= delta * or_game_H(pb, &x[j * dx], &y[j * dy], &p[j * dx], &q[j * dy]);
-    }
+    double val = game_value(pb, x, y, p, q, N, delta);
     if (!isfinite(val) || !all_finite(x, (int)sx) || !all_finite(y, (int)sy) ||
         !all_finite(p, (int)sx) || !all_finite(q, (int)sy))
         st = OR_PT_NONFINITE;
@@ -1379,7 +1422,10 @@ static int solve_batch(const or_problem *pb, long n, const double *x, const doub
         o.restarts = recipe->restarts;
         o.sigma_inc = recipe->sigma_inc;
         o.value_tol = recipe->value_tol;
-        if (game || hopf || fixed_iters || o.restarts < 0 || o.sigma_inc < 0.0 || o.value_tol < 0.0) return -1;
+        /* games: the sigma and value-change recipes only (one start), Algorithm 3 of the pursuit-evasion game */
+        if ((game && (isaacs || o.starts > 1)) || hopf || fixed_iters || o.restarts < 0 || o.sigma_inc < 0.0 ||
+            o.value_tol < 0.0)
+            return -1;
     }
     int d = pb->d;
 #ifdef _OPENMP
@@ -1438,7 +1484,8 @@ int or_solve_hopf(const or_problem *pb, long n, const double *x, const double *t
                        status, x_traj, p_traj, n_threads, 1, NULL, NULL);
 }
 
-/* Algorithm 1 with the robustness recipes (control path, tolerance mode). */
+/* Algorithm 1 with the robustness recipes (tolerance mode); Algorithm 3 of the
+ * pursuit-evasion game with the sigma and value-change recipes (starts = 1). */
 int or_solve_recipe(const or_problem *pb, long n, const double *x, const double *t, const int *N,
                     double sigma, double tau, double theta, double tol, int max_iter, uint64_t seed, int N_max,
                     const int64_t *ids, int starts, int restarts, double sigma_inc, double value_tol,

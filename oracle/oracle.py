@@ -335,7 +335,8 @@ def solve(pb: Problem, x, t, N, *, sigma, tau, theta=1.0, tol=1e-8, max_iter=500
     non-finite value stops the point first).  hopf=True runs the Hopf
     formulation (Algorithm 2; eikonal family with NORM or QUAD_SHIFT g); its
     trajectories have node 0 = 0.  starts / restarts / sigma_inc / value_tol
-    select the robustness recipes (control path, tolerance mode): see the
+    select the robustness recipes (tolerance mode; control path, and the
+    pursuit-evasion game with starts = 1): see the
     C source's header comment.  disc selects the time discretisation of the
     Lax path: "be" backward Euler (Algorithm 1), "fe" forward Euler,
     "trap" the trapezoidal average of the two (eikonal family), or a pair
@@ -367,7 +368,7 @@ def solve(pb: Problem, x, t, N, *, sigma, tau, theta=1.0, tol=1e-8, max_iter=500
                                 _dp(xt) if traj else None, _dp(pt) if traj else None, int(threads))
     elif starts > 1 or restarts > 0 or value_tol > 0.0:
         if hopf or fixed_iters:
-            raise ValueError("oracle: recipes are for the Lax control path in tolerance mode")
+            raise ValueError("oracle: recipes are for the Lax path in tolerance mode")
         rc = lib().or_solve_recipe(pb.c, n, _dp(x), _dp(t), N.ctypes.data_as(I), sigma, tau, theta, tol,
                                    int(max_iter), int(seed) & (2**64 - 1), int(N_max), idp, int(starts),
                                    int(restarts), float(sigma_inc), float(value_tol), _dp(phi),

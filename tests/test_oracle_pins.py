@@ -885,6 +885,69 @@ def test_multi_start_keeps_the_lowest_converged_value(oracle_mod):
         assert abs(multi.phi[i] - brute) < 1e-5
 
 
+def _pe_problem(oracle_mod, r0=0.5):
+    return oracle_mod.Problem(W.H_PURSUIT_EVASION, W.G_PAIR_DIST, 12, 6, W.PE_PARAMS, [r0])
+
+
+def test_game_recipe_continuation_is_the_longer_run(oracle_mod):
+    """The recipe path on the game continues from the iterate at the cap:
+    with sigma unchanged (sigma_inc = 0) one restart after a cap of K is
+    Algorithm 3 run to 2K, bit for bit (values, iterations, statuses and
+    both trajectories); starts > 1 is refused for a game."""
+    w = W.pursuit12().subset(np.arange(12))
+    pb = _pe_problem(oracle_mod)
+    kw = dict(sigma=w.sigma, tau=w.tau, tol=w.tol, seed=w.init_seed, traj=True)
+    a = oracle_mod.solve(pb, w.x, w.t, w.N, max_iter=8000, **kw)
+    b = oracle_mod.solve(pb, w.x, w.t, w.N, max_iter=4000, restarts=1, sigma_inc=0.0, **kw)
+    assert np.any(a.status == 1) and np.any(a.status == 0)
+    for f in ("phi", "iters", "status", "x_traj", "p_traj"):
+        assert np.array_equal(getattr(a, f), getattr(b, f)), f
+    with pytest.raises(ValueError):
+        oracle_mod.solve(pb, w.x, w.t, w.N, max_iter=600, starts=2, **kw)
+
+
+def test_game_sigma_raise_reaches_the_minmax(oracle_mod):
+    """Section 6.2's recipe on the pursuit-evasion game: at a small sigma and
+    a short cap Algorithm 3 stops at the cap; raising sigma by 20 at each cap
+    (tau = sigma0 tau0 / sigma) and continuing from the iterate converges, to
+    the open-loop min-max of the discretised game found by nested BFGS."""
+    rng = _rng(42)
+    r0, N, t = 0.5, 2, 0.4
+    pb = _pe_problem(oracle_mod, r0)
+    X = np.concatenate([rng.uniform(-1, 1, 3), rng.uniform(-.3, .3, 3), rng.uniform(-1, 1, 3) + 2,
+                        rng.uniform(-.3, .3, 3)])
+    kw = dict(sigma=0.5, tau=0.5, tol=1e-28, max_iter=300, seed=6)
+    plain = oracle_mod.solve(pb, X[None], t, N, **kw)
+    assert plain.status[0] == 1
+    r = oracle_mod.solve(pb, X[None], t, N, restarts=30, sigma_inc=20.0, **dict(kw, max_iter=20000))
+    assert r.status[0] == 0 and r.iters[0] > 300
+    brute = _pe_shoot_minmax(X, N, t, r0, W.PE_PARAMS)
+    assert abs(r.phi[0] - brute) < 1e-9 * max(1, abs(brute)), (r.phi[0], brute)
+
+
+def test_game_value_change_stop_after_the_cap(oracle_mod):
+    """After the first cap the value-change rule stops game points whose value
+    has settled (status VALUE_STALLED); their values agree with a long
+    Algorithm 3 run that converges, to the accuracy of a settled value; before
+    the first cap the rule is off."""
+    w = W.pursuit12().subset(np.arange(24))
+    pb = _pe_problem(oracle_mod)
+    kw = dict(sigma=w.sigma, tau=w.tau, seed=w.init_seed)
+    ref = oracle_mod.solve(pb, w.x, w.t, w.N, tol=1e-12, max_iter=100000, **kw)
+    r = oracle_mod.solve(pb, w.x, w.t, w.N, tol=1e-30, max_iter=2000, restarts=20, sigma_inc=0.0, value_tol=1e-12,
+                         **kw)
+    stalled = r.status == 4
+    assert stalled.mean() >= 0.4 and np.all(r.iters[stalled] > 2000)
+    assert np.all(r.status[~stalled] == 1)  # the others oscillate through every phase to the last cap
+    ok = stalled & (ref.status == 0)
+    assert ok.sum() >= 8
+    assert np.max(np.abs(r.phi[ok] - ref.phi[ok]) / np.maximum(np.abs(ref.phi[ok]), 1)) < 1e-6
+    # a single phase: the rule never engages and the run is Algorithm 3
+    a = oracle_mod.solve(pb, w.x, w.t, w.N, tol=w.tol, max_iter=3000, **kw)
+    b = oracle_mod.solve(pb, w.x, w.t, w.N, tol=w.tol, max_iter=3000, restarts=0, value_tol=1e-12, **kw)
+    assert np.array_equal(a.phi, b.phi) and np.array_equal(a.status, b.status)
+
+
 # --------------------------------------------------------------------------
 # Forward Euler and trapezoidal discretisations (section 4.1, eq. disclaxFE;
 # the remark after Algorithm 1 on averaging the two Euler approximations)
