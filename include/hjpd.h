@@ -199,12 +199,14 @@ typedef struct {
     int lanes_per_point; /* persistent tile override: lanes per point (8,16,32,64), 0 = tuned/default */
     int nodes_per_lane;  /* persistent tile override: time nodes per lane (1..4), 0 = tuned/default */
     /* Robustness recipes (section 6, remarks on slow points); all zero = plain
-     * Algorithm 1.  Control path, persistent kernels, tolerance mode, Lax
-     * formulation only (else HJPD_EUNSUPPORTED).
+     * Algorithm 1 (3).  Persistent kernels, tolerance mode, Lax formulation
+     * only: the control families, and the pursuit-evasion game with one start
+     * (section 6.2 applies the sigma and value-change recipes to a game); else
+     * HJPD_EUNSUPPORTED.
      *  starts:    random starts per point (seed, seed+1, ...); the reported
      *             point is the lowest value among the starts that met a
      *             stopping rule, else the lowest finite value, ties to the
-     *             earlier start (0 or 1 = one start);
+     *             earlier start (0 or 1 = one start; control path only);
      *  restarts:  times the iteration may continue past the cap max_iter with
      *             sigma raised by sigma_inc and tau = sigma0 tau0 / sigma
      *             (sigma_inc = 0: continue with the same steps);

@@ -170,6 +170,10 @@ def _variant_lib(variant: str):
                                    ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), R, R,
                                    Rp, I, I, Rp, Rp, ctypes.c_int]
         L.or_solve_mix.restype = ctypes.c_int
+        L.or_solve_recipe.argtypes = [ctypes.POINTER(_P), ctypes.c_long, Rp, Rp, I, R, R, R, R, ctypes.c_int,
+                                      ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int,
+                                      ctypes.c_int, R, R, Rp, I, I, Rp, Rp, ctypes.c_int]
+        L.or_solve_recipe.restype = ctypes.c_int
         _vlibs[variant] = L
     return _vlibs[variant]
 
@@ -279,15 +283,19 @@ DISC_WEIGHTS = {"be": (0.0, 1.0), "fe": (1.0, 0.0), "trap": (0.5, 0.5)}
 
 def solve_variant(variant: str, pb: Problem, x, t, N, *, sigma, tau, theta=1.0, tol=1e-8, max_iter=5000,
                   fixed_iters=False, seed=0, N_max=None, ids=None, traj=False, threads=0, hopf=False,
-                  disc="be") -> Result:
+                  disc="be", starts=1, restarts=0, sigma_inc=0.0, value_tol=0.0) -> Result:
     """solve() (Algorithms 1 to 3, the Hopf formulation, the weighted
-    discretisations; no recipes) in one of the rounding variants: "f64fma",
+    discretisations, the recipes) in one of the rounding variants: "f64fma",
     "f32" or "f32fma".  Binary32 variants take their inputs rounded to
     binary32; results are returned as float64 arrays."""
+    rec = dict(starts=starts, restarts=restarts, sigma_inc=sigma_inc, value_tol=value_tol)
+    recipe = starts > 1 or restarts > 0 or value_tol > 0.0
     if variant == "f64":
         return solve(pb, x, t, N, sigma=sigma, tau=tau, theta=theta, tol=tol, max_iter=max_iter,
                      fixed_iters=fixed_iters, seed=seed, N_max=N_max, ids=ids, traj=traj, threads=threads, hopf=hopf,
-                     disc=disc)
+                     disc=disc, **rec)
+    if recipe and (hopf or fixed_iters or disc != "be"):
+        raise ValueError("oracle: recipes are for the Lax path in tolerance mode")
     L = _variant_lib(variant)
     R = L.real
     Rp = ctypes.POINTER(ctypes.c_float if R == np.float32 else ctypes.c_double)
@@ -313,7 +321,11 @@ def solve_variant(variant: str, pb: Problem, x, t, N, *, sigma, tau, theta=1.0, 
               int(bool(fixed_iters)), int(seed) & (2**64 - 1), int(N_max), idp)
     outs = (rp(phi), iters.ctypes.data_as(I), status.ctypes.data_as(I), rp(xt) if traj else None,
             rp(pt) if traj else None, int(threads))
-    if disc != "be":
+    if recipe:
+        rc = L.or_solve_recipe(ctypes.byref(P), n, rp(x), rp(t), N.ctypes.data_as(I), sigma, tau, theta, tol,
+                               int(max_iter), int(seed) & (2**64 - 1), int(N_max), idp, int(starts), int(restarts),
+                               float(sigma_inc), float(value_tol), *outs)
+    elif disc != "be":
         wl, wr = (float(v) for v in (DISC_WEIGHTS.get(disc, disc) if isinstance(disc, str) else disc))
         rc = L.or_solve_mix(*common, wl, wr, *outs)
     else:

@@ -563,8 +563,11 @@ int validate_desc(const hjpd_desc* d) {
     return fail(HJPD_EINVAL, "recipes: starts in 0..1024, restarts >= 0, sigma_inc >= 0, value_tol >= 0");
   // supported pairs
   const bool game = d->d_y > 0;
-  if (has_recipe(*d) && (game || d->H == HJPD_H_LINEAR_TANH || (d->flags & (HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_HOPF))))
-    return fail(HJPD_EUNSUPPORTED, "recipes are built for the persistent Lax control path in tolerance mode");
+  if (has_recipe(*d) && (d->H == HJPD_H_LINEAR_TANH || d->H == HJPD_H_ISAACS ||
+                         (d->flags & (HJPD_PLAIN | HJPD_FIXED_ITERS | HJPD_HOPF))))
+    return fail(HJPD_EUNSUPPORTED, "recipes are built for the persistent Lax path in tolerance mode "
+                                   "(control families and the pursuit-evasion game)");
+  if (game && d->starts > 1) return fail(HJPD_EUNSUPPORTED, "several starts are built for the control path only");
   if ((d->flags & HJPD_HOPF) && !(d->H == HJPD_H_CNORM && !game && (d->g == HJPD_G_NORM || d->g == HJPD_G_QUAD_SHIFT)) &&
       !(d->H == HJPD_H_QUADROTOR && !game && d->g == HJPD_G_QUAD_SHIFT && !(d->flags & HJPD_PLAIN)) &&
       d->H != HJPD_H_ISAACS)

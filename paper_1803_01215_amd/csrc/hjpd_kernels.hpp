@@ -922,8 +922,12 @@ __global__ void __launch_bounds__(256, (kShiftWaves<T, K>)) k_group_control_shif
 // ---------------------------------------------------------------------------
 // Persistent lane-group kernel, game path (Algorithm 3) for games whose
 // Hamiltonian separates as H = Hx(x, p) + Hy(y, q): block order p, q, x, y.
+// kRec adds the two recipes of section 6 that the paper applies to a game
+// (sigma raised at the iteration cap, continuing from the iterate; after the
+// first cap a value-change stop), with per-point step sizes; kRec = false is
+// the plain iteration with constant steps.
 // ---------------------------------------------------------------------------
-template <typename T, class F, int L, int K>
+template <typename T, class F, int L, int K, bool kRec = false>
 __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game(KArgs<T> a) {
   constexpr int DX = F::DX, DY = F::DY, D = F::D;
   const int lane = threadIdx.x & 63;
@@ -935,7 +939,9 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game(KArgs<
   const WavePrio prio(a.max_iter);
   const int beg = a.cls_range[2 * a.cls], end = a.cls_range[2 * a.cls + 1];
   int32_t* head = a.heads + a.cls;
-  const T sigma = a.sigma, tau = a.tau, theta = a.theta;
+  const T theta = a.theta;
+  // step sizes: kernel constants, or per point when the recipes raise sigma
+  T sigma = a.sigma, tau = a.tau;
 
   T x[K][DX], p[K][DX], z[K][DX], y[K][DY], q[K][DY], w[K][DY];
   T x0[DX], z0[DX], y0[DY], w0[DY];
@@ -948,6 +954,27 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game(KArgs<
   int Np = 0, k = 0;
   int64_t pt = -1;
   bool active = false;
+  // recipe state (dead code without kRec)
+  int phase = 0, kp = 0;
+  T prev_val = T(0);
+  bool have_prev = false;
+
+  // per-node step sizes of the current point
+  auto set_steps = [&]() __attribute__((always_inline)) {
+    sd = sigma * delta;
+    td = tau * delta;
+    T ip, iq;
+    F::dual_scales(P, sd, ip, iq);
+#pragma unroll
+    for (int kk = 0; kk < K; kk++) {
+      const int j = 1 + l * K + kk;
+      tj[kk] = (j < Np) ? tau : T(0);
+      tdj[kk] = (j < Np) ? td : T(0);
+      sdj[kk] = (j <= Np) ? sd : T(0);
+      ipj[kk] = (j <= Np) ? ip : T(1);
+      iqj[kk] = (j <= Np) ? iq : T(1);
+    }
+  };
 
   auto pop_and_init = [&]() {
     int idx = 0;
@@ -961,9 +988,14 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game(KArgs<
     if (a.pops && l == 0) atomicAdd(a.pops + pt, 1);
     Np = a.N[pt];
     delta = a.t[pt] / T(Np);
-    sd = sigma * delta;
-    td = tau * delta;
     k = 0;
+    if constexpr (kRec) {
+      phase = 0;
+      kp = 0;
+      have_prev = false;
+      sigma = a.sigma;
+      tau = a.tau;
+    }
     T xt[D];
 #pragma unroll
     for (int i = 0; i < D; i++) xt[i] = a.x[pt * a.d + i];
@@ -994,17 +1026,40 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game(KArgs<
       y0[i] = (l == 0) ? init_x(xt[DX + i], a.seed, pt, kArrY, 0, i) : T(0);
       w0[i] = y0[i];
     }
-    T ip, iq;
-    F::dual_scales(P, sd, ip, iq);
+    set_steps();
+  };
+
+  // The value: the Lagrangian at the current iterate, g(x_0, y_0) +
+  // sum_j (<p_j, x_j - x_{j-1}> - <q_j, y_j - y_{j-1}>) - delta sum_j H,
+  // summed over the group; `bad` flags a non-finite entry.
+  auto lagrangian = [&](int& bad) __attribute__((always_inline)) {
+    T xprev[DX], yprev[DY];
+#pragma unroll
+    for (int i = 0; i < DX; i++) xprev[i] = group_prev_fill<L>(x[K - 1][i], l, x0[i]);
+#pragma unroll
+    for (int i = 0; i < DY; i++) yprev[i] = group_prev_fill<L>(y[K - 1][i], l, y0[i]);
+    T acc = T(0);
+    bad = 0;
 #pragma unroll
     for (int kk = 0; kk < K; kk++) {
       const int j = 1 + l * K + kk;
-      tj[kk] = (j < Np) ? tau : T(0);
-      tdj[kk] = (j < Np) ? td : T(0);
-      sdj[kk] = (j <= Np) ? sd : T(0);
-      ipj[kk] = (j <= Np) ? ip : T(1);
-      iqj[kk] = (j <= Np) ? iq : T(1);
+      if (j <= Np) {
+        T s = T(0);
+#pragma unroll
+        for (int i = 0; i < DX; i++) s += p[kk][i] * (x[kk][i] - (kk == 0 ? xprev[i] : x[kk - 1][i]));
+#pragma unroll
+        for (int i = 0; i < DY; i++) s -= q[kk][i] * (y[kk][i] - (kk == 0 ? yprev[i] : y[kk - 1][i]));
+        acc += s - delta * F::H(P, x[kk], y[kk], p[kk], q[kk]);
+        bad |= !(all_finite<T, DX>(x[kk]) && all_finite<T, DX>(p[kk]) && all_finite<T, DY>(y[kk]) &&
+                 all_finite<T, DY>(q[kk]));
+      }
     }
+    if (l == 0) {
+      acc += F::g(P, x0, y0);
+      bad |= !(all_finite<T, DX>(x0) && all_finite<T, DY>(y0));
+    }
+    bad = group_or<L>(bad);
+    return group_sum<L>(acc);
   };
 
   pop_and_init();
@@ -1108,8 +1163,53 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game(KArgs<
     const T rxs = group_sum<L>(rx), rps = group_sum<L>(rp), rys = group_sum<L>(ry), rqs = group_sum<L>(rq);
     const bool fin = M<T>::finite(rxs + rps + rys + rqs);
     const bool small = (rxs < a.tol) && (rps < a.tol) && (rys < a.tol) && (rqs < a.tol);
-    const bool done = active && (!fin || (!a.fixed && small) || k >= a.max_iter);
+    bool done;
+    int st = kMaxIter;
+    if constexpr (!kRec) {
+      done = active && (!fin || (!a.fixed && small) || k >= a.max_iter);
+    } else {
+      // recipes (tolerance mode): cap -> raise sigma and continue, up to
+      // a.restarts times; after the first cap also stop on a stalled value
+      kp++;
+      done = false;
+      if (active) {
+        if (!fin) {
+          done = true;
+          st = kNonFinite;
+        } else if (small) {
+          done = true;
+          st = kConverged;
+        } else {
+          if (phase >= 1 && a.value_tol > T(0)) {
+            int bad_v = 0;
+            const T val = lagrangian(bad_v);
+            if (have_prev && M<T>::fabs_(val - prev_val) <= a.value_tol * M<T>::fmax(M<T>::fabs_(val), T(1))) {
+              done = true;
+              st = kValueStalled;
+            }
+            prev_val = val;
+            have_prev = true;
+          }
+          if (!done && kp >= a.max_iter) {
+            if (phase < a.restarts) {
+              phase++;
+              kp = 0;
+              have_prev = false;
+              sigma += a.sigma_inc;
+              tau = a.sigma * a.tau / sigma;
+              set_steps();
+            } else {
+              done = true;
+              st = kMaxIter;
+            }
+          }
+        }
+      }
+    }
     if (done) {
+      // the value, as lagrangian() computes it, written out here: calling the
+      // lambda in this place measured 6 % slower for the plain kernel (the
+      // compiler schedules the iteration differently)
       T xprev[DX], yprev[DY];
 #pragma unroll
       for (int i = 0; i < DX; i++) xprev[i] = group_prev_fill<L>(x[K - 1][i], l, x0[i]);
@@ -1137,7 +1237,7 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_game(KArgs<
       }
       acc = group_sum<L>(acc);
       bad = group_or<L>(bad);
-      int st = !fin ? kNonFinite : (small ? kConverged : kMaxIter);
+      if constexpr (!kRec) st = !fin ? kNonFinite : (small ? kConverged : kMaxIter);
       if (bad || !M<T>::finite(acc)) st = kNonFinite;
       if (l == 0) {
         a.phi[pt] = acc;

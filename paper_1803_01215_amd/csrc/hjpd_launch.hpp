@@ -29,6 +29,8 @@ const void* group_ptr(int variant) {
       if (variant != kVarPlain) return nullptr;
       return reinterpret_cast<const void*>(&k_group_game_hopf<T, F, L, K>);
     } else {
+      // Algorithm 3; with the sigma and value-change recipes (kVarRecipe)
+      if (variant == kVarRecipe) return reinterpret_cast<const void*>(&k_group_game<T, F, L, K, true>);
       if (variant != kVarPlain) return nullptr;
       return reinterpret_cast<const void*>(&k_group_game<T, F, L, K>);
     }
@@ -47,7 +49,8 @@ const void* group_ptr(int variant) {
 }
 
 // variant: kVarPlain (Algorithm 1 / 2 / 3), kVarRecipe (control kernel with
-// the robustness recipes), kVarMix (weighted Euler discretisations),
+// the robustness recipes; the game kernel with the sigma and value-change
+// recipes), kVarMix (weighted Euler discretisations),
 // kVarShift / kVarShiftHopf (Algorithm 1 / 2 in the shifted layout, eikonal
 // family), kVarGameLax (Algorithm 3 for the scalar-player game).
 template <typename T, class F>

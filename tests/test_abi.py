@@ -80,6 +80,9 @@ def test_create_rejects_invalid_descriptors(lib, bad):
     dict(flags=64 | 1),                                  # no weighted discretisation on the plain kernel
     dict(flags=128 | 32),                                # nor with the Hopf formulation
     dict(flags=64, starts=3),                            # nor with the recipes
+    dict(H=2, d=12, d_y=6, g=2, starts=2),               # one start on the game path
+    dict(H=4, g=4, d=2, d_y=1, restarts=1),              # no recipes for Isaacs' game
+    dict(H=2, d=12, d_y=6, g=2, restarts=1, flags=1),    # nor on the plain kernel
     dict(H=4, g=4, d=2, d_y=1, flags=32 | 1),            # Isaacs: no plain kernel, Algorithm 4
     dict(H=4, g=4, d=2, d_y=1, flags=1),                 # nor Algorithm 3
     dict(H=4, g=4, d=3, d_y=1, flags=32),                # scalar players only
@@ -102,10 +105,12 @@ def test_null_arguments(lib):
     assert lib.hjpd_get_timing(None, ctypes.byref(ms), None) == hjpd.HJPD_EINVAL
 
 
-@pytest.mark.parametrize("ok", [dict(), dict(H=4, g=4, d=2, d_y=1), dict(H=4, g=4, d=2, d_y=1, flags=32)])
+@pytest.mark.parametrize("ok", [dict(), dict(H=4, g=4, d=2, d_y=1), dict(H=4, g=4, d=2, d_y=1, flags=32),
+                                dict(H=2, d=12, d_y=6, g=2, restarts=2, sigma_inc=20.0, value_tol=1e-9)])
 def test_valid_descriptor_without_gpu_reports_device_error(lib, ok):
     """Descriptors that validate (eikonal; Isaacs' game by Algorithm 3 and by
-    Algorithm 4) get as far as the device query."""
+    Algorithm 4; the pursuit-evasion game with the sigma and value-change
+    recipes) get as far as the device query."""
     import torch
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")

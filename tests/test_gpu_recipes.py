@@ -176,3 +176,96 @@ def test_recipes_largest_tile_f64(oracle_mod):
     w.t = np.full(w.n, 0.8)
     w.max_iter = 400
     _compare(oracle_mod, w, "f64", 0.99, restarts=2, sigma_inc=1.0)
+
+
+# ---- the pursuit-evasion game (Algorithm 3): sigma raised at the cap and the
+# value-change stop, as section 6.2 applies them to a game; one start --------
+
+def _pursuit(n, cap):
+    w = W.pursuit12().subset(np.arange(n))
+    w.max_iter = cap
+    return w
+
+
+def test_game_sigma_raise_pursuit_f64(oracle_mod):
+    """48 pursuit-evasion points (N 16..96) with a 1,500-iteration cap and up to
+    three raises of sigma by 20: most points pass at least one cap, and the GPU
+    stops where the oracle does, with its value and both trajectories."""
+    w = _pursuit(48, 1500)
+    g, o, same = _compare(oracle_mod, w, "f64", 0.95, restarts=3, sigma_inc=20.0)
+    assert np.mean(o.iters > 1500) > 0.5
+    assert np.array_equal(g["status"], o.status)
+
+
+def test_game_value_change_pursuit_f64(oracle_mod):
+    """tol 1e-30 (the residual rule never fires): after the first 2,000-iteration
+    cap the value-change rule stops the points whose value has settled, the
+    others run through five phases to the last cap."""
+    w = _pursuit(32, 2000)
+    w.tol = 1e-30
+    g, o, same = _compare(oracle_mod, w, "f64", 0.95, restarts=5, sigma_inc=0.0, value_tol=1e-12)
+    assert np.any(g["status"] == 4) and np.any(g["status"] == 1)
+
+
+def _recipe_floor(O, w, o, **rec):
+    """Per point, how far the oracle's own binary32 rounding sequences of the
+    same recipe run (the binary32 builds without and with FMA contraction, the
+    first also on x (1 +- 2^-23)) land from the oracle: value, x-trajectory and
+    p-trajectory floors, and whether every one of them stops at the oracle's
+    iteration with its status (else the point's stop is not determined by the
+    arithmetic and it is not compared)."""
+    pb = O.Problem(w.H, w.g, w.d, w.d_y, _round(w.hp, "f32"), _round(w.gp, "f32"))
+    kw = dict(sigma=float(_round(w.sigma, "f32")), tau=float(_round(w.tau, "f32")), theta=w.theta,
+              tol=float(_round(w.tol, "f32")), max_iter=w.max_iter, seed=w.init_seed, N_max=w.N_max, ids=w.ids,
+              traj=True, **rec)
+    x = _round(w.x, "f32")
+    t = _round(w.t, "f32")
+    fv, fx, fp = np.zeros(w.n), np.zeros(w.n), np.zeros(w.n)
+    det = np.ones(w.n, bool)
+    for v, sc in (("f32", 1.0), ("f32fma", 1.0), ("f32", 1.0 + 2.0 ** -23), ("f32", 1.0 - 2.0 ** -23)):
+        r = O.solve_variant(v, pb, x * sc, t, w.N, **kw)
+        det &= (r.iters == o.iters) & (r.status == o.status)
+        fv = np.maximum(fv, rel_err(r.phi, o.phi))
+        fx = np.maximum(fx, traj_err(r.x_traj, o.x_traj, w.N))
+        fp = np.maximum(fp, traj_err(r.p_traj, o.p_traj, w.N))
+    return fv, fx, fp, det
+
+
+def test_game_recipes_pursuit_f32(oracle_mod):
+    """FP32 at the headline's tolerance, cap 2,500 and two raises of sigma by
+    20.  Points where the GPU and the oracle stop at the same iteration with
+    the same status (at least 90 %) are compared element by element within
+    max(1e-4, 10 x the rounding floor of the same recipe run); points where
+    the oracle's own binary32 rounding sequences stop elsewhere have no
+    determined stop and are counted (at most 10 %)."""
+    w = _pursuit(64, 2500)
+    rec = dict(restarts=2, sigma_inc=20.0)
+    g = _gpu(w, "f32", **rec)
+    o = _oracle(oracle_mod, w, "f32", **rec)
+    fv, fx, fp, det = _recipe_floor(oracle_mod, w, o, **rec)
+    same = (g["iters"] == o.iters) & (g["status"] == o.status)
+    print("[pursuit12 f32 %s] statuses gpu %s oracle %s; same stop at %d of %d, determined %d" % (
+        rec, np.bincount(g["status"], minlength=5), np.bincount(o.status, minlength=5), same.sum(), w.n, det.sum()),
+        flush=True)
+    assert same.mean() >= 0.9 and det.mean() >= 0.9
+    c = same & det
+    ev = rel_err(g["phi"], o.phi)[c]
+    ex = traj_err(g["x_traj"][c], o.x_traj[c], w.N[c])
+    ep = traj_err(g["p_traj"][c], o.p_traj[c], w.N[c])
+    print("  phi %.3g x %.3g p %.3g; floors max phi %.3g x %.3g p %.3g" % (
+        ev.max(), ex.max(), ep.max(), fv[c].max(), fx[c].max(), fp[c].max()), flush=True)
+    assert np.all(ev <= np.maximum(1e-4, 10 * fv[c]))
+    assert np.all(ex <= np.maximum(1e-4, 10 * fx[c]))
+    assert np.all(ep <= np.maximum(1e-4, 10 * fp[c]))
+
+
+def test_game_recipes_off_match_plain_solve():
+    """A restart budget that is never used (cap above every point's stop) runs
+    the game recipe kernel through the same iterations as the plain one."""
+    w = _pursuit(96, 60000)
+    a = gpu_solve(w, dtype="f64", traj=True)
+    b = _gpu(w, "f64", restarts=1, sigma_inc=0.0)
+    conv = a["status"] == 0
+    assert conv.mean() > 0.9
+    assert np.array_equal(a["iters"][conv], b["iters"][conv].astype(a["iters"].dtype))
+    assert np.max(rel_err(b["phi"][conv], a["phi"][conv])) < 1e-12
