@@ -38,7 +38,8 @@
  *
  * Forward Euler and trapezoidal discretisations (section 4.1, eq.
  * disclaxFE; the remark after Algorithm 1 that averaging the forward and
- * backward Euler approximations gives a trapezoidal rule), eikonal family.
+ * backward Euler approximations gives a trapezoidal rule), eikonal and
+ * quadrotor families.
  * Writing p_j for the costate of the interval (j-1, j), j = 1..N, all three
  * discretisations are one saddle problem
  *
@@ -57,6 +58,10 @@
  *   x_j <- x_j - tau (p_j - p_{j+1}) + tau delta (wr grad_x H(x_j,p_j) + wl grad_x H(x_j,p_{j+1}))
  *
  * For H = c(x)|p| the p-step is a shrink by sigma delta (wl c(x_{j-1}) + wr c(x_j)).
+ * For the quadrotor H is quadratic in p, and so is the weighted sum: the
+ * p-step is one linear solve, (I + lam (wl b_{j-1} b_{j-1}^T + wr b_j b_j^T))
+ * in the velocity costate, the drift terms weighted, the body-rate costate
+ * scaled as in Algorithm 1 (its quadratic does not depend on x).
  *
  * Game Hopf formulation (section 4.2, eq. discgenlaxhopfdghopf; Algorithm 4)
  * for a separable convex-concave g(x,y) = e(x) + h(y), with e* the convex
@@ -324,6 +329,49 @@ static void quad_prox_p(const double *hp, const double *x, const double *v, doub
     for (int i = 0; i < 3; i++) p[3 + i] = wv[i] - coef * b[i];
     /* body-rate costate: (1 + lam / J_i^2) p = v */
     for (int i = 0; i < 3; i++) p[9 + i] = v[9 + i] / (1.0 + lam / (hp[1 + i] * hp[1 + i]));
+}
+
+/* argmin_p lam (wl H(xa,p) + wr H(xb,p)) + |p - v|^2 / 2: the weighted
+ * Hamiltonians are quadratic in p, so the minimiser solves one linear
+ * system, written out here block by block (the 3 x 3 velocity block by
+ * Gaussian elimination; it is symmetric positive definite). */
+static void quad_prox_p_mix(const double *hp, const double *xa, const double *xb, double wl, double wr,
+                            const double *v, double lam, double *p)
+{
+    double Wa[3][3], Wb[3][3], ba[3], bb[3];
+    quad_W(hp, xa, Wa, NULL, NULL);
+    quad_W(hp, xb, Wb, NULL, NULL);
+    quad_b(hp, xa, ba, NULL);
+    quad_b(hp, xb, bb, NULL);
+    /* position costate: linear terms -lam (wl <p_r, v_a> + wr <p_r, v_b>) */
+    for (int i = 0; i < 3; i++) p[i] = v[i] + lam * (wl * xa[3 + i] + wr * xb[3 + i]);
+    /* angle costate: linear terms -lam (wl <p_eta, W_a omega_a> + wr <p_eta, W_b omega_b>) */
+    for (int r = 0; r < 3; r++) {
+        double wa = 0.0, wb = 0.0;
+        for (int c = 0; c < 3; c++) {
+            wa += Wa[r][c] * xa[9 + c];
+            wb += Wb[r][c] * xb[9 + c];
+        }
+        p[6 + r] = v[6 + r] + lam * (wl * wa + wr * wb);
+    }
+    /* velocity costate: (I + lam (wl ba ba^T + wr bb bb^T)) p_v = v_v - lam (wl + wr) g_z e3 */
+    double A[3][4];
+    for (int r = 0; r < 3; r++) {
+        for (int c = 0; c < 3; c++) A[r][c] = (r == c ? 1.0 : 0.0) + lam * (wl * ba[r] * ba[c] + wr * bb[r] * bb[c]);
+        A[r][3] = v[3 + r] - (r == 2 ? lam * (wl + wr) * hp[4] : 0.0);
+    }
+    for (int c = 0; c < 3; c++)
+        for (int r = c + 1; r < 3; r++) {
+            double f = A[r][c] / A[c][c];
+            for (int k = c; k < 4; k++) A[r][k] -= f * A[c][k];
+        }
+    for (int r = 2; r >= 0; r--) {
+        double s2 = A[r][3];
+        for (int c = r + 1; c < 3; c++) s2 -= A[r][c] * p[3 + c];
+        p[3 + r] = s2 / A[r][r];
+    }
+    /* body-rate costate: (1 + lam (wl + wr) / J_i^2) p = v */
+    for (int i = 0; i < 3; i++) p[9 + i] = v[9 + i] / (1.0 + lam * (wl + wr) / (hp[1 + i] * hp[1 + i]));
 }
 
 static void quad_grad_x(const double *hp, const double *x, const double *p, double *gx)
@@ -1043,7 +1091,7 @@ static void solve_hopf_point(const or_problem *pb, const or_opts *o, long pt, co
 
 /* ------------------------------------------------------------------ */
 /* One query point: weighted Euler discretisations (forward Euler,     */
-/* trapezoid; backward Euler at wl = 0, wr = 1), eikonal family.       */
+/* trapezoid; backward Euler at wl = 0, wr = 1), eikonal and quadrotor. */
 /* ------------------------------------------------------------------ */
 
 /* The Lagrangian of the weighted saddle at (x, p). */
@@ -1080,12 +1128,17 @@ static void solve_mix_point(const or_problem *pb, const or_opts *o, long pt, con
 
     int k = 0, st = OR_PT_MAXITER;
     for (;;) {
-        /* p-step: shrink by sigma delta times the interval's weighted speed */
+        /* p-step: the prox of the interval's weighted Hamiltonians (eikonal: a
+           shrink by sigma delta times the weighted speed; quadrotor: a linear solve) */
         for (int i = 0; i < d; i++) pn[i] = 0.0;
         for (int j = 1; j <= N; j++) {
-            double c_eff = wl * cnorm_c(pb->hp, &x[(j - 1) * d]) + wr * cnorm_c(pb->hp, &x[j * d]);
             for (int i = 0; i < d; i++) v[i] = p[j * d + i] + o->sigma * (z[j * d + i] - z[(j - 1) * d + i]);
-            or_shrink2(v, o->sigma * delta * c_eff, d, &pn[j * d]);
+            if (pb->H == OR_H_QUADROTOR) {
+                quad_prox_p_mix(pb->hp, &x[(j - 1) * d], &x[j * d], wl, wr, v, o->sigma * delta, &pn[j * d]);
+            } else {
+                double c_eff = wl * cnorm_c(pb->hp, &x[(j - 1) * d]) + wr * cnorm_c(pb->hp, &x[j * d]);
+                or_shrink2(v, o->sigma * delta * c_eff, d, &pn[j * d]);
+            }
         }
         /* node 0: proximal-gradient step (gradient of -delta wl H(x_0, p_1), prox of g) */
         or_grad_x_H(pb, &x[0], &pn[d], 0.0, ga);
@@ -1414,7 +1467,9 @@ static int solve_batch(const or_problem *pb, long n, const double *x, const doub
     if (hopf && !isaacs && (game || !((pb->H == OR_H_CNORM && (pb->g == OR_G_NORM || pb->g == OR_G_QUAD_SHIFT)) ||
                                       (pb->H == OR_H_QUADROTOR && pb->g == OR_G_QUAD_SHIFT))))
         return -1;
-    if (mix && (game || hopf || recipe || pb->H != OR_H_CNORM || !(pb->g == OR_G_NORM || pb->g == OR_G_QUAD_SHIFT)))
+    if (mix && (game || hopf || recipe ||
+                !((pb->H == OR_H_CNORM && (pb->g == OR_G_NORM || pb->g == OR_G_QUAD_SHIFT)) ||
+                  (pb->H == OR_H_QUADROTOR && pb->g == OR_G_QUAD_SHIFT))))
         return -1;
     or_opts o = { sigma, tau, theta, tol, max_iter, fixed_iters, seed, N_max, 1, 0, 0.0, 0.0 };
     if (recipe) {
@@ -1497,7 +1552,7 @@ int or_solve_recipe(const or_problem *pb, long n, const double *x, const double 
 }
 
 /* Weighted Euler discretisations (forward Euler wl = 1, wr = 0; trapezoid
- * wl = wr = 1/2; backward Euler wl = 0, wr = 1), eikonal family. */
+ * wl = wr = 1/2; backward Euler wl = 0, wr = 1), eikonal and quadrotor families. */
 int or_solve_mix(const or_problem *pb, long n, const double *x, const double *t, const int *N,
                  double sigma, double tau, double theta, double tol, int max_iter, int fixed_iters,
                  uint64_t seed, int N_max, const int64_t *ids, double wl, double wr, double *phi, int *iters,

@@ -351,7 +351,8 @@ def solve(pb: Problem, x, t, N, *, sigma, tau, theta=1.0, tol=1e-8, max_iter=500
     pursuit-evasion game with starts = 1): see the
     C source's header comment.  disc selects the time discretisation of the
     Lax path: "be" backward Euler (Algorithm 1), "fe" forward Euler,
-    "trap" the trapezoidal average of the two (eikonal family), or a pair
+    "trap" the trapezoidal average of the two (eikonal and quadrotor
+    families), or a pair
     (wl, wr) of Hamiltonian weights; "be" is Algorithm 1 itself, any other
     value runs the weighted-discretisation solver.
     """

@@ -640,6 +640,71 @@ def test_quadrotor_fixed_point_is_stationary_for_independent_lagrangian(oracle_m
     assert abs(Lf(Z) - r.phi[0]) < 1e-9 * max(1, abs(r.phi[0]))
 
 
+def _quad_lagrangian_w(Z, N, hp, x_t, delta, wl, wr):
+    """The weighted Lax saddle of the quadrotor written out here:
+    g(x_0) + sum_j <p_j, x_j - x_{j-1}> - delta sum_j (wl H(x_{j-1}, p_j) + wr H(x_j, p_j)),
+    H = -<p, f0> + |B^T p|^2 / 2 from the dynamics in this file, g = |x|^2/2."""
+    xs = np.vstack([Z[:N * 12].reshape(N, 12), x_t])
+    ps = Z[N * 12:].reshape(N, 12)
+
+    def H(xx, pp):
+        f0 = quad_f_phys(xx, np.zeros(4), hp)
+        B = np.stack([quad_f_phys(xx, e, hp) - f0 for e in np.eye(4)], axis=1)
+        return -pp @ f0 + 0.5 * np.sum((B.T @ pp) ** 2)
+    L = 0.5 * xs[0] @ xs[0]
+    for j in range(1, N + 1):
+        L += ps[j - 1] @ (xs[j] - xs[j - 1]) - delta * (wl * H(xs[j - 1], ps[j - 1]) + wr * H(xs[j], ps[j - 1]))
+    return L
+
+
+@pytest.mark.parametrize("disc,w", [("fe", (1.0, 0.0)), ("trap", (0.5, 0.5))])
+def test_quadrotor_weighted_fixed_point_is_stationary(oracle_mod, disc, w):
+    """Forward Euler and trapezoid for the quadrotor (section 4.1, eq.
+    disclaxFE; the averaged rule): at the oracle's converged iterate the
+    weighted saddle written independently above has zero gradient in every
+    free block (x_0..x_{N-1}, p_1..p_N), and its value is the oracle's.  A
+    wrong weight, a weight on the wrong node, or a missing rank in the
+    velocity block of the p-step moves the fixed point off stationarity."""
+    rng = _rng(33)
+    hp = W.QUAD_PARAMS
+    pb = oracle_mod.Problem(W.H_QUADROTOR, W.G_QUAD_SHIFT, 12, 0, hp, np.zeros(13))
+    for _ in range(2):
+        x = rng.uniform(-0.6, 0.6, 12)
+        N, t = 8, 0.4
+        r = oracle_mod.solve(pb, x[None], t, N, sigma=2.0, tau=0.125, tol=1e-24, max_iter=300000, seed=7, traj=True,
+                             disc=disc)
+        assert r.status[0] == 0
+        Z = np.concatenate([r.x_traj[0, :N].ravel(), r.p_traj[0, 1:].ravel()])
+        Lf = lambda z: _quad_lagrangian_w(z, N, hp, x, t / N, *w)  # noqa: E731
+        g = _fd_grad(Lf, Z, h=1e-6)
+        assert np.max(np.abs(g)) < 1e-6 * max(1, np.max(np.abs(Z))), np.max(np.abs(g))
+        assert abs(Lf(Z) - r.phi[0]) < 1e-9 * max(1, abs(r.phi[0]))
+        # the backward-Euler weighting of the same saddle is not stationary there
+        Lb = lambda z: _quad_lagrangian_w(z, N, hp, x, t / N, 0.0, 1.0)  # noqa: E731
+        assert np.max(np.abs(_fd_grad(Lb, Z, h=1e-6))) > 1e-4
+
+
+def test_quadrotor_weighted_be_is_algorithm_1(oracle_mod):
+    """The weighted solver at the backward-Euler weights (0, 1) runs Algorithm
+    1's iteration: after 2,000 fixed iterations its values and trajectories
+    agree with Algorithm 1's to 1e-9 wherever Algorithm 1's own binary64 FMA
+    build does (the p-step is the same minimiser, found by a linear solve
+    instead of Sherman-Morrison, so the two differ by rounding, which the
+    quadrotor's flat attitude directions amplify at a few points)."""
+    w = W.quadrotor12().subset(np.arange(24))
+    pb = oracle_mod.Problem(w.H, w.g, w.d, w.d_y, w.hp, w.gp)
+    kw = dict(sigma=w.sigma, tau=w.tau, tol=w.tol, max_iter=2000, fixed_iters=True, seed=w.init_seed, traj=True)
+    a = oracle_mod.solve(pb, w.x, w.t, w.N, **kw)
+    b = oracle_mod.solve(pb, w.x, w.t, w.N, disc=(0.0, 1.0), **kw)
+    f = oracle_mod.solve_variant("f64fma", pb, w.x, w.t, w.N, **kw)
+    rel = lambda u, v: np.abs(u - v) / np.maximum(np.abs(v), 1)  # noqa: E731
+    tr = lambda u, v: np.max(np.abs(u - v), axis=(1, 2)) / np.maximum(np.max(np.abs(v), axis=(1, 2)), 1)  # noqa: E731
+    cond = (rel(f.phi, a.phi) < 1e-10) & (tr(f.x_traj, a.x_traj) < 1e-10) & (tr(f.p_traj, a.p_traj) < 1e-10)
+    assert cond.mean() >= 0.75
+    assert np.max(rel(b.phi, a.phi)[cond]) < 1e-9
+    assert np.max(tr(b.x_traj, a.x_traj)[cond]) < 1e-9 and np.max(tr(b.p_traj, a.p_traj)[cond]) < 1e-9
+
+
 def test_value_nonincreasing_in_t_for_nonnegative_H(oracle_mod):
     """H = c(x)||p|| >= 0: a longer horizon reaches more initial states, so
     phi(x, t) cannot increase with t."""
