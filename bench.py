@@ -541,6 +541,14 @@ def main():
         qp = B.plain(qs, f32)
         qb = B.batched(qs, f32, 3, 1)
         qb.pop("status"); qb.pop("iters")
+        # the weighted discretisations (forward Euler, trapezoid), default plan
+        qw = {}
+        for key, kw in (("forward_euler", dict(disc="fe")), ("trapezoid", dict(disc="trap"))):
+            r = B.batched(wq, f32, 1, 1, traj=True, **kw)
+            qw[key] = {"ms_per_step": r["ms"], "converged": r["converged"], "value": r["solves_per_s"],
+                       "status_counts": np.bincount(r["status"], minlength=4).tolist()}
+        log("quadrotor12 forward Euler %.1f ms, trapezoid %.1f ms" % (qw["forward_euler"]["ms_per_step"],
+                                                                      qw["trapezoid"]["ms_per_step"]))
         rec["quadrotor12"] = {
             "workload": "quadrotor12: 12-state quadrotor-like control, cost |u|^2/2, g=|x|^2/2, 131,072 points "
                         "x~U[-1,1]^12, t~U[0.5,3], N=ceil(t/0.05), Algorithm 1, tol 1e-6, cap 20,000, both "
@@ -555,7 +563,7 @@ def main():
             "plain": dict(qp, sample="first %d points" % qs.n),
             "batched_same_sample": dict(qb, sample="first %d points" % qs.n),
             "speedup_vs_plain": qb["solves_per_s"] / qp["solves_per_s"] if qp["solves_per_s"] > 0 else None,
-            "cpu_baseline": oracle_sample(wq, 512) if cpu else None}
+            "cpu_baseline": oracle_sample(wq, 512) if cpu else None, **qw}
         del q
 
         # ---- C2: cnorm10 (state-dependent eikonal, d = 10), FP32 and FP64 ------------------------

@@ -173,9 +173,11 @@ enum {
                                     Hamiltonian sums (the remark after Algorithm 1), i.e.
                                     - delta sum_j (H(x_{j-1}, p_j) + H(x_j, p_j)) / 2, second-order in
                                     delta where both Euler rules are first-order.  HJPD_FORWARD_EULER and
-                                    HJPD_TRAPEZOID are built for H = CNORM with g = NORM or QUAD_SHIFT on the
-                                    persistent control path (not with HJPD_PLAIN, HJPD_HOPF or the recipes:
-                                    HJPD_EUNSUPPORTED); setting both is HJPD_EINVAL. */,
+                                    HJPD_TRAPEZOID are built for H = CNORM with g = NORM or QUAD_SHIFT and
+                                    for H = QUADROTOR with g = QUAD_SHIFT (FP64: tiles of at most two nodes
+                                    per lane), on the persistent control path (not with HJPD_PLAIN,
+                                    HJPD_HOPF or the recipes: HJPD_EUNSUPPORTED); setting both is
+                                    HJPD_EINVAL. */,
     HJPD_NO_REFILL = 1u << 8      /* persistent kernels without retire and refill: every lane group solves
                                     exactly one point and the launch has a group for every point, so a wave
                                     stays resident until its slowest point stops (the same kernels, layout and

@@ -573,10 +573,12 @@ int validate_desc(const hjpd_desc* d) {
       d->H != HJPD_H_ISAACS)
     return fail(HJPD_EUNSUPPORTED, "the Hopf formulation is built for CNORM with NORM or QUAD_SHIFT, for QUADROTOR "
                                    "with QUAD_SHIFT (persistent kernel), and for ISAACS");
-  if (has_mix(*d) && (game || d->H != HJPD_H_CNORM || !(d->g == HJPD_G_NORM || d->g == HJPD_G_QUAD_SHIFT) ||
+  if (has_mix(*d) && (game ||
+                      !((d->H == HJPD_H_CNORM && (d->g == HJPD_G_NORM || d->g == HJPD_G_QUAD_SHIFT)) ||
+                        (d->H == HJPD_H_QUADROTOR && d->g == HJPD_G_QUAD_SHIFT)) ||
                       (d->flags & (HJPD_PLAIN | HJPD_HOPF)) || has_recipe(*d)))
-    return fail(HJPD_EUNSUPPORTED,
-                "forward Euler and trapezoid are built for CNORM with NORM or QUAD_SHIFT on the persistent Lax path");
+    return fail(HJPD_EUNSUPPORTED, "forward Euler and trapezoid are built for CNORM with NORM or QUAD_SHIFT and for "
+                                   "QUADROTOR with QUAD_SHIFT, on the persistent Lax path");
   if (d->H == HJPD_H_PURSUIT_EVASION) {
     if (!(game && d->g == HJPD_G_PAIR_DIST && d->d == 12 && d->d_y == 6))
       return fail(HJPD_EUNSUPPORTED, "pursuit-evasion needs d = 12, d_y = 6, g = PAIR_DIST");

@@ -318,6 +318,7 @@ struct Quad {
   static constexpr bool kHopf = false;      // no Hopf step in the plain kernel
   static constexpr bool kHopfGroup = true;  // Hopf formulation in k_group_control
   static constexpr bool kMix = false;
+  static constexpr bool kWeighted = true;  // forward Euler / trapezoid in k_group_control (kW)
 
   template <typename T> struct Par {
     T m_inv, gz, clamp;
@@ -438,6 +439,86 @@ struct Quad {
     g[7] = -dwt + bp * (C.db[1][0] * p[3] + C.db[1][1] * p[4] + C.db[1][2] * p[5]);
     g[8] = bp * (C.db[2][0] * p[3] + C.db[2][1] * p[4]);
     // -W^T p_eta
+    g[9] = -pe0;
+    g[10] = -(C.W01 * pe0 + C.W11 * pe1 + C.W21 * pe2);
+    g[11] = -(C.W02 * pe0 + C.W12 * pe1 + C.W22 * pe2);
+  }
+
+  // Weighted discretisations (forward Euler, trapezoid): an interval's dual
+  // step takes the Hamiltonians of both its end nodes, weighted (wl, wr).  What
+  // it needs of a node: its velocity, W(eta) omega and the thrust direction b.
+  template <typename T> struct Side {
+    T v[3], Ww[3], b[3];
+  };
+  template <typename T>
+  __device__ static void side(const T (&x)[12], const Cache<T>& C, Side<T>& S) {
+    const T w0 = x[9], w1 = x[10], w2 = x[11];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      S.v[i] = x[3 + i];
+      S.b[i] = C.b[i];
+    }
+    S.Ww[0] = w0 + C.W01 * w1 + C.W02 * w2;
+    S.Ww[1] = C.W11 * w1 + C.W12 * w2;
+    S.Ww[2] = C.W21 * w1 + C.W22 * w2;
+  }
+
+  // v -> argmin_p lam (wl H(x_a, p) + wr H(x_b, p)) + |p - v|^2/2, with the
+  // end nodes' side data Sa, Sb.  The drift terms are linear, the velocity
+  // block is (I + lam (wl a a^T + wr b b^T)) p_v = w: writing p_v = w -
+  // lam wl (a.p_v) a - lam wr (b.p_v) b gives two equations for a.p_v and
+  // b.p_v, solved by Cramer's rule; the body-rate scale is Algorithm 1's.
+  template <typename T>
+  __device__ static void dual_w(const Par<T>& P, const Side<T>& Sa, const Side<T>& Sb, T (&v)[12], T lam, T wl,
+                                T wr) {
+    const T la = lam * wl, lb = lam * wr;
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      v[i] += la * Sa.v[i] + lb * Sb.v[i];
+      v[6 + i] += la * Sa.Ww[i] + lb * Sb.Ww[i];
+    }
+    v[5] -= lam * P.gz;
+    const T aa = Sa.b[0] * Sa.b[0] + Sa.b[1] * Sa.b[1] + Sa.b[2] * Sa.b[2];
+    const T bb = Sb.b[0] * Sb.b[0] + Sb.b[1] * Sb.b[1] + Sb.b[2] * Sb.b[2];
+    const T ab = Sa.b[0] * Sb.b[0] + Sa.b[1] * Sb.b[1] + Sa.b[2] * Sb.b[2];
+    const T aw = Sa.b[0] * v[3] + Sa.b[1] * v[4] + Sa.b[2] * v[5];
+    const T bw = Sb.b[0] * v[3] + Sb.b[1] * v[4] + Sb.b[2] * v[5];
+    const T m11 = T(1) + la * aa, m22 = T(1) + lb * bb;
+    const T idet = M<T>::div(T(1), m11 * m22 - la * lb * ab * ab);
+    const T u = (m22 * aw - lb * ab * bw) * idet;  // a . p_v
+    const T t = (m11 * bw - la * ab * aw) * idet;  // b . p_v
+#pragma unroll
+    for (int i = 0; i < 3; i++) v[3 + i] -= la * u * Sa.b[i] + lb * t * Sb.b[i];
+#pragma unroll
+    for (int i = 0; i < 3; i++) v[9 + i] = M<T>::div(v[9 + i], T(1) + lam * P.iJ2[i]);
+  }
+
+  // wr grad_x H(x, p) + wl grad_x H(x, pn), x's geometry in C: the terms
+  // linear in the costate take wr p + wl pn, the thrust term (quadratic in
+  // p_v) is weighted per costate.
+  template <typename T>
+  __device__ static void grad_w(const Par<T>&, const T (&x)[12], const T (&p)[12], const T (&pn)[12], T wl, T wr,
+                                const Cache<T>& C, T (&g)[12]) {
+    const T w1 = x[10], w2 = x[11];
+    T q[12];
+#pragma unroll
+    for (int i = 0; i < 12; i++) q[i] = wr * p[i] + wl * pn[i];
+    const T bp = C.b[0] * p[3] + C.b[1] * p[4] + C.b[2] * p[5];
+    const T bq = C.b[0] * pn[3] + C.b[1] * pn[4] + C.b[2] * pn[5];
+    const T cp = wr * bp, cq = wl * bq;
+    g[0] = g[1] = g[2] = T(0);
+    g[3] = -q[0];
+    g[4] = -q[1];
+    g[5] = -q[2];
+    const T pe0 = q[6], pe1 = q[7], pe2 = q[8];
+    const T dwf = pe0 * (C.dWf01 * w1 + C.dWf02 * w2) + pe1 * (C.dWf11 * w1 + C.dWf12 * w2) +
+                  pe2 * (C.dWf21 * w1 + C.dWf22 * w2);
+    const T dwt = pe0 * (C.dWt01 * w1 + C.dWt02 * w2) + pe2 * (C.dWt21 * w1 + C.dWt22 * w2);
+    g[6] = -dwf + cp * (C.db[0][0] * p[3] + C.db[0][1] * p[4] + C.db[0][2] * p[5]) +
+           cq * (C.db[0][0] * pn[3] + C.db[0][1] * pn[4] + C.db[0][2] * pn[5]);
+    g[7] = -dwt + cp * (C.db[1][0] * p[3] + C.db[1][1] * p[4] + C.db[1][2] * p[5]) +
+           cq * (C.db[1][0] * pn[3] + C.db[1][1] * pn[4] + C.db[1][2] * pn[5]);
+    g[8] = cp * (C.db[2][0] * p[3] + C.db[2][1] * p[4]) + cq * (C.db[2][0] * pn[3] + C.db[2][1] * pn[4]);
     g[9] = -pe0;
     g[10] = -(C.W01 * pe0 + C.W11 * pe1 + C.W21 * pe2);
     g[11] = -(C.W02 * pe0 + C.W12 * pe1 + C.W22 * pe2);

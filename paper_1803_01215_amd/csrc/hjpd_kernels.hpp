@@ -116,12 +116,20 @@ __device__ __forceinline__ T init_x(T xt, uint64_t seed, int64_t pt, int arr, in
   return T(double(xt) + start_noise(seed, uint64_t(pt), arr, j, i));
 }
 
+// The per-node side data of the weighted discretisations (a placeholder for
+// kernels compiled without them).
+template <class F, typename T, bool W> struct SideOf { using type = int; };
+template <class F, typename T> struct SideOf<F, T, true> { using type = typename F::template Side<T>; };
+
 // ---------------------------------------------------------------------------
 // Persistent lane-group kernel, optimal-control path (Algorithm 1), for the
 // families whose dual step needs the whole neighbouring state (quadrotor).
-// The eikonal family runs k_group_control_shift below.
+// The eikonal family runs k_group_control_shift below.  kW: the weighted
+// discretisations (forward Euler, trapezoid; KArgs::wl, wr), where interval
+// j's dual step takes the Hamiltonians of x_{j-1} and x_j, x_j's gradient
+// collects both intervals it bounds, and x_0 takes a proximal-gradient step.
 // ---------------------------------------------------------------------------
-template <typename T, class F, int L, int K>
+template <typename T, class F, int L, int K, bool kW = false>
 __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_control(KArgs<T> a) {
   constexpr int D = F::D;
   const int lane = threadIdx.x & 63;
@@ -138,6 +146,7 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_control(KAr
   // difference operator), node 1's dual step is the joint prox with g*, and
   // the value has -g*(p_1) in place of g(x_0).  A uniform switch.
   const bool hopf = F::kHopfGroup && a.hopf;
+  const T wl = a.wl, wr = a.wr;  // kW: H weights at an interval's left / right node
 
   T x[K][D], p[K][D], z[K][D], x0[D], z0[D];
   T tj[K], tdj[K];  // per node: tau and tau*delta where the node takes a primal step, else 0
@@ -200,6 +209,26 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_control(KAr
     for (int i = 0; i < D; i++) zprev[i] = group_prev_fill<L>(z[K - 1][i], l, z0[i]);
     typename F::template Cache<T> C[K];
     T rp = T(0), rx = T(0);
+    // kW: every node's geometry first, then the side data of the node before
+    // the lane's first (the previous lane's last node, or node 0 in the
+    // group's first lane)
+    typename SideOf<F, T, kW>::type Sp;
+    if constexpr (kW) {
+#pragma unroll
+      for (int kk = 0; kk < K; kk++) F::geometry(P, x[kk], C[kk]);
+      typename F::template Cache<T> C0;
+      F::geometry(P, x0, C0);
+      typename F::template Side<T> S0, Sl;
+      F::side(x0, C0, S0);
+      F::side(x[K - 1], C[K - 1], Sl);
+      const T m0 = (l == 0) ? T(1) : T(0);  // fill is node 0's data in the first lane, 0 elsewhere
+#pragma unroll
+      for (int i = 0; i < 3; i++) {
+        Sp.v[i] = group_prev_fill<L>(Sl.v[i], l, m0 * S0.v[i]);
+        Sp.Ww[i] = group_prev_fill<L>(Sl.Ww[i], l, m0 * S0.Ww[i]);
+        Sp.b[i] = group_prev_fill<L>(Sl.b[i], l, m0 * S0.b[i]);
+      }
+    }
 #pragma unroll
     for (int kk = 0; kk < K; kk++) {
       T v[D];
@@ -209,7 +238,15 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_control(KAr
       if constexpr (F::kHopfGroup) {
         if (kk == 0 && hopf) F::hopf1_in(P, v, lam, sigma, l == 0);  // node 1: with g*
       }
-      F::dual(P, x[kk], v, lam, C[kk]);
+      if constexpr (kW) {
+        typename F::template Side<T> Sa, Sb;
+        if (kk == 0) Sa = Sp;
+        else F::side(x[kk - 1], C[kk - 1], Sa);
+        F::side(x[kk], C[kk], Sb);
+        F::dual_w(P, Sa, Sb, v, lam, wl, wr);
+      } else {
+        F::dual(P, x[kk], v, lam, C[kk]);
+      }
       if constexpr (!F::kZeroSafe) {
         // nodes past N keep p = 0
         const int j = 1 + l * K + kk;
@@ -229,7 +266,18 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_control(KAr
     for (int i = 0; i < D; i++) pnext[i] = group_next0<L>(p[0][i], l);
     if (l == 0 && !hopf) {
       T dx0[D];
-      F::step0(P, x0, p[0], tau, dx0);
+      if constexpr (kW) {
+        // proximal-gradient step: prox_{tau g}(x_0 + tau (p_1 + delta wl grad_x H(x_0, p_1)))
+        typename F::template Cache<T> C0;
+        F::geometry(P, x0, C0);
+        T g0[D], p1[D];
+        F::grad_w(P, x0, p[0], p[0], T(0), T(1), C0, g0);
+#pragma unroll
+        for (int i = 0; i < D; i++) p1[i] = p[0][i] + delta * wl * g0[i];
+        F::step0(P, x0, p1, tau, dx0);
+      } else {
+        F::step0(P, x0, p[0], tau, dx0);
+      }
 #pragma unroll
       for (int i = 0; i < D; i++) {
         rx += dx0[i] * dx0[i];
@@ -243,7 +291,14 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_control(KAr
 #pragma unroll
     for (int kk = 0; kk < K; kk++) {
       T g[D];
-      F::grad(P, x[kk], p[kk], C[kk], g);
+      if constexpr (kW) {
+        T pn[D];
+#pragma unroll
+        for (int i = 0; i < D; i++) pn[i] = (kk == K - 1) ? pnext[i] : p[kk + 1][i];
+        F::grad_w(P, x[kk], p[kk], pn, wl, wr, C[kk], g);
+      } else {
+        F::grad(P, x[kk], p[kk], C[kk], g);
+      }
 #pragma unroll
       for (int i = 0; i < D; i++) {
         const T pp = (kk == K - 1) ? pnext[i] : p[kk + 1][i];
@@ -273,7 +328,14 @@ __global__ void __launch_bounds__(256, (kFamWaves<T, F, K>)) k_group_control(KAr
           T s = T(0);
 #pragma unroll
           for (int i = 0; i < D; i++) s += p[kk][i] * (x[kk][i] - (kk == 0 ? xprev[i] : x[kk - 1][i]));
-          acc += s - delta * F::H(P, x[kk], p[kk]);
+          if constexpr (kW) {
+            T xl[D];
+#pragma unroll
+            for (int i = 0; i < D; i++) xl[i] = (kk == 0) ? xprev[i] : x[kk - 1][i];
+            acc += s - delta * (wl * F::H(P, xl, p[kk]) + wr * F::H(P, x[kk], p[kk]));
+          } else {
+            acc += s - delta * F::H(P, x[kk], p[kk]);
+          }
           bad |= !(all_finite<T, D>(x[kk]) && all_finite<T, D>(p[kk]));
         }
       }

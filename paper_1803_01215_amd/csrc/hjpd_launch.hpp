@@ -42,6 +42,12 @@ const void* group_ptr(int variant) {
       if (variant == kVarShiftHopf) return reinterpret_cast<const void*>(&k_group_control_shift<T, F, L, K, true>);
       return reinterpret_cast<const void*>(&k_group_control_shift<T, F, L, K, false>);
     } else {
+      // quadrotor: Algorithm 1 / 2, or the weighted rules (kVarMix; in FP64 built
+      // for at most two nodes per lane, the wider tiles spill most of their state)
+      if (variant == kVarMix) {
+        if constexpr (sizeof(T) == 8 && K > 2) return nullptr;
+        else return reinterpret_cast<const void*>(&k_group_control<T, F, L, K, true>);
+      }
       if (variant != kVarPlain) return nullptr;
       return reinterpret_cast<const void*>(&k_group_control<T, F, L, K>);
     }

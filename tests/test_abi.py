@@ -75,7 +75,7 @@ def test_create_rejects_invalid_descriptors(lib, bad):
     dict(H=1, d=12, flags=32 | 1),                       # quadrotor Hopf: persistent kernel only
     dict(H=1, d=12, g=0, flags=32),                      # quadrotor Hopf: QUAD_SHIFT g only
     dict(H=2, d=12, d_y=6, g=2, flags=32),               # no Hopf for the game path
-    dict(H=1, d=12, flags=64),                           # forward Euler: built for CNORM only
+    dict(H=1, d=12, g=0, flags=64),                      # forward Euler: quadrotor with QUAD_SHIFT g only
     dict(H=2, d=12, d_y=6, g=2, flags=128),              # no trapezoid for the game path
     dict(flags=64 | 1),                                  # no weighted discretisation on the plain kernel
     dict(flags=128 | 32),                                # nor with the Hopf formulation
@@ -106,11 +106,13 @@ def test_null_arguments(lib):
 
 
 @pytest.mark.parametrize("ok", [dict(), dict(H=4, g=4, d=2, d_y=1), dict(H=4, g=4, d=2, d_y=1, flags=32),
-                                dict(H=2, d=12, d_y=6, g=2, restarts=2, sigma_inc=20.0, value_tol=1e-9)])
+                                dict(H=2, d=12, d_y=6, g=2, restarts=2, sigma_inc=20.0, value_tol=1e-9),
+                                dict(H=1, d=12, flags=64), dict(H=1, d=12, flags=128, N_max=200)])
 def test_valid_descriptor_without_gpu_reports_device_error(lib, ok):
     """Descriptors that validate (eikonal; Isaacs' game by Algorithm 3 and by
     Algorithm 4; the pursuit-evasion game with the sigma and value-change
-    recipes) get as far as the device query."""
+    recipes; forward Euler and trapezoid for the quadrotor) get as far as the
+    device query."""
     import torch
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")

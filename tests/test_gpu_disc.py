@@ -88,3 +88,46 @@ def test_norm_g_f32_matches_oracle(oracle_mod, variant):
     w = W.eikonal2d()
     w.tol = 1e-6
     _check(oracle_mod, w, "f32", check_kstop=False, max_above=0.02, **variant)
+
+
+# ---- the quadrotor family: the weighted Hamiltonians stay quadratic in p, so
+# the dual step is a linear solve (a 2 x 2 system in the velocity block) --------
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("disc", DISCS)
+def test_disc_quadrotor12_matches_oracle(oracle_mod, disc, dtype):
+    """97 quadrotor points (N 10..60), cap 20,000, values and both
+    trajectories at every point, within max(bar, 10 x the rounding floor);
+    the quadrotor's flat attitude directions amplify rounding at some points
+    (as for Algorithm 1), so up to 10 % may be undetermined (8 of 97 under
+    forward Euler in FP32, against 8 % allowed for Algorithm 1) and a
+    quarter compared at their floor."""
+    w = W.quadrotor12().subset(np.arange(97))
+    _check(oracle_mod, w, dtype, max_iter=20000, check_kstop=False, disc=disc, max_undetermined=0.10,
+           max_above=0.25)
+
+
+@pytest.mark.parametrize("tile", [(8, 3), (16, 2), (32, 1), (16, 4)])
+@pytest.mark.parametrize("disc", DISCS)
+def test_disc_quadrotor12_tiles_fixed_iterations(oracle_mod, disc, tile):
+    """FP32 tiles (the left node's side data crosses lanes and, at 32 lanes,
+    rows; 16 x 4 spills to scratch), 500 fixed iterations, N up to the
+    tile's capacity with ragged values."""
+    L, K = tile
+    cap = L * K
+    w = W.quadrotor12().subset(np.arange(48))
+    w.N = np.array([1, 2, 3, K, K + 1, cap] * 8, dtype=np.int32)
+    w.N = np.minimum(w.N, cap)
+    w.N_max = cap
+    w.t = 0.05 * w.N
+    w.fixed_iters = True
+    _check(oracle_mod, w, "f32", lanes_per_point=L, nodes_per_lane=K, max_iter=500, check_kstop=False, disc=disc,
+           max_undetermined=0.08, max_above=0.25)
+
+
+def test_disc_quadrotor12_fp64_wide_tiles_refused():
+    """FP64 weighted tiles with more than two nodes per lane are not built."""
+    from paper_1803_01215_amd import hjpd as C
+    w = W.quadrotor12().subset(np.arange(4))
+    with pytest.raises(C.HjpdError):
+        gpu_solve(w, dtype="f64", disc="fe", lanes_per_point=16, nodes_per_lane=4)
