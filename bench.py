@@ -394,7 +394,7 @@ def bench_c5(B, steps, cpu):
                                   "peak": PEAK["fp32_matrix"] / 1e12, "unit": "TFLOP/s",
                                   "frac": bflops / (bwd_ms * 1e-3) / PEAK["fp32_matrix"],
                                   "kernel": "k_lt_backward<100>", "flops_per_launch": bflops, "traffic": None},
-            "cpu_baseline": oracle_sample(w, 64) if cpu else None}
+            "cpu_baseline": oracle_sample(w, 256) if cpu else None}
 
 
 def main():
@@ -406,7 +406,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--plain-sample", type=int, default=4096,
                     help="points of the seeded sample the plain kernel (and the batched path beside it) solves")
-    ap.add_argument("--cpu-sample", type=int, default=2048, help="headline points the CPU oracle solves")
+    ap.add_argument("--cpu-sample", type=int, default=6144,
+                    help="headline points the CPU oracle solves (about 10 s on 16 host threads)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--tune-cache", metavar="FILE",
