@@ -180,6 +180,13 @@ def oracle_sample(w, m, threads=None):
                 m, w.n, sub.max_iter, dt, done, "finished" if sub.fixed_iters else "converged")}
 
 
+# Tuner probe length for the quadrotor workload.  At 100 iterations per probe the
+# 49..60-node class picked 32x2 or 16x4 from run to run (657 vs 621 ms per solve);
+# at 400 and 1,000 it picked 16x4 in each of the four runs measured; 1,000 costs
+# about 5 s of tuning.
+QUAD_PROBE_ITERS = 1000
+
+
 class Bench:
     def __init__(self, torch, dev):
         self.torch, self.dev = torch, dev
@@ -415,9 +422,11 @@ def main():
                          "recorded (so a profiled run can repeat the measured plan without tuning)")
     ap.add_argument("--calibrate", action="store_true",
                     help="only the FMA calibration sweep (for hardware-counter runs), one JSON line")
-    ap.add_argument("--profile", nargs="?", const="pursuit12", choices=["pursuit12", "cnorm10"],
+    ap.add_argument("--profile", nargs="?", const="pursuit12",
+                    choices=["pursuit12", "cnorm10", "quadrotor12", "lintanh100"],
                     help="one workload's solves only, for rocprofv3: pursuit12 (the headline; plan from "
-                         "--tune-cache or tuned) or cnorm10 (FP32, cap 5,000)")
+                         "--tune-cache or tuned), cnorm10 (FP32, cap 5,000), quadrotor12 (plan from --tune-cache "
+                         "or tuned, trajectories written) or lintanh100 (forward and value_grad)")
     args = ap.parse_args()
     if args.tune_cache:
         os.environ["HJPD_TUNE_CACHE"] = os.path.abspath(args.tune_cache)
@@ -440,6 +449,28 @@ def main():
 
     if args.calibrate:
         print(json.dumps({"fma_calibration": fma_calibration()}))
+        return
+
+    if args.profile == "lintanh100":
+        r = bench_c5(B, args.steps, False)
+        print(json.dumps({"profile": "lintanh100 forward and value_grad", "steps": args.steps,
+                          "forward_kernel_ms": r["forward_kernel_ms"], "backward_kernel_ms": r["backward_kernel_ms"],
+                          "value_grad_ms": r["value_grad_ms"]}))
+        return
+
+    if args.profile == "quadrotor12":
+        wq = W.quadrotor12()
+        qplan, _ = B.tune(wq, f32, probe_iters=QUAD_PROBE_ITERS)
+        q = B.batched(wq, f32, args.steps, args.warmup, traj=True, plan=qplan)
+        cls, lo = [], 1
+        for hi, L, K in qplan:
+            m = (wq.N >= lo) & (wq.N <= hi)
+            cls.append({"N_lo": lo, "N_hi": hi, "L": L, "K": K, "points": int(m.sum()),
+                        "iters_sum": int(q["iters"][m].sum())})
+            lo = hi + 1
+        print(json.dumps({"profile": "quadrotor12 solves", "plan": qplan, "steps": args.steps,
+                          "warmup": args.warmup, "ms_per_step": q["ms"], "converged": q["converged"],
+                          "classes": cls}))
         return
 
     if args.profile == "cnorm10":
@@ -532,7 +563,7 @@ def main():
     if not args.no_extra:
         # ---- C3: quadrotor, full set, both trajectories written --------------------------------
         wq = W.quadrotor12()
-        qplan, qtune_s = B.tune(wq, f32)
+        qplan, qtune_s = B.tune(wq, f32, probe_iters=QUAD_PROBE_ITERS)
         q = B.batched(wq, f32, max(1, args.steps // 3), 1, traj=True, plan=qplan)
         log("quadrotor12 tuned plan %s; batched %.1f ms, %d converged" % (qplan, q["ms"], q["converged"]))
         qd = B.batched(wq, f32, 2, 1, traj=True)
