@@ -573,14 +573,15 @@ def main():
         qp = B.plain(qs, f32)
         qb = B.batched(qs, f32, 3, 1)
         qb.pop("status"); qb.pop("iters")
-        # the weighted discretisations (forward Euler, trapezoid), default plan
+        # the Hopf formulation (Algorithm 2) and the weighted discretisations (forward Euler,
+        # trapezoid), default plan
         qw = {}
-        for key, kw in (("forward_euler", dict(disc="fe")), ("trapezoid", dict(disc="trap"))):
+        for key, kw in (("hopf", dict(hopf=True)), ("forward_euler", dict(disc="fe")), ("trapezoid", dict(disc="trap"))):
             r = B.batched(wq, f32, 1, 1, traj=True, **kw)
             qw[key] = {"ms_per_step": r["ms"], "converged": r["converged"], "value": r["solves_per_s"],
                        "status_counts": np.bincount(r["status"], minlength=4).tolist()}
-        log("quadrotor12 forward Euler %.1f ms, trapezoid %.1f ms" % (qw["forward_euler"]["ms_per_step"],
-                                                                      qw["trapezoid"]["ms_per_step"]))
+        log("quadrotor12 Hopf %.1f ms, forward Euler %.1f ms, trapezoid %.1f ms" % (
+            qw["hopf"]["ms_per_step"], qw["forward_euler"]["ms_per_step"], qw["trapezoid"]["ms_per_step"]))
         rec["quadrotor12"] = {
             "workload": "quadrotor12: 12-state quadrotor-like control, cost |u|^2/2, g=|x|^2/2, 131,072 points "
                         "x~U[-1,1]^12, t~U[0.5,3], N=ceil(t/0.05), Algorithm 1, tol 1e-6, cap 20,000, both "
