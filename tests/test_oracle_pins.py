@@ -687,20 +687,25 @@ def test_quadrotor_weighted_fixed_point_is_stationary(oracle_mod, disc, w):
 def test_quadrotor_weighted_be_is_algorithm_1(oracle_mod):
     """The weighted solver at the backward-Euler weights (0, 1) runs Algorithm
     1's iteration: after 2,000 fixed iterations its values and trajectories
-    agree with Algorithm 1's to 1e-9 wherever Algorithm 1's own binary64 FMA
-    build does (the p-step is the same minimiser, found by a linear solve
-    instead of Sherman-Morrison, so the two differ by rounding, which the
-    quadrotor's flat attitude directions amplify at a few points)."""
+    agree with Algorithm 1's to 1e-9 wherever other rounding sequences of
+    Algorithm 1 itself do (its binary64 FMA build, and its inputs moved by
+    one unit in the last place): the p-step is the same minimiser, found by
+    a linear solve instead of Sherman-Morrison, so the two differ by
+    rounding, which the quadrotor's flat attitude directions amplify at a
+    few points."""
     w = W.quadrotor12().subset(np.arange(24))
     pb = oracle_mod.Problem(w.H, w.g, w.d, w.d_y, w.hp, w.gp)
     kw = dict(sigma=w.sigma, tau=w.tau, tol=w.tol, max_iter=2000, fixed_iters=True, seed=w.init_seed, traj=True)
     a = oracle_mod.solve(pb, w.x, w.t, w.N, **kw)
     b = oracle_mod.solve(pb, w.x, w.t, w.N, disc=(0.0, 1.0), **kw)
-    f = oracle_mod.solve_variant("f64fma", pb, w.x, w.t, w.N, **kw)
+    others = [oracle_mod.solve_variant("f64fma", pb, w.x, w.t, w.N, **kw)]
+    others += [oracle_mod.solve(pb, w.x * (1.0 + sg * 2.0 ** -52), w.t, w.N, **kw) for sg in (1.0, -1.0)]
     rel = lambda u, v: np.abs(u - v) / np.maximum(np.abs(v), 1)  # noqa: E731
     tr = lambda u, v: np.max(np.abs(u - v), axis=(1, 2)) / np.maximum(np.max(np.abs(v), axis=(1, 2)), 1)  # noqa: E731
-    cond = (rel(f.phi, a.phi) < 1e-10) & (tr(f.x_traj, a.x_traj) < 1e-10) & (tr(f.p_traj, a.p_traj) < 1e-10)
-    assert cond.mean() >= 0.75
+    cond = np.ones(w.n, bool)
+    for f in others:
+        cond &= (rel(f.phi, a.phi) < 1e-10) & (tr(f.x_traj, a.x_traj) < 1e-10) & (tr(f.p_traj, a.p_traj) < 1e-10)
+    assert cond.mean() >= 0.6
     assert np.max(rel(b.phi, a.phi)[cond]) < 1e-9
     assert np.max(tr(b.x_traj, a.x_traj)[cond]) < 1e-9 and np.max(tr(b.p_traj, a.p_traj)[cond]) < 1e-9
 
