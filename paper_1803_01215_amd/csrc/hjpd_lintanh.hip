@@ -686,7 +686,7 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
               float pbd = -tau * xb - (prim ? td * acc[c][r] : 0.f) - td * eps * om * xb + tau * xbm;
               if (j == 1) pbd += tau * wbar(L.ic[r] < D ? L.ic[r] : 0);
               if (ok) {
-                PB[e] += pbd;
+                PB[e] = (PB[e] + pbd) * c1;  // with (C1) vbar = c1 PB folded in
                 ZB[e] += xb + 2.f * td * eps * om * th * pp * xb;
               }
               deps += (ok && prim) ? -td * om * pp * xb : 0.f;
@@ -695,9 +695,9 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
           gemm_outer<D>(L, S1, XB, -td, 1, Np - 1, dA);
         }
         __syncthreads();
-        // (C1) vbar = c1 PB
-        for (int e = L.tid; e < (Np + 1) * LD; e += kLtThreads) PB[e] *= c1;
-        __syncthreads();
+        // (C1) vbar = c1 PB: applied above where (B2) writes PB (every entry
+        // of nodes 1..N is written there once; node 0's row and the padding
+        // column stay 0)
         // (C2) dual step transposed; Zpre into the XB array
         {
           f4 acc[kLtNT];
