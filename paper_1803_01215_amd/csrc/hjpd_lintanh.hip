@@ -51,7 +51,6 @@ __device__ __forceinline__ float tanh_fast(float x) {
 constexpr int kLtThreads = 512;
 constexpr int kLtWaves = kLtThreads / 64;
 constexpr int kLtNT = 4;                                                    // 16-node column tiles: up to 64 nodes
-constexpr int kLtPart = (kLtMaxD * kLtMaxD + kLtThreads - 1) / kLtThreads;  // rank-1 entries per thread
 
 // LDS rows per array: nodes 0 .. 16*NT + 1 (NT column tiles of 16 nodes), so
 // every GEMM column read and every j+1 read stays inside the array.
@@ -199,7 +198,6 @@ __device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af
   const float lam = sigma * delta, c1 = 1.f / (1.f + lam), td = tau * delta;
   int lo = (L.lr + 1) * LD;
   asm volatile("" : "+v"(lo));
-  const int lob = lo + L.lk;
   if (sx_out)
     for (int e = L.tid; e < (Np + 1) * D; e += kLtThreads) {
       const int j = e / D, i = e - j * D;
@@ -629,7 +627,6 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
         lt_load<D>(S0, S1, nullptr, Np, a.N_max, R, so);  // x^k, p^{k+1}
         int lo = (L.lr + 1) * LD;
         asm volatile("" : "+v"(lo));
-        const int lob = lo + L.lk;
         // (A) extrapolation
         for (int e = L.tid; e < (Np + 1) * LD; e += kLtThreads) {
           const int j = e / LD, i = e - j * LD;
