@@ -89,6 +89,28 @@ def test_quadrotor12_matches_oracle(oracle_mod, dtype, plain):
            max_above=0.25)
 
 
+@pytest.mark.parametrize("tile", [(8, 4), (16, 4), (64, 4)])
+def test_quadrotor12_four_node_tiles_f32(oracle_mod, tile):
+    """FP32 tiles with four nodes per lane take the interleaved step order
+    (each node's primal step right after the next node's dual step): 1,500
+    fixed iterations against the oracle, values and both trajectories.  The
+    8 x 4 tile holds N <= 32, so it takes the sample's points up to that N,
+    renumbered 0.. as the batch numbers them (the random start is keyed by
+    the point's index in the batch).  Mid-way to convergence more of the
+    quadrotor's points sit on its flat attitude directions than at the cap,
+    so up to 15 % may have no determined result."""
+    L, K = tile
+    w = W.quadrotor12().subset(np.arange(160))
+    if L * K < w.N_max:
+        w = w.subset(np.nonzero(w.N <= L * K)[0])
+        w.extra = dict(w.extra, ids=np.arange(w.n))
+        w.N_max = L * K
+    w.fixed_iters = True
+    g = _check(oracle_mod, w, "f32", max_iter=1500, lanes_per_point=L, nodes_per_lane=K, check_kstop=False,
+               max_undetermined=0.15, max_above=0.25)
+    assert np.all(g["iters"] == 1500)
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("plain", [False, True])
 def test_pursuit12_matches_oracle(oracle_mod, dtype, plain):
