@@ -230,18 +230,34 @@ __device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af
       sp_out[e] = sP[j * LD + i];
     }
   // ---- node 0 (VALU): x_0 <- M (x_0 + tau p_1), M symmetric, read by columns.
-  // Waves 0 and 1 compute it while the other waves start the primal product
-  // (the forward kernel and the reverse kernel's recompute use this same
-  // summation order, so the recompute reproduces the forward bit for bit).
+  // The four lanes of a quad share output i = tid / 4, each summing a quarter
+  // of its terms, and add the quarters with two quad exchanges (the forward
+  // kernel and the reverse kernel's recompute use this same summation order,
+  // so the recompute reproduces the forward bit for bit).
   float x0n = 0.f, z0n = 0.f;
-  if (L.tid < D) {
-    float acc0 = 0.f;
-    for (int kq = 0; kq < D; kq++) acc0 += a.M[kq * D + L.tid] * (sX[kq] + tau * sP[LD + kq]);
-    const float old = sX[L.tid];
-    const float dx = acc0 - old;
-    rx += dx * dx;
-    x0n = acc0;
-    z0n = acc0 + theta * dx;
+  const int i0 = L.tid >> 2, q0 = L.tid & 3;
+  {
+    constexpr int KQ = (D + 3) / 4;
+    // opaque column index: the loop-invariant loads of M stay in the iteration
+    int col = i0;
+    asm volatile("" : "+v"(col));
+    float part = 0.f;
+    if (i0 < D) {
+#pragma unroll 5
+      for (int s = 0; s < KQ; s++) {
+        const int kq = q0 * KQ + s;
+        if (kq < D) part += a.M[kq * D + col] * (sX[kq] + tau * sP[LD + kq]);
+      }
+    }
+    part += dpp_f<kDppQuad1032>(part);
+    part += dpp_f<kDppQuad2301>(part);
+    if (i0 < D && q0 == 0) {
+      const float old = sX[i0];
+      const float dx = part - old;
+      rx += dx * dx;
+      x0n = part;
+      z0n = part + theta * dx;
+    }
   }
   // ---- primal step, j = 1..N-1, with G = A^T P ----------------------------------
   gemm_nodes<D>(atf, sP, L, R, acc);
@@ -264,9 +280,9 @@ __device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af
     }
   }
   __syncthreads();
-  if (L.tid < D) {
-    sX[L.tid] = x0n;
-    sZ[L.tid] = z0n;
+  if (i0 < D && q0 == 0) {
+    sX[i0] = x0n;
+    sZ[i0] = z0n;
   }
   __syncthreads();
 }
