@@ -243,7 +243,7 @@ __device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af
     asm volatile("" : "+v"(col));
     float part = 0.f;
     if (i0 < D) {
-#pragma unroll 5
+#pragma unroll
       for (int s = 0; s < KQ; s++) {
         const int kq = q0 * KQ + s;
         if (kq < D) part += a.M[kq * D + col] * (sX[kq] + tau * sP[LD + kq]);
