@@ -505,7 +505,6 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
   __shared__ float s_red[2 * kLtWaves];
   __shared__ float s_wb[4 * 128];  // quarters of wbar = M XB_0 (B1)
   auto wbar = [&](int i) { return (s_wb[i] + s_wb[128 + i]) + (s_wb[256 + i] + s_wb[384 + i]); };
-  __shared__ int s_pt;
   const LtLane<D> L;
   const int R = lt_rows(a.N_max);
   const int NT = (a.N_max + 15) / 16;
@@ -545,12 +544,10 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
   float* adjsave = segx + int64_t(E) * 2 * CK;
   float* stage = adjsave + 3 * CK;  // per step of a segment: XB_0 (node-0 adjoint) and w = x_0 + tau p'_1
 
-  for (;;) {
-    if (L.tid == 0) s_pt = atomicAdd(a.head + 2, 1);
-    __syncthreads();
-    const int64_t pt = s_pt;
-    __syncthreads();
-    if (pt >= a.n) break;
+  // Points are dealt to the workgroups in a fixed order (every point costs
+  // the same K iterations), so each workgroup's partial sums of dA, dM, dQ and
+  // deps, and with them the gradients, are the same from call to call.
+  for (int64_t pt = blockIdx.x; pt < a.n; pt += gridDim.x) {
     const float w = b.grad_phi[pt];
     if (lt_bad_input<D>(a, pt) || w == 0.f) {
       for (int i = L.tid; i < D; i += kLtThreads) b.dphi_dx[pt * D + i] = 0.f;
