@@ -57,11 +57,11 @@ constexpr int kLtNT = 4;                                                    // 1
 __host__ __device__ constexpr int lt_rows(int N_max) { return 16 * ((N_max + 15) / 16) + 2; }
 inline size_t lt_lds_forward(int d, int N_max) { return size_t(3) * lt_rows(N_max) * (d + 1) * sizeof(float); }
 inline size_t lt_lds_backward(int d, int N_max) { return size_t(5) * lt_rows(N_max) * (d + 1) * sizeof(float); }
-// Per-workgroup reverse-mode buffer (floats): E recomputed steps of (x^k, p^{k+1}),
+// Per-workgroup reverse-mode buffer (floats): E recomputed steps of (x^k, p^{k+1}) in the LDS layout,
 // the saved adjoint (3 arrays), and E staged (XB_0, w) pairs for dM.
 __host__ __device__ inline int64_t lt_seg_floats(int d, int N_max, int E) {
-  const int64_t CK = int64_t(N_max + 1) * d;
-  return int64_t(E) * 2 * CK + 3 * CK + int64_t(E) * 2 * d;
+  const int64_t CK = int64_t(N_max + 1) * d, RL = int64_t(lt_rows(N_max)) * (d + 1);
+  return int64_t(E) * 2 * RL + 3 * CK + int64_t(E) * 2 * d;
 }
 
 struct LtArgs {
@@ -151,14 +151,14 @@ __device__ __forceinline__ void gemm_nodes(const float (&frag)[D / 4], const flo
     asm volatile("" : "+v"(base[c]));
     acc[c] = f4{0.f, 0.f, 0.f, 0.f};
   }
-  // Scheduling fence every kGemmWindow k-steps: bounds how many B reads the
-  // scheduler hoists ahead of their MFMAs (each hoisted read holds a VGPR).
-  constexpr int kGemmWindow = 2;
+  // Scheduling fence after every k-step: the scheduler cannot hoist B reads
+  // ahead of earlier k-steps' MFMAs (each hoisted read holds a VGPR).  A fence
+  // every second or fourth step measured slower in both kernels.
 #pragma unroll
   for (int s = 0; s < D / 4; s++) {
 #pragma unroll
     for (int c = 0; c < kLtNT; c++) acc[c] = mfma4(frag[s], sB[base[c] + 4 * s], acc[c]);
-    if (s % kGemmWindow == kGemmWindow - 1) __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -170,16 +170,27 @@ __device__ __forceinline__ void gemm_outer(const LtLane<D>& L, const float* sU, 
   constexpr int LD = D + 1, CT = (D + 15) / 16;
   const int row = 16 * L.wave + L.lr;
   const int rc = (L.has && row < D) ? row : D;
-  for (int j0 = jlo; j0 <= jhi; j0 += 4) {
-    const int j = j0 + L.lk;
-    const bool ok = j <= jhi;
-    const int jr = ok ? j : jlo;
-    const float a = ok ? scale * sU[jr * LD + rc] : 0.f;
+  // two k-steps per trip, all of their LDS reads issued before the products;
+  // the second step of the last trip runs only if it has nodes
+  for (int j0 = jlo; j0 <= jhi; j0 += 8) {
+    float a[2], b[2][CT];
 #pragma unroll
-    for (int ct = 0; ct < CT; ct++) {
-      const int col = 16 * ct + L.lr;
-      const float b = sV[jr * LD + (col < D ? col : D)];
-      out[ct] = mfma4(a, b, out[ct]);
+    for (int h = 0; h < 2; h++) {
+      const int j = j0 + 4 * h + L.lk;
+      const bool ok = j <= jhi;
+      const int jr = ok ? j : jlo;
+      a[h] = ok ? scale * sU[jr * LD + rc] : 0.f;
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) {
+        const int col = 16 * ct + L.lr;
+        b[h][ct] = sV[jr * LD + (col < D ? col : D)];
+      }
+    }
+#pragma unroll
+    for (int ct = 0; ct < CT; ct++) out[ct] = mfma4(a[0], b[0][ct], out[ct]);
+    if (j0 + 4 <= jhi) {
+#pragma unroll
+      for (int ct = 0; ct < CT; ct++) out[ct] = mfma4(a[1], b[1][ct], out[ct]);
     }
   }
 }
@@ -199,10 +210,7 @@ __device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af
   int lo = (L.lr + 1) * LD;
   asm volatile("" : "+v"(lo));
   if (sx_out)
-    for (int e = L.tid; e < (Np + 1) * D; e += kLtThreads) {
-      const int j = e / D, i = e - j * D;
-      sx_out[e] = sX[j * LD + i];
-    }
+    for (int e = L.tid; e < (Np + 1) * LD; e += kLtThreads) sx_out[e] = sX[e];
   // ---- dual step: p_j <- (p_j + sigma (z_j - z_{j-1}) + lam f_j) c1 ----------
   f4 acc[kLtNT];
   gemm_nodes<D>(af, sX, L, R, acc);
@@ -225,10 +233,7 @@ __device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af
   }
   __syncthreads();
   if (sp_out)
-    for (int e = L.tid; e < (Np + 1) * D; e += kLtThreads) {
-      const int j = e / D, i = e - j * D;
-      sp_out[e] = sP[j * LD + i];
-    }
+    for (int e = L.tid; e < (Np + 1) * LD; e += kLtThreads) sp_out[e] = sP[e];
   // ---- node 0 (VALU): x_0 <- M (x_0 + tau p_1), M symmetric, read by columns.
   // The four lanes of a quad share output i = tid / 4, each summing a quarter
   // of its terms, and add the quarters with two quad exchanges (the forward
@@ -351,6 +356,30 @@ __device__ void lt_load(float* s0, float* s1, float* s2, int Np, int N_max, int 
       const int e = tid + u * kLtThreads;
       if (e < R * LD) dst[q][e] = v[u];
     }
+  }
+  __syncthreads();
+}
+
+// Copy rows 0..N of two arrays stored in the LDS layout (src, src + RL) into
+// LDS; rows past N already hold zero there.  Every thread issues its loads
+// together and no branch guards them: indices past row N are clamped to the
+// last entry of row N, which those threads then write with its own value.
+template <int D>
+__device__ void lt_copy_rows(float* s0, float* s1, int Np, const float* src, int64_t RL) {
+  constexpr int LD = D + 1;
+  constexpr int NL = (lt_rows(kLtMaxN) * LD + kLtThreads - 1) / kLtThreads;
+  const int last = (Np + 1) * LD - 1;
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+#pragma unroll
+  for (int q = 0; q < 2; q++) {
+    const float* sq = src + q * RL;
+    float* dq = q ? s1 : s0;
+    float v[NL];
+#pragma unroll
+    for (int u = 0; u < NL; u++) v[u] = sq[min(tid + u * kLtThreads, last)];
+#pragma unroll
+    for (int u = 0; u < NL; u++) dq[min(tid + u * kLtThreads, last)] = v[u];
   }
   __syncthreads();
 }
@@ -540,8 +569,9 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
   const int E = a.ckpt_every;
   const int64_t CK = int64_t(a.N_max + 1) * D;
   const int64_t slot = 3 * CK;
+  const int64_t RL = int64_t(R) * LD;  // a recomputed x^k or p^{k+1}, in the LDS layout
   float* segx = b.seg + int64_t(blockIdx.x) * lt_seg_floats(D, a.N_max, E);
-  float* adjsave = segx + int64_t(E) * 2 * CK;
+  float* adjsave = segx + int64_t(E) * 2 * RL;
   float* stage = adjsave + 3 * CK;  // per step of a segment: XB_0 (node-0 adjoint) and w = x_0 + tau p'_1
 
   // Points are dealt to the workgroups in a fixed order (every point costs
@@ -627,8 +657,8 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
       lt_load<D>(S0, S1, S2, Np, a.N_max, R, ck_pt + sg * slot);
       for (int k = k0; k < k1; k++) {
         float rx = 0.f, rp = 0.f;
-        float* so = segx + int64_t(k - k0) * 2 * CK;
-        lt_iterate<D>(L, a, af, atf, S0, S1, S2, Np, NT, delta, eps, so, so + CK, rx, rp);
+        float* so = segx + int64_t(k - k0) * 2 * RL;
+        lt_iterate<D>(L, a, af, atf, S0, S1, S2, Np, NT, delta, eps, so, so + RL, rx, rp);
       }
       XB = S2;
       PB = S3;
@@ -636,22 +666,19 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
       lt_load<D>(XB, PB, ZB, Np, a.N_max, R, adjsave);
       // reverse sweep through the segment
       for (int k = k1 - 1; k >= k0; k--) {
-        const float* so = segx + int64_t(k - k0) * 2 * CK;
-        lt_load<D>(S0, S1, nullptr, Np, a.N_max, R, so);  // x^k, p^{k+1}
+        const float* so = segx + int64_t(k - k0) * 2 * RL;
+        lt_copy_rows<D>(S0, S1, Np, so, RL);  // x^k, p^{k+1}
         int lo = (L.lr + 1) * LD;
         asm volatile("" : "+v"(lo));
         // (A) extrapolation
+        // branch-free: the padding column holds zero in both arrays and stays
+        // zero (0 - theta * 0 = +0), row N's x-adjoint is written back unchanged
         for (int e = L.tid; e < (Np + 1) * LD; e += kLtThreads) {
-          const int j = e / LD, i = e - j * LD;
-          if (i < D) {
-            const float zb = ZB[e];
-            if (j < Np) {
-              XB[e] += (1.f + theta) * zb;
-              ZB[e] = -theta * zb;
-            } else {
-              ZB[e] = zb + XB[e];
-            }
-          }
+          const int j = e / LD;
+          const float zb = ZB[e], xb = XB[e];
+          const bool mid = j < Np;
+          XB[e] = mid ? xb + (1.f + theta) * zb : xb;
+          ZB[e] = mid ? 0.f - theta * zb : zb + xb;
         }
         __syncthreads();
         // (B1) node 0: w = x_0 + tau p'_1, wbar = M XB_0 (quarters of each row's
@@ -661,9 +688,27 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
           const int i = L.tid & 127, g = L.tid >> 7;
           if (i < D) {
             constexpr int KQ = (D + 3) / 4;
-            const int k1 = (g + 1) * KQ < D ? (g + 1) * KQ : D;
+            // W terms per trip, their loads issued together ahead of the
+            // products (g < 4, so with d a multiple of 4 every term exists and
+            // no branch guards a load); the opaque column keeps M's loads
+            // inside the step
+            constexpr int W = KQ % 5 == 0 ? 5 : (KQ % 4 == 0 ? 4 : 1);
+            int col = i;
+            asm volatile("" : "+v"(col));
             float part = 0.f;
-            for (int kq = g * KQ; kq < k1; kq++) part += a.M[kq * D + i] * XB[kq];
+            for (int s0 = 0; s0 < KQ; s0 += W) {
+              float mv[W], xv[W];
+#pragma unroll
+              for (int h = 0; h < W; h++) {
+                const int kq = g * KQ + s0 + h;
+                const bool ok = 4 * KQ == D || kq < D;
+                mv[h] = ok ? a.M[kq * D + col] : 0.f;
+                xv[h] = ok ? XB[kq] : 0.f;
+              }
+              __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+              for (int h = 0; h < W; h++) part += mv[h] * xv[h];
+            }
             s_wb[g * 128 + i] = part;
           }
         }
@@ -695,10 +740,10 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
               // x_N is fixed: no primal step and no (A XB)_N term at j = N
               float pbd = -tau * xb - (prim ? td * acc[c][r] : 0.f) - td * eps * om * xb + tau * xbm;
               if (j == 1) pbd += tau * wbar(L.ic[r] < D ? L.ic[r] : 0);
-              if (ok) {
-                PB[e] = (PB[e] + pbd) * c1;  // with (C1) vbar = c1 PB folded in
-                ZB[e] += xb + 2.f * td * eps * om * th * pp * xb;
-              }
+              // entries that do not move are written back unchanged (no branch)
+              const float pbo = PB[e], zbo = ZB[e];
+              PB[e] = ok ? (pbo + pbd) * c1 : pbo;  // with (C1) vbar = c1 PB folded in
+              ZB[e] = ok ? zbo + (xb + 2.f * td * eps * om * th * pp * xb) : zbo;
               deps += (ok && prim) ? -td * om * pp * xb : 0.f;
             }
           }
@@ -723,10 +768,10 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
               const float vb = PB[e], vbn = (j < Np) ? PB[e + LD] : 0.f;
               const float xk = S0[e];
               const float th = tanh_fast(xk);
-              if (ok) {
-                ZB[e] += lam * acc[c][r] + lam * eps * (1.f - th * th) * vb;
-                XB[e] = sigma * (vb - vbn);
-              }
+              // entries past N and in the padding column hold zero in every array
+              const float zbo = ZB[e];
+              ZB[e] = ok ? zbo + (lam * acc[c][r] + lam * eps * (1.f - th * th) * vb) : zbo;
+              XB[e] = ok ? sigma * (vb - vbn) : 0.f;
               deps += ok ? lam * th * vb : 0.f;
             }
           }
