@@ -364,6 +364,7 @@ __device__ void lt_load(float* s0, float* s1, float* s2, int Np, int N_max, int 
 // LDS; rows past N already hold zero there.  Every thread issues its loads
 // together and no branch guards them: indices past row N are clamped to the
 // last entry of row N, which those threads then write with its own value.
+// No barrier: the caller synchronises before the rows are read.
 template <int D>
 __device__ void lt_copy_rows(float* s0, float* s1, int Np, const float* src, int64_t RL) {
   constexpr int LD = D + 1;
@@ -381,7 +382,6 @@ __device__ void lt_copy_rows(float* s0, float* s1, int Np, const float* src, int
 #pragma unroll
     for (int u = 0; u < NL; u++) dq[min(tid + u * kLtThreads, last)] = v[u];
   }
-  __syncthreads();
 }
 
 template <int D>
@@ -533,7 +533,11 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
   extern __shared__ float smem[];
   __shared__ float s_red[2 * kLtWaves];
   __shared__ float s_wb[4 * 128];  // quarters of wbar = M XB_0 (B1)
-  auto wbar = [&](int i) { return (s_wb[i] + s_wb[128 + i]) + (s_wb[256 + i] + s_wb[384 + i]); };
+  constexpr int kIdleWaves = kLtWaves - (D + 15) / 16;  // waves with no row tile of their own
+  auto wbar = [&](int i) {
+    if constexpr (kIdleWaves > 0) return s_wb[i];
+    else return (s_wb[i] + s_wb[128 + i]) + (s_wb[256 + i] + s_wb[384 + i]);
+  };
   const LtLane<D> L;
   const int R = lt_rows(a.N_max);
   const int NT = (a.N_max + 15) / 16;
@@ -667,7 +671,7 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
       // reverse sweep through the segment
       for (int k = k1 - 1; k >= k0; k--) {
         const float* so = segx + int64_t(k - k0) * 2 * RL;
-        lt_copy_rows<D>(S0, S1, Np, so, RL);  // x^k, p^{k+1}
+        lt_copy_rows<D>(S0, S1, Np, so, RL);  // x^k, p^{k+1}: read after the barrier that ends (A)
         int lo = (L.lr + 1) * LD;
         asm volatile("" : "+v"(lo));
         // (A) extrapolation
@@ -681,10 +685,45 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
           ZB[e] = mid ? 0.f - theta * zb : zb + xb;
         }
         __syncthreads();
-        // (B1) node 0: w = x_0 + tau p'_1, wbar = M XB_0 (quarters of each row's
-        // terms summed by the eight waves, added below); dM += XB_0 w^T is
-        // applied once per segment from the staged (XB_0, w) pairs
-        {
+        // (B1) node 0: w = x_0 + tau p'_1, wbar = M XB_0; dM += XB_0 w^T is
+        // applied once per segment from the staged (XB_0, w) pairs.  With fewer
+        // row tiles than waves, the waves past the last tile (whose product
+        // tiles are padding) form wbar, one thread per output summing its terms
+        // in order, and stage the pair while the others run (B2)'s product
+        // A XB; otherwise the eight waves first sum quarters of each row's terms.
+        float* st = stage + int64_t(k - k0) * 2 * D;
+        f4 acc[kLtNT];
+        if constexpr (kIdleWaves > 0) {
+          if (L.has) {
+            gemm_nodes<D>(af, XB, L, R, acc);  // (A XB)_j
+          } else {
+#pragma unroll
+            for (int c = 0; c < kLtNT; c++) acc[c] = f4{0.f, 0.f, 0.f, 0.f};
+            // the terms' loads are issued W at a time ahead of their products;
+            // the opaque column keeps M's loads inside the step
+            constexpr int W = D % 25 == 0 ? 25 : (D % 16 == 0 ? 16 : (D % 8 == 0 ? 8 : 4));
+            for (int i = L.tid - 64 * L.RT; i < D; i += 64 * kIdleWaves) {
+              int col = i;
+              asm volatile("" : "+v"(col));
+              float part = 0.f;
+              for (int s0 = 0; s0 < D; s0 += W) {
+                float mv[W], xv[W];
+#pragma unroll
+                for (int h = 0; h < W; h++) {
+                  mv[h] = a.M[(s0 + h) * D + col];
+                  xv[h] = XB[s0 + h];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int h = 0; h < W; h++) part += mv[h] * xv[h];
+              }
+              s_wb[i] = part;
+              st[i] = XB[i];
+              st[D + i] = S0[i] + tau * S1[LD + i];
+            }
+          }
+          __syncthreads();
+        } else {
           const int i = L.tid & 127, g = L.tid >> 7;
           if (i < D) {
             constexpr int KQ = (D + 3) / 4;
@@ -711,19 +750,16 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
             }
             s_wb[g * 128 + i] = part;
           }
+          if (L.tid < D) {
+            st[L.tid] = XB[L.tid];
+            st[D + L.tid] = S0[L.tid] + tau * S1[LD + L.tid];
+          }
+          __syncthreads();
+          gemm_nodes<D>(af, XB, L, R, acc);  // (A XB)_j
         }
-        if (L.tid < D) {
-          const float wv = S0[L.tid] + tau * S1[LD + L.tid];
-          float* st = stage + int64_t(k - k0) * 2 * D;
-          st[L.tid] = XB[L.tid];
-          st[D + L.tid] = wv;
-        }
-        __syncthreads();
         if (L.tid < D) ZB[L.tid] += wbar(L.tid);
         // (B2) primal step transposed
         {
-          f4 acc[kLtNT];
-          gemm_nodes<D>(af, XB, L, R, acc);  // (A XB)_j
 #pragma unroll
           for (int c = 0; c < kLtNT; c++) {
             if (c >= NT) continue;
