@@ -532,7 +532,7 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
   const LtArgs& a = b.f;
   extern __shared__ float smem[];
   __shared__ float s_red[2 * kLtWaves];
-  __shared__ float s_wb[4 * 128];  // quarters of wbar = M XB_0 (B1)
+  __shared__ float s_wb[4 * 128];  // wbar = M XB_0 (B1): whole sums, or quarters when no wave is idle
   constexpr int kIdleWaves = kLtWaves - (D + 15) / 16;  // waves with no row tile of their own
   auto wbar = [&](int i) {
     if constexpr (kIdleWaves > 0) return s_wb[i];
