@@ -145,6 +145,18 @@ def test_lintanh_small_gradients_match_central_differences(oracle_mod):
     assert errs.max() <= 1e-4
 
 
+@pytest.mark.parametrize("d", [32, 128])
+def test_lintanh_other_sizes_values_and_gradients(oracle_mod, d):
+    """d = 32 leaves six waves without a row tile of their own, and the reverse
+    step forms node 0's adjoint product on them; d = 128 leaves none, and every
+    wave sums a quarter of each row's terms."""
+    w = _small_workload(d=d, n=3, N=12, K=60, seed=11)
+    errs, g = _check_grads(oracle_mod, w, K=60, E=20, n_dirs=1)
+    assert errs.max() <= 1e-4
+    o = _oracle_phi(oracle_mod, w, 60)
+    assert rel_err(g["phi"], o.phi).max() <= 1e-4
+
+
 def test_lintanh100_gradients_match_central_differences(oracle_mod):
     w = W.lintanh100().subset(np.arange(3))
     errs, _ = _check_grads(oracle_mod, w, K=w.max_iter, E=50, n_dirs=1)
