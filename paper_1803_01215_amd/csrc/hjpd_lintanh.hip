@@ -243,16 +243,32 @@ __device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af
   const int i0 = L.tid >> 2, q0 = L.tid & 3;
   {
     constexpr int KQ = (D + 3) / 4;
-    // opaque column index: the loop-invariant loads of M stay in the iteration
-    int col = i0;
+    // Half of M's terms are loaded before the primal product, the rest after
+    // it, and all are summed after it, so part of their latency overlaps the
+    // product (loading all of them first spills registers).  Quads past row d
+    // load row d - 1 and discard the sum.  The opaque column keeps the loads in
+    // the iteration.
+    int col = i0 < D ? i0 : D - 1;
     asm volatile("" : "+v"(col));
-    float part = 0.f;
-    if (i0 < D) {
+    constexpr int KP = KQ / 2;  // terms loaded ahead of the product
+    float mv[KQ];
 #pragma unroll
-      for (int s = 0; s < KQ; s++) {
-        const int kq = q0 * KQ + s;
-        if (kq < D) part += a.M[kq * D + col] * (sX[kq] + tau * sP[LD + kq]);
-      }
+    for (int s = 0; s < KP; s++) {
+      const int kq = q0 * KQ + s;
+      mv[s] = (4 * KQ == D || kq < D) ? a.M[kq * D + col] : 0.f;
+    }
+    // ---- primal step, j = 1..N-1, with G = A^T P: the product -------------------
+    gemm_nodes<D>(atf, sP, L, R, acc);
+#pragma unroll
+    for (int s = KP; s < KQ; s++) {
+      const int kq = q0 * KQ + s;
+      mv[s] = (4 * KQ == D || kq < D) ? a.M[kq * D + col] : 0.f;
+    }
+    float part = 0.f;
+#pragma unroll
+    for (int s = 0; s < KQ; s++) {
+      const int kq = q0 * KQ + s;
+      if (4 * KQ == D || kq < D) part += mv[s] * (sX[kq] + tau * sP[LD + kq]);
     }
     part += dpp_f<kDppQuad1032>(part);
     part += dpp_f<kDppQuad2301>(part);
@@ -264,8 +280,7 @@ __device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af
       z0n = part + theta * dx;
     }
   }
-  // ---- primal step, j = 1..N-1, with G = A^T P ----------------------------------
-  gemm_nodes<D>(atf, sP, L, R, acc);
+  // ---- primal step: the update ----------------------------------------------------
 #pragma unroll
   for (int c = 0; c < kLtNT; c++) {
     if (c >= NT) continue;
