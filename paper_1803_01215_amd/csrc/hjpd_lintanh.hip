@@ -241,13 +241,14 @@ __device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af
   // so the recompute reproduces the forward bit for bit).
   float x0n = 0.f, z0n = 0.f;
   const int i0 = L.tid >> 2, q0 = L.tid & 3;
-  {
-    constexpr int KQ = (D + 3) / 4;
-    // Half of M's terms are loaded before the primal product, the rest after
-    // it, and all are summed after it, so part of their latency overlaps the
-    // product (loading all of them first spills registers).  Quads past row d
-    // load row d - 1 and discard the sum.  The opaque column keeps the loads in
-    // the iteration.
+  // With d up to 112, half of M's terms are loaded before the primal product
+  // and the rest after it, and all are summed after it, so part of their
+  // latency overlaps the product (loading all of them first spills registers);
+  // at d = 128 that measured slower, and the sum runs before the product.
+  constexpr int KQ = (D + 3) / 4;
+  if constexpr (D <= 112) {
+    // Quads past row d load row d - 1 and discard the sum.  The opaque column
+    // keeps the loads in the iteration.
     int col = i0 < D ? i0 : D - 1;
     asm volatile("" : "+v"(col));
     constexpr int KP = KQ / 2;  // terms loaded ahead of the product
@@ -257,7 +258,7 @@ __device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af
       const int kq = q0 * KQ + s;
       mv[s] = (4 * KQ == D || kq < D) ? a.M[kq * D + col] : 0.f;
     }
-    // ---- primal step, j = 1..N-1, with G = A^T P: the product -------------------
+    // ---- primal step, j = 1..N-1, with G = A^T P: the product ---------------------
     gemm_nodes<D>(atf, sP, L, R, acc);
 #pragma unroll
     for (int s = KP; s < KQ; s++) {
@@ -279,6 +280,29 @@ __device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af
       x0n = part;
       z0n = part + theta * dx;
     }
+  } else {
+    // opaque column index: the loop-invariant loads of M stay in the iteration
+    int col = i0;
+    asm volatile("" : "+v"(col));
+    float part = 0.f;
+    if (i0 < D) {
+#pragma unroll
+      for (int s = 0; s < KQ; s++) {
+        const int kq = q0 * KQ + s;
+        if (kq < D) part += a.M[kq * D + col] * (sX[kq] + tau * sP[LD + kq]);
+      }
+    }
+    part += dpp_f<kDppQuad1032>(part);
+    part += dpp_f<kDppQuad2301>(part);
+    if (i0 < D && q0 == 0) {
+      const float old = sX[i0];
+      const float dx = part - old;
+      rx += dx * dx;
+      x0n = part;
+      z0n = part + theta * dx;
+    }
+    // ---- primal step, j = 1..N-1, with G = A^T P: the product ---------------------
+    gemm_nodes<D>(atf, sP, L, R, acc);
   }
   // ---- primal step: the update ----------------------------------------------------
 #pragma unroll
@@ -375,27 +399,37 @@ __device__ void lt_load(float* s0, float* s1, float* s2, int Np, int N_max, int 
   __syncthreads();
 }
 
-// Copy rows 0..N of two arrays stored in the LDS layout (src, src + RL) into
-// LDS; rows past N already hold zero there.  Every thread issues its loads
-// together and no branch guards them: indices past row N are clamped to the
-// last entry of row N, which those threads then write with its own value.
-// No barrier: the caller synchronises before the rows are read.
+// Rows 0..N of two arrays stored in the LDS layout (src, src + RL), read into
+// registers by lt_rows_load and written to LDS by lt_rows_store; rows past N
+// already hold zero there.  Every thread issues its loads together and no
+// branch guards them: indices past row N are clamped to the last entry of row
+// N, which those threads then write with its own value.
 template <int D>
-__device__ void lt_copy_rows(float* s0, float* s1, int Np, const float* src, int64_t RL) {
-  constexpr int LD = D + 1;
-  constexpr int NL = (lt_rows(kLtMaxN) * LD + kLtThreads - 1) / kLtThreads;
-  const int last = (Np + 1) * LD - 1;
+constexpr int lt_rows_per_thread() { return (lt_rows(kLtMaxN) * (D + 1) + kLtThreads - 1) / kLtThreads; }
+
+template <int D>
+__device__ __forceinline__ void lt_rows_load(const float* src, int64_t RL, int Np, float (&v)[2][lt_rows_per_thread<D>()]) {
+  constexpr int NL = lt_rows_per_thread<D>();
+  const int last = (Np + 1) * (D + 1) - 1;
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
 #pragma unroll
-  for (int q = 0; q < 2; q++) {
-    const float* sq = src + q * RL;
-    float* dq = q ? s1 : s0;
-    float v[NL];
+  for (int q = 0; q < 2; q++)
 #pragma unroll
-    for (int u = 0; u < NL; u++) v[u] = sq[min(tid + u * kLtThreads, last)];
+    for (int u = 0; u < NL; u++) v[q][u] = src[q * RL + min(tid + u * kLtThreads, last)];
+}
+
+template <int D>
+__device__ __forceinline__ void lt_rows_store(float* s0, float* s1, int Np, const float (&v)[2][lt_rows_per_thread<D>()]) {
+  constexpr int NL = lt_rows_per_thread<D>();
+  const int last = (Np + 1) * (D + 1) - 1;
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
 #pragma unroll
-    for (int u = 0; u < NL; u++) dq[min(tid + u * kLtThreads, last)] = v[u];
+  for (int u = 0; u < NL; u++) {
+    const int e = min(tid + u * kLtThreads, last);
+    s0[e] = v[0][u];
+    s1[e] = v[1][u];
   }
 }
 
@@ -684,9 +718,13 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
       ZB = S4;
       lt_load<D>(XB, PB, ZB, Np, a.N_max, R, adjsave);
       // reverse sweep through the segment
+      // x^k and p^{k+1} of each step are loaded into registers during the
+      // previous step's last outer product and written to LDS at the step's
+      // start (read after the barrier that ends (A))
+      float rows[2][lt_rows_per_thread<D>()];
+      lt_rows_load<D>(segx + int64_t(k1 - 1 - k0) * 2 * RL, RL, Np, rows);
       for (int k = k1 - 1; k >= k0; k--) {
-        const float* so = segx + int64_t(k - k0) * 2 * RL;
-        lt_copy_rows<D>(S0, S1, Np, so, RL);  // x^k, p^{k+1}: read after the barrier that ends (A)
+        lt_rows_store<D>(S0, S1, Np, rows);
         int lo = (L.lr + 1) * LD;
         asm volatile("" : "+v"(lo));
         // (A) extrapolation
@@ -827,6 +865,7 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
             }
           }
           if (L.tid < D) XB[L.tid] = -sigma * PB[LD + L.tid];
+          if (k > k0) lt_rows_load<D>(segx + int64_t(k - 1 - k0) * 2 * RL, RL, Np, rows);
           gemm_outer<D>(L, PB, S0, lam, 1, Np, dA);
         }
         __syncthreads();
