@@ -199,7 +199,7 @@ __device__ __forceinline__ void gemm_outer(const LtLane<D>& L, const float* sU, 
 // LDS state.  If sx_out / sp_out are given, x^k (before the iteration) and
 // p^{k+1} (after the dual step) are stored there ([N+1][d], row stride d).
 // Adds this thread's partial residual sums to rx, rp.
-template <int D>
+template <int D, bool kReuseTanh = false>
 __device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af)[D / 4], const float (&atf)[D / 4],
                            float* sX, float* sP, float* sZ, int Np, int NT, float delta, float eps, float* sx_out,
                            float* sp_out, float& rx, float& rp) {
@@ -213,9 +213,14 @@ __device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af
     for (int e = L.tid; e < (Np + 1) * LD; e += kLtThreads) sx_out[e] = sX[e];
   // ---- dual step: p_j <- (p_j + sigma (z_j - z_{j-1}) + lam f_j) c1 ----------
   f4 acc[kLtNT];
+  // With kReuseTanh the dual step keeps tanh(x_j) for the primal step (x is
+  // unchanged until then): faster in the reverse sweep's recompute, slower in
+  // the forward kernel, whose 128 registers then spill more.
+  f4 thc[kLtNT];
   gemm_nodes<D>(af, sX, L, R, acc);
 #pragma unroll
   for (int c = 0; c < kLtNT; c++) {
+    thc[c] = f4{0.f, 0.f, 0.f, 0.f};
     if (c >= NT) continue;
     const int j = 16 * c + L.lr + 1;
 #pragma unroll
@@ -224,7 +229,9 @@ __device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af
       const int e = lo + 16 * c * LD + L.ic[r];
       const float xv = sX[e], pv = sP[e];
       const float v = pv + sigma * (sZ[e] - sZ[e - LD]);
-      const float f = acc[c][r] + eps * tanh_fast(xv);
+      const float thd = tanh_fast(xv);
+      if constexpr (kReuseTanh) thc[c][r] = thd;
+      const float f = acc[c][r] + eps * thd;
       const float pn = (v + lam * f) * c1;
       const float dp = pn - pv;
       rp += ok ? dp * dp : 0.f;
@@ -314,7 +321,7 @@ __device__ void lt_iterate(const LtLane<D>& L, const LtArgs& a, const float (&af
       const bool ok = L.iok[r] && j <= Np - 1;
       const int e = lo + 16 * c * LD + L.ic[r];
       const float xv = sX[e], pv = sP[e], pp = sP[e + LD], zv = sZ[e];
-      const float th = tanh_fast(xv);
+      const float th = kReuseTanh ? thc[c][r] : tanh_fast(xv);
       const float gx = acc[c][r] + eps * (1.f - th * th) * pv;  // -grad_x H
       const float xn = xv - tau * (pv - pp) - td * gx;
       const float dx = xn - xv;
@@ -711,7 +718,7 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
       for (int k = k0; k < k1; k++) {
         float rx = 0.f, rp = 0.f;
         float* so = segx + int64_t(k - k0) * 2 * RL;
-        lt_iterate<D>(L, a, af, atf, S0, S1, S2, Np, NT, delta, eps, so, so + RL, rx, rp);
+        lt_iterate<D, true>(L, a, af, atf, S0, S1, S2, Np, NT, delta, eps, so, so + RL, rx, rp);
       }
       XB = S2;
       PB = S3;
