@@ -745,6 +745,9 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
           ZB[e] = mid ? 0.f - theta * zb : zb + xb;
         }
         __syncthreads();
+        f4 thk[kLtNT];  // tanh(x_j^k): formed in (B2), used again in (C2)
+#pragma unroll
+        for (int c = 0; c < kLtNT; c++) thk[c] = f4{0.f, 0.f, 0.f, 0.f};
         // (B1) node 0: w = x_0 + tau p'_1, wbar = M XB_0; dM += XB_0 w^T is
         // applied once per segment from the staged (XB_0, w) pairs.  With fewer
         // row tiles than waves, the waves past the last tile (whose product
@@ -833,6 +836,7 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
               const float xbm = (j >= 2) ? XB[e - LD] : 0.f;
               const float pp = S1[e], xk = S0[e];
               const float th = tanh_fast(xk), om = 1.f - th * th;
+              thk[c][r] = th;
               // x_N is fixed: no primal step and no (A XB)_N term at j = N
               float pbd = -tau * xb - (prim ? td * acc[c][r] : 0.f) - td * eps * om * xb + tau * xbm;
               if (j == 1) pbd += tau * wbar(L.ic[r] < D ? L.ic[r] : 0);
@@ -862,8 +866,7 @@ __global__ void __launch_bounds__(kLtThreads, 2) k_lt_backward(LtBwdArgs b) {
               const bool ok = L.iok[r] && j <= Np;
               const int e = lo + 16 * c * LD + L.ic[r];
               const float vb = PB[e], vbn = (j < Np) ? PB[e + LD] : 0.f;
-              const float xk = S0[e];
-              const float th = tanh_fast(xk);
+              const float th = thk[c][r];
               // entries past N and in the padding column hold zero in every array
               const float zbo = ZB[e];
               ZB[e] = ok ? zbo + (lam * acc[c][r] + lam * eps * (1.f - th * th) * vb) : zbo;
